@@ -1,0 +1,297 @@
+"""CPU oracle for multi-volume TSDF mapping -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP
+library in ``paper_1511_07106_amd``; neither imports the other.
+
+The numeric core is plain C (``mvf_oracle.c``, built with gcc
+``-O2 -ffp-contract=off``); this module builds it, wraps it with numpy, and
+holds the placement policy (plain Python) and the SE(3) exponential used by
+finite-difference checks.
+
+Paper: Salvato, Finman, Leonard, arXiv 1511.07106.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mvf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-msse2",
+          "-mfpmath=sse", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (always, unless ``force`` is False and a
+    library newer than the source exists)."""
+    if (not force and os.path.exists(_LIB)
+            and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC)):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = C.CDLL(_LIB)
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, np.float32))
+
+
+# --------------------------------------------------------------------------
+# Grid and volumes
+# --------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class OGrid:
+    """World voxel lattice: origin o, voxel size s, truncation in voxels and
+    the weight cap.  Global voxel g has its centre at o + s (g + 1/2)."""
+
+    origin: Tuple[float, float, float]
+    voxel_size: float
+    trunc_voxels: float = 4.0
+    w_max: int = 128
+
+    def arr5(self) -> np.ndarray:
+        return _f32([*self.origin, self.voxel_size, self.trunc_voxels])
+
+    def arr4(self) -> np.ndarray:
+        return _f32([*self.origin, self.voxel_size])
+
+    @property
+    def mu(self) -> float:
+        return float(np.float32(self.trunc_voxels) * np.float32(self.voxel_size))
+
+
+@dataclasses.dataclass
+class OVolume:
+    """Oracle volume state, x-fastest arrays of shape (nz, ny, nx)."""
+
+    dims: Tuple[int, int, int]  # (nx, ny, nz)
+    offset: Tuple[int, int, int]  # global voxel offset h_t
+    F: np.ndarray  # float64 TSDF (truncation units), 0 where unobserved
+    W: np.ndarray  # uint16 weight
+    Cc: np.ndarray  # uint8 RGBA (A = colour weight), shape (nz, ny, nx, 4)
+
+    @classmethod
+    def empty(cls, dims, offset=(0, 0, 0)) -> "OVolume":
+        nx, ny, nz = dims
+        return cls(tuple(int(d) for d in dims), tuple(int(o) for o in offset),
+                   np.zeros((nz, ny, nx), np.float64), np.zeros((nz, ny, nx), np.uint16),
+                   np.zeros((nz, ny, nx, 4), np.uint8))
+
+    def F32(self) -> np.ndarray:
+        return self.F.astype(np.float32)
+
+
+def integrate(vol: OVolume, grid: OGrid, depth: np.ndarray, rgb: Optional[np.ndarray],
+              K, T) -> Tuple[int, int, int]:
+    """Fuse one frame into ``vol`` in place.  Returns (voxels projecting to a
+    valid pixel, voxels updated, voxels in the colour band)."""
+    depth = _f32(depth)
+    h, w = depth.shape
+    rgbc = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
+    if rgbc is not None:
+        assert rgbc.shape == (h, w, 3)
+    stats = np.zeros(3, np.int64)
+    r = lib().orc_integrate(_p(np.asarray(vol.dims, np.int32)), _p(np.asarray(vol.offset, np.int32)),
+                            _p(grid.arr5()), C.c_int(grid.w_max), _p(vol.F), _p(vol.W), _p(vol.Cc),
+                            _p(depth), _p(rgbc), C.c_int(w), C.c_int(h), _p(_f32(K)),
+                            _p(_f32(np.asarray(T).reshape(12))), _p(stats))
+    if r != 0:
+        raise ValueError("orc_integrate rejected its arguments")
+    return int(stats[0]), int(stats[1]), int(stats[2])
+
+
+def raycast(vols: Sequence[OVolume], grid: OGrid, K, T, width: int, height: int,
+            step: float = 0.5, t_far: float = 10.0,
+            F32: Optional[Sequence[np.ndarray]] = None) -> Dict[str, np.ndarray]:
+    """Raycast one view through all volumes.  ``F32`` optionally gives the
+    binary32 TSDF planes to read (default: each volume's F rounded to f32)."""
+    n = len(vols)
+    dims = np.asarray([v.dims for v in vols], np.int32).reshape(n, 3)
+    offs = np.asarray([v.offset for v in vols], np.int32).reshape(n, 3)
+    Fs = [(_f32(F32[i]) if F32 is not None else vols[i].F32()).reshape(-1) for i in range(n)]
+    Ws = [np.ascontiguousarray(v.W).reshape(-1) for v in vols]
+    base = np.zeros(n, np.int64)
+    if n > 1:
+        base[1:] = np.cumsum([f.size for f in Fs])[:-1]
+    Fcat = np.ascontiguousarray(np.concatenate(Fs) if n else np.zeros(1, np.float32))
+    Wcat = np.ascontiguousarray(np.concatenate(Ws) if n else np.zeros(1, np.uint16))
+    P = width * height
+    out = dict(depth=np.zeros(P), vertex=np.zeros((P, 3)), normal=np.zeros((P, 3)),
+               hit=np.zeros(P, np.int32), k=np.zeros(P, np.int32), tstar=np.zeros(P, np.float32),
+               cells=np.zeros((P, 9), np.int32), ambiguous=np.zeros(P, np.uint8))
+    r = lib().orc_raycast(C.c_int(n), _p(dims), _p(offs), _p(Fcat), _p(Wcat), _p(base),
+                          _p(grid.arr4()), C.c_float(step), C.c_float(t_far), _p(_f32(K)),
+                          _p(_f32(np.asarray(T).reshape(12))), C.c_int(width), C.c_int(height),
+                          _p(out["depth"]), _p(out["vertex"]), _p(out["normal"]), _p(out["hit"]),
+                          _p(out["k"]), _p(out["tstar"]), _p(out["cells"]), _p(out["ambiguous"]))
+    if r != 0:
+        raise ValueError("orc_raycast rejected its arguments")
+    shp = (height, width)
+    return dict(depth=out["depth"].reshape(shp), vertex=out["vertex"].reshape(shp + (3,)),
+                normal=out["normal"].reshape(shp + (3,)), hit=out["hit"].reshape(shp),
+                k=out["k"].reshape(shp), tstar=out["tstar"].reshape(shp),
+                cells=out["cells"].reshape(shp + (9,)), ambiguous=out["ambiguous"].reshape(shp))
+
+
+def structure(rc: Dict[str, np.ndarray]) -> np.ndarray:
+    """Per-pixel frozen structure (k, cell_a, cell_b) from a one-volume raycast
+    result, k = -1 where there is no hit."""
+    k = rc["k"].reshape(-1, 1)
+    cells = rc["cells"].reshape(-1, 9)[:, :6]
+    return np.ascontiguousarray(np.concatenate([k, cells], axis=1).astype(np.int32))
+
+
+def depth_fixed(vol: OVolume, grid: OGrid, K, T64, width, height, kcells,
+                step: float = 0.5, F32: Optional[np.ndarray] = None) -> np.ndarray:
+    """Binary64 depth at pose ``T64`` with the discrete structure fixed."""
+    F = _f32(F32 if F32 is not None else vol.F32())
+    out = np.zeros(width * height)
+    lib().orc_depth_fixed(_p(np.asarray(vol.dims, np.int32)), _p(np.asarray(vol.offset, np.int32)),
+                          _p(F), _p(np.ascontiguousarray(vol.W)), _p(grid.arr4()), C.c_float(step),
+                          _p(_f32(K)), _p(np.ascontiguousarray(np.asarray(T64, np.float64).reshape(12))),
+                          C.c_int(width), C.c_int(height), _p(np.ascontiguousarray(kcells, np.int32)),
+                          _p(out))
+    return out.reshape(height, width)
+
+
+def depth_grad(vol: OVolume, grid: OGrid, K, T64, width, height, kcells, grad_depth,
+               step: float = 0.5, F32: Optional[np.ndarray] = None, want_voxels: bool = True):
+    """Gradient of sum(grad_depth * depth) w.r.t. the right pose perturbation
+    (rho, omega) and the voxel values, binary64."""
+    F = _f32(F32 if F32 is not None else vol.F32())
+    gxi = np.zeros(6)
+    gF = np.zeros(vol.W.shape) if want_voxels else None
+    gd = np.ascontiguousarray(np.asarray(grad_depth, np.float64).reshape(-1))
+    lib().orc_depth_grad(_p(np.asarray(vol.dims, np.int32)), _p(np.asarray(vol.offset, np.int32)),
+                         _p(F), _p(np.ascontiguousarray(vol.W)), _p(grid.arr4()), C.c_float(step),
+                         _p(_f32(K)), _p(np.ascontiguousarray(np.asarray(T64, np.float64).reshape(12))),
+                         C.c_int(width), C.c_int(height), _p(np.ascontiguousarray(kcells, np.int32)),
+                         _p(gd), _p(gxi), _p(gF))
+    return gxi, gF
+
+
+# --------------------------------------------------------------------------
+# SE(3)
+# --------------------------------------------------------------------------
+
+
+def se3_exp(xi) -> np.ndarray:
+    """Exp of xi = (rho, omega) as a 3x4 [R | V rho] (binary64)."""
+    xi = np.asarray(xi, np.float64)
+    rho, w = xi[:3], xi[3:]
+    th = float(np.linalg.norm(w))
+    Wx = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    if th < 1e-10:
+        R = np.eye(3) + Wx + 0.5 * Wx @ Wx
+        V = np.eye(3) + 0.5 * Wx + Wx @ Wx / 6.0
+    else:
+        A = np.sin(th) / th
+        B = (1 - np.cos(th)) / th ** 2
+        Cc = (th - np.sin(th)) / th ** 3
+        R = np.eye(3) + A * Wx + B * Wx @ Wx
+        V = np.eye(3) + B * Wx + Cc * Wx @ Wx
+    out = np.zeros((3, 4))
+    out[:, :3] = R
+    out[:, 3] = V @ rho
+    return out
+
+
+def compose(T1, T2) -> np.ndarray:
+    T1 = np.asarray(T1, np.float64).reshape(3, 4)
+    T2 = np.asarray(T2, np.float64).reshape(3, 4)
+    out = np.zeros((3, 4))
+    out[:, :3] = T1[:, :3] @ T2[:, :3]
+    out[:, 3] = T1[:, :3] @ T2[:, 3] + T1[:, 3]
+    return out
+
+
+# --------------------------------------------------------------------------
+# Placement (Dynamic Mapping for SLAM; Insertion and Removal sections)
+# --------------------------------------------------------------------------
+
+
+def placement_counts(depth, K, T, grid: OGrid, d_v: int) -> Dict[Tuple[int, int, int], int]:
+    """c(l): number of valid depth rays whose endpoint falls in placement
+    cell l (cells of side d_v - 2 voxels)."""
+    depth = _f32(depth)
+    h, w = depth.shape
+    cells = np.zeros((h * w, 3), np.int32)
+    valid = np.zeros(h * w, np.uint8)
+    r = lib().orc_placement_cells(_p(depth), C.c_int(w), C.c_int(h), _p(_f32(K)),
+                                  _p(_f32(np.asarray(T).reshape(12))), _p(grid.arr4()),
+                                  C.c_int(d_v), _p(cells), _p(valid))
+    if r != 0:
+        raise ValueError("orc_placement_cells rejected its arguments")
+    keys, cnt = np.unique(cells[valid.astype(bool)], axis=0, return_counts=True)
+    return {tuple(int(x) for x in k): int(c) for k, c in zip(keys, cnt)}
+
+
+def placement_policy(active: Sequence[Tuple[int, int, int]],
+                     counts: Dict[Tuple[int, int, int], int], n_max: int,
+                     beta: float = 1.5):
+    """One insertion/removal step.
+
+    ``active``: cells of the volumes currently in H (unique: a translation
+    identifies a volume).  Returns (new active list, added cells, removed
+    cells).
+
+    Readings: f fills H up to n_max with the highest-count cells not already
+    in H (count descending, then cell lexicographic ascending); afterwards a
+    candidate displaces the lowest-count member of H (g removes it) only
+    while its count exceeds beta times that member's count.  Members whose
+    cell saw no rays this frame count 0; ties among members to remove go to
+    the lexicographically larger cell.  Members never displaced stay.
+    """
+    H = list(dict.fromkeys(tuple(a) for a in active))
+    Hs = set(H)
+    cand = sorted(((c, k) for k, c in counts.items() if k not in Hs and c > 0),
+                  key=lambda ck: (-ck[0], ck[1]))
+    added: List[Tuple[int, int, int]] = []
+    removed: List[Tuple[int, int, int]] = []
+    ci = 0
+    while len(H) < n_max and ci < len(cand):
+        H.append(cand[ci][1])
+        added.append(cand[ci][1])
+        ci += 1
+    while ci < len(cand) and H:
+        c_new, k_new = cand[ci]
+        # lowest-count member; ties -> lexicographically larger cell
+        low = min(H, key=lambda k: (counts.get(k, 0), tuple(-x for x in k)))
+        if c_new > beta * counts.get(low, 0):
+            H.remove(low)
+            if low in added:
+                added.remove(low)
+            else:
+                removed.append(low)
+            H.append(k_new)
+            added.append(k_new)
+            ci += 1
+        else:
+            break
+    return H, added, removed
