@@ -1,0 +1,228 @@
+"""Benchmark: TSDF integration voxel-updates/s and raycast Mpix/s on one
+MI355X, with the fraction of HBM bandwidth the integration kernel reaches,
+and the batched form against the plain per-volume form.
+
+Workload (the KinectFusion-scale equivalence case): synthetic 640x480
+depth + RGB frames (fx = fy = 525, cx = 319.5, cy = 239.5) of a 4 m room
+with 12 seeded spheres/boxes on a seeded 0.5 m/s handheld path at 30 fps
+(300 frames).  One step = one frame: frame preparation, integration into
+every active volume, raycast of the frame's pose.  Inputs are rendered on
+the host and resident in device memory before the timed region.
+
+Phases:
+  single   one 512^3 volume over a 3 m cube (5.86 mm voxels), plain calls
+  tiled    8 volumes of 257^3 at offsets {0,255}^3 (same voxels), plain
+           per-volume calls
+  batched  the same 8 volumes through mvf_step (one persistent launch each
+           for integration and raycast, replayed as a HIP graph)
+
+Prints one JSON line.  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TSDF voxel-updates/s + raycast Mpix/s at 1 GPU; % HBM peak; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+N_VOX = 512
+EXTENT = 3.0
+W_IMG, H_IMG = 640, 480
+# algorithmic bytes of the integration kernel: F (4) + W (2) read and written
+# per updated voxel, colour (4) read and written per band voxel, and the
+# prepared range (4) and colour (4) maps read once per pixel
+B_UPDATED, B_BAND, B_PIXEL = 12, 8, 8
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1511_07106_amd", "csrc", "mvf_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def render_frames(n_frames: int, total: int = 300):
+    from synth import scenes as S
+    seq = S.large_room_sequence(seed=2, n_frames=total)
+    idx = [i % total for i in range(n_frames)]
+    t0 = time.time()
+    frames = seq.frames(sorted(set(idx)), threads=16)
+    by = dict(zip(sorted(set(idx)), frames))
+    log(f"rendered {len(by)} frames in {time.time() - t0:.1f}s")
+    return seq, [(by[i], seq.poses[i]) for i in idx]
+
+
+def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps):
+    origin = (-EXTENT / 2,) * 3
+    s = EXTENT / N_VOX
+    ctx = mvf.Context(timing=True)
+    gid = ctx.grid(origin, s, 4.0, 128)
+    if phase == "single":
+        ctx.volume(gid, (0, 0, 0), (N_VOX,) * 3)
+    else:
+        h = N_VOX // 2
+        for oz in (0, h - 1):
+            for oy in (0, h - 1):
+                for ox in (0, h - 1):
+                    ctx.volume(gid, (ox, oy, oz), (h + 1,) * 3)
+    dev = torch.device("cuda", 0)
+    out = {"depth": torch.empty((H_IMG, W_IMG), device=dev),
+           "vertex": torch.empty((H_IMG, W_IMG, 3), device=dev),
+           "normal": torch.empty((H_IMG, W_IMG, 3), device=dev),
+           "hit": torch.empty((H_IMG, W_IMG), dtype=torch.int32, device=dev)}
+
+    def one(i):
+        d, c = dev_frames[i]
+        if phase == "batched":
+            ctx.step([(0, d, c, poses[i], K)], [out])
+        else:
+            ctx.integrate(d, c, poses[i], K)
+            ctx.raycast(poses[i], K, W_IMG, H_IMG, out=out)
+
+    for i in range(warmup):
+        one(i)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, warmup + steps):
+        one(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.stats()
+    hit_frac = float((out["depth"] > 0).float().mean())
+    ctx.close()
+    r = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "voxels_updated": st["voxels_updated"],
+         "voxels_band": st["voxels_band"], "integrate_ms": st["integrate_ms"], "raycast_ms": st["raycast_ms"],
+         "step_ms": st["step_ms"], "integrate_launches": st["integrate_launches"],
+         "raycast_launches": st["raycast_launches"], "hit_fraction_last": hit_frac}
+    r["voxel_updates_per_s"] = st["voxels_updated"] / wall
+    r["raycast_mpix_s"] = steps * W_IMG * H_IMG / wall / 1e6
+    if st["integrate_ms"] > 0:
+        r["integrate_kernel_voxel_updates_per_s"] = st["voxels_updated"] / (st["integrate_ms"] * 1e-3)
+    if st["raycast_ms"] > 0:
+        r["raycast_kernel_mpix_s"] = steps * W_IMG * H_IMG / (st["raycast_ms"] * 1e-3) / 1e6
+    return r
+
+
+def cpu_baseline(seq_frames, K, n_sample=2):
+    """The CPU oracle on a bounded sample of the same workload: n_sample
+    steps (integrate + raycast) into a 512^3 volume."""
+    import oracle as O
+    og = O.OGrid((-EXTENT / 2,) * 3, EXTENT / N_VOX, 4.0, 128)
+    ov = O.OVolume.empty((N_VOX,) * 3)
+    upd = 0
+    t0 = time.perf_counter()
+    for (d, c), T in seq_frames[:n_sample]:
+        st = O.integrate(ov, og, d, c, K, T)
+        upd += st[1]
+        O.raycast([ov], og, K, T, W_IMG, H_IMG)
+    wall = time.perf_counter() - t0
+    return {"value": upd / wall, "unit": "voxel-updates/s", "cores": int(O.lib().orc_threads()),
+            "kind": "oracle", "sample": f"{n_sample} of the 300 frames (integrate + raycast each) into the "
+                                         f"512^3 volume; {upd} voxel updates in {wall:.1f} s"}
+
+
+def traffic_from_profile(launch_bytes):
+    """HBM bytes per integration launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "integrate_large_room_512_pmc.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_dispatch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--phases", default="single,tiled,batched")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1511_07106_amd as mvf
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    mvf._lib.load()
+    from synth import scenes as S
+    K = S.K_VGA.as_array()
+    n = args.warmup + args.steps
+    seq, frames = render_frames(n)
+    dev = torch.device("cuda", 0)
+    dev_frames = [(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev)) for (d, c), _ in frames]
+    poses = [T for _, T in frames]
+    torch.cuda.synchronize()
+    phases = {}
+    for ph in args.phases.split(","):
+        log(f"phase {ph}")
+        phases[ph] = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps)
+        log(json.dumps(phases[ph]))
+    main_ph = phases.get("single") or next(iter(phases.values()))
+    steps = args.steps
+    # roofline of the integration kernel
+    upd, band = main_ph["voxels_updated"], main_ph["voxels_band"]
+    launches = max(1, main_ph["integrate_launches"])
+    bytes_per_launch = (B_UPDATED * upd + B_BAND * band + B_PIXEL * W_IMG * H_IMG * steps) / launches
+    achieved = None
+    if main_ph["integrate_ms"] > 0:
+        avg_s = main_ph["integrate_ms"] * 1e-3 / launches
+        achieved = bytes_per_launch / avg_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic_from_profile(bytes_per_launch),
+            "kernel": "mvf_integrate_kernel", "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": main_ph["integrate_ms"] / launches if main_ph["integrate_ms"] else None}
+    res = {
+        "metric": METRIC,
+        "value": main_ph["voxel_updates_per_s"],
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_ph["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "large_room_512: one 512^3 volume over 3 m (5.86 mm voxels), 640x480 "
+                               "synthetic depth+RGB, 300-frame handheld path, integrate + raycast every frame",
+                   "volume_voxels": N_VOX ** 3, "image": [W_IMG, H_IMG], "trunc_voxels": 4, "w_max": 128,
+                   "ray_step_voxels": 0.5, "global_batch": 1, "parallelism": "none"},
+        "raycast_mpix_s": main_ph["raycast_mpix_s"],
+        "integrate_kernel_voxel_updates_per_s": main_ph.get("integrate_kernel_voxel_updates_per_s"),
+        "raycast_kernel_mpix_s": main_ph.get("raycast_kernel_mpix_s"),
+        "roofline": roof,
+        "phases": phases,
+    }
+    if "tiled" in phases and "batched" in phases:
+        res["batched_vs_plain_speedup"] = phases["tiled"]["ms_per_step"] / phases["batched"]["ms_per_step"]
+    if not args.no_cpu:
+        log("cpu baseline")
+        res["cpu_baseline"] = cpu_baseline(frames, K)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,301 @@
+/*
+ * mvf.h -- C ABI of the MI355X multi-volume TSDF mapping library (libmvf).
+ *
+ * Implements the data-parallel core of Salvato, Finman, Leonard,
+ * "Multi-Volume High Resolution RGB-D Mapping with Dynamic Volume
+ * Placement" (arXiv 1511.07106): projective TSDF integration of a depth +
+ * RGB frame into every active subvolume, raycasting of all subvolumes into
+ * one shared depth/vertex/normal map, host<->device volume passing under a
+ * device-memory budget, and the ray-endpoint placement rule.  Beside the
+ * plain per-volume form it offers a batched form (all volumes of many
+ * independent scenes in one launch) and a differentiable raycast.
+ *
+ * Conventions (all calls):
+ *  - Units are metres.  Poses T_wc are row-major 3x4 camera-to-world
+ *    [R | t] (x_w = R x_c + t), OpenCV camera axes (x right, y down,
+ *    z forward).  Intrinsics are (fx, fy, cx, cy); pixel (u, v) has its
+ *    centre at integer coordinates.
+ *  - A grid is a world voxel lattice: voxel g (int3) has its centre at
+ *    origin + voxel_size * (g + 1/2).  A volume covers global voxels
+ *    [offset, offset + dims) of one grid ("t_s = t_l + h_t", Volumetric
+ *    Integration section; translations in voxel units, Dynamic Mapping for
+ *    SLAM section).
+ *  - "device" pointers are HIP device memory (e.g. a torch tensor's
+ *    data_ptr()); "host" pointers are ordinary process memory.  `stream` is
+ *    a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *    enqueued on `stream` and the call returns before it completes unless
+ *    the call says it synchronises; device buffers passed in must stay
+ *    valid until the stream reaches the work.
+ *  - Every call returns an mvf_status; on failure mvf_last_error() gives a
+ *    message for the calling thread.  No call throws.  A context is used by
+ *    one host thread at a time.  Asynchronous device faults surface at the
+ *    next synchronising call as MVF_ERR_HIP.
+ *
+ * Numeric contract (shared with the CPU oracle used by the tests): every
+ * decision (voxel -> pixel, update or not, colour band, ray sample in
+ * domain/valid, zero crossing, nearest volume, placement cell) is made in
+ * IEEE binary32 with one rounding per operation in a fixed order and no
+ * fused multiply-add, so integer weights and colours are bit-exact.
+ */
+#ifndef MVF_H
+#define MVF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mvf_status;
+#define MVF_OK 0
+#define MVF_ERR_INVALID_ARG 1 /* bad pointer, size, id or parameter */
+#define MVF_ERR_NOT_FOUND 2   /* unknown grid or volume id */
+#define MVF_ERR_OOM 3         /* device or pinned host allocation failed */
+#define MVF_ERR_BUDGET 4      /* one volume is larger than the device budget */
+#define MVF_ERR_HIP 5         /* a HIP runtime call failed (message has details) */
+#define MVF_ERR_STATE 6       /* call not valid in the object's current state */
+#define MVF_ERR_UNSUPPORTED 7 /* feature not available */
+
+typedef struct mvf_ctx mvf_ctx;
+
+/* Context flags. */
+#define MVF_FLAG_TIMING 1u /* time integrate/raycast kernels with HIP events */
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* device bytes volumes may occupy; 0 = no limit */
+    float ray_step;            /* raycast sample spacing in voxels, (0, 1); 0 = 0.5 */
+    float t_far;               /* raycast range in metres; 0 = 10 */
+    int32_t device;            /* HIP device ordinal */
+    uint32_t flags;            /* MVF_FLAG_* */
+} mvf_config;
+
+typedef struct {
+    float origin[3];    /* world position of the corner of voxel (0,0,0) */
+    float voxel_size;   /* s, metres */
+    float trunc_voxels; /* truncation mu = trunc_voxels * s */
+    uint16_t w_max;     /* running-weight cap, >= 1 */
+    uint16_t reserved;
+} mvf_grid_desc;
+
+typedef struct {
+    int32_t grid_id;
+    int32_t offset[3];  /* h_t: global voxel index of local voxel (0,0,0) */
+    int32_t dims[3];    /* h_r per axis, each in [2, 2048] */
+    int32_t stream_id;  /* scene this volume belongs to, >= 0 */
+} mvf_volume_desc;
+
+typedef struct {
+    float fx, fy, cx, cy;
+} mvf_intrinsics;
+
+typedef struct {
+    const float* depth;  /* device, height rows of depth_pitch floats; z-depth, <=0/NaN/inf = none */
+    const uint8_t* rgb;  /* device, height rows of rgb_pitch bytes, RGB8; may be NULL */
+    int32_t width, height;
+    int32_t depth_pitch; /* floats per row; 0 = width */
+    int32_t rgb_pitch;   /* bytes per row; 0 = 3 * width */
+} mvf_frame;
+
+typedef struct {
+    float* depth;    /* device H*W: camera z of the surface, 0 = no surface */
+    float* vertex;   /* device H*W*3 world position, NaN = none; may be NULL */
+    float* normal;   /* device H*W*3 world unit normal, NaN = none; may be NULL */
+    int32_t* hit;    /* device H*W id of the volume hit, -1 = none; may be NULL */
+    int32_t width, height;
+} mvf_raycast_out;
+
+typedef struct {
+    uint64_t voxels_updated;     /* voxels that passed the truncation test */
+    uint64_t voxels_band;        /* of those, voxels inside the colour band */
+    uint64_t pixels_raycast;     /* output pixels written by raycasts */
+    uint64_t bytes_h2d;          /* volume bytes swapped in */
+    uint64_t bytes_d2h;          /* volume bytes swapped out */
+    uint64_t swaps_in, swaps_out;
+    uint64_t integrate_launches, raycast_launches, step_launches;
+    double integrate_ms;         /* HIP-event time of integrate kernels (MVF_FLAG_TIMING) */
+    double raycast_ms;           /* HIP-event time of raycast kernels (MVF_FLAG_TIMING) */
+    double step_ms;              /* HIP-event time of batched step graphs (MVF_FLAG_TIMING) */
+    uint64_t resident_bytes;     /* device bytes held by volumes now */
+    int32_t resident_volumes;
+    int32_t reserved;
+} mvf_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on cfg->device.  cfg may be NULL (defaults).  Output
+ * *out owns every volume slab and pinned mirror it creates. */
+mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg);
+/* Synchronise and free everything the context owns.  NULL is a no-op. */
+mvf_status mvf_destroy(mvf_ctx* ctx);
+/* Block until all work the context enqueued (any stream) has finished. */
+mvf_status mvf_synchronize(mvf_ctx* ctx);
+/* Change the device budget; volumes above it are swapped out lazily. */
+mvf_status mvf_set_budget(mvf_ctx* ctx, uint64_t bytes);
+/* Synchronising.  Counters since creation or the last reset. */
+mvf_status mvf_get_stats(mvf_ctx* ctx, mvf_stats* out);
+mvf_status mvf_reset_stats(mvf_ctx* ctx);
+const char* mvf_status_string(mvf_status s);
+/* Message of the calling thread's last failure ("" if none). */
+const char* mvf_last_error(void);
+/* Library version string. */
+const char* mvf_version(void);
+
+/* ---- grids and volumes (Initialization; Dynamic Volume Allocation) ---- */
+
+/* Register a voxel lattice shared by volumes (origin, s, mu, W cap). */
+mvf_status mvf_grid_create(mvf_ctx* ctx, const mvf_grid_desc* desc, int32_t* grid_id);
+
+/* Describe a subvolume h = (h_l, h_r, h_t) on a grid.  Its state starts
+ * empty (TSDF 0, weight 0, colour 0); no memory is touched until it is
+ * first used.  It is not active until placed. */
+mvf_status mvf_volume_create(mvf_ctx* ctx, const mvf_volume_desc* desc, int32_t* vol_id);
+/* Forget a volume and release its device slab and host mirror
+ * (synchronises with work using it). */
+mvf_status mvf_volume_destroy(mvf_ctx* ctx, int32_t vol_id);
+/* Add a volume to the active set H: every later integrate/raycast of its
+ * stream processes it (Dynamic Volume Allocation, Input and Output). */
+mvf_status mvf_volume_place(mvf_ctx* ctx, int32_t vol_id);
+/* Remove a volume from H (the removal function g).  Its state is kept.
+ * flags & MVF_EVICT_SWAP_OUT also moves it to host memory now. */
+#define MVF_EVICT_SWAP_OUT 1u
+mvf_status mvf_volume_evict(mvf_ctx* ctx, int32_t vol_id, uint32_t flags);
+/* Explicit memory passing (Memory Passing section; "upload to GPU" and
+ * the download after raycasting): make the volume device-resident, or copy
+ * it to its pinned host mirror and release the device slab.  Copies run on
+ * the context's copy stream, ordered after the work already enqueued on
+ * `stream` and before later work on it. */
+mvf_status mvf_volume_swap_in(mvf_ctx* ctx, int32_t vol_id, void* stream);
+mvf_status mvf_volume_swap_out(mvf_ctx* ctx, int32_t vol_id, void* stream);
+/* Synchronising.  Copy the volume's state to host buffers in canonical
+ * x-fastest layout (index (z*ny + y)*nx + x): F float32 in truncation
+ * units (0 where W == 0), W uint16, rgba 4 bytes per voxel (A = colour
+ * weight).  Any pointer may be NULL to skip that plane. */
+mvf_status mvf_volume_read(mvf_ctx* ctx, int32_t vol_id, float* F, uint16_t* W, uint8_t* rgba);
+/* Synchronising.  Overwrite the volume's state from host buffers in the
+ * same layout (F of voxels with W == 0 is ignored).  NULL planes are set
+ * to their empty value. */
+mvf_status mvf_volume_write(mvf_ctx* ctx, int32_t vol_id, const float* F, const uint16_t* W,
+                            const uint8_t* rgba);
+/* The descriptor a volume was created with (also for volumes the
+ * placement step created). */
+mvf_status mvf_volume_describe(mvf_ctx* ctx, int32_t vol_id, mvf_volume_desc* out);
+/* Resident (1) or not (0), device bytes of its slab, active flag. */
+mvf_status mvf_volume_query(mvf_ctx* ctx, int32_t vol_id, int32_t* resident, uint64_t* bytes,
+                            int32_t* active);
+
+/* ---- per-frame hot path ----------------------------------------------- */
+
+/* Volumetric integration (Volumetric Integration section; Algorithm 1's
+ * voxel loop) of one frame into every active volume of `stream_id` whose
+ * box meets the view frustum.  Volumes not resident are swapped in first;
+ * if they do not all fit in the budget they are processed in waves, the
+ * paper's one-volume-at-a-time memory passing being the smallest case. */
+mvf_status mvf_integrate(mvf_ctx* ctx, int32_t stream_id, const mvf_frame* frame,
+                         const float T_wc[12], const mvf_intrinsics* K, void* stream);
+/* Raycast (Raycasting section; Algorithm 1's pixel loop) every active
+ * volume of `stream_id` into one shared map: per pixel the first
+ * plus-to-minus zero crossing of the trilinear TSDF along the ray, the
+ * nearest over all volumes winning (ties: lower volume id); normal = the
+ * gradient of the trilinear interpolant.  out->width/height give the image
+ * size. */
+mvf_status mvf_raycast(mvf_ctx* ctx, int32_t stream_id, const float T_wc[12],
+                       const mvf_intrinsics* K, const mvf_raycast_out* out, void* stream);
+
+/* ---- batched form ------------------------------------------------------ */
+
+typedef struct {
+    int32_t stream_id;
+    mvf_frame frame;
+    float T_wc[12];
+    mvf_intrinsics K;
+} mvf_stream_frame;
+
+/* Integrate frames[i] into the active volumes of frames[i].stream_id, then
+ * raycast every stream at its frame's pose into outs[i], for all n streams
+ * at once: one persistent integration launch and one persistent raycast
+ * launch over a device volume table, captured once into a HIP graph and
+ * replayed.  Results equal the plain calls bit for bit.  All active
+ * volumes of the streams must fit the budget together (else
+ * MVF_ERR_BUDGET; use the plain calls). */
+mvf_status mvf_step(mvf_ctx* ctx, int32_t n, const mvf_stream_frame* frames,
+                    const mvf_raycast_out* outs, void* stream);
+
+/* ---- placement (Dynamic Mapping for SLAM; Insertion and Removal) -------- */
+
+typedef struct {
+    int32_t grid_id;
+    int32_t d_v;        /* voxels per side of placed volumes (>= 3) */
+    int32_t n_max;      /* most volumes alive at once */
+    float beta;         /* a newcomer must exceed beta x the lowest count; >= 1 */
+} mvf_placement_params;
+
+typedef struct {
+    int32_t n_added, n_removed;
+    int32_t added[64];     /* volume ids created and placed */
+    int32_t removed[64];   /* volume ids evicted (state kept on the host) */
+    int32_t n_cells;       /* distinct endpoint cells this frame */
+    int32_t reserved;
+} mvf_placement_result;
+
+/* Count, per cell k of the placement lattice (side d_v - 2 voxels), the
+ * valid depth rays of `frame` whose endpoint R (D K^-1 [u v 1]) + t falls in
+ * it, then run the insertion f and removal g steps on the stream's volumes
+ * created by this call: keep the n_max highest-count cells with hysteresis
+ * beta; new volumes get offset k (d_v - 2) and dims d_v; removed volumes
+ * are evicted and swapped out.  Synchronises on `stream`. */
+mvf_status mvf_placement_update(mvf_ctx* ctx, int32_t stream_id, const mvf_frame* frame,
+                                const float T_wc[12], const mvf_intrinsics* K,
+                                const mvf_placement_params* p, mvf_placement_result* r,
+                                void* stream);
+/* The endpoint counts alone: up to max_cells (cell xyz, count) tuples written
+ * to host `cells` (3 ints) and `counts`; *n_cells = number of distinct cells.
+ * Synchronises on `stream`. */
+mvf_status mvf_placement_count(mvf_ctx* ctx, const mvf_frame* frame, const float T_wc[12],
+                               const mvf_intrinsics* K, int32_t grid_id, int32_t d_v,
+                               int32_t* cells, int32_t* counts, int32_t max_cells,
+                               int32_t* n_cells, void* stream);
+/* Host-only insertion/removal step on cell keys (no device work).  active:
+ * n_active cells (3 ints each) in H; counts: n_cells (cell, count) pairs.
+ * Writes the new active set (out_active, up to n_max cells), the added and
+ * removed cells (each up to n_active + n_cells) and their numbers. */
+mvf_status mvf_placement_policy(const int32_t* active, int32_t n_active, const int32_t* cells,
+                                const int32_t* counts, int32_t n_cells, int32_t n_max,
+                                float beta, int32_t* out_active, int32_t* n_out,
+                                int32_t* added, int32_t* n_added, int32_t* removed,
+                                int32_t* n_removed);
+
+/* ---- differentiable raycast ------------------------------------------- */
+
+typedef struct {
+    const float* F;      /* device, dims[2] x dims[1] x dims[0] x-fastest, truncation units */
+    const uint16_t* W;   /* device, same layout; W == 0 marks unobserved voxels */
+    int32_t dims[3];
+    int32_t offset[3];
+    float origin[3];
+    float voxel_size;
+} mvf_dense_tsdf;
+
+/* Raycast depth of one dense volume (same rules as mvf_raycast) and a
+ * per-pixel record of the crossing (k of the second sample, -1 = none),
+ * device int32 H*W. */
+mvf_status mvf_diffray_forward(mvf_ctx* ctx, const mvf_dense_tsdf* v, const float T_wc[12],
+                               const mvf_intrinsics* K, int32_t width, int32_t height,
+                               float* depth, int32_t* record, void* stream);
+/* Backward of L given dL/d(depth) (device H*W): with the crossings of the
+ * forward record held fixed, accumulate dL/dF into grad_F (device, same
+ * layout as F; may be NULL) and write dL/dxi for the right pose
+ * perturbation T_wc Exp(xi), xi = (rho, omega), to grad_xi (device, 6
+ * doubles).  The two bracketing ray samples are recomputed, not stored. */
+mvf_status mvf_diffray_backward(mvf_ctx* ctx, const mvf_dense_tsdf* v, const float T_wc[12],
+                                const mvf_intrinsics* K, int32_t width, int32_t height,
+                                const float* grad_depth, const int32_t* record,
+                                float* grad_F, double* grad_xi, void* stream);
+/* Host-only: T_out = T Exp(xi) for xi = (rho, omega) (binary64 3x4). */
+mvf_status mvf_pose_retract(const double T[12], const double xi[6], double T_out[12]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MVF_H */

@@ -132,6 +132,12 @@ def raycast(vols: Sequence[OVolume], grid: OGrid, K, T, width: int, height: int,
     """Raycast one view through all volumes.  ``F32`` optionally gives the
     binary32 TSDF planes to read (default: each volume's F rounded to f32)."""
     n = len(vols)
+    if F32 is not None:
+        if isinstance(F32, np.ndarray) or len(F32) != n:
+            raise TypeError("F32 must be a list with one array per volume")
+        for f, v in zip(F32, vols):
+            if np.asarray(f).shape != v.W.shape:
+                raise ValueError(f"F32 plane of shape {np.asarray(f).shape} for a volume of shape {v.W.shape}")
     dims = np.asarray([v.dims for v in vols], np.int32).reshape(n, 3)
     offs = np.asarray([v.offset for v in vols], np.int32).reshape(n, 3)
     Fs = [(_f32(F32[i]) if F32 is not None else vols[i].F32()).reshape(-1) for i in range(n)]

@@ -136,9 +136,11 @@ int orc_integrate(const int32_t dims[3], const int32_t off[3],
  * z, with lerp(a, b, t) = a (1 - t) + b t); a surface is the first pair of
  * consecutive valid samples going from F > 0 to F <= 0 (front faces only);
  * its distance is the linear interpolation between the two samples; the
- * normal is the gradient of the trilinear interpolant in the cell of the
- * vertex; across volumes the smallest distance wins (ties: lower volume
- * index), as the shared-map rule of the Raycasting section requires.
+ * normal is the gradient, at the vertex, of the trilinear interpolant of the
+ * cell holding the crossing's second sample (a cell whose 8 voxels are all
+ * observed, so the normal never reads an unobserved voxel); across volumes
+ * the smallest distance wins (ties: lower volume index), as the shared-map
+ * rule of the Raycasting section requires.
  * ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -344,7 +346,7 @@ static double eval_crossing64(const orc_vol* v, const float grid[4], double delt
  *  Outputs per pixel (row-major H x W): depth (camera z, 0 when no hit),
  *  vertex and normal (world, x3, NaN when no hit), hit volume index (-1),
  *  k of the crossing's second sample (-1), the binary32 crossing distance,
- *  the cells of the two samples (6 ints) and of the vertex (3 ints), and an
+ *  the cells of the two samples (6 ints) and of the normal (3 ints), and an
  *  ambiguity flag (a sign test with |F| < 1e-5 or F_a - F_b < 1e-3 on the
  *  winning ray).
  */
@@ -358,7 +360,6 @@ int orc_raycast(int nvol, const int32_t* dims, const int32_t* offs,
 {
     if (!(step > 0.0f && step < 1.0f)) return 1;
     const float delta = step * grid[3];
-    const float inv_s = 1.0f / grid[3];
     const int kmax = (int)floorf(t_far / delta);
     double T64[12];
     for (int i = 0; i < 12; ++i) T64[i] = (double)T[i];
@@ -393,16 +394,9 @@ int orc_raycast(int nvol, const int32_t* dims, const int32_t* offs,
             const orc_vol vol = { dims + 3 * best, offs + 3 * best, Fcat + base[best], Wcat + base[best] };
             hit_k[p] = hb.k;
             tstar32[p] = hb.tstar;
-            /* cell of the vertex (binary32 decision, clamped to the domain) */
-            int cv[3];
-            for (int a = 0; a < 3; ++a) {
-                const float x = C[a] + (hb.tstar * dw[a]);
-                const float l = (((x - grid[a]) * inv_s) - 0.5f) - (float)vol.off[a];
-                int c = (int)floorf(l);
-                if (c < 0) c = 0;
-                if (c > vol.dims[a] - 2) c = vol.dims[a] - 2;
-                cv[a] = c;
-            }
+            /* the normal is taken from the cell of the crossing's second sample,
+             * whose 8 voxels are all observed */
+            int cv[3] = { hb.cell_b[0], hb.cell_b[1], hb.cell_b[2] };
             for (int a = 0; a < 3; ++a) {
                 cells[9 * p + a] = hb.cell_a[a];
                 cells[9 * p + 3 + a] = hb.cell_b[a];
@@ -571,3 +565,11 @@ int orc_placement_cells(const float* depth, int width, int height,
     }
     return 0;
 }
+
+/* Threads the oracle's parallel loops use (for reporting CPU timings). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

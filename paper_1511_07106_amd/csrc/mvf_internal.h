@@ -1,0 +1,154 @@
+// Internal types shared by the host runtime (mvf_runtime.cpp) and the HIP
+// kernels (mvf_kernels.hip).  Not part of the public ABI.
+//
+// Device volume layout ("brick-linear"): a volume of dims (nx, ny, nz) is
+// padded to bricks of 8x8x8 voxels, bd = ceil(dims / 8) bricks per axis.
+// Bricks are numbered z-fastest, brick(bx, by, bz) = (bx * bd.y + by) * bd.z
+// + bz, so a column of bricks (fixed bx, by) is one contiguous run.  Inside a
+// brick voxels are x-fastest: (z & 7) * 64 + (y & 7) * 8 + (x & 7); one
+// z-slice of a brick is 64 consecutive elements, exactly one wavefront.
+//
+// Planes, each padded to a 256-byte multiple, in one slab per volume:
+//   F     float32  TSDF in truncation units; NaN while the voxel is
+//                  unobserved (W == 0), so one trilinear read both
+//                  interpolates and tests that all 8 corners were observed
+//   W     uint16   running weight
+//   C     uint32   RGBA8 colour, A = colour weight
+//   flag  uint8    per brick: 1 if some voxel of the brick may hold
+//                  F <= 2^-100 (set by integration, never cleared except by
+//                  a full recompute); 0 guarantees F > 0 or NaN everywhere
+//                  in the brick, which lets the raycast skip it exactly.
+#pragma once
+#include <stdint.h>
+
+namespace mvf {
+
+constexpr int kBrick = 8;
+constexpr int kBrickVox = 512;
+constexpr float kFlagThreshold = 0x1p-100f;
+
+struct DevVolume {
+    float* F;
+    uint16_t* W;
+    uint32_t* C;
+    uint8_t* flag;
+    int32_t dims[3];
+    int32_t off[3];
+    int32_t bd[3];
+    int32_t id;          // public volume id (hit output, tie-break)
+    float o[3];          // grid origin
+    float s;             // voxel size
+    float inv_s;         // 1 / s (binary32, correctly rounded)
+    float mu;            // trunc_voxels * s (binary32)
+    float inv_mu;        // 1 / mu
+    int32_t w_max;
+    int32_t frame;       // index of the stream's frame in the frame table
+    int32_t pad;
+};
+
+struct DevFrame {
+    const float* range;      // H*W: depth * ray-length factor, 0 = invalid
+    const uint32_t* color;   // H*W packed RGB (may be null)
+    float* rmax;             // device scalar: max range of the frame (+mu, for clipping)
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float T[12];
+    // raycast outputs
+    float* depth;
+    float* vertex;
+    float* normal;
+    int32_t* hit;
+    float* best_t;           // per-pixel running best (multi-wave raycast)
+    int32_t* best_id;
+    int32_t out_w, out_h;
+};
+
+struct RayParams {
+    float delta;             // step * s (binary32); all volumes of a call share one grid
+    int32_t kmax;            // floor(t_far / delta)
+};
+
+// 64-bit counters written by kernels
+enum Counter { kCntUpdated = 0, kCntBand = 1, kCntNum = 8 };
+
+// Launch parameters that live in device memory, so that a captured graph
+// replays with new tables (volume set, frame pointers, poses) without
+// re-capture.
+struct LaunchHeader {
+    int32_t nvol;          // entries of the volume table used by integration
+    int32_t total_items;   // integration work items
+    int32_t zchunk;        // bricks per integration item along z
+    int32_t nstreams;      // frames in the frame table
+    int32_t total_tiles;   // raycast pixel tiles over all streams
+    int32_t first_wave;    // raycast: 1 = start from no hit, 0 = merge with best_t/best_id
+    RayParams rp;
+};
+
+// Frame preparation input for one stream.
+struct PrepItem {
+    const float* depth;
+    const uint8_t* rgb;
+    int32_t depth_pitch, rgb_pitch;
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float* range;
+    uint32_t* color;
+    float* rmax;
+};
+
+// Integration work item: a brick column (8x8 voxel columns) of one volume
+// over a chunk of zchunk bricks along z.  Items of table entry v are
+// [item_base[v], item_base[v+1]).
+struct IntegrateLaunch {
+    const LaunchHeader* hdr;
+    const DevVolume* vols;
+    const DevFrame* frames;
+    const int32_t* item_base;  // nvol + 1 prefix sums
+    unsigned long long* counters;
+};
+
+struct RaycastLaunch {
+    const LaunchHeader* hdr;
+    const DevVolume* vols;      // table
+    const DevFrame* frames;     // one per stream
+    const int32_t* lists;       // concatenated per-stream lists of table indices, nearest first
+    const int32_t* list_base;   // per stream: [list_base[s], list_base[s+1])
+    const int32_t* tile_base;   // per stream: first pixel tile; nstreams + 1 entries
+    int32_t tile_w, tile_h;     // pixel tile (tile_w * tile_h == block size)
+};
+
+// Host-side launchers (defined in mvf_kernels.hip).  All return hipError_t
+// as int (0 = success).
+int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream);
+int launch_volume_init(DevVolume v, void* stream);
+int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream);
+int launch_raycast(const RaycastLaunch& L, int blocks, void* stream);
+int launch_brick_summary(DevVolume v, void* stream);
+int launch_to_canonical(DevVolume v, float* F, uint16_t* W, uint32_t* C, void* stream);
+int launch_from_canonical(DevVolume v, const float* F, const uint16_t* W, const uint32_t* C,
+                          void* stream);
+int launch_fill_u64(unsigned long long* p, int n, unsigned long long value, void* stream);
+int launch_placement_clear(unsigned long long* table, int table_size, void* stream);
+int launch_placement_count(const float* depth, int depth_pitch, int width, int height,
+                           float fx, float fy, float cx, float cy, const float* T,
+                           float o0, float o1, float o2, float cell,
+                           unsigned long long* table, int table_size, int* overflow, void* stream);
+
+struct DiffVolume {
+    const float* F;
+    const uint16_t* W;
+    int32_t dims[3];
+    int32_t off[3];
+    float o[3];
+    float s, inv_s;
+};
+int launch_diffray_forward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy,
+                           int width, int height, RayParams rp, float* depth, int32_t* record,
+                           void* stream);
+int launch_diffray_backward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy,
+                            int width, int height, RayParams rp, const float* grad_depth,
+                            const int32_t* record, float* grad_F, double* partials,
+                            int n_partials, double* grad_xi, void* stream);
+int diffray_partials_needed(int width, int height);
+
+}  // namespace mvf

@@ -1,0 +1,1067 @@
+// HIP kernels for gfx950 (MI355X): TSDF integration, multi-volume raycast,
+// brick summaries, layout conversion, placement counting, differentiable
+// raycast.  Built with -ffp-contract=off and IEEE division/sqrt so the
+// decision path reproduces the binary32 contract of the CPU reference
+// bit for bit.  Paper: Salvato, Finman, Leonard, arXiv 1511.07106.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mvf_internal.h"
+
+namespace mvf {
+
+static __host__ __device__ __forceinline__ float qnan() { return __builtin_nanf(""); }
+static __host__ __device__ __forceinline__ float pinf() { return __builtin_inff(); }
+
+static __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+static __host__ __device__ __forceinline__ size_t brick_index(const int bd[3], int bx, int by, int bz) {
+    return ((size_t)bx * bd[1] + by) * bd[2] + bz;
+}
+
+// ---------------------------------------------------------------------------
+// Frame preparation: per pixel the range R = D * lambda along the pixel ray
+// (lambda = |K^-1 [u v 1]|, the same binary32 operations the voxel test
+// uses), 0 for an invalid depth; packed RGB; the frame's maximum range.
+// ---------------------------------------------------------------------------
+__global__ void mvf_reset_rmax_kernel(const PrepItem* items, int n)
+{
+    const int i = threadIdx.x;
+    if (i < n) *items[i].rmax = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __restrict__ items)
+{
+    const PrepItem& it = items[blockIdx.z];
+    const int u = blockIdx.x * 32 + (threadIdx.x & 31);
+    const int v = blockIdx.y * 8 + (threadIdx.x >> 5);
+    float R = 0.0f;
+    if (u < it.width && v < it.height) {
+        const float Dz = it.depth[(size_t)v * it.depth_pitch + u];
+        if (Dz > 0.0f && Dz < INFINITY) {
+            const float a = ((float)u - it.cx) / it.fx;
+            const float b = ((float)v - it.cy) / it.fy;
+            const float lam = sqrtf(((a * a) + (b * b)) + 1.0f);
+            R = Dz * lam;
+        }
+        it.range[(size_t)v * it.width + u] = R;
+        uint32_t c = 0;
+        if (it.rgb) {
+            const uint8_t* q = it.rgb + (size_t)v * it.rgb_pitch + 3 * u;
+            c = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
+        }
+        it.color[(size_t)v * it.width + u] = c;
+    }
+    // block max (non-negative floats order like their bit patterns)
+    float m = R;
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    __shared__ float wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        if (m > 0.0f) atomicMax((unsigned int*)it.rmax, __float_as_uint(m));
+    }
+}
+
+int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream)
+{
+    if (n <= 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(mvf_reset_rmax_kernel, dim3(1), dim3(64 * ((n + 63) / 64)), 0, s, items, n);
+    dim3 grid((max_w + 31) / 32, (max_h + 7) / 8, n);
+    hipLaunchKernelGGL(mvf_frame_prep_kernel, grid, dim3(256), 0, s, items);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Volume initialisation: F = NaN (unobserved), W = 0, C = 0, flags = 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mvf_volume_init_kernel(DevVolume v, size_t nvox, size_t nbricks)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox; i += stride) {
+        v.F[i] = __uint_as_float(0x7fc00000u);
+        v.W[i] = 0;
+        v.C[i] = 0;
+        if (i < nbricks) v.flag[i] = 0;
+    }
+}
+
+int launch_volume_init(DevVolume v, void* stream)
+{
+    const size_t nb = (size_t)v.bd[0] * v.bd[1] * v.bd[2];
+    const size_t nvox = nb * kBrickVox;
+    int blocks = (int)((nvox + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(mvf_volume_init_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, v,
+                       nvox, nb);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Integration.  One wavefront owns an 8x8 tile of voxel columns (one brick
+// column) and walks z through a chunk of bricks; each lane is one column
+// (Volumetric Integration section: one thread per (x, y), iterating z).  A
+// z-slice of a brick is 64 consecutive voxels, so every load/store of the
+// wave is one contiguous 256-byte (F, C) or 128-byte (W) access.  A
+// conservative per-column z interval (frustum, near plane, farthest range
+// of the frame) limits the walk; bricks no lane needs are skipped with a
+// ballot; the exact binary32 test decides every visited voxel.
+// ---------------------------------------------------------------------------
+
+// Conservative interval of local z (inclusive lo, exclusive hi) for which a
+// voxel of this column can pass the exact test.  Each condition is a
+// half-line a + b z >= 0 of the affine camera-frame position p(z); margins
+// (1 px, 1 mm, 2 voxels) dominate the binary32 rounding of the exact test.
+static __device__ __forceinline__ void clip_halfline(float a, float b, float& zl, float& zh)
+{
+    if (b > 0.0f) {
+        zl = fmaxf(zl, -a / b - 1.0f);
+    } else if (b < 0.0f) {
+        zh = fminf(zh, -a / b + 2.0f);
+    } else if (a < 0.0f) {
+        zh = -1e30f;
+    }
+}
+
+__global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
+{
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int total_waves = gridDim.x * wpb;
+    unsigned long long n_upd = 0, n_band = 0;
+    const int total_items = L.hdr->total_items;
+    const int nvol = L.hdr->nvol;
+    const int zchunk = L.hdr->zchunk;
+
+    for (int item = wave_uniform(blockIdx.x * wpb + wib); item < total_items; item += total_waves) {
+        // volume owning this item
+        int lo = 0, hi = nvol - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.item_base[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const DevVolume V = L.vols[lo];
+        const DevFrame& Fr = L.frames[V.frame];
+        const int local = item - L.item_base[lo];
+        const int ncols = V.bd[0] * V.bd[1];
+        const int zc = local / ncols;
+        const int col = local - zc * ncols;
+        const int byi = col / V.bd[0];
+        const int bxi = col - byi * V.bd[0];
+        const int bz0 = zc * zchunk;
+        const int bz1 = min(bz0 + zchunk, V.bd[2]);
+
+        const float T0 = Fr.T[0], T1 = Fr.T[1], T2 = Fr.T[2], T3 = Fr.T[3];
+        const float T4 = Fr.T[4], T5 = Fr.T[5], T6 = Fr.T[6], T7 = Fr.T[7];
+        const float T8 = Fr.T[8], T9 = Fr.T[9], T10 = Fr.T[10], T11 = Fr.T[11];
+        const float fx = Fr.fx, fy = Fr.fy, cx = Fr.cx, cy = Fr.cy;
+        const int W = Fr.width, H = Fr.height;
+        const float fW = (float)W, fH = (float)H;
+
+        const int x = bxi * kBrick + (lane & 7);
+        const int y = byi * kBrick + (lane >> 3);
+        const bool col_ok = x < V.dims[0] && y < V.dims[1];
+        // column constants of the binary32 contract
+        const float xw_x = V.o[0] + (V.s * ((float)(V.off[0] + x) + 0.5f));
+        const float xw_y = V.o[1] + (V.s * ((float)(V.off[1] + y) + 0.5f));
+        const float dx = xw_x - T3;
+        const float dy = xw_y - T7;
+        const float Px = (T0 * dx) + (T4 * dy);
+        const float Py = (T1 * dx) + (T5 * dy);
+        const float Pz = (T2 * dx) + (T6 * dy);
+
+        // conservative z interval of this column
+        float zl = (float)(bz0 * kBrick), zh = (float)min(bz1 * kBrick, V.dims[2]);
+        {
+            const float A = (V.o[2] + V.s * ((float)V.off[2] + 0.5f)) - T11;
+            const float ax = Px + T8 * A, bx = T8 * V.s;
+            const float ay = Py + T9 * A, by = T9 * V.s;
+            const float az = Pz + T10 * A, bzc = T10 * V.s;
+            const float E = 1e-3f;
+            clip_halfline(az + 2.0f * V.s, bzc, zl, zh);
+            clip_halfline(fx * ax + (cx + 1.5f) * az + fx * E, fx * bx + (cx + 1.5f) * bzc, zl, zh);
+            clip_halfline(-fx * ax + (fW + 0.5f - cx) * az + fx * E, -fx * bx + (fW + 0.5f - cx) * bzc, zl, zh);
+            clip_halfline(fy * ay + (cy + 1.5f) * az + fy * E, fy * by + (cy + 1.5f) * bzc, zl, zh);
+            clip_halfline(-fy * ay + (fH + 0.5f - cy) * az + fy * E, -fy * by + (fH + 0.5f - cy) * bzc, zl, zh);
+            const float rfar = *Fr.rmax + V.mu + 2.0f * V.s;
+            clip_halfline(rfar - az, -bzc, zl, zh);
+        }
+        int zlo = (int)fmaxf(zl, -1.0f), zhi = (int)fminf(fmaxf(zh, -1.0f), 1e8f);
+        if (!col_ok) { zlo = 0; zhi = 0; }
+        zlo = max(zlo, bz0 * kBrick);
+        zhi = min(zhi, min(bz1 * kBrick, V.dims[2]));
+
+        const size_t colbase = brick_index(V.bd, bxi, byi, 0) * kBrickVox + lane;
+        bool any_flag = false;
+        for (int bz = bz0; bz < bz1; ++bz) {
+            const int zb = bz * kBrick;
+            const bool mine = zlo < zb + kBrick && zhi > zb;
+            if (__ballot(mine) == 0) continue;
+            const size_t base = colbase + (size_t)bz * kBrickVox;
+            float sdfv[kBrick];
+            int pixv[kBrick];
+            unsigned updm = 0;
+#pragma unroll
+            for (int zz = 0; zz < kBrick; ++zz) {
+                const int z = zb + zz;
+                sdfv[zz] = 0.0f;
+                pixv[zz] = 0;
+                if (z >= zlo && z < zhi) {
+                    const float xw_z = V.o[2] + (V.s * ((float)(V.off[2] + z) + 0.5f));
+                    const float dz = xw_z - T11;
+                    const float px = Px + (T8 * dz);
+                    const float py = Py + (T9 * dz);
+                    const float pz = Pz + (T10 * dz);
+                    if (pz > 0.0f) {
+                        const float iz = 1.0f / pz;
+                        const float uf = ((fx * px) * iz) + cx;
+                        const float vf = ((fy * py) * iz) + cy;
+                        const float ur = floorf(uf + 0.5f);
+                        const float vr = floorf(vf + 0.5f);
+                        if (ur >= 0.0f && ur < fW && vr >= 0.0f && vr < fH) {
+                            const int pix = (int)vr * W + (int)ur;
+                            const float R = Fr.range[pix];
+                            if (R > 0.0f) {
+                                const float rho = sqrtf(((px * px) + (py * py)) + (pz * pz));
+                                const float sdf = R - rho;
+                                if (!(sdf < -V.mu)) {
+                                    updm |= 1u << zz;
+                                    sdfv[zz] = sdf;
+                                    pixv[zz] = pix;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            float Fo[kBrick];
+            uint16_t Wo[kBrick];
+#pragma unroll
+            for (int zz = 0; zz < kBrick; ++zz) {
+                if (updm & (1u << zz)) {
+                    Fo[zz] = V.F[base + zz * 64];
+                    Wo[zz] = V.W[base + zz * 64];
+                }
+            }
+            bool flag_here = false;
+#pragma unroll
+            for (int zz = 0; zz < kBrick; ++zz) {
+                if (updm & (1u << zz)) {
+                    const size_t i = base + zz * 64;
+                    const float sdf = sdfv[zz];
+                    const float phi = fminf(1.0f, sdf * V.inv_mu);
+                    const int w = Wo[zz];
+                    const float Wf = (float)w;
+                    const float Fn = (w == 0) ? phi : (fmaf(Fo[zz], Wf, phi) / (Wf + 1.0f));
+                    V.F[i] = Fn;
+                    V.W[i] = (uint16_t)min(w + 1, V.w_max);
+                    flag_here |= Fn <= kFlagThreshold;
+                    ++n_upd;
+                    if (sdf <= V.mu) {
+                        ++n_band;
+                        if (Fr.color) {
+                            const uint32_t obs = Fr.color[pixv[zz]];
+                            const uint32_t c = V.C[i];
+                            const uint32_t Aw = c >> 24;
+                            const uint32_t r = (((c & 255u) * Aw + (obs & 255u) + ((Aw + 1u) >> 1)) / (Aw + 1u));
+                            const uint32_t g = ((((c >> 8) & 255u) * Aw + ((obs >> 8) & 255u) + ((Aw + 1u) >> 1)) / (Aw + 1u));
+                            const uint32_t b = ((((c >> 16) & 255u) * Aw + ((obs >> 16) & 255u) + ((Aw + 1u) >> 1)) / (Aw + 1u));
+                            const uint32_t An = Aw + 1u < 255u ? Aw + 1u : 255u;
+                            V.C[i] = r | (g << 8) | (b << 16) | (An << 24);
+                        }
+                    }
+                }
+            }
+            if (__ballot(flag_here) != 0 && lane == 0)
+                V.flag[brick_index(V.bd, bxi, byi, bz)] = 1;
+            any_flag |= flag_here;
+        }
+        (void)any_flag;
+    }
+    // one atomic per wave for the counters
+    for (int o = 32; o >= 1; o >>= 1) {
+        n_upd += __shfl_xor(n_upd, o);
+        n_band += __shfl_xor(n_band, o);
+    }
+    if (lane == 0 && L.counters && (n_upd | n_band)) {
+        atomicAdd(&L.counters[kCntUpdated], n_upd);
+        atomicAdd(&L.counters[kCntBand], n_band);
+    }
+}
+
+int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream)
+{
+    if (blocks <= 0) return 0;
+    hipLaunchKernelGGL(mvf_integrate_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, L);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Raycast.  One thread per pixel; a 256-thread block covers a 16x16 pixel
+// tile (4 wavefronts of 8x8-ish coherent rays), tiles are assigned so that
+// neighbouring tiles land on the same XCD (shared L2 for the voxels they
+// gather).  Each ray walks the global sample lattice t_k = k delta through
+// every volume of its stream (nearest first), skipping runs of samples
+// whose cell lies in bricks flagged "no F <= 0" (exact: such samples can
+// never be the far end of a plus-to-minus crossing), and keeps the nearest
+// crossing over all volumes.
+// ---------------------------------------------------------------------------
+static __host__ __device__ __forceinline__ float lerp32(float a, float b, float t) { return (a * (1.0f - t)) + (b * t); }
+
+struct Ray {
+    float C[3];
+    float dw[3];
+};
+
+// local continuous voxel coordinate of sample k in volume V (binary32 contract)
+static __host__ __device__ __forceinline__ void sample_coord(const DevVolume& V, const Ray& r, float tk, float l[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float x = r.C[a] + (tk * r.dw[a]);
+        const float c = ((x - V.o[a]) * V.inv_s) - 0.5f;
+        l[a] = c - (float)V.off[a];
+    }
+}
+
+static __host__ __device__ __forceinline__ bool in_domain(const DevVolume& V, const float l[3])
+{
+    return l[0] >= 0.0f && l[0] < (float)(V.dims[0] - 1) && l[1] >= 0.0f &&
+           l[1] < (float)(V.dims[1] - 1) && l[2] >= 0.0f && l[2] < (float)(V.dims[2] - 1);
+}
+
+// 8 corner values of the cell with base i (brick-linear addressing)
+static __host__ __device__ __forceinline__ void gather8(const DevVolume& V, const int i[3], float c[8])
+{
+    const size_t base = brick_index(V.bd, i[0] >> 3, i[1] >> 3, i[2] >> 3) * kBrickVox +
+                        (size_t)(((i[2] & 7) << 6) | ((i[1] & 7) << 3) | (i[0] & 7));
+    const size_t sx = ((i[0] & 7) == 7) ? (size_t)V.bd[1] * V.bd[2] * kBrickVox - 7 : 1;
+    const size_t sy = ((i[1] & 7) == 7) ? (size_t)V.bd[2] * kBrickVox - 56 : 8;
+    const size_t sz = ((i[2] & 7) == 7) ? (size_t)(kBrickVox - 448) : 64;
+    const float* F = V.F;
+    c[0] = F[base];
+    c[1] = F[base + sx];
+    c[2] = F[base + sy];
+    c[3] = F[base + sy + sx];
+    c[4] = F[base + sz];
+    c[5] = F[base + sz + sx];
+    c[6] = F[base + sz + sy];
+    c[7] = F[base + sz + sy + sx];
+}
+
+// trilinear value in the contract's order (x, then y, then z); NaN when a
+// corner is unobserved
+static __host__ __device__ __forceinline__ float trilinear(const float c[8], const float f[3])
+{
+    const float c00 = lerp32(c[0], c[1], f[0]);
+    const float c10 = lerp32(c[2], c[3], f[0]);
+    const float c01 = lerp32(c[4], c[5], f[0]);
+    const float c11 = lerp32(c[6], c[7], f[0]);
+    const float c0 = lerp32(c00, c10, f[1]);
+    const float c1 = lerp32(c01, c11, f[1]);
+    return lerp32(c0, c1, f[2]);
+}
+
+// Evaluate sample with local coordinate l: returns validity, value.
+static __host__ __device__ __forceinline__ bool eval_sample(const DevVolume& V, const float l[3], float& Fk)
+{
+    int i[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float fl = floorf(l[a]);
+        i[a] = (int)fl;
+        f[a] = l[a] - fl;
+    }
+    float c[8];
+    gather8(V, i, c);
+    Fk = trilinear(c, f);
+    return !isnan(Fk);
+}
+
+// Conservative sample range [k0, k1] of the ray inside V's domain box grown
+// by one voxel, plus two samples each side.
+static __host__ __device__ __forceinline__ void ray_k_range(const DevVolume& V, const Ray& r, float delta, int kmax,
+                                                   int& k0, int& k1)
+{
+    float t0 = 0.0f, t1 = (float)kmax * delta;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float lo = V.o[a] + V.s * ((float)V.off[a] + 0.5f) - V.s;
+        const float hi = V.o[a] + V.s * ((float)V.off[a] + (float)V.dims[a] - 0.5f) + V.s;
+        if (r.dw[a] == 0.0f) {
+            if (r.C[a] < lo || r.C[a] > hi) { k0 = 1; k1 = 0; return; }
+        } else {
+            float ta = (lo - r.C[a]) / r.dw[a], tb = (hi - r.C[a]) / r.dw[a];
+            if (ta > tb) { const float t = ta; ta = tb; tb = t; }
+            t0 = fmaxf(t0, ta);
+            t1 = fminf(t1, tb);
+        }
+    }
+    if (!(t0 <= t1)) { k0 = 1; k1 = 0; return; }
+    k0 = max(1, (int)floorf(t0 / delta) - 2);
+    k1 = min(kmax, (int)ceilf(t1 / delta) + 2);
+}
+
+// Is some brick holding a corner of the cell with base i flagged?  Also
+// returns the brick box [blo, bhi] that was checked.
+static __host__ __device__ __forceinline__ bool cell_flagged(const DevVolume& V, const int i[3], int blo[3], int bhi[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        blo[a] = i[a] >> 3;
+        bhi[a] = ((i[a] & 7) == 7) ? blo[a] + 1 : blo[a];
+    }
+    for (int bx = blo[0]; bx <= bhi[0]; ++bx)
+        for (int by = blo[1]; by <= bhi[1]; ++by)
+            for (int bz = blo[2]; bz <= bhi[2]; ++bz)
+                if (V.flag[brick_index(V.bd, bx, by, bz)]) return true;
+    return false;
+}
+
+// March one volume.  Returns true with t* and k when a crossing nearer than
+// (best_t, best_id) exists.
+static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, float delta, int kmax,
+                                    float best_t, int best_id, float& tstar, int& kstar, int cell[3])
+{
+    int k0, k1;
+    ray_k_range(V, r, delta, kmax, k0, k1);
+    if (k0 > k1) return false;
+    {
+        const float t0 = (float)k0 * delta;
+        if (t0 > best_t || (t0 == best_t && V.id > best_id)) return false;
+    }
+    // per-sample advance in local voxel units (for skipping only)
+    float dl[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dl[a] = delta * r.dw[a] * V.inv_s;
+
+    int prev_k = -2;     // index of the last evaluated sample
+    bool prev_ok = false;
+    float Fprev = 0.0f;
+    int k = k0;
+    while (k <= k1) {
+        if ((float)(k - 1) * delta > best_t) break;   // nothing nearer can follow
+        const float tk = (float)k * delta;
+        float l[3];
+        sample_coord(V, r, tk, l);
+        if (!in_domain(V, l)) {
+            prev_k = k; prev_ok = false;
+            ++k;
+            continue;
+        }
+        int i[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) i[a] = (int)floorf(l[a]);
+        int blo[3], bhi[3];
+        if (!cell_flagged(V, i, blo, bhi)) {
+            // samples whose cells stay inside the checked bricks cannot hold F <= 0
+            float m = 1e30f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (dl[a] > 0.0f) m = fminf(m, ((float)(8 * bhi[a] + 7) - 0.01f - l[a]) / dl[a]);
+                else if (dl[a] < 0.0f) m = fminf(m, (l[a] - ((float)(8 * blo[a]) + 0.01f)) / -dl[a]);
+            }
+            int jump = (int)fminf(fmaxf(m, 0.0f), 4096.0f);
+            if (jump < 1) jump = 1;
+            prev_ok = false;
+            prev_k = -2;
+            k += jump;
+            continue;
+        }
+        if (prev_k != k - 1) {
+            // re-evaluate the previous sample (skipped or never seen)
+            float lp[3];
+            sample_coord(V, r, (float)(k - 1) * delta, lp);
+            prev_ok = in_domain(V, lp) && eval_sample(V, lp, Fprev);
+        }
+        float Fk;
+        const bool ok = eval_sample(V, l, Fk);
+        if (prev_ok && ok && Fprev > 0.0f && Fk <= 0.0f) {
+            const float ta = (float)(k - 1) * delta;
+            const float ts = ta + ((delta * Fprev) / (Fprev - Fk));
+            if (ts < best_t || (ts == best_t && V.id < best_id)) {
+                tstar = ts;
+                kstar = k;
+                cell[0] = i[0]; cell[1] = i[1]; cell[2] = i[2];
+                return true;
+            }
+            return false;
+        }
+        prev_k = k;
+        prev_ok = ok;
+        Fprev = Fk;
+        ++k;
+    }
+    return false;
+}
+
+// unit normal: the gradient, at world point x, of the trilinear interpolant
+// of the given cell (the cell of the crossing's second sample, whose 8
+// voxels are all observed)
+static __host__ __device__ void surface_normal(const DevVolume& V, const float x[3], const int i[3], float n[3])
+{
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float l = (((x[a] - V.o[a]) * V.inv_s) - 0.5f) - (float)V.off[a];
+        f[a] = l - (float)i[a];
+    }
+    float c[8];
+    gather8(V, i, c);
+    const float gx0 = lerp32(c[1] - c[0], c[3] - c[2], f[1]);
+    const float gx1 = lerp32(c[5] - c[4], c[7] - c[6], f[1]);
+    const float gx = lerp32(gx0, gx1, f[2]);
+    const float c00 = lerp32(c[0], c[1], f[0]);
+    const float c10 = lerp32(c[2], c[3], f[0]);
+    const float c01 = lerp32(c[4], c[5], f[0]);
+    const float c11 = lerp32(c[6], c[7], f[0]);
+    const float gy = lerp32(c10 - c00, c11 - c01, f[2]);
+    const float gz = lerp32(c01, c11, f[1]) - lerp32(c00, c10, f[1]);
+    const float nn = sqrtf(gx * gx + gy * gy + gz * gz);
+    if (nn > 0.0f) {
+        const float inv = 1.0f / nn;
+        n[0] = gx * inv; n[1] = gy * inv; n[2] = gz * inv;
+    } else {
+        n[0] = n[1] = n[2] = qnan();
+    }
+}
+
+static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v);
+
+__global__ __launch_bounds__(256) void mvf_raycast_kernel(RaycastLaunch L)
+{
+    const LaunchHeader H = *L.hdr;
+    // XCD-aware order: hardware deals blocks round-robin over 8 XCDs; give
+    // each XCD a contiguous run of tiles, then each block a contiguous chunk.
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int q = nb >> 3, rr = nb & 7, xcd = b & 7, j = b >> 3;
+    const int chunk = xcd * q + min(xcd, rr) + j;
+    const int per = (H.total_tiles + nb - 1) / nb;
+    const int t_begin = chunk * per;
+    const int t_end = min(t_begin + per, H.total_tiles);
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        int s = 0;
+        while (s + 1 < H.nstreams && L.tile_base[s + 1] <= tile) ++s;
+        s = wave_uniform(s);
+        const DevFrame& Fr = L.frames[s];
+        const int local = tile - L.tile_base[s];
+        const int tiles_x = (Fr.out_w + L.tile_w - 1) / L.tile_w;
+        const int ty = local / tiles_x, tx = local - ty * tiles_x;
+        const int u = tx * L.tile_w + (int)(threadIdx.x % L.tile_w);
+        const int v = ty * L.tile_h + (int)(threadIdx.x / L.tile_w);
+        if (u < Fr.out_w && v < Fr.out_h) raycast_pixel(L, H, s, u, v);
+    }
+}
+
+static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v)
+{
+    const DevFrame& Fr = L.frames[s];
+    const size_t p = (size_t)v * Fr.out_w + u;
+
+    // ray (binary32 contract)
+    Ray r;
+    float dh[3];
+    {
+        const float dc0 = ((float)u - Fr.cx) / Fr.fx;
+        const float dc1 = ((float)v - Fr.cy) / Fr.fy;
+        const float n = sqrtf(((dc0 * dc0) + (dc1 * dc1)) + (1.0f * 1.0f));
+        const float inv_n = 1.0f / n;
+        dh[0] = dc0 * inv_n;
+        dh[1] = dc1 * inv_n;
+        dh[2] = 1.0f * inv_n;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.dw[a] = ((Fr.T[4 * a + 0] * dh[0]) + (Fr.T[4 * a + 1] * dh[1])) + (Fr.T[4 * a + 2] * dh[2]);
+            r.C[a] = Fr.T[4 * a + 3];
+        }
+    }
+    float best_t = pinf();
+    int best_id = 0x7fffffff;
+    int best_vol = -1;
+    int best_cell[3] = {0, 0, 0};
+    if (!H.first_wave) {
+        const int prev = Fr.best_id[p];
+        if (prev >= 0) { best_t = Fr.best_t[p]; best_id = prev; }
+    }
+    const int l0 = L.list_base[s], l1 = L.list_base[s + 1];
+    for (int li = l0; li < l1; ++li) {
+        const DevVolume& V = L.vols[L.lists[li]];
+        float ts;
+        int ks, cell[3];
+        if (march_volume(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell)) {
+            best_t = ts;
+            best_id = V.id;
+            best_vol = L.lists[li];
+            best_cell[0] = cell[0]; best_cell[1] = cell[1]; best_cell[2] = cell[2];
+        }
+    }
+    if (best_vol >= 0) {
+        const DevVolume& V = L.vols[best_vol];
+        float x[3], n[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] = r.C[a] + (best_t * r.dw[a]);
+        surface_normal(V, x, best_cell, n);
+        Fr.depth[p] = best_t * dh[2];
+        if (Fr.vertex) { Fr.vertex[3 * p] = x[0]; Fr.vertex[3 * p + 1] = x[1]; Fr.vertex[3 * p + 2] = x[2]; }
+        if (Fr.normal) { Fr.normal[3 * p] = n[0]; Fr.normal[3 * p + 1] = n[1]; Fr.normal[3 * p + 2] = n[2]; }
+        if (Fr.hit) Fr.hit[p] = V.id;
+        if (Fr.best_t) { Fr.best_t[p] = best_t; Fr.best_id[p] = best_id; }
+    } else if (H.first_wave) {
+        const float qn = qnan();
+        Fr.depth[p] = 0.0f;
+        if (Fr.vertex) { Fr.vertex[3 * p] = qn; Fr.vertex[3 * p + 1] = qn; Fr.vertex[3 * p + 2] = qn; }
+        if (Fr.normal) { Fr.normal[3 * p] = qn; Fr.normal[3 * p + 1] = qn; Fr.normal[3 * p + 2] = qn; }
+        if (Fr.hit) Fr.hit[p] = -1;
+        if (Fr.best_t) { Fr.best_t[p] = pinf(); Fr.best_id[p] = -1; }
+    }
+}
+
+int launch_raycast(const RaycastLaunch& L, int blocks, void* stream)
+{
+    if (blocks <= 0) return 0;
+    hipLaunchKernelGGL(mvf_raycast_kernel, dim3(blocks), dim3(L.tile_w * L.tile_h), 0,
+                       (hipStream_t)stream, L);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Brick summary: exact recompute of the per-brick "may hold F <= 0" flags
+// (after a volume is written from the host).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mvf_brick_summary_kernel(DevVolume v, size_t nbricks)
+{
+    const int lane = threadIdx.x & 63;
+    const size_t brick = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (brick >= nbricks) return;
+    bool any = false;
+    for (int j = lane; j < kBrickVox; j += 64) any |= v.F[brick * kBrickVox + j] <= kFlagThreshold;
+    const unsigned long long m = __ballot(any);
+    if (lane == 0) v.flag[brick] = m ? 1 : 0;
+}
+
+int launch_brick_summary(DevVolume v, void* stream)
+{
+    const size_t nb = (size_t)v.bd[0] * v.bd[1] * v.bd[2];
+    hipLaunchKernelGGL(mvf_brick_summary_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0,
+                       (hipStream_t)stream, v, nb);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion between brick-linear device planes and canonical
+// x-fastest planes.  One thread per canonical voxel.
+// ---------------------------------------------------------------------------
+static __device__ __forceinline__ size_t brick_offset(const DevVolume& v, int x, int y, int z)
+{
+    return brick_index(v.bd, x >> 3, y >> 3, z >> 3) * kBrickVox +
+           (size_t)(((z & 7) << 6) | ((y & 7) << 3) | (x & 7));
+}
+
+__global__ __launch_bounds__(256) void mvf_to_canonical_kernel(DevVolume v, float* F, uint16_t* W, uint32_t* C)
+{
+    const size_t n = (size_t)v.dims[0] * v.dims[1] * v.dims[2];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int x = (int)(i % v.dims[0]);
+        const int y = (int)((i / v.dims[0]) % v.dims[1]);
+        const int z = (int)(i / ((size_t)v.dims[0] * v.dims[1]));
+        const size_t b = brick_offset(v, x, y, z);
+        const uint16_t w = v.W[b];
+        if (F) F[i] = w ? v.F[b] : 0.0f;
+        if (W) W[i] = w;
+        if (C) C[i] = v.C[b];
+    }
+}
+
+__global__ __launch_bounds__(256) void mvf_from_canonical_kernel(DevVolume v, const float* F, const uint16_t* W,
+                                                                 const uint32_t* C)
+{
+    const size_t n = (size_t)v.dims[0] * v.dims[1] * v.dims[2];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int x = (int)(i % v.dims[0]);
+        const int y = (int)((i / v.dims[0]) % v.dims[1]);
+        const int z = (int)(i / ((size_t)v.dims[0] * v.dims[1]));
+        const size_t b = brick_offset(v, x, y, z);
+        const uint16_t w = W ? W[i] : 0;
+        v.W[b] = w;
+        v.F[b] = (w && F) ? F[i] : (w ? 0.0f : __uint_as_float(0x7fc00000u));
+        v.C[b] = C ? C[i] : 0u;
+    }
+}
+
+static int conv_blocks(const DevVolume& v)
+{
+    const size_t n = (size_t)v.dims[0] * v.dims[1] * v.dims[2];
+    size_t b = (n + 255) / 256;
+    return (int)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
+}
+
+int launch_to_canonical(DevVolume v, float* F, uint16_t* W, uint32_t* C, void* stream)
+{
+    hipLaunchKernelGGL(mvf_to_canonical_kernel, dim3(conv_blocks(v)), dim3(256), 0, (hipStream_t)stream,
+                       v, F, W, C);
+    return (int)hipGetLastError();
+}
+
+int launch_from_canonical(DevVolume v, const float* F, const uint16_t* W, const uint32_t* C, void* stream)
+{
+    hipLaunchKernelGGL(mvf_from_canonical_kernel, dim3(conv_blocks(v)), dim3(256), 0, (hipStream_t)stream,
+                       v, F, W, C);
+    return (int)hipGetLastError();
+}
+
+__global__ void mvf_fill_u64_kernel(unsigned long long* p, int n, unsigned long long value)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+int launch_fill_u64(unsigned long long* p, int n, unsigned long long value, void* stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(mvf_fill_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, p, n,
+                       value);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Placement counting (Dynamic Mapping for SLAM section): per valid pixel,
+// endpoint e = R (D K^-1 [u v 1]) + t, cell k = floor((e - o) / cell), then
+// an open-addressing hash count.  Slot h holds the packed cell key in
+// table[2h] (all ones = empty) and its count in table[2h + 1].
+// ---------------------------------------------------------------------------
+static __device__ __forceinline__ unsigned long long pack_cell(int kx, int ky, int kz)
+{
+    return ((unsigned long long)(uint32_t)(kx + (1 << 20)) << 42) |
+           ((unsigned long long)(uint32_t)(ky + (1 << 20)) << 21) |
+           (unsigned long long)(uint32_t)(kz + (1 << 20));
+}
+
+__global__ __launch_bounds__(256) void mvf_placement_count_kernel(
+    const float* __restrict__ depth, int depth_pitch, int width, int height, float fx, float fy,
+    float cx, float cy, const float* __restrict__ Tp, float o0, float o1, float o2, float cell,
+    unsigned long long* table, int table_size, int* overflow)
+{
+    const int u = blockIdx.x * 32 + (threadIdx.x & 31);
+    const int v = blockIdx.y * 8 + (threadIdx.x >> 5);
+    if (u >= width || v >= height) return;
+    const float Dz = depth[(size_t)v * depth_pitch + u];
+    if (!(Dz > 0.0f && Dz < INFINITY)) return;
+    float T[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) T[i] = Tp[i];
+    const float ra = ((float)u - cx) / fx;
+    const float rb = ((float)v - cy) / fy;
+    const float q0 = Dz * ra, q1 = Dz * rb, q2 = Dz;
+    const float o[3] = { o0, o1, o2 };
+    int k[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float e = (((T[4 * r + 0] * q0) + (T[4 * r + 1] * q1)) + (T[4 * r + 2] * q2)) + T[4 * r + 3];
+        const float kf = floorf((e - o[r]) / cell);
+        if (!(kf >= -1048576.0f && kf < 1048576.0f)) { atomicOr(overflow, 2); return; }
+        k[r] = (int)kf;
+    }
+    const unsigned long long key = pack_cell(k[0], k[1], k[2]);
+    unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 40) & (unsigned)(table_size - 1);
+    for (int probe = 0; probe < table_size; ++probe) {
+        unsigned long long* slot = table + 2 * (size_t)h;
+        const unsigned long long prev = atomicCAS(slot, ~0ull, key);
+        if (prev == ~0ull || prev == key) {
+            atomicAdd(slot + 1, 1ull);
+            return;
+        }
+        h = (h + 1) & (unsigned)(table_size - 1);
+    }
+    atomicOr(overflow, 1);
+}
+
+__global__ void mvf_placement_clear_kernel(unsigned long long* table, int table_size)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < table_size) {
+        table[2 * (size_t)i] = ~0ull;
+        table[2 * (size_t)i + 1] = 0ull;
+    }
+}
+
+int launch_placement_clear(unsigned long long* table, int table_size, void* stream)
+{
+    hipLaunchKernelGGL(mvf_placement_clear_kernel, dim3((table_size + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, table, table_size);
+    return (int)hipGetLastError();
+}
+
+int launch_placement_count(const float* depth, int depth_pitch, int width, int height, float fx, float fy,
+                           float cx, float cy, const float* T, float o0, float o1, float o2, float cell,
+                           unsigned long long* table, int table_size, int* overflow, void* stream)
+{
+    dim3 grid((width + 31) / 32, (height + 7) / 8);
+    hipLaunchKernelGGL(mvf_placement_count_kernel, grid, dim3(256), 0, (hipStream_t)stream, depth, depth_pitch,
+                       width, height, fx, fy, cx, cy, T, o0, o1, o2, cell, table, table_size, overflow);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Differentiable raycast on one dense x-fastest volume (F, W).  The forward
+// is the same march (binary32 contract; validity from W) without brick
+// skipping; it records k of the crossing's second sample.  The backward
+// recomputes the two bracketing samples from k, and with the structure held
+// fixed scatters dL/dF (16 voxels per pixel, float atomics) and reduces
+// dL/dxi per block into binary64 partials, summed by a second kernel in a
+// fixed order (deterministic).
+// ---------------------------------------------------------------------------
+struct DSample {
+    int i[3];
+    float f[3];
+    float c[8];
+    float F;
+    bool ok;
+};
+
+static __device__ __forceinline__ size_t dense_idx(const DiffVolume& v, int x, int y, int z)
+{
+    return ((size_t)z * v.dims[1] + y) * v.dims[0] + x;
+}
+
+static __device__ __forceinline__ void dense_sample(const DiffVolume& v, const Ray& r, float tk, DSample& S)
+{
+    S.ok = false;
+    float l[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float x = r.C[a] + (tk * r.dw[a]);
+        const float c = ((x - v.o[a]) * v.inv_s) - 0.5f;
+        l[a] = c - (float)v.off[a];
+        if (!(l[a] >= 0.0f && l[a] < (float)(v.dims[a] - 1))) return;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float fl = floorf(l[a]);
+        S.i[a] = (int)fl;
+        S.f[a] = l[a] - fl;
+    }
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const size_t id = dense_idx(v, S.i[0] + dx, S.i[1] + dy, S.i[2] + dz);
+                if (v.W[id] == 0) return;
+                S.c[dz * 4 + dy * 2 + dx] = v.F[id];
+            }
+    S.F = trilinear(S.c, S.f);
+    S.ok = true;
+}
+
+static __device__ __forceinline__ void make_ray(int u, int v, float fx, float fy, float cx, float cy,
+                                                const float* T, Ray& r, float dh[3])
+{
+    const float dc0 = ((float)u - cx) / fx;
+    const float dc1 = ((float)v - cy) / fy;
+    const float n = sqrtf(((dc0 * dc0) + (dc1 * dc1)) + (1.0f * 1.0f));
+    const float inv_n = 1.0f / n;
+    dh[0] = dc0 * inv_n;
+    dh[1] = dc1 * inv_n;
+    dh[2] = 1.0f * inv_n;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.dw[a] = ((T[4 * a + 0] * dh[0]) + (T[4 * a + 1] * dh[1])) + (T[4 * a + 2] * dh[2]);
+        r.C[a] = T[4 * a + 3];
+    }
+}
+
+struct PoseArgs {
+    float T[12];
+};
+
+__global__ __launch_bounds__(256) void mvf_diffray_forward_kernel(DiffVolume v, PoseArgs P, float fx, float fy,
+                                                                  float cx, float cy, int width, int height,
+                                                                  RayParams rp, float* depth, int32_t* record)
+{
+    const int u = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int vv = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (u >= width || vv >= height) return;
+    const size_t p = (size_t)vv * width + u;
+    Ray r;
+    float dh[3];
+    make_ray(u, vv, fx, fy, cx, cy, P.T, r, dh);
+    // conservative k range (domain box grown by a voxel, +-2 samples)
+    float t0 = 0.0f, t1 = (float)rp.kmax * rp.delta;
+    bool none = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float lo = v.o[a] + v.s * ((float)v.off[a] + 0.5f) - v.s;
+        const float hi = v.o[a] + v.s * ((float)v.off[a] + (float)v.dims[a] - 0.5f) + v.s;
+        if (r.dw[a] == 0.0f) {
+            if (r.C[a] < lo || r.C[a] > hi) none = true;
+        } else {
+            float ta = (lo - r.C[a]) / r.dw[a], tb = (hi - r.C[a]) / r.dw[a];
+            if (ta > tb) { const float t = ta; ta = tb; tb = t; }
+            t0 = fmaxf(t0, ta);
+            t1 = fminf(t1, tb);
+        }
+    }
+    float ts = 0.0f;
+    int kfound = -1;
+    if (!none && t0 <= t1) {
+        const int k0 = max(1, (int)floorf(t0 / rp.delta) - 2);
+        const int k1 = min(rp.kmax, (int)ceilf(t1 / rp.delta) + 2);
+        bool prev_ok = false;
+        float Fprev = 0.0f;
+        for (int k = k0; k <= k1; ++k) {
+            DSample S;
+            dense_sample(v, r, (float)k * rp.delta, S);
+            if (prev_ok && S.ok && Fprev > 0.0f && S.F <= 0.0f) {
+                const float ta = (float)(k - 1) * rp.delta;
+                ts = ta + ((rp.delta * Fprev) / (Fprev - S.F));
+                kfound = k;
+                break;
+            }
+            prev_ok = S.ok;
+            Fprev = S.F;
+        }
+    }
+    depth[p] = kfound >= 0 ? ts * dh[2] : 0.0f;
+    record[p] = kfound;
+}
+
+int launch_diffray_forward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy, int width,
+                           int height, RayParams rp, float* depth, int32_t* record, void* stream)
+{
+    PoseArgs P;
+    for (int i = 0; i < 12; ++i) P.T[i] = T[i];
+    dim3 grid((width + 15) / 16, (height + 15) / 16);
+    hipLaunchKernelGGL(mvf_diffray_forward_kernel, grid, dim3(256), 0, (hipStream_t)stream, v, P, fx, fy, cx, cy,
+                       width, height, rp, depth, record);
+    return (int)hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void mvf_diffray_backward_kernel(
+    DiffVolume v, PoseArgs P, float fx, float fy, float cx, float cy, int width, int height, RayParams rp,
+    const float* __restrict__ grad_depth, const int32_t* __restrict__ record, float* grad_F, double* partials)
+{
+    const int u = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int vv = blockIdx.y * 16 + (threadIdx.x >> 4);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (u < width && vv < height) {
+        const size_t p = (size_t)vv * width + u;
+        const int k = record[p];
+        const float gd = grad_depth[p];
+        if (k >= 1 && gd != 0.0f) {
+            Ray r;
+            float dh[3];
+            make_ray(u, vv, fx, fy, cx, cy, P.T, r, dh);
+            DSample S[2];
+            dense_sample(v, r, (float)(k - 1) * rp.delta, S[0]);
+            dense_sample(v, r, (float)k * rp.delta, S[1]);
+            if (S[0].ok && S[1].ok) {
+                const float Fa = S[0].F, Fb = S[1].F;
+                const float den = Fa - Fb;
+                const float inv2 = 1.0f / (den * den);
+                const float dt[2] = { -rp.delta * Fb * inv2, rp.delta * Fa * inv2 };
+                const float gz = gd * dh[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const DSample& s = S[j];
+                    const float kk = gz * dt[j];
+                    const float t = (float)(k - 1 + j) * rp.delta;
+                    // gradient of the trilinear interpolant w.r.t. the local coordinate
+                    const float* c = s.c;
+                    const float gx = lerp32(lerp32(c[1] - c[0], c[3] - c[2], s.f[1]),
+                                            lerp32(c[5] - c[4], c[7] - c[6], s.f[1]), s.f[2]);
+                    const float c00 = lerp32(c[0], c[1], s.f[0]), c10 = lerp32(c[2], c[3], s.f[0]);
+                    const float c01 = lerp32(c[4], c[5], s.f[0]), c11 = lerp32(c[6], c[7], s.f[0]);
+                    const float gy = lerp32(c10 - c00, c11 - c01, s.f[2]);
+                    const float gzl = lerp32(c01, c11, s.f[1]) - lerp32(c00, c10, s.f[1]);
+                    const float gw[3] = { gx * v.inv_s, gy * v.inv_s, gzl * v.inv_s };
+                    float gc[3], q[3];
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) {
+                        gc[cc] = P.T[cc] * gw[0] + P.T[4 + cc] * gw[1] + P.T[8 + cc] * gw[2];
+                        q[cc] = t * dh[cc];
+                    }
+                    acc[0] += (double)(kk * gc[0]);
+                    acc[1] += (double)(kk * gc[1]);
+                    acc[2] += (double)(kk * gc[2]);
+                    acc[3] += (double)(kk * (q[1] * gc[2] - q[2] * gc[1]));
+                    acc[4] += (double)(kk * (q[2] * gc[0] - q[0] * gc[2]));
+                    acc[5] += (double)(kk * (q[0] * gc[1] - q[1] * gc[0]));
+                    if (grad_F) {
+#pragma unroll
+                        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                                for (int dx = 0; dx < 2; ++dx) {
+                                    const float w = (dx ? s.f[0] : 1.0f - s.f[0]) * (dy ? s.f[1] : 1.0f - s.f[1]) *
+                                                    (dz ? s.f[2] : 1.0f - s.f[2]);
+                                    atomicAdd(&grad_F[dense_idx(v, s.i[0] + dx, s.i[1] + dy, s.i[2] + dz)], kk * w);
+                                }
+                    }
+                }
+            }
+        }
+    }
+    // deterministic block reduction of the 6 pose terms
+    __shared__ double red[6][256];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) red[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int stride = 128; stride >= 1; stride >>= 1) {
+        if ((int)threadIdx.x < stride) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + stride];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) {
+        const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        partials[blk * 6 + threadIdx.x] = red[threadIdx.x][0];
+    }
+}
+
+__global__ void mvf_reduce_partials_kernel(const double* partials, int nblocks, double* out)
+{
+    __shared__ double red[256];
+    const int comp = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(size_t)b * 6 + comp];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int stride = 128; stride >= 1; stride >>= 1) {
+        if ((int)threadIdx.x < stride) red[threadIdx.x] += red[threadIdx.x + stride];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[comp] = red[0];
+}
+
+int diffray_partials_needed(int width, int height)
+{
+    return ((width + 15) / 16) * ((height + 15) / 16);
+}
+
+int launch_diffray_backward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy, int width,
+                            int height, RayParams rp, const float* grad_depth, const int32_t* record,
+                            float* grad_F, double* partials, int n_partials, double* grad_xi, void* stream)
+{
+    PoseArgs P;
+    for (int i = 0; i < 12; ++i) P.T[i] = T[i];
+    dim3 grid((width + 15) / 16, (height + 15) / 16);
+    if ((int)(grid.x * grid.y) > n_partials) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(mvf_diffray_backward_kernel, grid, dim3(256), 0, (hipStream_t)stream, v, P, fx, fy, cx,
+                       cy, width, height, rp, grad_depth, record, grad_F, partials);
+    hipLaunchKernelGGL(mvf_reduce_partials_kernel, dim3(6), dim3(256), 0, (hipStream_t)stream, partials,
+                       (int)(grid.x * grid.y), grad_xi);
+    return (int)hipGetLastError();
+}
+
+}  // namespace mvf

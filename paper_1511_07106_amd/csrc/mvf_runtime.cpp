@@ -1,0 +1,1706 @@
+// Host runtime of libmvf: context, grid/volume registry, residency manager
+// (device budget, slab pool, pinned host mirrors, swaps on a side copy
+// stream ordered by events), launch-table arena, the plain per-volume
+// integrate/raycast, the batched graph-captured step, placement, the
+// differentiable raycast, read/write and statistics.  Implements include/mvf.h.
+// Paper: Salvato, Finman, Leonard, arXiv 1511.07106.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mvf.h"
+#include "mvf_internal.h"
+
+using namespace mvf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mvf_status set_error(mvf_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define CHECK_HIP(call)                                                                        \
+    do {                                                                                       \
+        hipError_t e__ = (call);                                                               \
+        if (e__ != hipSuccess)                                                                 \
+            return set_error(MVF_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e__));    \
+    } while (0)
+
+#define CHECK_LAUNCH(call)                                                                     \
+    do {                                                                                       \
+        int e__ = (call);                                                                      \
+        if (e__ != 0)                                                                          \
+            return set_error(MVF_ERR_HIP, "%s failed: %s", #call,                              \
+                             hipGetErrorString((hipError_t)e__));                              \
+    } while (0)
+
+#define CHECK_ST(call)                   \
+    do {                                 \
+        mvf_status s__ = (call);         \
+        if (s__ != MVF_OK) return s__;   \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Grid {
+    mvf_grid_desc d;
+    float mu, inv_s, inv_mu;
+};
+
+enum class State { Empty, Device, Host };
+
+struct Volume {
+    bool alive = false;
+    mvf_volume_desc d{};
+    int bd[3] = {0, 0, 0};
+    size_t nvox_pad = 0, off_W = 0, off_C = 0, off_flag = 0, bytes = 0;
+    uint8_t* dev = nullptr;    // device slab while resident
+    uint8_t* host = nullptr;   // pinned mirror (allocated on first swap-out)
+    State state = State::Empty;
+    bool active = false;
+    uint64_t last_use = 0;
+    hipEvent_t host_ready = nullptr;  // mirror written (swap-out finished)
+    bool host_pending = false;
+};
+
+struct Slab {
+    uint8_t* ptr;
+    size_t bytes;
+    hipEvent_t free_after;   // slab may be reused once this event completes
+};
+
+struct Scratch {
+    int w = 0, h = 0;
+    float* range = nullptr;
+    uint32_t* color = nullptr;
+    float* rmax = nullptr;
+    float* best_t = nullptr;
+    int32_t* best_id = nullptr;
+};
+
+// Ring of pinned host + device slots for per-launch tables.  A slot is
+// reused only after the event recorded behind the launches that read it.
+struct Arena {
+    static constexpr int kSlots = 32;
+    static constexpr size_t kSlotBytes = 1 << 20;
+    uint8_t* host = nullptr;
+    uint8_t* dev = nullptr;
+    hipEvent_t ev[kSlots] = {};
+    bool pending[kSlots] = {};
+    int next = 0;
+};
+
+struct Writer {
+    uint8_t* host;
+    uint8_t* dev;
+    size_t used = 0;
+    bool overflow = false;
+    template <class T>
+    T* alloc(size_t n, T** dev_ptr)
+    {
+        size_t off = align_up(used, 64);
+        size_t sz = sizeof(T) * (n ? n : 1);
+        if (off + sz > Arena::kSlotBytes) { overflow = true; return nullptr; }
+        used = off + sz;
+        *dev_ptr = reinterpret_cast<T*>(dev + off);
+        return reinterpret_cast<T*>(host + off);
+    }
+};
+
+struct TimedPair {
+    hipEvent_t a, b;
+    int kind;  // 0 integrate, 1 raycast, 2 batched step
+};
+
+struct StepGraph {
+    bool valid = false;
+    int n = 0;
+    std::vector<int> widths, heights, out_w, out_h;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // persistent device tables read by the captured kernels
+    uint8_t* dev = nullptr;
+    size_t dev_bytes = 0;
+    size_t off_hdr, off_prep, off_frames, off_vols, off_items, off_lists, off_lbase, off_tbase;
+    int max_vols = 0, max_w = 0, max_h = 0;
+    int integ_blocks = 0, ray_blocks = 0;
+};
+
+}  // namespace
+
+struct mvf_ctx {
+    mvf_config cfg{};
+    int device = 0;
+    hipStream_t copy_stream = nullptr;
+    std::vector<Grid> grids;
+    std::vector<Volume> vols;
+    std::map<int, Scratch> scratch;
+    unsigned long long* counters = nullptr;
+    uint64_t budget = 0;
+    uint64_t resident_bytes = 0;  // slabs held by resident volumes
+    uint64_t pooled_bytes = 0;    // slabs in the free pool
+    std::vector<Slab> pool;
+    uint64_t tick = 0;
+    mvf_stats stats{};
+    Arena arena;
+    std::vector<TimedPair> timed;
+    std::vector<hipEvent_t> event_pool;
+    hipEvent_t tail = nullptr;
+    hipStream_t tail_stream = nullptr;
+    bool tail_valid = false;
+    int n_cus = 256;
+    // placement bookkeeping: per stream, cell -> volume id (volumes created by placement)
+    std::map<int, std::map<std::vector<int>, int>> placed;
+    unsigned long long* place_table = nullptr;
+    int* place_overflow = nullptr;
+    float* place_T = nullptr;
+    static constexpr int kPlaceTable = 8192;
+    double* diff_partials = nullptr;
+    int diff_partials_n = 0;
+    StepGraph step;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+mvf_status get_event(mvf_ctx* c, hipEvent_t* ev)
+{
+    if (!c->event_pool.empty()) {
+        *ev = c->event_pool.back();
+        c->event_pool.pop_back();
+        return MVF_OK;
+    }
+    CHECK_HIP(hipEventCreate(ev));
+    return MVF_OK;
+}
+
+// Make `stream` run after everything the previous call enqueued.
+mvf_status order_after_previous(mvf_ctx* c, hipStream_t stream)
+{
+    if (c->tail_valid && c->tail_stream != stream) CHECK_HIP(hipStreamWaitEvent(stream, c->tail, 0));
+    return MVF_OK;
+}
+
+mvf_status mark_tail(mvf_ctx* c, hipStream_t stream)
+{
+    CHECK_HIP(hipEventRecord(c->tail, stream));
+    c->tail_stream = stream;
+    c->tail_valid = true;
+    return MVF_OK;
+}
+
+mvf_status arena_acquire(mvf_ctx* c, int* slot, Writer* w)
+{
+    Arena& A = c->arena;
+    int s = A.next;
+    A.next = (A.next + 1) % Arena::kSlots;
+    if (A.pending[s]) {
+        CHECK_HIP(hipEventSynchronize(A.ev[s]));
+        A.pending[s] = false;
+    }
+    *slot = s;
+    w->host = A.host + (size_t)s * Arena::kSlotBytes;
+    w->dev = A.dev + (size_t)s * Arena::kSlotBytes;
+    w->used = 0;
+    w->overflow = false;
+    return MVF_OK;
+}
+
+mvf_status arena_upload(mvf_ctx* c, const Writer& w, hipStream_t stream)
+{
+    if (w.overflow) return set_error(MVF_ERR_INVALID_ARG, "launch tables exceed %zu bytes", Arena::kSlotBytes);
+    if (w.used) CHECK_HIP(hipMemcpyAsync(w.dev, w.host, w.used, hipMemcpyHostToDevice, stream));
+    return MVF_OK;
+}
+
+mvf_status arena_release(mvf_ctx* c, int slot, hipStream_t stream)
+{
+    CHECK_HIP(hipEventRecord(c->arena.ev[slot], stream));
+    c->arena.pending[slot] = true;
+    return MVF_OK;
+}
+
+Volume* find_volume(mvf_ctx* c, int32_t id)
+{
+    if (id < 0 || id >= (int32_t)c->vols.size() || !c->vols[id].alive) return nullptr;
+    return &c->vols[id];
+}
+
+DevVolume make_dev(mvf_ctx* c, const Volume& v)
+{
+    const Grid& g = c->grids[v.d.grid_id];
+    DevVolume d{};
+    d.F = reinterpret_cast<float*>(v.dev);
+    d.W = reinterpret_cast<uint16_t*>(v.dev + v.off_W);
+    d.C = reinterpret_cast<uint32_t*>(v.dev + v.off_C);
+    d.flag = v.dev + v.off_flag;
+    for (int a = 0; a < 3; ++a) {
+        d.dims[a] = v.d.dims[a];
+        d.off[a] = v.d.offset[a];
+        d.bd[a] = v.bd[a];
+        d.o[a] = g.d.origin[a];
+    }
+    d.id = (int32_t)(&v - c->vols.data());
+    d.s = g.d.voxel_size;
+    d.inv_s = g.inv_s;
+    d.mu = g.mu;
+    d.inv_mu = g.inv_mu;
+    d.w_max = g.d.w_max;
+    d.frame = 0;
+    return d;
+}
+
+// ---- residency ------------------------------------------------------------
+
+mvf_status release_pool(mvf_ctx* c, uint64_t need_room)
+{
+    // free pooled slabs (oldest first) until `need_room` more bytes fit
+    while (!c->pool.empty() && c->resident_bytes + c->pooled_bytes + need_room > c->budget) {
+        Slab s = c->pool.front();
+        c->pool.erase(c->pool.begin());
+        CHECK_HIP(hipEventSynchronize(s.free_after));
+        c->event_pool.push_back(s.free_after);
+        CHECK_HIP(hipFree(s.ptr));
+        c->pooled_bytes -= s.bytes;
+    }
+    return MVF_OK;
+}
+
+mvf_status swap_out(mvf_ctx* c, Volume& v, hipStream_t stream, bool keep_slab_pooled = true)
+{
+    if (v.state != State::Device) return MVF_OK;
+    if (!v.host) {
+        hipError_t e = hipHostMalloc((void**)&v.host, v.bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            v.host = nullptr;
+            return set_error(MVF_ERR_OOM, "pinned host mirror of %zu bytes: %s", v.bytes, hipGetErrorString(e));
+        }
+    }
+    hipEvent_t used;
+    CHECK_ST(get_event(c, &used));
+    CHECK_HIP(hipEventRecord(used, stream));
+    CHECK_HIP(hipStreamWaitEvent(c->copy_stream, used, 0));
+    c->event_pool.push_back(used);  // recorded; safe to reuse after the wait is enqueued
+    CHECK_HIP(hipMemcpyAsync(v.host, v.dev, v.bytes, hipMemcpyDeviceToHost, c->copy_stream));
+    if (!v.host_ready) CHECK_HIP(hipEventCreate(&v.host_ready));
+    CHECK_HIP(hipEventRecord(v.host_ready, c->copy_stream));
+    v.host_pending = true;
+    hipEvent_t done;
+    CHECK_ST(get_event(c, &done));
+    CHECK_HIP(hipEventRecord(done, c->copy_stream));
+    c->resident_bytes -= v.bytes;
+    if (keep_slab_pooled) {
+        c->pool.push_back(Slab{v.dev, v.bytes, done});
+        c->pooled_bytes += v.bytes;
+    } else {
+        CHECK_HIP(hipEventSynchronize(done));
+        c->event_pool.push_back(done);
+        CHECK_HIP(hipFree(v.dev));
+    }
+    v.dev = nullptr;
+    v.state = State::Host;
+    c->stats.bytes_d2h += v.bytes;
+    c->stats.swaps_out += 1;
+    return MVF_OK;
+}
+
+// Obtain a slab of v.bytes for v, usable on `stream`.
+mvf_status get_slab(mvf_ctx* c, Volume& v, hipStream_t stream)
+{
+    for (size_t i = 0; i < c->pool.size(); ++i) {
+        if (c->pool[i].bytes == v.bytes) {
+            Slab s = c->pool[i];
+            c->pool.erase(c->pool.begin() + i);
+            c->pooled_bytes -= s.bytes;
+            CHECK_HIP(hipStreamWaitEvent(stream, s.free_after, 0));
+            CHECK_HIP(hipStreamWaitEvent(c->copy_stream, s.free_after, 0));
+            c->event_pool.push_back(s.free_after);
+            v.dev = s.ptr;
+            return MVF_OK;
+        }
+    }
+    CHECK_ST(release_pool(c, v.bytes));
+    hipError_t e = hipMalloc((void**)&v.dev, v.bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // drop every pooled slab and retry once
+        uint64_t saved = c->budget;
+        c->budget = 0;
+        mvf_status st = release_pool(c, 0);
+        c->budget = saved;
+        if (st != MVF_OK) return st;
+        e = hipMalloc((void**)&v.dev, v.bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            v.dev = nullptr;
+            return set_error(MVF_ERR_OOM, "device slab of %zu bytes: %s", v.bytes, hipGetErrorString(e));
+        }
+    }
+    return MVF_OK;
+}
+
+// Make every volume of `need` resident (evicting least recently used
+// volumes outside `need`).  Fails with MVF_ERR_BUDGET if they cannot all fit.
+mvf_status ensure_resident(mvf_ctx* c, const std::vector<int>& need, hipStream_t stream)
+{
+    uint64_t want = 0;
+    for (int id : need) {
+        Volume& v = c->vols[id];
+        if (v.bytes > c->budget)
+            return set_error(MVF_ERR_BUDGET, "volume %d needs %zu bytes, budget is %llu", id, v.bytes,
+                             (unsigned long long)c->budget);
+        if (v.state != State::Device) want += v.bytes;
+    }
+    if (c->resident_bytes + want > c->budget) {
+        std::vector<char> needed(c->vols.size(), 0);
+        for (int id : need) needed[id] = 1;
+        while (c->resident_bytes + want > c->budget) {
+            int victim = -1;
+            for (size_t i = 0; i < c->vols.size(); ++i) {
+                Volume& v = c->vols[i];
+                if (v.alive && v.state == State::Device && !needed[i] &&
+                    (victim < 0 || v.last_use < c->vols[victim].last_use))
+                    victim = (int)i;
+            }
+            if (victim < 0)
+                return set_error(MVF_ERR_BUDGET, "needed volumes (%llu bytes) exceed the budget",
+                                 (unsigned long long)(c->resident_bytes + want));
+            CHECK_ST(swap_out(c, c->vols[victim], stream));
+        }
+    }
+    bool copied = false;
+    for (int id : need) {
+        Volume& v = c->vols[id];
+        v.last_use = ++c->tick;
+        if (v.state == State::Device) continue;
+        CHECK_ST(get_slab(c, v, stream));
+        c->resident_bytes += v.bytes;
+        if (v.state == State::Host) {
+            // stream-ordered after earlier work on the caller's stream
+            hipEvent_t before;
+            CHECK_ST(get_event(c, &before));
+            CHECK_HIP(hipEventRecord(before, stream));
+            CHECK_HIP(hipStreamWaitEvent(c->copy_stream, before, 0));
+            c->event_pool.push_back(before);
+            CHECK_HIP(hipMemcpyAsync(v.dev, v.host, v.bytes, hipMemcpyHostToDevice, c->copy_stream));
+            c->stats.bytes_h2d += v.bytes;
+            c->stats.swaps_in += 1;
+            copied = true;
+        } else {
+            CHECK_LAUNCH(launch_volume_init(make_dev(c, v), stream));
+        }
+        v.state = State::Device;
+    }
+    if (copied) {
+        hipEvent_t done;
+        CHECK_ST(get_event(c, &done));
+        CHECK_HIP(hipEventRecord(done, c->copy_stream));
+        CHECK_HIP(hipStreamWaitEvent(stream, done, 0));
+        c->event_pool.push_back(done);
+    }
+    return MVF_OK;
+}
+
+// Split `ids` into consecutive groups that each fit in the budget.
+// Volumes already resident go first so the first wave copies least.
+std::vector<std::vector<int>> plan_waves(mvf_ctx* c, std::vector<int> ids)
+{
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+        return (c->vols[a].state == State::Device) > (c->vols[b].state == State::Device);
+    });
+    uint64_t total = 0;
+    for (int id : ids) total += c->vols[id].bytes;
+    std::vector<std::vector<int>> waves;
+    if (total <= c->budget) {
+        waves.push_back(ids);
+        return waves;
+    }
+    std::vector<int> cur;
+    uint64_t cur_bytes = 0;
+    for (int id : ids) {
+        const uint64_t b = c->vols[id].bytes;
+        if (!cur.empty() && cur_bytes + b > c->budget) {
+            waves.push_back(cur);
+            cur.clear();
+            cur_bytes = 0;
+        }
+        cur.push_back(id);
+        cur_bytes += b;
+    }
+    if (!cur.empty()) waves.push_back(cur);
+    return waves;
+}
+
+// ---- geometry helpers -------------------------------------------------------
+
+bool finite_pose(const float* T)
+{
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(T[i])) return false;
+    return true;
+}
+
+bool valid_K(const mvf_intrinsics* K)
+{
+    return K && std::isfinite(K->fx) && std::isfinite(K->fy) && std::isfinite(K->cx) && std::isfinite(K->cy) &&
+           K->fx != 0.0f && K->fy != 0.0f;
+}
+
+// Conservative test: can the view frustum (pixels [0,W)x[0,H), in front of
+// the camera) meet the volume's voxel box grown by one voxel?
+bool volume_in_view(mvf_ctx* c, const Volume& v, const float* T, const mvf_intrinsics& K, int W, int H)
+{
+    const Grid& g = c->grids[v.d.grid_id];
+    const double s = g.d.voxel_size;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = g.d.origin[a] + s * (v.d.offset[a] + 0.5) - s;
+        hi[a] = g.d.origin[a] + s * (v.d.offset[a] + v.d.dims[a] - 0.5) + s;
+    }
+    double p[8][3];
+    for (int k = 0; k < 8; ++k) {
+        double x[3] = { (k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2] };
+        double d[3] = { x[0] - T[3], x[1] - T[7], x[2] - T[11] };
+        for (int cc = 0; cc < 3; ++cc) p[k][cc] = T[cc] * d[0] + T[4 + cc] * d[1] + T[8 + cc] * d[2];
+    }
+    const double E = 1e-3;
+    auto all_out = [&](double ax, double ay, double az, double a0) {
+        for (int k = 0; k < 8; ++k)
+            if (ax * p[k][0] + ay * p[k][1] + az * p[k][2] + a0 >= 0.0) return false;
+        return true;
+    };
+    if (all_out(0, 0, 1, 2 * s)) return false;
+    if (all_out(K.fx, 0, K.cx + 1.5, std::fabs(K.fx) * E)) return false;
+    if (all_out(-K.fx, 0, W + 0.5 - K.cx, std::fabs(K.fx) * E)) return false;
+    if (all_out(0, K.fy, K.cy + 1.5, std::fabs(K.fy) * E)) return false;
+    if (all_out(0, -K.fy, H + 0.5 - K.cy, std::fabs(K.fy) * E)) return false;
+    return true;
+}
+
+double box_distance(mvf_ctx* c, const Volume& v, const float* T)
+{
+    const Grid& g = c->grids[v.d.grid_id];
+    const double s = g.d.voxel_size;
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double lo = g.d.origin[a] + s * (v.d.offset[a] + 0.5);
+        const double hi = g.d.origin[a] + s * (v.d.offset[a] + v.d.dims[a] - 0.5);
+        const double t = T[4 * a + 3];
+        const double q = t < lo ? lo - t : (t > hi ? t - hi : 0.0);
+        d2 += q * q;
+    }
+    return std::sqrt(d2);
+}
+
+mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratch** out)
+{
+    Scratch& s = c->scratch[sid];
+    if (w * h > s.w * s.h || !s.rmax) {
+        if (s.range) { CHECK_HIP(hipFree(s.range)); s.range = nullptr; }
+        if (s.color) { CHECK_HIP(hipFree(s.color)); s.color = nullptr; }
+        if (s.best_t) { CHECK_HIP(hipFree(s.best_t)); s.best_t = nullptr; }
+        if (s.best_id) { CHECK_HIP(hipFree(s.best_id)); s.best_id = nullptr; }
+        if (!s.rmax) CHECK_HIP(hipMalloc((void**)&s.rmax, 256));
+        const size_t n = (size_t)std::max(w * h, s.w * s.h);
+        CHECK_HIP(hipMalloc((void**)&s.range, n * sizeof(float)));
+        CHECK_HIP(hipMalloc((void**)&s.color, n * sizeof(uint32_t)));
+        s.w = w;
+        s.h = h;
+    }
+    if (need_best && !s.best_t) {
+        const size_t n = (size_t)s.w * s.h;
+        CHECK_HIP(hipMalloc((void**)&s.best_t, n * sizeof(float)));
+        CHECK_HIP(hipMalloc((void**)&s.best_id, n * sizeof(int32_t)));
+    }
+    *out = &s;
+    return MVF_OK;
+}
+
+mvf_status check_frame(const mvf_frame* f)
+{
+    if (!f || !f->depth) return set_error(MVF_ERR_INVALID_ARG, "frame or frame->depth is NULL");
+    if (f->width <= 0 || f->height <= 0 || f->width > 16384 || f->height > 16384)
+        return set_error(MVF_ERR_INVALID_ARG, "frame size %dx%d out of range", f->width, f->height);
+    if (f->depth_pitch != 0 && f->depth_pitch < f->width)
+        return set_error(MVF_ERR_INVALID_ARG, "depth_pitch %d < width %d", f->depth_pitch, f->width);
+    if (f->rgb && f->rgb_pitch != 0 && f->rgb_pitch < 3 * f->width)
+        return set_error(MVF_ERR_INVALID_ARG, "rgb_pitch %d < 3*width", f->rgb_pitch);
+    return MVF_OK;
+}
+
+mvf_status timing_begin(mvf_ctx* c, hipStream_t stream, hipEvent_t* a)
+{
+    *a = nullptr;
+    if (!(c->cfg.flags & MVF_FLAG_TIMING)) return MVF_OK;
+    CHECK_ST(get_event(c, a));
+    CHECK_HIP(hipEventRecord(*a, stream));
+    return MVF_OK;
+}
+
+mvf_status timing_end(mvf_ctx* c, hipStream_t stream, hipEvent_t a, int kind)
+{
+    if (!a) return MVF_OK;
+    hipEvent_t b;
+    CHECK_ST(get_event(c, &b));
+    CHECK_HIP(hipEventRecord(b, stream));
+    c->timed.push_back(TimedPair{a, b, kind});
+    return MVF_OK;
+}
+
+mvf_status drain_timing(mvf_ctx* c)
+{
+    for (auto& t : c->timed) {
+        CHECK_HIP(hipEventSynchronize(t.b));
+        float ms = 0.0f;
+        CHECK_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+        if (t.kind == 0) c->stats.integrate_ms += ms;
+        else if (t.kind == 1) c->stats.raycast_ms += ms;
+        else c->stats.step_ms += ms;
+        c->event_pool.push_back(t.a);
+        c->event_pool.push_back(t.b);
+    }
+    c->timed.clear();
+    return MVF_OK;
+}
+
+int zchunk_for(const Volume&) { return 4; }
+
+void fill_frame(DevFrame* f, const Scratch* s, int w, int h, const float* T, const mvf_intrinsics& K)
+{
+    memset(f, 0, sizeof(*f));
+    if (s) {
+        f->range = s->range;
+        f->color = s->color;
+        f->rmax = s->rmax;
+    }
+    f->width = w;
+    f->height = h;
+    f->fx = K.fx;
+    f->fy = K.fy;
+    f->cx = K.cx;
+    f->cy = K.cy;
+    memcpy(f->T, T, sizeof(float) * 12);
+}
+
+RayParams ray_params(mvf_ctx* c, const Grid& g)
+{
+    RayParams rp;
+    rp.delta = c->cfg.ray_step * g.d.voxel_size;
+    rp.kmax = (int32_t)std::floor(c->cfg.t_far / rp.delta);
+    return rp;
+}
+
+// Integration of one frame into the given volumes, one launch per volume
+// (the paper's per-volume loop), in budget-sized waves.
+mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float* T, const mvf_intrinsics& K,
+                           const std::vector<int>& ids, hipStream_t stream)
+{
+    Scratch* sc;
+    CHECK_ST(get_scratch(c, sid, f->width, f->height, false, &sc));
+    int slot;
+    Writer w;
+    CHECK_ST(arena_acquire(c, &slot, &w));
+    PrepItem* dprep;
+    PrepItem* prep = w.alloc<PrepItem>(1, &dprep);
+    DevFrame* dframe;
+    DevFrame* frame = w.alloc<DevFrame>(1, &dframe);
+    if (!prep || !frame) return set_error(MVF_ERR_INVALID_ARG, "arena overflow");
+    memset(prep, 0, sizeof(*prep));
+    prep->depth = f->depth;
+    prep->rgb = f->rgb;
+    prep->depth_pitch = f->depth_pitch ? f->depth_pitch : f->width;
+    prep->rgb_pitch = f->rgb_pitch ? f->rgb_pitch : 3 * f->width;
+    prep->width = f->width;
+    prep->height = f->height;
+    prep->fx = K.fx; prep->fy = K.fy; prep->cx = K.cx; prep->cy = K.cy;
+    prep->range = sc->range;
+    prep->color = sc->color;
+    prep->rmax = sc->rmax;
+    fill_frame(frame, sc, f->width, f->height, T, K);
+    if (!f->rgb) frame->color = nullptr;
+    // per-volume tables are filled after residency is known (slab pointers)
+    std::vector<std::vector<int>> waves = plan_waves(c, ids);
+    // first upload: prep + frame; volume tables go into fresh slots per wave
+    CHECK_ST(arena_upload(c, w, stream));
+    CHECK_LAUNCH(launch_frame_prep(dprep, 1, f->width, f->height, stream));
+    CHECK_ST(arena_release(c, slot, stream));
+    for (auto& wave : waves) {
+        CHECK_ST(ensure_resident(c, wave, stream));
+        int slot2;
+        Writer w2;
+        CHECK_ST(arena_acquire(c, &slot2, &w2));
+        DevFrame* dfr;
+        DevFrame* fr = w2.alloc<DevFrame>(1, &dfr);
+        *fr = *frame;
+        struct Per { LaunchHeader* dh; DevVolume* dv; int32_t* dib; int items; };
+        std::vector<Per> per;
+        for (int id : wave) {
+            Volume& v = c->vols[id];
+            Per p;
+            LaunchHeader* h = w2.alloc<LaunchHeader>(1, &p.dh);
+            DevVolume* dv = w2.alloc<DevVolume>(1, &p.dv);
+            int32_t* ib = w2.alloc<int32_t>(2, &p.dib);
+            if (!h || !dv || !ib) return set_error(MVF_ERR_INVALID_ARG, "arena overflow");
+            *dv = make_dev(c, v);
+            dv->frame = 0;
+            const int zc = zchunk_for(v);
+            p.items = v.bd[0] * v.bd[1] * ((v.bd[2] + zc - 1) / zc);
+            memset(h, 0, sizeof(*h));
+            h->nvol = 1;
+            h->total_items = p.items;
+            h->zchunk = zc;
+            h->nstreams = 1;
+            ib[0] = 0;
+            ib[1] = p.items;
+            per.push_back(p);
+        }
+        CHECK_ST(arena_upload(c, w2, stream));
+        for (auto& p : per) {
+            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters};
+            hipEvent_t t0;
+            CHECK_ST(timing_begin(c, stream, &t0));
+            CHECK_LAUNCH(launch_integrate(L, (p.items + 3) / 4, stream));
+            CHECK_ST(timing_end(c, stream, t0, 0));
+            c->stats.integrate_launches += 1;
+        }
+        CHECK_ST(arena_release(c, slot2, stream));
+    }
+    return MVF_OK;
+}
+
+mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsics& K, const mvf_raycast_out* out,
+                         const std::vector<int>& ids_in, hipStream_t stream)
+{
+    std::vector<int> ids = ids_in;
+    // nearest first (ties by id) -- only affects speed, not results
+    std::vector<double> dist(c->vols.size(), 0.0);
+    for (int id : ids) dist[id] = box_distance(c, c->vols[id], T);
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return dist[a] < dist[b] || (dist[a] == dist[b] && a < b); });
+    std::vector<std::vector<int>> waves = plan_waves(c, ids);
+    if (waves.empty()) waves.push_back({});
+    const bool multi = waves.size() > 1;
+    Scratch* sc = nullptr;
+    if (multi) CHECK_ST(get_scratch(c, sid, out->width, out->height, true, &sc));
+    RayParams rp{};
+    if (!c->grids.empty()) rp = ray_params(c, c->grids[ids.empty() ? 0 : c->vols[ids[0]].d.grid_id]);
+    const int tw = 16, th = 16;
+    const int tiles = ((out->width + tw - 1) / tw) * ((out->height + th - 1) / th);
+    for (size_t wi = 0; wi < waves.size(); ++wi) {
+        auto& wave = waves[wi];
+        CHECK_ST(ensure_resident(c, wave, stream));
+        // keep nearest-first order inside the wave
+        int slot;
+        Writer w;
+        CHECK_ST(arena_acquire(c, &slot, &w));
+        LaunchHeader* dh;
+        LaunchHeader* h = w.alloc<LaunchHeader>(1, &dh);
+        DevFrame* dfr;
+        DevFrame* fr = w.alloc<DevFrame>(1, &dfr);
+        DevVolume* dvols;
+        DevVolume* vt = w.alloc<DevVolume>(wave.size(), &dvols);
+        int32_t* dlists;
+        int32_t* lists = w.alloc<int32_t>(wave.size(), &dlists);
+        int32_t* dlb;
+        int32_t* lb = w.alloc<int32_t>(2, &dlb);
+        int32_t* dtb;
+        int32_t* tb = w.alloc<int32_t>(2, &dtb);
+        if (!h || !fr || !vt || !lists || !lb || !tb) return set_error(MVF_ERR_INVALID_ARG, "arena overflow");
+        for (size_t j = 0; j < wave.size(); ++j) {
+            vt[j] = make_dev(c, c->vols[wave[j]]);
+            lists[j] = (int32_t)j;
+        }
+        fill_frame(fr, nullptr, out->width, out->height, T, K);
+        fr->depth = out->depth;
+        fr->vertex = out->vertex;
+        fr->normal = out->normal;
+        fr->hit = out->hit;
+        fr->out_w = out->width;
+        fr->out_h = out->height;
+        if (multi) {
+            fr->best_t = sc->best_t;
+            fr->best_id = sc->best_id;
+        }
+        lb[0] = 0;
+        lb[1] = (int32_t)wave.size();
+        tb[0] = 0;
+        tb[1] = tiles;
+        memset(h, 0, sizeof(*h));
+        h->nvol = (int32_t)wave.size();
+        h->nstreams = 1;
+        h->total_tiles = tiles;
+        h->first_wave = wi == 0 ? 1 : 0;
+        h->rp = rp;
+        CHECK_ST(arena_upload(c, w, stream));
+        RaycastLaunch L{dh, dvols, dfr, dlists, dlb, dtb, tw, th};
+        hipEvent_t t0;
+        CHECK_ST(timing_begin(c, stream, &t0));
+        CHECK_LAUNCH(launch_raycast(L, tiles, stream));
+        CHECK_ST(timing_end(c, stream, t0, 1));
+        CHECK_ST(arena_release(c, slot, stream));
+        c->stats.raycast_launches += 1;
+    }
+    c->stats.pixels_raycast += (uint64_t)out->width * out->height;
+    return MVF_OK;
+}
+
+std::vector<int> stream_volumes(mvf_ctx* c, int sid, const float* T, const mvf_intrinsics& K, int w, int h)
+{
+    std::vector<int> ids;
+    for (size_t i = 0; i < c->vols.size(); ++i) {
+        const Volume& v = c->vols[i];
+        if (v.alive && v.active && v.d.stream_id == sid && volume_in_view(c, v, T, K, w, h)) ids.push_back((int)i);
+    }
+    return ids;
+}
+
+mvf_status destroy_step_graph(mvf_ctx* c)
+{
+    StepGraph& g = c->step;
+    if (g.exec) { CHECK_HIP(hipGraphExecDestroy(g.exec)); g.exec = nullptr; }
+    if (g.graph) { CHECK_HIP(hipGraphDestroy(g.graph)); g.graph = nullptr; }
+    if (g.dev) { CHECK_HIP(hipFree(g.dev)); g.dev = nullptr; }
+    g.valid = false;
+    return MVF_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// Public API
+// ============================================================================
+
+extern "C" {
+
+const char* mvf_version(void) { return "mvf 0.1 (gfx950)"; }
+
+const char* mvf_status_string(mvf_status s)
+{
+    switch (s) {
+    case MVF_OK: return "ok";
+    case MVF_ERR_INVALID_ARG: return "invalid argument";
+    case MVF_ERR_NOT_FOUND: return "not found";
+    case MVF_ERR_OOM: return "out of memory";
+    case MVF_ERR_BUDGET: return "exceeds device budget";
+    case MVF_ERR_HIP: return "HIP runtime error";
+    case MVF_ERR_STATE: return "invalid state";
+    case MVF_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char* mvf_last_error(void) { return g_last_error.c_str(); }
+
+mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg)
+{
+    if (!out) return set_error(MVF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    mvf_config c0{};
+    if (cfg) c0 = *cfg;
+    if (c0.ray_step == 0.0f) c0.ray_step = 0.5f;
+    if (c0.t_far == 0.0f) c0.t_far = 10.0f;
+    if (!(c0.ray_step > 0.0f && c0.ray_step < 1.0f))
+        return set_error(MVF_ERR_INVALID_ARG, "ray_step must be in (0, 1), got %g", (double)c0.ray_step);
+    if (!(c0.t_far > 0.0f && std::isfinite(c0.t_far)))
+        return set_error(MVF_ERR_INVALID_ARG, "t_far must be positive");
+    int ndev = 0;
+    CHECK_HIP(hipGetDeviceCount(&ndev));
+    if (c0.device < 0 || c0.device >= ndev)
+        return set_error(MVF_ERR_INVALID_ARG, "device %d not present (%d devices)", c0.device, ndev);
+    CHECK_HIP(hipSetDevice(c0.device));
+    mvf_ctx* c = new mvf_ctx();
+    c->cfg = c0;
+    c->device = c0.device;
+    c->budget = c0.hbm_budget_bytes ? c0.hbm_budget_bytes : ~0ull;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c0.device) == hipSuccess) c->n_cus = prop.multiProcessorCount;
+    auto fail = [&](mvf_status st) {
+        mvf_destroy(c);
+        return st;
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * kCntNum)) != hipSuccess ||
+        (e = hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&c->arena.host, Arena::kSlots * Arena::kSlotBytes, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipMalloc((void**)&c->arena.dev, Arena::kSlots * Arena::kSlotBytes)) != hipSuccess ||
+        (e = hipEventCreate(&c->tail)) != hipSuccess)
+        return fail(set_error(MVF_ERR_HIP, "context setup: %s", hipGetErrorString(e)));
+    for (int i = 0; i < Arena::kSlots; ++i)
+        if ((e = hipEventCreate(&c->arena.ev[i])) != hipSuccess)
+            return fail(set_error(MVF_ERR_HIP, "context setup: %s", hipGetErrorString(e)));
+    if ((e = hipDeviceSynchronize()) != hipSuccess)
+        return fail(set_error(MVF_ERR_HIP, "context setup: %s", hipGetErrorString(e)));
+    *out = c;
+    return MVF_OK;
+}
+
+mvf_status mvf_destroy(mvf_ctx* c)
+{
+    if (!c) return MVF_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    destroy_step_graph(c);
+    for (auto& v : c->vols) {
+        if (v.dev) (void)hipFree(v.dev);
+        if (v.host) (void)hipHostFree(v.host);
+        if (v.host_ready) (void)hipEventDestroy(v.host_ready);
+    }
+    for (auto& s : c->pool) {
+        (void)hipFree(s.ptr);
+        (void)hipEventDestroy(s.free_after);
+    }
+    for (auto& kv : c->scratch) {
+        Scratch& s = kv.second;
+        if (s.range) (void)hipFree(s.range);
+        if (s.color) (void)hipFree(s.color);
+        if (s.rmax) (void)hipFree(s.rmax);
+        if (s.best_t) (void)hipFree(s.best_t);
+        if (s.best_id) (void)hipFree(s.best_id);
+    }
+    for (auto& t : c->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto ev : c->event_pool) (void)hipEventDestroy(ev);
+    for (int i = 0; i < Arena::kSlots; ++i)
+        if (c->arena.ev[i]) (void)hipEventDestroy(c->arena.ev[i]);
+    if (c->arena.host) (void)hipHostFree(c->arena.host);
+    if (c->arena.dev) (void)hipFree(c->arena.dev);
+    if (c->counters) (void)hipFree(c->counters);
+    if (c->place_table) (void)hipFree(c->place_table);
+    if (c->place_overflow) (void)hipFree(c->place_overflow);
+    if (c->place_T) (void)hipFree(c->place_T);
+    if (c->diff_partials) (void)hipFree(c->diff_partials);
+    if (c->tail) (void)hipEventDestroy(c->tail);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+    return MVF_OK;
+}
+
+mvf_status mvf_synchronize(mvf_ctx* c)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    CHECK_HIP(hipSetDevice(c->device));
+    if (c->tail_valid) CHECK_HIP(hipEventSynchronize(c->tail));
+    CHECK_HIP(hipStreamSynchronize(c->copy_stream));
+    CHECK_HIP(hipDeviceSynchronize());
+    return MVF_OK;
+}
+
+mvf_status mvf_set_budget(mvf_ctx* c, uint64_t bytes)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    c->budget = bytes ? bytes : ~0ull;
+    c->cfg.hbm_budget_bytes = bytes;
+    return MVF_OK;
+}
+
+mvf_status mvf_get_stats(mvf_ctx* c, mvf_stats* out)
+{
+    if (!c || !out) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    CHECK_HIP(hipSetDevice(c->device));
+    CHECK_ST(mvf_synchronize(c));
+    CHECK_ST(drain_timing(c));
+    unsigned long long cnt[kCntNum];
+    CHECK_HIP(hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    *out = c->stats;
+    out->voxels_updated = cnt[kCntUpdated];
+    out->voxels_band = cnt[kCntBand];
+    out->resident_bytes = c->resident_bytes;
+    int n = 0;
+    for (auto& v : c->vols)
+        if (v.alive && v.state == State::Device) ++n;
+    out->resident_volumes = n;
+    return MVF_OK;
+}
+
+mvf_status mvf_reset_stats(mvf_ctx* c)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    CHECK_ST(mvf_synchronize(c));
+    CHECK_ST(drain_timing(c));
+    c->stats = mvf_stats{};
+    CHECK_HIP(hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum));
+    CHECK_HIP(hipDeviceSynchronize());
+    return MVF_OK;
+}
+
+mvf_status mvf_grid_create(mvf_ctx* c, const mvf_grid_desc* d, int32_t* grid_id)
+{
+    if (!c || !d || !grid_id) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    if (!(d->voxel_size > 0.0f) || !std::isfinite(d->voxel_size))
+        return set_error(MVF_ERR_INVALID_ARG, "voxel_size must be positive");
+    if (!(d->trunc_voxels > 0.0f) || !std::isfinite(d->trunc_voxels))
+        return set_error(MVF_ERR_INVALID_ARG, "trunc_voxels must be positive");
+    if (d->w_max < 1) return set_error(MVF_ERR_INVALID_ARG, "w_max must be >= 1");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d->origin[a])) return set_error(MVF_ERR_INVALID_ARG, "origin not finite");
+    Grid g;
+    g.d = *d;
+    g.mu = d->trunc_voxels * d->voxel_size;
+    g.inv_s = 1.0f / d->voxel_size;
+    g.inv_mu = 1.0f / g.mu;
+    c->grids.push_back(g);
+    *grid_id = (int32_t)c->grids.size() - 1;
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_create(mvf_ctx* c, const mvf_volume_desc* d, int32_t* vol_id)
+{
+    if (!c || !d || !vol_id) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    if (d->grid_id < 0 || d->grid_id >= (int32_t)c->grids.size())
+        return set_error(MVF_ERR_NOT_FOUND, "grid %d", d->grid_id);
+    for (int a = 0; a < 3; ++a) {
+        if (d->dims[a] < 2 || d->dims[a] > 2048)
+            return set_error(MVF_ERR_INVALID_ARG, "dims[%d] = %d outside [2, 2048]", a, d->dims[a]);
+        if (d->offset[a] < -(1 << 22) || d->offset[a] > (1 << 22))
+            return set_error(MVF_ERR_INVALID_ARG, "offset[%d] = %d out of range", a, d->offset[a]);
+    }
+    if (d->stream_id < 0) return set_error(MVF_ERR_INVALID_ARG, "stream_id must be >= 0");
+    Volume v;
+    v.alive = true;
+    v.d = *d;
+    for (int a = 0; a < 3; ++a) v.bd[a] = (d->dims[a] + kBrick - 1) / kBrick;
+    const size_t nb = (size_t)v.bd[0] * v.bd[1] * v.bd[2];
+    v.nvox_pad = nb * kBrickVox;
+    v.off_W = align_up(v.nvox_pad * 4, kAlign);
+    v.off_C = align_up(v.off_W + v.nvox_pad * 2, kAlign);
+    v.off_flag = align_up(v.off_C + v.nvox_pad * 4, kAlign);
+    v.bytes = align_up(v.off_flag + nb, kAlign);
+    c->vols.push_back(v);
+    *vol_id = (int32_t)c->vols.size() - 1;
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_destroy(mvf_ctx* c, int32_t id)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    CHECK_ST(mvf_synchronize(c));
+    if (v->dev) {
+        CHECK_HIP(hipFree(v->dev));
+        c->resident_bytes -= v->bytes;
+    }
+    if (v->host) CHECK_HIP(hipHostFree(v->host));
+    if (v->host_ready) CHECK_HIP(hipEventDestroy(v->host_ready));
+    *v = Volume();
+    for (auto& kv : c->placed)
+        for (auto it = kv.second.begin(); it != kv.second.end();)
+            it = it->second == id ? kv.second.erase(it) : std::next(it);
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_place(mvf_ctx* c, int32_t id)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    v->active = true;
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_evict(mvf_ctx* c, int32_t id, uint32_t flags)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    v->active = false;
+    if (flags & MVF_EVICT_SWAP_OUT) {
+        hipStream_t s = c->tail_valid ? c->tail_stream : nullptr;
+        CHECK_ST(swap_out(c, *v, s));
+    }
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_swap_in(mvf_ctx* c, int32_t id, void* stream)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    if (!find_volume(c, id)) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    CHECK_ST(ensure_resident(c, std::vector<int>{id}, s));
+    return mark_tail(c, s);
+}
+
+mvf_status mvf_volume_swap_out(mvf_ctx* c, int32_t id, void* stream)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    CHECK_ST(swap_out(c, *v, s));
+    return mark_tail(c, s);
+}
+
+mvf_status mvf_volume_describe(mvf_ctx* c, int32_t id, mvf_volume_desc* out)
+{
+    if (!c || !out) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    *out = v->d;
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_query(mvf_ctx* c, int32_t id, int32_t* resident, uint64_t* bytes, int32_t* active)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    if (resident) *resident = v->state == State::Device ? 1 : 0;
+    if (bytes) *bytes = v->bytes;
+    if (active) *active = v->active ? 1 : 0;
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_read(mvf_ctx* c, int32_t id, float* F, uint16_t* W, uint8_t* rgba)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    CHECK_HIP(hipSetDevice(c->device));
+    CHECK_ST(mvf_synchronize(c));
+    const size_t n = (size_t)v->d.dims[0] * v->d.dims[1] * v->d.dims[2];
+    if (v->state == State::Empty) {
+        if (F) memset(F, 0, n * sizeof(float));
+        if (W) memset(W, 0, n * sizeof(uint16_t));
+        if (rgba) memset(rgba, 0, n * 4);
+        return MVF_OK;
+    }
+    // bring the state to the device (the mirror is in device layout)
+    uint8_t* slab = v->dev;
+    uint8_t* tmp_slab = nullptr;
+    if (v->state == State::Host) {
+        CHECK_HIP(hipMalloc((void**)&tmp_slab, v->bytes));
+        CHECK_HIP(hipMemcpy(tmp_slab, v->host, v->bytes, hipMemcpyHostToDevice));
+        slab = tmp_slab;
+    }
+    Volume view = *v;
+    view.dev = slab;
+    DevVolume dv = make_dev(c, view);
+    dv.id = id;
+    float* dF = nullptr;
+    uint16_t* dW = nullptr;
+    uint32_t* dC = nullptr;
+    mvf_status st = MVF_OK;
+    hipError_t e = hipSuccess;
+    if (F && (e = hipMalloc((void**)&dF, n * 4)) != hipSuccess) st = MVF_ERR_OOM;
+    if (st == MVF_OK && W && (e = hipMalloc((void**)&dW, n * 2)) != hipSuccess) st = MVF_ERR_OOM;
+    if (st == MVF_OK && rgba && (e = hipMalloc((void**)&dC, n * 4)) != hipSuccess) st = MVF_ERR_OOM;
+    if (st == MVF_OK) {
+        int le = launch_to_canonical(dv, dF, dW, dC, nullptr);
+        if (le) { st = MVF_ERR_HIP; e = (hipError_t)le; }
+    }
+    if (st == MVF_OK && (e = hipDeviceSynchronize()) != hipSuccess) st = MVF_ERR_HIP;
+    if (st == MVF_OK && F && (e = hipMemcpy(F, dF, n * 4, hipMemcpyDeviceToHost)) != hipSuccess) st = MVF_ERR_HIP;
+    if (st == MVF_OK && W && (e = hipMemcpy(W, dW, n * 2, hipMemcpyDeviceToHost)) != hipSuccess) st = MVF_ERR_HIP;
+    if (st == MVF_OK && rgba && (e = hipMemcpy(rgba, dC, n * 4, hipMemcpyDeviceToHost)) != hipSuccess) st = MVF_ERR_HIP;
+    if (dF) (void)hipFree(dF);
+    if (dW) (void)hipFree(dW);
+    if (dC) (void)hipFree(dC);
+    if (tmp_slab) (void)hipFree(tmp_slab);
+    if (st != MVF_OK) return set_error(st, "volume_read: %s", hipGetErrorString(e));
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_write(mvf_ctx* c, int32_t id, const float* F, const uint16_t* W, const uint8_t* rgba)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    CHECK_HIP(hipSetDevice(c->device));
+    CHECK_ST(mvf_synchronize(c));
+    CHECK_ST(ensure_resident(c, std::vector<int>{id}, nullptr));
+    const size_t n = (size_t)v->d.dims[0] * v->d.dims[1] * v->d.dims[2];
+    float* dF = nullptr;
+    uint16_t* dW = nullptr;
+    uint32_t* dC = nullptr;
+    mvf_status st = MVF_OK;
+    hipError_t e = hipSuccess;
+    if (F && (e = hipMalloc((void**)&dF, n * 4)) != hipSuccess) st = MVF_ERR_OOM;
+    if (st == MVF_OK && W && (e = hipMalloc((void**)&dW, n * 2)) != hipSuccess) st = MVF_ERR_OOM;
+    if (st == MVF_OK && rgba && (e = hipMalloc((void**)&dC, n * 4)) != hipSuccess) st = MVF_ERR_OOM;
+    if (st == MVF_OK && F && (e = hipMemcpy(dF, F, n * 4, hipMemcpyHostToDevice)) != hipSuccess) st = MVF_ERR_HIP;
+    if (st == MVF_OK && W && (e = hipMemcpy(dW, W, n * 2, hipMemcpyHostToDevice)) != hipSuccess) st = MVF_ERR_HIP;
+    if (st == MVF_OK && rgba && (e = hipMemcpy(dC, rgba, n * 4, hipMemcpyHostToDevice)) != hipSuccess) st = MVF_ERR_HIP;
+    if (st == MVF_OK) {
+        DevVolume dv = make_dev(c, *v);
+        int le = launch_volume_init(dv, nullptr);
+        if (!le) le = launch_from_canonical(dv, dF, dW, dC, nullptr);
+        if (!le) le = launch_brick_summary(dv, nullptr);
+        if (le) { st = MVF_ERR_HIP; e = (hipError_t)le; }
+    }
+    if (st == MVF_OK && (e = hipDeviceSynchronize()) != hipSuccess) st = MVF_ERR_HIP;
+    if (dF) (void)hipFree(dF);
+    if (dW) (void)hipFree(dW);
+    if (dC) (void)hipFree(dC);
+    if (st != MVF_OK) return set_error(st, "volume_write: %s", hipGetErrorString(e));
+    return MVF_OK;
+}
+
+mvf_status mvf_integrate(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12], const mvf_intrinsics* K,
+                         void* stream)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    CHECK_ST(check_frame(f));
+    if (!T_wc || !finite_pose(T_wc)) return set_error(MVF_ERR_INVALID_ARG, "pose is NULL or not finite");
+    if (!valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "intrinsics NULL, not finite or zero focal length");
+    if (sid < 0) return set_error(MVF_ERR_INVALID_ARG, "stream_id must be >= 0");
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    std::vector<int> ids = stream_volumes(c, sid, T_wc, *K, f->width, f->height);
+    CHECK_ST(integrate_plain(c, sid, f, T_wc, *K, ids, s));
+    return mark_tail(c, s);
+}
+
+mvf_status mvf_raycast(mvf_ctx* c, int32_t sid, const float T_wc[12], const mvf_intrinsics* K,
+                       const mvf_raycast_out* out, void* stream)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    if (!out || !out->depth) return set_error(MVF_ERR_INVALID_ARG, "out or out->depth is NULL");
+    if (out->width <= 0 || out->height <= 0 || out->width > 16384 || out->height > 16384)
+        return set_error(MVF_ERR_INVALID_ARG, "output size %dx%d out of range", out->width, out->height);
+    if (!T_wc || !finite_pose(T_wc)) return set_error(MVF_ERR_INVALID_ARG, "pose is NULL or not finite");
+    if (!valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "intrinsics NULL, not finite or zero focal length");
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    std::vector<int> ids = stream_volumes(c, sid, T_wc, *K, out->width, out->height);
+    // all volumes of one raycast must share one grid (one sample lattice)
+    for (int id : ids)
+        if (c->vols[id].d.grid_id != c->vols[ids[0]].d.grid_id)
+            return set_error(MVF_ERR_UNSUPPORTED, "volumes of stream %d lie on different grids", sid);
+    CHECK_ST(raycast_plain(c, sid, T_wc, *K, out, ids, s));
+    return mark_tail(c, s);
+}
+
+// ---- batched step -------------------------------------------------------------
+
+mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const mvf_raycast_out* outs, void* stream)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    if (n <= 0 || n > 1024 || !frames || !outs) return set_error(MVF_ERR_INVALID_ARG, "bad stream count or NULL arrays");
+    for (int i = 0; i < n; ++i) {
+        CHECK_ST(check_frame(&frames[i].frame));
+        if (!finite_pose(frames[i].T_wc)) return set_error(MVF_ERR_INVALID_ARG, "pose %d not finite", i);
+        if (!valid_K(&frames[i].K)) return set_error(MVF_ERR_INVALID_ARG, "intrinsics %d invalid", i);
+        if (!outs[i].depth || outs[i].width <= 0 || outs[i].height <= 0 || outs[i].width > 16384 ||
+            outs[i].height > 16384)
+            return set_error(MVF_ERR_INVALID_ARG, "output %d invalid", i);
+        if (frames[i].stream_id < 0) return set_error(MVF_ERR_INVALID_ARG, "stream_id %d", frames[i].stream_id);
+        for (int j = 0; j < i; ++j)
+            if (frames[j].stream_id == frames[i].stream_id)
+                return set_error(MVF_ERR_INVALID_ARG, "stream %d appears twice", frames[i].stream_id);
+    }
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+
+    // volumes per stream (integration set == raycast set: active and in view)
+    std::vector<std::vector<int>> per(n);
+    std::vector<int> all;
+    int grid0 = -1;
+    for (int i = 0; i < n; ++i) {
+        const mvf_stream_frame& fr = frames[i];
+        per[i] = stream_volumes(c, fr.stream_id, fr.T_wc, fr.K, fr.frame.width, fr.frame.height);
+        // raycast view may differ in size from the frame; use the union test
+        std::vector<int> rv = stream_volumes(c, fr.stream_id, fr.T_wc, fr.K, outs[i].width, outs[i].height);
+        for (int id : rv)
+            if (std::find(per[i].begin(), per[i].end(), id) == per[i].end()) per[i].push_back(id);
+        std::sort(per[i].begin(), per[i].end());
+        for (int id : per[i]) {
+            all.push_back(id);
+            if (grid0 < 0) grid0 = c->vols[id].d.grid_id;
+            if (c->vols[id].d.grid_id != grid0)
+                return set_error(MVF_ERR_UNSUPPORTED, "batched step needs all volumes on one grid");
+        }
+    }
+    uint64_t total = 0;
+    for (int id : all) total += c->vols[id].bytes;
+    if (total > c->budget)
+        return set_error(MVF_ERR_BUDGET, "active volumes of the step (%llu bytes) exceed the budget",
+                         (unsigned long long)total);
+    CHECK_ST(ensure_resident(c, all, s));
+
+    StepGraph& G = c->step;
+    int max_w = 0, max_h = 0;
+    for (int i = 0; i < n; ++i) {
+        max_w = std::max(max_w, frames[i].frame.width);
+        max_h = std::max(max_h, frames[i].frame.height);
+    }
+    bool same_shape = G.valid && G.n == n && (int)all.size() <= G.max_vols && max_w <= G.max_w && max_h <= G.max_h;
+    if (same_shape) {
+        for (int i = 0; i < n; ++i)
+            if (G.out_w[i] != outs[i].width || G.out_h[i] != outs[i].height) same_shape = false;
+    }
+    const int tw = 16, th = 16;
+    if (!same_shape) {
+        CHECK_ST(destroy_step_graph(c));
+        G.n = n;
+        G.max_vols = std::max<int>((int)all.size() * 2, 16);
+        G.max_w = max_w;
+        G.max_h = max_h;
+        G.out_w.assign(n, 0);
+        G.out_h.assign(n, 0);
+        for (int i = 0; i < n; ++i) {
+            G.out_w[i] = outs[i].width;
+            G.out_h[i] = outs[i].height;
+        }
+        size_t off = 0;
+        auto take = [&](size_t bytes) { size_t o = align_up(off, 256); off = o + bytes; return o; };
+        G.off_hdr = take(sizeof(LaunchHeader));
+        G.off_prep = take(sizeof(PrepItem) * n);
+        G.off_frames = take(sizeof(DevFrame) * n);
+        G.off_vols = take(sizeof(DevVolume) * G.max_vols);
+        G.off_items = take(sizeof(int32_t) * (G.max_vols + 1));
+        G.off_lists = take(sizeof(int32_t) * G.max_vols);
+        G.off_lbase = take(sizeof(int32_t) * (n + 1));
+        G.off_tbase = take(sizeof(int32_t) * (n + 1));
+        G.dev_bytes = align_up(off, 256);
+        if (G.dev_bytes > Arena::kSlotBytes) return set_error(MVF_ERR_INVALID_ARG, "step tables too large");
+        CHECK_HIP(hipMalloc((void**)&G.dev, G.dev_bytes));
+        G.integ_blocks = c->n_cus * 8;
+        int tiles = 0;
+        for (int i = 0; i < n; ++i) tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
+        G.ray_blocks = std::min(tiles, c->n_cus * 8);
+    }
+    // scratch per stream
+    std::vector<Scratch*> sc(n);
+    for (int i = 0; i < n; ++i)
+        CHECK_ST(get_scratch(c, frames[i].stream_id, frames[i].frame.width, frames[i].frame.height, false, &sc[i]));
+
+    // host image of the tables, uploaded to G.dev before the graph runs
+    int slot;
+    Writer w;
+    CHECK_ST(arena_acquire(c, &slot, &w));
+    uint8_t* img = w.host;
+    memset(img, 0, G.dev_bytes);
+    w.used = G.dev_bytes;
+    LaunchHeader* h = reinterpret_cast<LaunchHeader*>(img + G.off_hdr);
+    PrepItem* prep = reinterpret_cast<PrepItem*>(img + G.off_prep);
+    DevFrame* dfr = reinterpret_cast<DevFrame*>(img + G.off_frames);
+    DevVolume* vt = reinterpret_cast<DevVolume*>(img + G.off_vols);
+    int32_t* ib = reinterpret_cast<int32_t*>(img + G.off_items);
+    int32_t* lists = reinterpret_cast<int32_t*>(img + G.off_lists);
+    int32_t* lb = reinterpret_cast<int32_t*>(img + G.off_lbase);
+    int32_t* tb = reinterpret_cast<int32_t*>(img + G.off_tbase);
+    int nv = 0;
+    int items = 0;
+    int tiles = 0;
+    const int zc = 4;
+    lb[0] = 0;
+    tb[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        const mvf_stream_frame& fr = frames[i];
+        PrepItem& p = prep[i];
+        p.depth = fr.frame.depth;
+        p.rgb = fr.frame.rgb;
+        p.depth_pitch = fr.frame.depth_pitch ? fr.frame.depth_pitch : fr.frame.width;
+        p.rgb_pitch = fr.frame.rgb_pitch ? fr.frame.rgb_pitch : 3 * fr.frame.width;
+        p.width = fr.frame.width;
+        p.height = fr.frame.height;
+        p.fx = fr.K.fx; p.fy = fr.K.fy; p.cx = fr.K.cx; p.cy = fr.K.cy;
+        p.range = sc[i]->range;
+        p.color = sc[i]->color;
+        p.rmax = sc[i]->rmax;
+        fill_frame(&dfr[i], sc[i], fr.frame.width, fr.frame.height, fr.T_wc, fr.K);
+        if (!fr.frame.rgb) dfr[i].color = nullptr;
+        dfr[i].depth = outs[i].depth;
+        dfr[i].vertex = outs[i].vertex;
+        dfr[i].normal = outs[i].normal;
+        dfr[i].hit = outs[i].hit;
+        dfr[i].out_w = outs[i].width;
+        dfr[i].out_h = outs[i].height;
+        // this stream's volumes, nearest first for the raycast list
+        std::vector<int> ids = per[i];
+        std::vector<double> dist(ids.size());
+        for (size_t j = 0; j < ids.size(); ++j) dist[j] = box_distance(c, c->vols[ids[j]], fr.T_wc);
+        std::vector<int> order(ids.size());
+        for (size_t j = 0; j < ids.size(); ++j) order[j] = (int)j;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return dist[a] < dist[b] || (dist[a] == dist[b] && ids[a] < ids[b]);
+        });
+        const int first = nv;
+        for (size_t j = 0; j < ids.size(); ++j) {
+            Volume& v = c->vols[ids[j]];
+            vt[nv] = make_dev(c, v);
+            vt[nv].frame = i;
+            ib[nv] = items;
+            items += v.bd[0] * v.bd[1] * ((v.bd[2] + zc - 1) / zc);
+            ++nv;
+        }
+        for (size_t j = 0; j < ids.size(); ++j) lists[first + j] = first + order[j];
+        lb[i + 1] = nv;
+        tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
+        tb[i + 1] = tiles;
+    }
+    ib[nv] = items;
+    h->nvol = nv;
+    h->total_items = items;
+    h->zchunk = zc;
+    h->nstreams = n;
+    h->total_tiles = tiles;
+    h->first_wave = 1;
+    h->rp = grid0 >= 0 ? ray_params(c, c->grids[grid0]) : RayParams{1.0f, 0};
+    // upload into the graph's fixed tables (stream-ordered before the replay)
+    CHECK_HIP(hipMemcpyAsync(G.dev, w.host, G.dev_bytes, hipMemcpyHostToDevice, s));
+    CHECK_ST(arena_release(c, slot, s));
+
+    if (!G.valid) {
+        hipStream_t cs = c->capture_stream;
+        const LaunchHeader* dh = reinterpret_cast<const LaunchHeader*>(G.dev + G.off_hdr);
+        const PrepItem* dprep = reinterpret_cast<const PrepItem*>(G.dev + G.off_prep);
+        const DevFrame* dframes = reinterpret_cast<const DevFrame*>(G.dev + G.off_frames);
+        const DevVolume* dvols = reinterpret_cast<const DevVolume*>(G.dev + G.off_vols);
+        const int32_t* ditems = reinterpret_cast<const int32_t*>(G.dev + G.off_items);
+        const int32_t* dlists = reinterpret_cast<const int32_t*>(G.dev + G.off_lists);
+        const int32_t* dlb = reinterpret_cast<const int32_t*>(G.dev + G.off_lbase);
+        const int32_t* dtb = reinterpret_cast<const int32_t*>(G.dev + G.off_tbase);
+        CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        int e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
+        IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters};
+        int e2 = e1 ? e1 : launch_integrate(IL, G.integ_blocks, cs);
+        RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th};
+        int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
+        hipError_t ee = hipStreamEndCapture(cs, &G.graph);
+        if (e3) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString((hipError_t)e3));
+        if (ee != hipSuccess) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString(ee));
+        CHECK_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+        G.valid = true;
+    }
+    hipEvent_t t0;
+    CHECK_ST(timing_begin(c, s, &t0));
+    CHECK_HIP(hipGraphLaunch(G.exec, s));
+    CHECK_ST(timing_end(c, s, t0, 2));
+    c->stats.step_launches += 1;
+    for (int i = 0; i < n; ++i) c->stats.pixels_raycast += (uint64_t)outs[i].width * outs[i].height;
+    return mark_tail(c, s);
+}
+
+// ---- placement ------------------------------------------------------------------
+
+mvf_status mvf_placement_policy(const int32_t* active, int32_t n_active, const int32_t* cells,
+                                const int32_t* counts, int32_t n_cells, int32_t n_max, float beta,
+                                int32_t* out_active, int32_t* n_out, int32_t* added, int32_t* n_added,
+                                int32_t* removed, int32_t* n_removed)
+{
+    if (n_active < 0 || n_cells < 0 || n_max < 0 || !(beta >= 1.0f) || !n_out || !n_added || !n_removed ||
+        (n_active && !active) || (n_cells && (!cells || !counts)) || (n_max && !out_active))
+        return set_error(MVF_ERR_INVALID_ARG, "placement_policy: bad arguments");
+    typedef std::vector<int> Key;
+    auto key_of = [](const int32_t* p) { return Key{p[0], p[1], p[2]}; };
+    std::map<Key, long long> cnt;
+    for (int i = 0; i < n_cells; ++i) {
+        if (counts[i] < 0) return set_error(MVF_ERR_INVALID_ARG, "negative count");
+        cnt[key_of(cells + 3 * i)] += counts[i];
+    }
+    std::vector<Key> H;
+    for (int i = 0; i < n_active; ++i) {
+        Key k = key_of(active + 3 * i);
+        if (std::find(H.begin(), H.end(), k) == H.end()) H.push_back(k);
+    }
+    // candidates: counted cells not in H, count desc then cell asc
+    std::vector<std::pair<long long, Key>> cand;
+    for (auto& kv : cnt)
+        if (kv.second > 0 && std::find(H.begin(), H.end(), kv.first) == H.end()) cand.push_back({kv.second, kv.first});
+    std::sort(cand.begin(), cand.end(), [](const std::pair<long long, Key>& a, const std::pair<long long, Key>& b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+    });
+    std::vector<Key> add, rem;
+    size_t ci = 0;
+    while ((int)H.size() < n_max && ci < cand.size()) {
+        H.push_back(cand[ci].second);
+        add.push_back(cand[ci].second);
+        ++ci;
+    }
+    auto count_of = [&](const Key& k) { auto it = cnt.find(k); return it == cnt.end() ? 0LL : it->second; };
+    while (ci < cand.size() && !H.empty()) {
+        // lowest-count member; ties go to the lexicographically larger cell
+        size_t low = 0;
+        for (size_t i = 1; i < H.size(); ++i) {
+            const long long a = count_of(H[i]), b = count_of(H[low]);
+            if (a < b || (a == b && H[i] > H[low])) low = i;
+        }
+        if ((double)cand[ci].first > (double)beta * (double)count_of(H[low])) {
+            Key gone = H[low];
+            H.erase(H.begin() + low);
+            auto it = std::find(add.begin(), add.end(), gone);
+            if (it != add.end()) add.erase(it); else rem.push_back(gone);
+            H.push_back(cand[ci].second);
+            add.push_back(cand[ci].second);
+            ++ci;
+        } else {
+            break;
+        }
+    }
+    if ((int)H.size() > n_max) return set_error(MVF_ERR_STATE, "placement_policy: internal size error");
+    for (size_t i = 0; i < H.size(); ++i)
+        for (int a = 0; a < 3; ++a) out_active[3 * i + a] = H[i][a];
+    *n_out = (int32_t)H.size();
+    for (size_t i = 0; i < add.size(); ++i)
+        if (added) for (int a = 0; a < 3; ++a) added[3 * i + a] = add[i][a];
+    for (size_t i = 0; i < rem.size(); ++i)
+        if (removed) for (int a = 0; a < 3; ++a) removed[3 * i + a] = rem[i][a];
+    *n_added = (int32_t)add.size();
+    *n_removed = (int32_t)rem.size();
+    return MVF_OK;
+}
+
+static mvf_status placement_count_impl(mvf_ctx* c, const mvf_frame* f, const float* T, const mvf_intrinsics* K,
+                                       const Grid& g, int d_v, std::vector<std::pair<std::vector<int>, int>>* out,
+                                       hipStream_t s)
+{
+    if (!c->place_table) {
+        CHECK_HIP(hipMalloc((void**)&c->place_table, sizeof(unsigned long long) * 2 * mvf_ctx::kPlaceTable));
+        CHECK_HIP(hipMalloc((void**)&c->place_overflow, 256));
+        CHECK_HIP(hipMalloc((void**)&c->place_T, 256));
+    }
+    const float cell = g.d.voxel_size * (float)(d_v - 2);
+    CHECK_HIP(hipMemcpyAsync(c->place_T, T, sizeof(float) * 12, hipMemcpyHostToDevice, s));
+    CHECK_LAUNCH(launch_placement_clear(c->place_table, mvf_ctx::kPlaceTable, s));
+    CHECK_HIP(hipMemsetAsync(c->place_overflow, 0, sizeof(int), s));
+    CHECK_LAUNCH(launch_placement_count(f->depth, f->depth_pitch ? f->depth_pitch : f->width, f->width, f->height,
+                                        K->fx, K->fy, K->cx, K->cy, c->place_T, g.d.origin[0], g.d.origin[1],
+                                        g.d.origin[2], cell, c->place_table, mvf_ctx::kPlaceTable,
+                                        c->place_overflow, s));
+    std::vector<unsigned long long> tab(2 * mvf_ctx::kPlaceTable);
+    int ovf = 0;
+    CHECK_HIP(hipMemcpyAsync(tab.data(), c->place_table, tab.size() * 8, hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipMemcpyAsync(&ovf, c->place_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    if (ovf & 1) return set_error(MVF_ERR_STATE, "more than %d distinct placement cells", mvf_ctx::kPlaceTable);
+    if (ovf & 2) return set_error(MVF_ERR_INVALID_ARG, "placement cell index out of range");
+    out->clear();
+    for (int i = 0; i < mvf_ctx::kPlaceTable; ++i) {
+        const unsigned long long key = tab[2 * i];
+        if (key == ~0ull) continue;
+        const long long nrays = (long long)tab[2 * i + 1];
+        std::vector<int> k = { (int)((key >> 42) & 0x1FFFFF) - (1 << 20), (int)((key >> 21) & 0x1FFFFF) - (1 << 20),
+                               (int)(key & 0x1FFFFF) - (1 << 20) };
+        out->push_back({k, (int)nrays});
+    }
+    std::sort(out->begin(), out->end());
+    return MVF_OK;
+}
+
+mvf_status mvf_placement_count(mvf_ctx* c, const mvf_frame* f, const float T_wc[12], const mvf_intrinsics* K,
+                               int32_t grid_id, int32_t d_v, int32_t* cells, int32_t* counts, int32_t max_cells,
+                               int32_t* n_cells, void* stream)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    CHECK_ST(check_frame(f));
+    if (!T_wc || !finite_pose(T_wc) || !valid_K(K) || !n_cells || max_cells < 0 || (max_cells && (!cells || !counts)))
+        return set_error(MVF_ERR_INVALID_ARG, "bad pose, intrinsics or output arrays");
+    if (grid_id < 0 || grid_id >= (int32_t)c->grids.size()) return set_error(MVF_ERR_NOT_FOUND, "grid %d", grid_id);
+    if (d_v < 3) return set_error(MVF_ERR_INVALID_ARG, "d_v must be >= 3");
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    std::vector<std::pair<std::vector<int>, int>> res;
+    CHECK_ST(placement_count_impl(c, f, T_wc, K, c->grids[grid_id], d_v, &res, s));
+    *n_cells = (int32_t)res.size();
+    for (int i = 0; i < (int)res.size() && i < max_cells; ++i) {
+        for (int a = 0; a < 3; ++a) cells[3 * i + a] = res[i].first[a];
+        counts[i] = res[i].second;
+    }
+    return mark_tail(c, s);
+}
+
+mvf_status mvf_placement_update(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
+                                const mvf_intrinsics* K, const mvf_placement_params* p, mvf_placement_result* r,
+                                void* stream)
+{
+    if (!c || !p || !r) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    CHECK_ST(check_frame(f));
+    if (!T_wc || !finite_pose(T_wc) || !valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "bad pose or intrinsics");
+    if (p->grid_id < 0 || p->grid_id >= (int32_t)c->grids.size()) return set_error(MVF_ERR_NOT_FOUND, "grid %d", p->grid_id);
+    if (p->d_v < 3 || p->d_v > 2048) return set_error(MVF_ERR_INVALID_ARG, "d_v out of range");
+    if (p->n_max < 0 || p->n_max > 64) return set_error(MVF_ERR_INVALID_ARG, "n_max must be in [0, 64]");
+    if (!(p->beta >= 1.0f)) return set_error(MVF_ERR_INVALID_ARG, "beta must be >= 1");
+    if (sid < 0) return set_error(MVF_ERR_INVALID_ARG, "stream_id must be >= 0");
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    std::vector<std::pair<std::vector<int>, int>> res;
+    CHECK_ST(placement_count_impl(c, f, T_wc, K, c->grids[p->grid_id], p->d_v, &res, s));
+    memset(r, 0, sizeof(*r));
+    r->n_cells = (int32_t)res.size();
+    auto& placed = c->placed[sid];
+    std::vector<int32_t> act, cellv, cntv;
+    for (auto& kv : placed) {
+        Volume* v = find_volume(c, kv.second);
+        if (v && v->active) act.insert(act.end(), kv.first.begin(), kv.first.end());
+    }
+    for (auto& e : res) {
+        cellv.insert(cellv.end(), e.first.begin(), e.first.end());
+        cntv.push_back(e.second);
+    }
+    const int n_act = (int)act.size() / 3;
+    std::vector<int32_t> out(3 * std::max(1, p->n_max)), add(3 * (n_act + (int)res.size() + 1)),
+        rem(3 * (n_act + (int)res.size() + 1));
+    int32_t n_out = 0, n_add = 0, n_rem = 0;
+    CHECK_ST(mvf_placement_policy(act.data(), n_act, cellv.data(), cntv.data(), (int32_t)res.size(), p->n_max,
+                                  p->beta, out.data(), &n_out, add.data(), &n_add, rem.data(), &n_rem));
+    for (int i = 0; i < n_rem && r->n_removed < 64; ++i) {
+        std::vector<int> k = { rem[3 * i], rem[3 * i + 1], rem[3 * i + 2] };
+        const int id = placed[k];
+        CHECK_ST(mvf_volume_evict(c, id, MVF_EVICT_SWAP_OUT));
+        r->removed[r->n_removed++] = id;
+    }
+    for (int i = 0; i < n_add && r->n_added < 64; ++i) {
+        std::vector<int> k = { add[3 * i], add[3 * i + 1], add[3 * i + 2] };
+        int id;
+        auto it = placed.find(k);
+        if (it != placed.end() && find_volume(c, it->second)) {
+            id = it->second;  // seen before: state kept on the host
+        } else {
+            mvf_volume_desc d{};
+            d.grid_id = p->grid_id;
+            for (int a = 0; a < 3; ++a) {
+                d.offset[a] = k[a] * (p->d_v - 2);
+                d.dims[a] = p->d_v;
+            }
+            d.stream_id = sid;
+            CHECK_ST(mvf_volume_create(c, &d, &id));
+            placed[k] = id;
+        }
+        CHECK_ST(mvf_volume_place(c, id));
+        r->added[r->n_added++] = id;
+    }
+    return mark_tail(c, s);
+}
+
+// ---- differentiable raycast --------------------------------------------------------
+
+static mvf_status diff_volume(mvf_ctx* c, const mvf_dense_tsdf* v, DiffVolume* out)
+{
+    if (!v || !v->F || !v->W) return set_error(MVF_ERR_INVALID_ARG, "dense volume or its planes NULL");
+    for (int a = 0; a < 3; ++a)
+        if (v->dims[a] < 2 || v->dims[a] > 4096) return set_error(MVF_ERR_INVALID_ARG, "dense dims out of range");
+    if (!(v->voxel_size > 0.0f)) return set_error(MVF_ERR_INVALID_ARG, "voxel_size must be positive");
+    out->F = v->F;
+    out->W = v->W;
+    for (int a = 0; a < 3; ++a) {
+        out->dims[a] = v->dims[a];
+        out->off[a] = v->offset[a];
+        out->o[a] = v->origin[a];
+    }
+    out->s = v->voxel_size;
+    out->inv_s = 1.0f / v->voxel_size;
+    (void)c;
+    return MVF_OK;
+}
+
+mvf_status mvf_diffray_forward(mvf_ctx* c, const mvf_dense_tsdf* v, const float T_wc[12], const mvf_intrinsics* K,
+                               int32_t width, int32_t height, float* depth, int32_t* record, void* stream)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    DiffVolume dv;
+    CHECK_ST(diff_volume(c, v, &dv));
+    if (!T_wc || !finite_pose(T_wc) || !valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "bad pose or intrinsics");
+    if (width <= 0 || height <= 0 || width > 16384 || height > 16384 || !depth || !record)
+        return set_error(MVF_ERR_INVALID_ARG, "bad output");
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    RayParams rp;
+    rp.delta = c->cfg.ray_step * v->voxel_size;
+    rp.kmax = (int32_t)std::floor(c->cfg.t_far / rp.delta);
+    CHECK_LAUNCH(launch_diffray_forward(dv, T_wc, K->fx, K->fy, K->cx, K->cy, width, height, rp, depth, record, s));
+    return mark_tail(c, s);
+}
+
+mvf_status mvf_diffray_backward(mvf_ctx* c, const mvf_dense_tsdf* v, const float T_wc[12], const mvf_intrinsics* K,
+                                int32_t width, int32_t height, const float* grad_depth, const int32_t* record,
+                                float* grad_F, double* grad_xi, void* stream)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    DiffVolume dv;
+    CHECK_ST(diff_volume(c, v, &dv));
+    if (!T_wc || !finite_pose(T_wc) || !valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "bad pose or intrinsics");
+    if (width <= 0 || height <= 0 || width > 16384 || height > 16384 || !grad_depth || !record || !grad_xi)
+        return set_error(MVF_ERR_INVALID_ARG, "bad gradient buffers");
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    const int need = diffray_partials_needed(width, height);
+    if (need > c->diff_partials_n) {
+        if (c->diff_partials) {
+            CHECK_HIP(hipStreamSynchronize(s));
+            CHECK_HIP(hipFree(c->diff_partials));
+        }
+        CHECK_HIP(hipMalloc((void**)&c->diff_partials, sizeof(double) * 6 * need));
+        c->diff_partials_n = need;
+    }
+    RayParams rp;
+    rp.delta = c->cfg.ray_step * v->voxel_size;
+    rp.kmax = (int32_t)std::floor(c->cfg.t_far / rp.delta);
+    CHECK_LAUNCH(launch_diffray_backward(dv, T_wc, K->fx, K->fy, K->cx, K->cy, width, height, rp, grad_depth, record,
+                                         grad_F, c->diff_partials, c->diff_partials_n, grad_xi, s));
+    return mark_tail(c, s);
+}
+
+mvf_status mvf_pose_retract(const double T[12], const double xi[6], double T_out[12])
+{
+    if (!T || !xi || !T_out) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    const double* rho = xi;
+    const double* w = xi + 3;
+    const double th = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double Wx[9] = { 0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0 };
+    double W2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += Wx[3 * i + k] * Wx[3 * k + j];
+            W2[3 * i + j] = acc;
+        }
+    double A, B, C;
+    if (th < 1e-10) {
+        A = 1.0; B = 0.5; C = 1.0 / 6.0;
+    } else {
+        A = std::sin(th) / th;
+        B = (1.0 - std::cos(th)) / (th * th);
+        C = (th - std::sin(th)) / (th * th * th);
+    }
+    double R[9], V[9];
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i % 4 == 0) ? 1.0 : 0.0;
+        R[i] = I + A * Wx[i] + B * W2[i];
+        V[i] = I + B * Wx[i] + C * W2[i];
+    }
+    double t[3];
+    for (int i = 0; i < 3; ++i) t[i] = V[3 * i] * rho[0] + V[3 * i + 1] * rho[1] + V[3 * i + 2] * rho[2];
+    double out[12];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            out[4 * i + j] = T[4 * i] * R[j] + T[4 * i + 1] * R[3 + j] + T[4 * i + 2] * R[6 + j];
+        out[4 * i + 3] = T[4 * i] * t[0] + T[4 * i + 1] * t[1] + T[4 * i + 2] * t[2] + T[4 * i + 3];
+    }
+    memcpy(T_out, out, sizeof(out));
+    return MVF_OK;
+}
+
+}  // extern "C"
