@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--phases", default="single,tiled,batched")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the phases, copy a buffer of this size 5 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -178,6 +180,15 @@ def main():
         log(f"phase {ph}")
         phases[ph] = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps)
         log(json.dumps(phases[ph]))
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 5 copies of {args.copy_probe_mib} MiB")
+        del a, b
     main_ph = phases.get("single") or next(iter(phases.values()))
     steps = args.steps
     # roofline of the integration kernel

@@ -18,6 +18,11 @@
 //                  F <= 2^-100 (set by integration, never cleared except by
 //                  a full recompute); 0 guarantees F > 0 or NaN everywhere
 //                  in the brick, which lets the raycast skip it exactly.
+//   dist  uint8    per brick: Chebyshev distance, in bricks, to the nearest
+//                  flagged brick, capped at kDistCap (0 = flagged); every
+//                  brick within dist - 1 of this one is unflagged.  Derived
+//                  from the flags after each integration.
+//   tmp   2 x uint8 per brick: passes of the distance transform.
 #pragma once
 #include <stdint.h>
 
@@ -26,12 +31,15 @@ namespace mvf {
 constexpr int kBrick = 8;
 constexpr int kBrickVox = 512;
 constexpr float kFlagThreshold = 0x1p-100f;
+constexpr int kDistCap = 12;
 
 struct DevVolume {
     float* F;
     uint16_t* W;
     uint32_t* C;
     uint8_t* flag;
+    uint8_t* dist;
+    uint8_t* tmp;            // 2 * nbricks bytes of scratch for the distance passes
     int32_t dims[3];
     int32_t off[3];
     int32_t bd[3];
@@ -80,6 +88,7 @@ struct LaunchHeader {
     int32_t zchunk;        // bricks per integration item along z
     int32_t nstreams;      // frames in the frame table
     int32_t total_tiles;   // raycast pixel tiles over all streams
+    int32_t total_bricks;  // bricks over all volumes of the table (distance passes)
     int32_t first_wave;    // raycast: 1 = start from no hit, 0 = merge with best_t/best_id
     RayParams rp;
 };
@@ -124,6 +133,10 @@ int launch_volume_init(DevVolume v, void* stream);
 int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream);
 int launch_raycast(const RaycastLaunch& L, int blocks, void* stream);
 int launch_brick_summary(DevVolume v, void* stream);
+// Brick distance transform of every volume in the table (3 passes).
+// brick_base: nvol + 1 prefix sums of the volumes' brick counts.
+int launch_brick_distance(const LaunchHeader* hdr, const DevVolume* vols, const int32_t* brick_base,
+                          int blocks, void* stream);
 int launch_to_canonical(DevVolume v, float* F, uint16_t* W, uint32_t* C, void* stream);
 int launch_from_canonical(DevVolume v, const float* F, const uint16_t* W, const uint32_t* C,
                           void* stream);

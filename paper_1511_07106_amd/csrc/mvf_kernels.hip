@@ -14,6 +14,22 @@ namespace mvf {
 static __host__ __device__ __forceinline__ float qnan() { return __builtin_nanf(""); }
 static __host__ __device__ __forceinline__ float pinf() { return __builtin_inff(); }
 
+// Pointers into global memory.  Volume and frame pointers reach the kernels
+// through tables in memory, so the compiler cannot infer their address space
+// and would emit flat accesses; the cast makes them global accesses.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GPTR(T) __attribute__((address_space(1))) T*
+template <class T>
+static __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+#else
+#define GPTR(T) T*
+template <class T>
+static __host__ __device__ inline T* gptr(T* p) { return p; }
+#endif
+
 static __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 static __host__ __device__ __forceinline__ size_t brick_index(const int bd[3], int bx, int by, int bz) {
@@ -85,7 +101,10 @@ __global__ __launch_bounds__(256) void mvf_volume_init_kernel(DevVolume v, size_
         v.F[i] = __uint_as_float(0x7fc00000u);
         v.W[i] = 0;
         v.C[i] = 0;
-        if (i < nbricks) v.flag[i] = 0;
+        if (i < nbricks) {
+            v.flag[i] = 0;
+            v.dist[i] = kDistCap;
+        }
     }
 }
 
@@ -115,6 +134,17 @@ int launch_volume_init(DevVolume v, void* stream)
 // voxel of this column can pass the exact test.  Each condition is a
 // half-line a + b z >= 0 of the affine camera-frame position p(z); margins
 // (1 px, 1 mm, 2 voxels) dominate the binary32 rounding of the exact test.
+// n / d for n < 2^17 and 1 <= d <= 256 exactly: a quotient from the
+// reciprocal estimate, then one correction step each way.
+static __device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d, float rd)
+{
+    int q = (int)((float)n * rd);
+    int r = (int)n - q * (int)d;
+    q += (r >= (int)d) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return (uint32_t)q;
+}
+
 static __device__ __forceinline__ void clip_halfline(float a, float b, float& zl, float& zh)
 {
     if (b > 0.0f) {
@@ -132,7 +162,7 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
     const int wib = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     const int total_waves = gridDim.x * wpb;
-    unsigned long long n_upd = 0, n_band = 0;
+    unsigned n_upd = 0, n_band = 0;
     const int total_items = L.hdr->total_items;
     const int nvol = L.hdr->nvol;
     const int zchunk = L.hdr->zchunk;
@@ -145,7 +175,6 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
             if (L.item_base[mid] <= item) lo = mid; else hi = mid - 1;
         }
         const DevVolume V = L.vols[lo];
-        const DevFrame& Fr = L.frames[V.frame];
         const int local = item - L.item_base[lo];
         const int ncols = V.bd[0] * V.bd[1];
         const int zc = local / ncols;
@@ -155,12 +184,21 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
         const int bz0 = zc * zchunk;
         const int bz1 = min(bz0 + zchunk, V.bd[2]);
 
-        const float T0 = Fr.T[0], T1 = Fr.T[1], T2 = Fr.T[2], T3 = Fr.T[3];
-        const float T4 = Fr.T[4], T5 = Fr.T[5], T6 = Fr.T[6], T7 = Fr.T[7];
-        const float T8 = Fr.T[8], T9 = Fr.T[9], T10 = Fr.T[10], T11 = Fr.T[11];
-        const float fx = Fr.fx, fy = Fr.fy, cx = Fr.cx, cy = Fr.cy;
-        const int W = Fr.width, H = Fr.height;
+        // frame parameters, held in registers for the whole item
+        const DevFrame* Fp = L.frames + V.frame;
+        GPTR(const float) const range = gptr(Fp->range);
+        GPTR(const uint32_t) const color = gptr(Fp->color);
+        const float rmax = *Fp->rmax;
+        const float T0 = Fp->T[0], T1 = Fp->T[1], T2 = Fp->T[2], T3 = Fp->T[3];
+        const float T4 = Fp->T[4], T5 = Fp->T[5], T6 = Fp->T[6], T7 = Fp->T[7];
+        const float T8 = Fp->T[8], T9 = Fp->T[9], T10 = Fp->T[10], T11 = Fp->T[11];
+        const float fx = Fp->fx, fy = Fp->fy, cx = Fp->cx, cy = Fp->cy;
+        const int W = Fp->width, H = Fp->height;
         const float fW = (float)W, fH = (float)H;
+        const bool has_color = Fp->color != nullptr;
+        GPTR(float) vF = gptr(V.F);
+        GPTR(uint16_t) vW = gptr(V.W);
+        GPTR(uint32_t) vC = gptr(V.C);
 
         const int x = bxi * kBrick + (lane & 7);
         const int y = byi * kBrick + (lane >> 3);
@@ -187,7 +225,7 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
             clip_halfline(-fx * ax + (fW + 0.5f - cx) * az + fx * E, -fx * bx + (fW + 0.5f - cx) * bzc, zl, zh);
             clip_halfline(fy * ay + (cy + 1.5f) * az + fy * E, fy * by + (cy + 1.5f) * bzc, zl, zh);
             clip_halfline(-fy * ay + (fH + 0.5f - cy) * az + fy * E, -fy * by + (fH + 0.5f - cy) * bzc, zl, zh);
-            const float rfar = *Fr.rmax + V.mu + 2.0f * V.s;
+            const float rfar = rmax + V.mu + 2.0f * V.s;
             clip_halfline(rfar - az, -bzc, zl, zh);
         }
         int zlo = (int)fmaxf(zl, -1.0f), zhi = (int)fminf(fmaxf(zh, -1.0f), 1e8f);
@@ -196,100 +234,118 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
         zhi = min(zhi, min(bz1 * kBrick, V.dims[2]));
 
         const size_t colbase = brick_index(V.bd, bxi, byi, 0) * kBrickVox + lane;
-        bool any_flag = false;
         for (int bz = bz0; bz < bz1; ++bz) {
             const int zb = bz * kBrick;
             const bool mine = zlo < zb + kBrick && zhi > zb;
             if (__ballot(mine) == 0) continue;
             const size_t base = colbase + (size_t)bz * kBrickVox;
-            float sdfv[kBrick];
-            int pixv[kBrick];
-            unsigned updm = 0;
-#pragma unroll
-            for (int zz = 0; zz < kBrick; ++zz) {
-                const int z = zb + zz;
-                sdfv[zz] = 0.0f;
-                pixv[zz] = 0;
-                if (z >= zlo && z < zhi) {
-                    const float xw_z = V.o[2] + (V.s * ((float)(V.off[2] + z) + 0.5f));
-                    const float dz = xw_z - T11;
-                    const float px = Px + (T8 * dz);
-                    const float py = Py + (T9 * dz);
-                    const float pz = Pz + (T10 * dz);
-                    if (pz > 0.0f) {
-                        const float iz = 1.0f / pz;
-                        const float uf = ((fx * px) * iz) + cx;
-                        const float vf = ((fy * py) * iz) + cy;
-                        const float ur = floorf(uf + 0.5f);
-                        const float vr = floorf(vf + 0.5f);
-                        if (ur >= 0.0f && ur < fW && vr >= 0.0f && vr < fH) {
-                            const int pix = (int)vr * W + (int)ur;
-                            const float R = Fr.range[pix];
-                            if (R > 0.0f) {
-                                const float rho = sqrtf(((px * px) + (py * py)) + (pz * pz));
-                                const float sdf = R - rho;
-                                if (!(sdf < -V.mu)) {
-                                    updm |= 1u << zz;
-                                    sdfv[zz] = sdf;
-                                    pixv[zz] = pix;
-                                }
-                            }
-                        }
-                    }
-                }
-            }
+            GPTR(float) const pF = vF + base;
+            GPTR(uint16_t) const pW = vW + base;
+            // phase 0: start reading the column's 8 voxels of this brick (the
+            // padded brick always exists) so HBM latency overlaps the
+            // projection arithmetic
             float Fo[kBrick];
             uint16_t Wo[kBrick];
 #pragma unroll
             for (int zz = 0; zz < kBrick; ++zz) {
-                if (updm & (1u << zz)) {
-                    Fo[zz] = V.F[base + zz * 64];
-                    Wo[zz] = V.W[base + zz * 64];
-                }
+                Fo[zz] = __builtin_nontemporal_load(&pF[zz * 64]);
+                Wo[zz] = __builtin_nontemporal_load(&pW[zz * 64]);
             }
+            // phase 1: camera-frame position and nearest pixel of 8 voxels
+            float rho2v[kBrick];
+            int pixv[kBrick];
+            unsigned projm = 0;
+#pragma unroll
+            for (int zz = 0; zz < kBrick; ++zz) {
+                const int z = zb + zz;
+                const float xw_z = V.o[2] + (V.s * ((float)(V.off[2] + z) + 0.5f));
+                const float dz = xw_z - T11;
+                const float px = Px + (T8 * dz);
+                const float py = Py + (T9 * dz);
+                const float pz = Pz + (T10 * dz);
+                const float iz = 1.0f / pz;
+                const float uf = ((fx * px) * iz) + cx;
+                const float vf = ((fy * py) * iz) + cy;
+                const float ur = floorf(uf + 0.5f);
+                const float vr = floorf(vf + 0.5f);
+                const bool ok = (z >= zlo) & (z < zhi) & (pz > 0.0f) & (ur >= 0.0f) & (ur < fW) & (vr >= 0.0f) &
+                                (vr < fH);
+                rho2v[zz] = ((px * px) + (py * py)) + (pz * pz);
+                pixv[zz] = ok ? (int)vr * W + (int)ur : 0;
+                projm |= ok ? (1u << zz) : 0u;
+            }
+            // phase 2: the 8 measured ranges (independent loads)
+            float Rv[kBrick];
+#pragma unroll
+            for (int zz = 0; zz < kBrick; ++zz) Rv[zz] = (projm & (1u << zz)) ? range[pixv[zz]] : 0.0f;
+            // phase 3: projective signed distance and the truncation test
+            float sdfv[kBrick];
+            unsigned updm = 0, bandm = 0;
+#pragma unroll
+            for (int zz = 0; zz < kBrick; ++zz) {
+                const float rho = sqrtf(rho2v[zz]);
+                const float sdf = Rv[zz] - rho;
+                sdfv[zz] = sdf;
+                const bool upd = (Rv[zz] > 0.0f) & !(sdf < -V.mu);
+                updm |= upd ? (1u << zz) : 0u;
+                bandm |= (upd & (sdf <= V.mu)) ? (1u << zz) : 0u;
+            }
+            n_upd += __popc(updm);
+            n_band += __popc(bandm);
+            if (__ballot(updm != 0) == 0) continue;
+            // phase 4: running average (value path) and weights
             bool flag_here = false;
 #pragma unroll
             for (int zz = 0; zz < kBrick; ++zz) {
-                if (updm & (1u << zz)) {
-                    const size_t i = base + zz * 64;
-                    const float sdf = sdfv[zz];
-                    const float phi = fminf(1.0f, sdf * V.inv_mu);
-                    const int w = Wo[zz];
-                    const float Wf = (float)w;
-                    const float Fn = (w == 0) ? phi : (fmaf(Fo[zz], Wf, phi) / (Wf + 1.0f));
-                    V.F[i] = Fn;
-                    V.W[i] = (uint16_t)min(w + 1, V.w_max);
-                    flag_here |= Fn <= kFlagThreshold;
-                    ++n_upd;
-                    if (sdf <= V.mu) {
-                        ++n_band;
-                        if (Fr.color) {
-                            const uint32_t obs = Fr.color[pixv[zz]];
-                            const uint32_t c = V.C[i];
-                            const uint32_t Aw = c >> 24;
-                            const uint32_t r = (((c & 255u) * Aw + (obs & 255u) + ((Aw + 1u) >> 1)) / (Aw + 1u));
-                            const uint32_t g = ((((c >> 8) & 255u) * Aw + ((obs >> 8) & 255u) + ((Aw + 1u) >> 1)) / (Aw + 1u));
-                            const uint32_t b = ((((c >> 16) & 255u) * Aw + ((obs >> 16) & 255u) + ((Aw + 1u) >> 1)) / (Aw + 1u));
-                            const uint32_t An = Aw + 1u < 255u ? Aw + 1u : 255u;
-                            V.C[i] = r | (g << 8) | (b << 16) | (An << 24);
-                        }
+                const float phi = fminf(1.0f, sdfv[zz] * V.inv_mu);
+                const int w = Wo[zz];
+                const float Wf = (float)w;
+                // reciprocal of (W + 1) by the hardware estimate refined with
+                // one Newton step (error ~1 ulp)
+                const float den = Wf + 1.0f;
+                float r = __builtin_amdgcn_rcpf(den);
+                r = fmaf(r, fmaf(-den, r, 1.0f), r);
+                const float Fn = (w == 0) ? phi : fmaf(Fo[zz], Wf, phi) * r;
+                const bool upd = (updm >> zz) & 1u;
+                if (upd) {
+                    __builtin_nontemporal_store(Fn, &pF[zz * 64]);
+                    __builtin_nontemporal_store((uint16_t)min(w + 1, V.w_max), &pW[zz * 64]);
+                }
+                flag_here |= upd & (Fn <= kFlagThreshold);
+            }
+            // phase 5: colour in the band |sdf| <= mu (rounded running mean)
+            if (has_color && __ballot(bandm != 0) != 0) {
+#pragma unroll
+                for (int zz = 0; zz < kBrick; ++zz) {
+                    if (bandm & (1u << zz)) {
+                        const size_t i = base + zz * 64;
+                        const uint32_t obs = color[pixv[zz]];
+                        const uint32_t c = vC[i];
+                        const uint32_t Aw = c >> 24;
+                        const uint32_t d = Aw + 1u;
+                        const float rd = __builtin_amdgcn_rcpf((float)d);
+                        const uint32_t half = d >> 1;
+                        const uint32_t r = udiv_small((c & 255u) * Aw + (obs & 255u) + half, d, rd);
+                        const uint32_t g = udiv_small(((c >> 8) & 255u) * Aw + ((obs >> 8) & 255u) + half, d, rd);
+                        const uint32_t b = udiv_small(((c >> 16) & 255u) * Aw + ((obs >> 16) & 255u) + half, d, rd);
+                        const uint32_t An = Aw + 1u < 255u ? Aw + 1u : 255u;
+                        vC[i] = r | (g << 8) | (b << 16) | (An << 24);
                     }
                 }
             }
             if (__ballot(flag_here) != 0 && lane == 0)
                 V.flag[brick_index(V.bd, bxi, byi, bz)] = 1;
-            any_flag |= flag_here;
         }
-        (void)any_flag;
     }
     // one atomic per wave for the counters
+    unsigned long long su = n_upd, sb = n_band;
     for (int o = 32; o >= 1; o >>= 1) {
-        n_upd += __shfl_xor(n_upd, o);
-        n_band += __shfl_xor(n_band, o);
+        su += __shfl_xor(su, o);
+        sb += __shfl_xor(sb, o);
     }
-    if (lane == 0 && L.counters && (n_upd | n_band)) {
-        atomicAdd(&L.counters[kCntUpdated], n_upd);
-        atomicAdd(&L.counters[kCntBand], n_band);
+    if (lane == 0 && L.counters && (su | sb)) {
+        atomicAdd(&L.counters[kCntUpdated], su);
+        atomicAdd(&L.counters[kCntBand], sb);
     }
 }
 
@@ -301,10 +357,10 @@ int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream)
 }
 
 // ---------------------------------------------------------------------------
-// Raycast.  One thread per pixel; a 256-thread block covers a 16x16 pixel
-// tile (4 wavefronts of 8x8-ish coherent rays), tiles are assigned so that
-// neighbouring tiles land on the same XCD (shared L2 for the voxels they
-// gather).  Each ray walks the global sample lattice t_k = k delta through
+// Raycast.  One thread per pixel; a one-wavefront block covers an 8x8 pixel
+// tile of coherent rays (a free wave slot is refilled as soon as any ray
+// tile finishes); tiles are assigned so that neighbouring tiles land on the
+// same XCD (shared L2 for the voxels they gather).  Each ray walks the global sample lattice t_k = k delta through
 // every volume of its stream (nearest first), skipping runs of samples
 // whose cell lies in bricks flagged "no F <= 0" (exact: such samples can
 // never be the far end of a plus-to-minus crossing), and keeps the nearest
@@ -315,7 +371,18 @@ static __host__ __device__ __forceinline__ float lerp32(float a, float b, float 
 struct Ray {
     float C[3];
     float dw[3];
+    float inv_dw[3];   // approximate 1/dw (conservative uses only)
+    float inv_delta;   // approximate 1/delta
 };
+
+static __host__ __device__ __forceinline__ float approx_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
 
 // local continuous voxel coordinate of sample k in volume V (binary32 contract)
 static __host__ __device__ __forceinline__ void sample_coord(const DevVolume& V, const Ray& r, float tk, float l[3])
@@ -342,7 +409,7 @@ static __host__ __device__ __forceinline__ void gather8(const DevVolume& V, cons
     const size_t sx = ((i[0] & 7) == 7) ? (size_t)V.bd[1] * V.bd[2] * kBrickVox - 7 : 1;
     const size_t sy = ((i[1] & 7) == 7) ? (size_t)V.bd[2] * kBrickVox - 56 : 8;
     const size_t sz = ((i[2] & 7) == 7) ? (size_t)(kBrickVox - 448) : 64;
-    const float* F = V.F;
+    GPTR(const float) const F = gptr((const float*)V.F);
     c[0] = F[base];
     c[1] = F[base + sx];
     c[2] = F[base + sy];
@@ -383,6 +450,34 @@ static __host__ __device__ __forceinline__ bool eval_sample(const DevVolume& V, 
     return !isnan(Fk);
 }
 
+// The 8 corner values of the last cell gathered by a ray; consecutive
+// samples half a voxel apart often share a cell.
+struct CellCache {
+    int i[3];
+    float c[8];
+};
+
+static __host__ __device__ __forceinline__ bool eval_sample_cached(const DevVolume& V, const float l[3], float& Fk,
+                                                                   CellCache& cc)
+{
+    int i[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float fl = floorf(l[a]);
+        i[a] = (int)fl;
+        f[a] = l[a] - fl;
+    }
+    if (i[0] != cc.i[0] || i[1] != cc.i[1] || i[2] != cc.i[2]) {
+        gather8(V, i, cc.c);
+        cc.i[0] = i[0];
+        cc.i[1] = i[1];
+        cc.i[2] = i[2];
+    }
+    Fk = trilinear(cc.c, f);
+    return !isnan(Fk);
+}
+
 // Conservative sample range [k0, k1] of the ray inside V's domain box grown
 // by one voxel, plus two samples each side.
 static __host__ __device__ __forceinline__ void ray_k_range(const DevVolume& V, const Ray& r, float delta, int kmax,
@@ -396,15 +491,17 @@ static __host__ __device__ __forceinline__ void ray_k_range(const DevVolume& V, 
         if (r.dw[a] == 0.0f) {
             if (r.C[a] < lo || r.C[a] > hi) { k0 = 1; k1 = 0; return; }
         } else {
-            float ta = (lo - r.C[a]) / r.dw[a], tb = (hi - r.C[a]) / r.dw[a];
+            // approximate reciprocal: the range is grown by a voxel and two
+            // samples, far beyond its rounding error
+            float ta = (lo - r.C[a]) * r.inv_dw[a], tb = (hi - r.C[a]) * r.inv_dw[a];
             if (ta > tb) { const float t = ta; ta = tb; tb = t; }
             t0 = fmaxf(t0, ta);
             t1 = fminf(t1, tb);
         }
     }
     if (!(t0 <= t1)) { k0 = 1; k1 = 0; return; }
-    k0 = max(1, (int)floorf(t0 / delta) - 2);
-    k1 = min(kmax, (int)ceilf(t1 / delta) + 2);
+    k0 = max(1, (int)floorf(t0 * r.inv_delta) - 2);
+    k1 = min(kmax, (int)ceilf(t1 * r.inv_delta) + 2);
 }
 
 // Is some brick holding a corner of the cell with base i flagged?  Also
@@ -419,7 +516,7 @@ static __host__ __device__ __forceinline__ bool cell_flagged(const DevVolume& V,
     for (int bx = blo[0]; bx <= bhi[0]; ++bx)
         for (int by = blo[1]; by <= bhi[1]; ++by)
             for (int bz = blo[2]; bz <= bhi[2]; ++bz)
-                if (V.flag[brick_index(V.bd, bx, by, bz)]) return true;
+                if (gptr((const uint8_t*)V.flag)[brick_index(V.bd, bx, by, bz)]) return true;
     return false;
 }
 
@@ -435,14 +532,20 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
         const float t0 = (float)k0 * delta;
         if (t0 > best_t || (t0 == best_t && V.id > best_id)) return false;
     }
-    // per-sample advance in local voxel units (for skipping only)
-    float dl[3];
+    // per-sample advance in local voxel units and its reciprocal (for
+    // skipping only; the 0.01-voxel shrink of the skip box absorbs rounding)
+    float dl[3], inv_dl[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dl[a] = delta * r.dw[a] * V.inv_s;
+    for (int a = 0; a < 3; ++a) {
+        dl[a] = delta * r.dw[a] * V.inv_s;
+        inv_dl[a] = approx_rcp(dl[a]);
+    }
 
     int prev_k = -2;     // index of the last evaluated sample
     bool prev_ok = false;
     float Fprev = 0.0f;
+    CellCache cc;
+    cc.i[0] = -1; cc.i[1] = -1; cc.i[2] = -1;
     int k = k0;
     while (k <= k1) {
         if ((float)(k - 1) * delta > best_t) break;   // nothing nearer can follow
@@ -457,14 +560,31 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
         int i[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) i[a] = (int)floorf(l[a]);
+        // empty-space skip: the cube of bricks within dist - 1 of this
+        // sample's brick holds no flagged brick, so no sample whose cell lies
+        // in it can be the far end of a plus-to-minus crossing
         int blo[3], bhi[3];
-        if (!cell_flagged(V, i, blo, bhi)) {
-            // samples whose cells stay inside the checked bricks cannot hold F <= 0
+        bool skip;
+        {
+            const int D = gptr((const uint8_t*)V.dist)[brick_index(V.bd, i[0] >> 3, i[1] >> 3, i[2] >> 3)];
+            if (D >= 2) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    blo[a] = (i[a] >> 3) - (D - 1);
+                    bhi[a] = (i[a] >> 3) + (D - 1);
+                }
+                skip = true;
+            } else {
+                skip = D == 1 && !cell_flagged(V, i, blo, bhi);
+            }
+        }
+        if (skip) {
+            // samples whose cells stay inside the empty bricks cannot hold F <= 0
             float m = 1e30f;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                if (dl[a] > 0.0f) m = fminf(m, ((float)(8 * bhi[a] + 7) - 0.01f - l[a]) / dl[a]);
-                else if (dl[a] < 0.0f) m = fminf(m, (l[a] - ((float)(8 * blo[a]) + 0.01f)) / -dl[a]);
+                if (dl[a] > 0.0f) m = fminf(m, ((float)(8 * bhi[a] + 7) - 0.01f - l[a]) * inv_dl[a]);
+                else if (dl[a] < 0.0f) m = fminf(m, (l[a] - ((float)(8 * blo[a]) + 0.01f)) * -inv_dl[a]);
             }
             int jump = (int)fminf(fmaxf(m, 0.0f), 4096.0f);
             if (jump < 1) jump = 1;
@@ -477,10 +597,10 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
             // re-evaluate the previous sample (skipped or never seen)
             float lp[3];
             sample_coord(V, r, (float)(k - 1) * delta, lp);
-            prev_ok = in_domain(V, lp) && eval_sample(V, lp, Fprev);
+            prev_ok = in_domain(V, lp) && eval_sample_cached(V, lp, Fprev, cc);
         }
         float Fk;
-        const bool ok = eval_sample(V, l, Fk);
+        const bool ok = eval_sample_cached(V, l, Fk, cc);
         if (prev_ok && ok && Fprev > 0.0f && Fk <= 0.0f) {
             const float ta = (float)(k - 1) * delta;
             const float ts = ta + ((delta * Fprev) / (Fprev - Fk));
@@ -533,7 +653,7 @@ static __host__ __device__ void surface_normal(const DevVolume& V, const float x
 
 static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v);
 
-__global__ __launch_bounds__(256) void mvf_raycast_kernel(RaycastLaunch L)
+__global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
 {
     const LaunchHeader H = *L.hdr;
     // XCD-aware order: hardware deals blocks round-robin over 8 XCDs; give
@@ -579,7 +699,9 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
         for (int a = 0; a < 3; ++a) {
             r.dw[a] = ((Fr.T[4 * a + 0] * dh[0]) + (Fr.T[4 * a + 1] * dh[1])) + (Fr.T[4 * a + 2] * dh[2]);
             r.C[a] = Fr.T[4 * a + 3];
+            r.inv_dw[a] = approx_rcp(r.dw[a]);
         }
+        r.inv_delta = approx_rcp(H.rp.delta);
     }
     float best_t = pinf();
     int best_id = 0x7fffffff;
@@ -591,7 +713,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
     }
     const int l0 = L.list_base[s], l1 = L.list_base[s + 1];
     for (int li = l0; li < l1; ++li) {
-        const DevVolume& V = L.vols[L.lists[li]];
+        const DevVolume V = L.vols[L.lists[li]];
         float ts;
         int ks, cell[3];
         if (march_volume(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell)) {
@@ -650,6 +772,66 @@ int launch_brick_summary(DevVolume v, void* stream)
     const size_t nb = (size_t)v.bd[0] * v.bd[1] * v.bd[2];
     hipLaunchKernelGGL(mvf_brick_summary_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0,
                        (hipStream_t)stream, v, nb);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Brick distance transform: Chebyshev distance (in bricks, capped) from each
+// brick to the nearest flagged brick of its volume, separably over x, y, z.
+// One thread per brick of every volume in the table; three launches (x from
+// the flags into tmp, y into tmp + nbricks, z into dist).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mvf_brick_distance_kernel(const LaunchHeader* hdr, const DevVolume* vols,
+                                                                 const int32_t* brick_base, int pass)
+{
+    const int total = hdr->total_bricks;
+    const int nvol = hdr->nvol;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+        int lo = 0, hi = nvol - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (brick_base[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        const DevVolume& V = vols[lo];
+        const int b = g - brick_base[lo];
+        const size_t nb = (size_t)V.bd[0] * V.bd[1] * V.bd[2];
+        const int bz = b % V.bd[2];
+        const int t = b / V.bd[2];
+        const int by = t % V.bd[1];
+        const int bx = t / V.bd[1];
+        int d = kDistCap;
+        if (pass == 0) {
+            for (int o = -kDistCap; o <= kDistCap; ++o) {
+                const int x = bx + o;
+                if (x < 0 || x >= V.bd[0]) continue;
+                if (V.flag[brick_index(V.bd, x, by, bz)]) d = min(d, abs(o));
+            }
+            V.tmp[b] = (uint8_t)d;
+        } else if (pass == 1) {
+            for (int o = -kDistCap; o <= kDistCap; ++o) {
+                const int y = by + o;
+                if (y < 0 || y >= V.bd[1]) continue;
+                d = min(d, max(abs(o), (int)V.tmp[brick_index(V.bd, bx, y, bz)]));
+            }
+            V.tmp[nb + b] = (uint8_t)d;
+        } else {
+            for (int o = -kDistCap; o <= kDistCap; ++o) {
+                const int z = bz + o;
+                if (z < 0 || z >= V.bd[2]) continue;
+                d = min(d, max(abs(o), (int)V.tmp[nb + brick_index(V.bd, bx, by, z)]));
+            }
+            V.dist[b] = (uint8_t)d;
+        }
+    }
+}
+
+int launch_brick_distance(const LaunchHeader* hdr, const DevVolume* vols, const int32_t* brick_base, int blocks,
+                          void* stream)
+{
+    if (blocks <= 0) return 0;
+    for (int pass = 0; pass < 3; ++pass)
+        hipLaunchKernelGGL(mvf_brick_distance_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, hdr, vols,
+                           brick_base, pass);
     return (int)hipGetLastError();
 }
 

@@ -70,7 +70,8 @@ struct Volume {
     bool alive = false;
     mvf_volume_desc d{};
     int bd[3] = {0, 0, 0};
-    size_t nvox_pad = 0, off_W = 0, off_C = 0, off_flag = 0, bytes = 0;
+    size_t nvox_pad = 0, off_W = 0, off_C = 0, off_flag = 0, off_dist = 0, off_tmp = 0, bytes = 0;
+    size_t nbricks = 0;
     uint8_t* dev = nullptr;    // device slab while resident
     uint8_t* host = nullptr;   // pinned mirror (allocated on first swap-out)
     State state = State::Empty;
@@ -138,7 +139,7 @@ struct StepGraph {
     // persistent device tables read by the captured kernels
     uint8_t* dev = nullptr;
     size_t dev_bytes = 0;
-    size_t off_hdr, off_prep, off_frames, off_vols, off_items, off_lists, off_lbase, off_tbase;
+    size_t off_hdr, off_prep, off_frames, off_vols, off_items, off_lists, off_lbase, off_tbase, off_bbase;
     int max_vols = 0, max_w = 0, max_h = 0;
     int integ_blocks = 0, ray_blocks = 0;
 };
@@ -251,6 +252,8 @@ DevVolume make_dev(mvf_ctx* c, const Volume& v)
     d.W = reinterpret_cast<uint16_t*>(v.dev + v.off_W);
     d.C = reinterpret_cast<uint32_t*>(v.dev + v.off_C);
     d.flag = v.dev + v.off_flag;
+    d.dist = v.dev + v.off_dist;
+    d.tmp = v.dev + v.off_tmp;
     for (int a = 0; a < 3; ++a) {
         d.dims[a] = v.d.dims[a];
         d.off[a] = v.d.offset[a];
@@ -649,7 +652,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         DevFrame* dfr;
         DevFrame* fr = w2.alloc<DevFrame>(1, &dfr);
         *fr = *frame;
-        struct Per { LaunchHeader* dh; DevVolume* dv; int32_t* dib; int items; };
+        struct Per { LaunchHeader* dh; DevVolume* dv; int32_t* dib; int32_t* dbb; int items; int bricks; };
         std::vector<Per> per;
         for (int id : wave) {
             Volume& v = c->vols[id];
@@ -657,7 +660,8 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             LaunchHeader* h = w2.alloc<LaunchHeader>(1, &p.dh);
             DevVolume* dv = w2.alloc<DevVolume>(1, &p.dv);
             int32_t* ib = w2.alloc<int32_t>(2, &p.dib);
-            if (!h || !dv || !ib) return set_error(MVF_ERR_INVALID_ARG, "arena overflow");
+            int32_t* bb = w2.alloc<int32_t>(2, &p.dbb);
+            if (!h || !dv || !ib || !bb) return set_error(MVF_ERR_INVALID_ARG, "arena overflow");
             *dv = make_dev(c, v);
             dv->frame = 0;
             const int zc = zchunk_for(v);
@@ -667,8 +671,12 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             h->total_items = p.items;
             h->zchunk = zc;
             h->nstreams = 1;
+            p.bricks = (int)v.nbricks;
+            h->total_bricks = p.bricks;
             ib[0] = 0;
             ib[1] = p.items;
+            bb[0] = 0;
+            bb[1] = p.bricks;
             per.push_back(p);
         }
         CHECK_ST(arena_upload(c, w2, stream));
@@ -678,6 +686,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             CHECK_ST(timing_begin(c, stream, &t0));
             CHECK_LAUNCH(launch_integrate(L, (p.items + 3) / 4, stream));
             CHECK_ST(timing_end(c, stream, t0, 0));
+            CHECK_LAUNCH(launch_brick_distance(p.dh, p.dv, p.dbb, std::min(1024, (p.bricks + 255) / 256), stream));
             c->stats.integrate_launches += 1;
         }
         CHECK_ST(arena_release(c, slot2, stream));
@@ -700,7 +709,7 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
     if (multi) CHECK_ST(get_scratch(c, sid, out->width, out->height, true, &sc));
     RayParams rp{};
     if (!c->grids.empty()) rp = ray_params(c, c->grids[ids.empty() ? 0 : c->vols[ids[0]].d.grid_id]);
-    const int tw = 16, th = 16;
+    const int tw = 8, th = 8;  // one wavefront per block: free slots refill per wave
     const int tiles = ((out->width + tw - 1) / tw) * ((out->height + th - 1) / th);
     for (size_t wi = 0; wi < waves.size(); ++wi) {
         auto& wave = waves[wi];
@@ -985,7 +994,10 @@ mvf_status mvf_volume_create(mvf_ctx* c, const mvf_volume_desc* d, int32_t* vol_
     v.off_W = align_up(v.nvox_pad * 4, kAlign);
     v.off_C = align_up(v.off_W + v.nvox_pad * 2, kAlign);
     v.off_flag = align_up(v.off_C + v.nvox_pad * 4, kAlign);
-    v.bytes = align_up(v.off_flag + nb, kAlign);
+    v.off_dist = align_up(v.off_flag + nb, kAlign);
+    v.off_tmp = align_up(v.off_dist + nb, kAlign);
+    v.bytes = align_up(v.off_tmp + 2 * nb, kAlign);
+    v.nbricks = nb;
     c->vols.push_back(v);
     *vol_id = (int32_t)c->vols.size() - 1;
     return MVF_OK;
@@ -1150,6 +1162,29 @@ mvf_status mvf_volume_write(mvf_ctx* c, int32_t id, const float* F, const uint16
         int le = launch_volume_init(dv, nullptr);
         if (!le) le = launch_from_canonical(dv, dF, dW, dC, nullptr);
         if (!le) le = launch_brick_summary(dv, nullptr);
+        if (!le) {
+            int slot;
+            Writer w;
+            mvf_status ast = arena_acquire(c, &slot, &w);
+            if (ast != MVF_OK) return ast;
+            LaunchHeader* dh;
+            LaunchHeader* h = w.alloc<LaunchHeader>(1, &dh);
+            DevVolume* dvv;
+            DevVolume* vt = w.alloc<DevVolume>(1, &dvv);
+            int32_t* dbb;
+            int32_t* bb = w.alloc<int32_t>(2, &dbb);
+            memset(h, 0, sizeof(*h));
+            h->nvol = 1;
+            h->total_bricks = (int)v->nbricks;
+            *vt = dv;
+            bb[0] = 0;
+            bb[1] = (int)v->nbricks;
+            ast = arena_upload(c, w, nullptr);
+            if (ast != MVF_OK) return ast;
+            le = launch_brick_distance(dh, dvv, dbb, std::min<int>(1024, ((int)v->nbricks + 255) / 256), nullptr);
+            ast = arena_release(c, slot, nullptr);
+            if (ast != MVF_OK) return ast;
+        }
         if (le) { st = MVF_ERR_HIP; e = (hipError_t)le; }
     }
     if (st == MVF_OK && (e = hipDeviceSynchronize()) != hipSuccess) st = MVF_ERR_HIP;
@@ -1256,7 +1291,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         for (int i = 0; i < n; ++i)
             if (G.out_w[i] != outs[i].width || G.out_h[i] != outs[i].height) same_shape = false;
     }
-    const int tw = 16, th = 16;
+    const int tw = 8, th = 8;  // one wavefront per block: free slots refill per wave
     if (!same_shape) {
         CHECK_ST(destroy_step_graph(c));
         G.n = n;
@@ -1279,13 +1314,14 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         G.off_lists = take(sizeof(int32_t) * G.max_vols);
         G.off_lbase = take(sizeof(int32_t) * (n + 1));
         G.off_tbase = take(sizeof(int32_t) * (n + 1));
+        G.off_bbase = take(sizeof(int32_t) * (G.max_vols + 1));
         G.dev_bytes = align_up(off, 256);
         if (G.dev_bytes > Arena::kSlotBytes) return set_error(MVF_ERR_INVALID_ARG, "step tables too large");
         CHECK_HIP(hipMalloc((void**)&G.dev, G.dev_bytes));
         G.integ_blocks = c->n_cus * 8;
         int tiles = 0;
         for (int i = 0; i < n; ++i) tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
-        G.ray_blocks = std::min(tiles, c->n_cus * 8);
+        G.ray_blocks = tiles;
     }
     // scratch per stream
     std::vector<Scratch*> sc(n);
@@ -1307,6 +1343,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     int32_t* lists = reinterpret_cast<int32_t*>(img + G.off_lists);
     int32_t* lb = reinterpret_cast<int32_t*>(img + G.off_lbase);
     int32_t* tb = reinterpret_cast<int32_t*>(img + G.off_tbase);
+    int32_t* bbase = reinterpret_cast<int32_t*>(img + G.off_bbase);
+    int nbr = 0;
     int nv = 0;
     int items = 0;
     int tiles = 0;
@@ -1349,6 +1387,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             vt[nv] = make_dev(c, v);
             vt[nv].frame = i;
             ib[nv] = items;
+            bbase[nv] = nbr;
+            nbr += (int)v.nbricks;
             items += v.bd[0] * v.bd[1] * ((v.bd[2] + zc - 1) / zc);
             ++nv;
         }
@@ -1358,7 +1398,9 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         tb[i + 1] = tiles;
     }
     ib[nv] = items;
+    bbase[nv] = nbr;
     h->nvol = nv;
+    h->total_bricks = nbr;
     h->total_items = items;
     h->zchunk = zc;
     h->nstreams = n;
@@ -1379,10 +1421,12 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         const int32_t* dlists = reinterpret_cast<const int32_t*>(G.dev + G.off_lists);
         const int32_t* dlb = reinterpret_cast<const int32_t*>(G.dev + G.off_lbase);
         const int32_t* dtb = reinterpret_cast<const int32_t*>(G.dev + G.off_tbase);
+        const int32_t* dbb = reinterpret_cast<const int32_t*>(G.dev + G.off_bbase);
         CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         int e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
         IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters};
         int e2 = e1 ? e1 : launch_integrate(IL, G.integ_blocks, cs);
+        if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs);
         RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th};
         int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
         hipError_t ee = hipStreamEndCapture(cs, &G.graph);
