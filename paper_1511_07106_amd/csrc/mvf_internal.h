@@ -51,7 +51,7 @@ struct DevVolume {
     float inv_mu;        // 1 / mu
     int32_t w_max;
     int32_t frame;       // index of the stream's frame in the frame table
-    int32_t pad;
+    int32_t zt_base;     // first entry of this volume in the launch's z table
 };
 
 struct DevFrame {
@@ -76,8 +76,11 @@ struct RayParams {
     int32_t kmax;            // floor(t_far / delta)
 };
 
-// 64-bit counters written by kernels
-enum Counter { kCntUpdated = 0, kCntBand = 1, kCntNum = 8 };
+// 64-bit counters written by kernels.  kCntSlots copies, each on its own
+// 128-byte line (slot k at counters + k * kCntNum), spread the atomics of
+// many blocks over several addresses; a reader sums the slots.
+enum Counter { kCntUpdated = 0, kCntBand = 1, kCntNum = 16 };
+constexpr int kCntSlots = 64;
 
 // Launch parameters that live in device memory, so that a captured graph
 // replays with new tables (volume set, frame pointers, poses) without
@@ -91,6 +94,7 @@ struct LaunchHeader {
     int32_t total_bricks;  // bricks over all volumes of the table (distance passes)
     int32_t first_wave;    // raycast: 1 = start from no hit, 0 = merge with best_t/best_id
     RayParams rp;
+    int32_t total_z;       // entries of the integration z table (sum of 8 * bd[2])
 };
 
 // Frame preparation input for one stream.
@@ -108,12 +112,19 @@ struct PrepItem {
 // Integration work item: a brick column (8x8 voxel columns) of one volume
 // over a chunk of zchunk bricks along z.  Items of table entry v are
 // [item_base[v], item_base[v+1]).
+//
+// z table: for volume v and local z in [0, 8 * bd[2]), entry
+// vols[v].zt_base + z holds 3 floats: T[8], T[9], T[10] times
+// (x_w(z) - T[11]), the camera-frame offset of the voxel plane z (binary32,
+// the same operations as the voxel test).  Written by launch_ztable before
+// the integration kernel runs; ztab holds >= hdr->total_z entries.
 struct IntegrateLaunch {
     const LaunchHeader* hdr;
     const DevVolume* vols;
     const DevFrame* frames;
     const int32_t* item_base;  // nvol + 1 prefix sums
     unsigned long long* counters;
+    float* ztab;
 };
 
 struct RaycastLaunch {
@@ -130,6 +141,10 @@ struct RaycastLaunch {
 // as int (0 = success).
 int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream);
 int launch_volume_init(DevVolume v, void* stream);
+// The z table of a launch (must precede launch_integrate on the stream).
+int launch_ztable(const IntegrateLaunch& L, void* stream);
+// Integration kernel: blocks of 256 threads, 4 items in flight per block; a
+// grid smaller than total_items / 4 walks the items.
 int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream);
 int launch_raycast(const RaycastLaunch& L, int blocks, void* stream);
 int launch_brick_summary(DevVolume v, void* stream);

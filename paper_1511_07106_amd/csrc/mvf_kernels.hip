@@ -30,6 +30,22 @@ template <class T>
 static __host__ __device__ inline T* gptr(T* p) { return p; }
 #endif
 
+// Read-only tables written before the launch (volume, frame and z tables):
+// in the constant address space a load with a wave-uniform address becomes
+// a scalar load.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CPTR(T) const __attribute__((address_space(4))) T*
+template <class T>
+static __device__ __forceinline__ const __attribute__((address_space(4))) T* cptr(const T* p)
+{
+    return (const __attribute__((address_space(4))) T*)p;
+}
+#else
+#define CPTR(T) const T*
+template <class T>
+static __host__ __device__ inline const T* cptr(const T* p) { return p; }
+#endif
+
 static __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 static __host__ __device__ __forceinline__ size_t brick_index(const int bd[3], int bx, int by, int bz) {
@@ -40,11 +56,16 @@ static __host__ __device__ __forceinline__ size_t brick_index(const int bd[3], i
 // Frame preparation: per pixel the range R = D * lambda along the pixel ray
 // (lambda = |K^-1 [u v 1]|, the same binary32 operations the voxel test
 // uses), 0 for an invalid depth; packed RGB; the frame's maximum range.
+// The range map holds one more element, range[W * H] = 0, read by voxels
+// that project outside the image.
 // ---------------------------------------------------------------------------
 __global__ void mvf_reset_rmax_kernel(const PrepItem* items, int n)
 {
     const int i = threadIdx.x;
-    if (i < n) *items[i].rmax = 0.0f;
+    if (i < n) {
+        *items[i].rmax = 0.0f;
+        items[i].range[(size_t)items[i].width * items[i].height] = 0.0f;
+    }
 }
 
 __global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __restrict__ items)
@@ -126,14 +147,19 @@ int launch_volume_init(DevVolume v, void* stream)
 // z-slice of a brick is 64 consecutive voxels, so every load/store of the
 // wave is one contiguous 256-byte (F, C) or 128-byte (W) access.  A
 // conservative per-column z interval (frustum, near plane, farthest range
-// of the frame) limits the walk; bricks no lane needs are skipped with a
-// ballot; the exact binary32 test decides every visited voxel.
+// of the frame) skips bricks no lane needs; the exact binary32 test decides
+// every voxel of a visited brick.
+//
+// Per voxel the work is the projection (one division), a gather of the
+// measured range, a square root and the running average.  The camera-frame
+// offset of each z, the same for all lanes, comes from a table computed by
+// a small kernel before the launch (scalar loads).  The square root uses the hardware estimate and takes the correctly
+// rounded value only in lanes where the estimate lies within its error
+// bound of the truncation band: elsewhere the update test, the band test
+// and the stored value (phi = 1, or no update) do not depend on which of
+// the two roots is used.
 // ---------------------------------------------------------------------------
 
-// Conservative interval of local z (inclusive lo, exclusive hi) for which a
-// voxel of this column can pass the exact test.  Each condition is a
-// half-line a + b z >= 0 of the affine camera-frame position p(z); margins
-// (1 px, 1 mm, 2 voxels) dominate the binary32 rounding of the exact test.
 // n / d for n < 2^17 and 1 <= d <= 256 exactly: a quotient from the
 // reciprocal estimate, then one correction step each way.
 static __device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d, float rd)
@@ -145,12 +171,18 @@ static __device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d, fl
     return (uint32_t)q;
 }
 
+// Conservative interval of local z (inclusive lo, exclusive hi) for which a
+// voxel of this column can pass the exact test.  Each condition is a
+// half-line a + b z >= 0 of the affine camera-frame position p(z); margins
+// (1 px, 1 mm, 2 voxels, and 1-2 voxels on the bound itself) dominate the
+// binary32 rounding of the exact test and the 2^-22 relative error of the
+// estimated quotient; a bound beyond the volume is clamped away.
 static __device__ __forceinline__ void clip_halfline(float a, float b, float& zl, float& zh)
 {
     if (b > 0.0f) {
-        zl = fmaxf(zl, -a / b - 1.0f);
+        zl = fmaxf(zl, -a * __builtin_amdgcn_rcpf(b) - 1.0f);
     } else if (b < 0.0f) {
-        zh = fminf(zh, -a / b + 2.0f);
+        zh = fminf(zh, -a * __builtin_amdgcn_rcpf(b) + 2.0f);
     } else if (a < 0.0f) {
         zh = -1e30f;
     }
@@ -162,20 +194,23 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
     const int wib = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     const int total_waves = gridDim.x * wpb;
-    unsigned n_upd = 0, n_band = 0;
+    unsigned n_upd = 0, n_band = 0;  // wave totals
     const int total_items = L.hdr->total_items;
     const int nvol = L.hdr->nvol;
     const int zchunk = L.hdr->zchunk;
+    CPTR(float) const ztab = cptr(L.ztab);
 
     for (int item = wave_uniform(blockIdx.x * wpb + wib); item < total_items; item += total_waves) {
         // volume owning this item
+        CPTR(int32_t) const item_base = cptr(L.item_base);
         int lo = 0, hi = nvol - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (L.item_base[mid] <= item) lo = mid; else hi = mid - 1;
+            if (item_base[mid] <= item) lo = mid; else hi = mid - 1;
         }
-        const DevVolume V = L.vols[lo];
-        const int local = item - L.item_base[lo];
+        lo = wave_uniform(lo);
+        const DevVolume V = cptr(L.vols)[lo];
+        const int local = item - item_base[lo];
         const int ncols = V.bd[0] * V.bd[1];
         const int zc = local / ncols;
         const int col = local - zc * ncols;
@@ -185,7 +220,7 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
         const int bz1 = min(bz0 + zchunk, V.bd[2]);
 
         // frame parameters, held in registers for the whole item
-        const DevFrame* Fp = L.frames + V.frame;
+        CPTR(DevFrame) const Fp = cptr(L.frames) + V.frame;
         GPTR(const float) const range = gptr(Fp->range);
         GPTR(const uint32_t) const color = gptr(Fp->color);
         const float rmax = *Fp->rmax;
@@ -195,6 +230,8 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
         const float fx = Fp->fx, fy = Fp->fy, cx = Fp->cx, cy = Fp->cy;
         const int W = Fp->width, H = Fp->height;
         const float fW = (float)W, fH = (float)H;
+        const float fW1 = (float)(W - 1), fH1 = (float)(H - 1);
+        const uint32_t npix = (uint32_t)W * (uint32_t)H;  // index of the zero range
         const bool has_color = Fp->color != nullptr;
         GPTR(float) vF = gptr(V.F);
         GPTR(uint16_t) vW = gptr(V.W);
@@ -232,6 +269,10 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
         if (!col_ok) { zlo = 0; zhi = 0; }
         zlo = max(zlo, bz0 * kBrick);
         zhi = min(zhi, min(bz1 * kBrick, V.dims[2]));
+        // threshold of the square-root filter: the estimate is within 2 ulp
+        // of the correctly rounded root (within 2^-48 below 2^-96); 8 ulp of
+        // margin plus the absolute term cover both roundings of sdf
+        const float mu_f = V.mu + 0x1p-46f;
 
         const size_t colbase = brick_index(V.bd, bxi, byi, 0) * kBrickVox + lane;
         for (int bz = bz0; bz < bz1; ++bz) {
@@ -241,6 +282,10 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
             const size_t base = colbase + (size_t)bz * kBrickVox;
             GPTR(float) const pF = vF + base;
             GPTR(uint16_t) const pW = vW + base;
+            // the brick's 8 z-table entries, one scalar block
+            struct ZRow { float v[3 * kBrick]; };
+            const ZRow zr = *(CPTR(ZRow))(ztab + 3 * (V.zt_base + zb));
+            const int nz_here = min(kBrick, V.dims[2] - zb);
             // phase 0: start reading the column's 8 voxels of this brick (the
             // padded brick always exists) so HBM latency overlaps the
             // projection arithmetic
@@ -251,49 +296,60 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
                 Fo[zz] = __builtin_nontemporal_load(&pF[zz * 64]);
                 Wo[zz] = __builtin_nontemporal_load(&pW[zz * 64]);
             }
-            // phase 1: camera-frame position and nearest pixel of 8 voxels
-            float rho2v[kBrick];
-            int pixv[kBrick];
-            unsigned projm = 0;
+            // phase 1: camera-frame position and nearest pixel of 8 voxels.
+            // The pixel coordinates are clamped into the image (a NaN goes
+            // to 0); the voxel projects into the image iff clamping left them
+            // unchanged.  A voxel that does not reads the zero range behind
+            // the image, so R > 0 below carries the projection test.
+            float rho2v[kBrick], Rv[kBrick];
 #pragma unroll
             for (int zz = 0; zz < kBrick; ++zz) {
-                const int z = zb + zz;
-                const float xw_z = V.o[2] + (V.s * ((float)(V.off[2] + z) + 0.5f));
-                const float dz = xw_z - T11;
-                const float px = Px + (T8 * dz);
-                const float py = Py + (T9 * dz);
-                const float pz = Pz + (T10 * dz);
+                const float px = Px + zr.v[3 * zz];
+                const float py = Py + zr.v[3 * zz + 1];
+                const float pz = Pz + zr.v[3 * zz + 2];
                 const float iz = 1.0f / pz;
                 const float uf = ((fx * px) * iz) + cx;
                 const float vf = ((fy * py) * iz) + cy;
                 const float ur = floorf(uf + 0.5f);
                 const float vr = floorf(vf + 0.5f);
-                const bool ok = (z >= zlo) & (z < zhi) & (pz > 0.0f) & (ur >= 0.0f) & (ur < fW) & (vr >= 0.0f) &
-                                (vr < fH);
+                const float uc = __builtin_amdgcn_fmed3f(ur, 0.0f, fW1);
+                const float vc = __builtin_amdgcn_fmed3f(vr, 0.0f, fH1);
+                const bool ok = col_ok & (zz < nz_here) & (pz > 0.0f) & (uc == ur) & (vc == vr);
                 rho2v[zz] = ((px * px) + (py * py)) + (pz * pz);
-                pixv[zz] = ok ? (int)vr * W + (int)ur : 0;
-                projm |= ok ? (1u << zz) : 0u;
+                const uint32_t pix = ok ? __umul24((uint32_t)vc, (uint32_t)W) + (uint32_t)uc : npix;
+                Rv[zz] = *(GPTR(const float))((GPTR(const uint8_t))range + (pix << 2));
             }
-            // phase 2: the 8 measured ranges (independent loads)
-            float Rv[kBrick];
-#pragma unroll
-            for (int zz = 0; zz < kBrick; ++zz) Rv[zz] = (projm & (1u << zz)) ? range[pixv[zz]] : 0.0f;
-            // phase 3: projective signed distance and the truncation test
+            // phase 2: projective signed distance and the truncation test
             float sdfv[kBrick];
-            unsigned updm = 0, bandm = 0;
+            bool nearv[kBrick];
+            bool any_near = false;
 #pragma unroll
             for (int zz = 0; zz < kBrick; ++zz) {
-                const float rho = sqrtf(rho2v[zz]);
+                const float rho = __builtin_amdgcn_sqrtf(rho2v[zz]);
                 const float sdf = Rv[zz] - rho;
                 sdfv[zz] = sdf;
-                const bool upd = (Rv[zz] > 0.0f) & !(sdf < -V.mu);
-                updm |= upd ? (1u << zz) : 0u;
-                bandm |= (upd & (sdf <= V.mu)) ? (1u << zz) : 0u;
+                nearv[zz] = !(fabsf(sdf) > fmaf(rho, 0x1p-20f, mu_f));
+                any_near |= nearv[zz];
             }
-            n_upd += __popc(updm);
-            n_band += __popc(bandm);
-            if (__ballot(updm != 0) == 0) continue;
-            // phase 4: running average (value path) and weights
+            if (__ballot(any_near) != 0) {
+#pragma unroll
+                for (int zz = 0; zz < kBrick; ++zz)
+                    if (nearv[zz]) sdfv[zz] = Rv[zz] - sqrtf(rho2v[zz]);
+            }
+            bool updv[kBrick], bandv[kBrick];
+            bool any_upd = false, any_band = false;
+#pragma unroll
+            for (int zz = 0; zz < kBrick; ++zz) {
+                const float sdf = sdfv[zz];
+                updv[zz] = (Rv[zz] > 0.0f) & !(sdf < -V.mu);
+                bandv[zz] = updv[zz] & (sdf <= V.mu);
+                n_upd += (unsigned)__popcll(__ballot(updv[zz]));
+                n_band += (unsigned)__popcll(__ballot(bandv[zz]));
+                any_upd |= updv[zz];
+                any_band |= bandv[zz];
+            }
+            if (__ballot(any_upd) == 0) continue;
+            // phase 3: running average (value path) and weights
             bool flag_here = false;
 #pragma unroll
             for (int zz = 0; zz < kBrick; ++zz) {
@@ -306,20 +362,28 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
                 float r = __builtin_amdgcn_rcpf(den);
                 r = fmaf(r, fmaf(-den, r, 1.0f), r);
                 const float Fn = (w == 0) ? phi : fmaf(Fo[zz], Wf, phi) * r;
-                const bool upd = (updm >> zz) & 1u;
-                if (upd) {
+                if (updv[zz]) {
                     __builtin_nontemporal_store(Fn, &pF[zz * 64]);
                     __builtin_nontemporal_store((uint16_t)min(w + 1, V.w_max), &pW[zz * 64]);
                 }
-                flag_here |= upd & (Fn <= kFlagThreshold);
+                flag_here |= updv[zz] & (Fn <= kFlagThreshold);
             }
-            // phase 5: colour in the band |sdf| <= mu (rounded running mean)
-            if (has_color && __ballot(bandm != 0) != 0) {
+            // phase 4: colour in the band |sdf| <= mu (rounded running mean)
+            if (has_color && __ballot(any_band) != 0) {
 #pragma unroll
                 for (int zz = 0; zz < kBrick; ++zz) {
-                    if (bandm & (1u << zz)) {
+                    if (bandv[zz]) {
+                        // the voxel's pixel again (band voxels are few)
+                        const float xw_z = V.o[2] + (V.s * ((float)(V.off[2] + zb + zz) + 0.5f));
+                        const float dz = xw_z - T11;
+                        const float px = Px + (T8 * dz);
+                        const float py = Py + (T9 * dz);
+                        const float pz = Pz + (T10 * dz);
+                        const float iz = 1.0f / pz;
+                        const float ur = floorf((((fx * px) * iz) + cx) + 0.5f);
+                        const float vr = floorf((((fy * py) * iz) + cy) + 0.5f);
                         const size_t i = base + zz * 64;
-                        const uint32_t obs = color[pixv[zz]];
+                        const uint32_t obs = color[__umul24((uint32_t)vr, (uint32_t)W) + (uint32_t)ur];
                         const uint32_t c = vC[i];
                         const uint32_t Aw = c >> 24;
                         const uint32_t d = Aw + 1u;
@@ -337,16 +401,54 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
                 V.flag[brick_index(V.bd, bxi, byi, bz)] = 1;
         }
     }
-    // one atomic per wave for the counters
-    unsigned long long su = n_upd, sb = n_band;
-    for (int o = 32; o >= 1; o >>= 1) {
-        su += __shfl_xor(su, o);
-        sb += __shfl_xor(sb, o);
+    // counters: the block's total (the wave totals are the same in every
+    // lane), one atomic per block into one of kCntSlots copies
+    __shared__ unsigned cnt_upd[4], cnt_band[4];
+    if (lane == 0) {
+        cnt_upd[wib & 3] = n_upd;
+        cnt_band[wib & 3] = n_band;
     }
-    if (lane == 0 && L.counters && (su | sb)) {
-        atomicAdd(&L.counters[kCntUpdated], su);
-        atomicAdd(&L.counters[kCntBand], sb);
+    __syncthreads();
+    if (threadIdx.x == 0 && L.counters) {
+        unsigned long long su = 0, sb = 0;
+        for (int w = 0; w < wpb && w < 4; ++w) {
+            su += cnt_upd[w];
+            sb += cnt_band[w];
+        }
+        unsigned long long* slot = L.counters + (blockIdx.x % kCntSlots) * kCntNum;
+        if (su) atomicAdd(&slot[kCntUpdated], su);
+        if (sb) atomicAdd(&slot[kCntBand], sb);
     }
+}
+
+// z table of every volume of the launch (see IntegrateLaunch).
+__global__ __launch_bounds__(256) void mvf_ztable_kernel(const LaunchHeader* hdr, const DevVolume* vols,
+                                                         const DevFrame* frames, float* ztab)
+{
+    const int total = hdr->total_z;
+    const int nvol = hdr->nvol;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        int lo = 0, hi = nvol - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (vols[mid].zt_base <= i) lo = mid; else hi = mid - 1;
+        }
+        const DevVolume& V = vols[lo];
+        const DevFrame& Fr = frames[V.frame];
+        const int z = i - V.zt_base;
+        const float xw_z = V.o[2] + (V.s * ((float)(V.off[2] + z) + 0.5f));
+        const float dz = xw_z - Fr.T[11];
+        ztab[3 * i] = Fr.T[8] * dz;
+        ztab[3 * i + 1] = Fr.T[9] * dz;
+        ztab[3 * i + 2] = Fr.T[10] * dz;
+    }
+}
+
+int launch_ztable(const IntegrateLaunch& L, void* stream)
+{
+    hipLaunchKernelGGL(mvf_ztable_kernel, dim3(16), dim3(256), 0, (hipStream_t)stream, L.hdr, L.vols, L.frames,
+                       L.ztab);
+    return (int)hipGetLastError();
 }
 
 int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream)

@@ -94,6 +94,8 @@ struct Scratch {
     float* rmax = nullptr;
     float* best_t = nullptr;
     int32_t* best_id = nullptr;
+    float* ztab = nullptr;  // integration z table (3 floats per entry)
+    int ztab_cap = 0;
 };
 
 // Ring of pinned host + device slots for per-launch tables.  A slot is
@@ -142,6 +144,8 @@ struct StepGraph {
     size_t off_hdr, off_prep, off_frames, off_vols, off_items, off_lists, off_lbase, off_tbase, off_bbase;
     int max_vols = 0, max_w = 0, max_h = 0;
     int integ_blocks = 0, ray_blocks = 0;
+    float* ztab = nullptr;  // integration z table read by the captured launch
+    int ztab_cap = 0;
 };
 
 }  // namespace
@@ -522,7 +526,7 @@ mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratc
         if (s.best_id) { CHECK_HIP(hipFree(s.best_id)); s.best_id = nullptr; }
         if (!s.rmax) CHECK_HIP(hipMalloc((void**)&s.rmax, 256));
         const size_t n = (size_t)std::max(w * h, s.w * s.h);
-        CHECK_HIP(hipMalloc((void**)&s.range, n * sizeof(float)));
+        CHECK_HIP(hipMalloc((void**)&s.range, (n + 64) * sizeof(float)));  // + the zero range behind the image
         CHECK_HIP(hipMalloc((void**)&s.color, n * sizeof(uint32_t)));
         s.w = w;
         s.h = h;
@@ -644,6 +648,19 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
     CHECK_ST(arena_upload(c, w, stream));
     CHECK_LAUNCH(launch_frame_prep(dprep, 1, f->width, f->height, stream));
     CHECK_ST(arena_release(c, slot, stream));
+    int zmax = 0;
+    for (int id : ids) zmax = std::max(zmax, kBrick * c->vols[id].bd[2]);
+    if (zmax > sc->ztab_cap) {
+        // stream-ordered: earlier launches reading the old table have been
+        // queued on this stream, so free only after they finish
+        if (sc->ztab) {
+            CHECK_HIP(hipStreamSynchronize(stream));
+            CHECK_HIP(hipFree(sc->ztab));
+            sc->ztab = nullptr;
+        }
+        CHECK_HIP(hipMalloc((void**)&sc->ztab, (size_t)zmax * 3 * sizeof(float)));
+        sc->ztab_cap = zmax;
+    }
     for (auto& wave : waves) {
         CHECK_ST(ensure_resident(c, wave, stream));
         int slot2;
@@ -664,6 +681,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             if (!h || !dv || !ib || !bb) return set_error(MVF_ERR_INVALID_ARG, "arena overflow");
             *dv = make_dev(c, v);
             dv->frame = 0;
+            dv->zt_base = 0;
             const int zc = zchunk_for(v);
             p.items = v.bd[0] * v.bd[1] * ((v.bd[2] + zc - 1) / zc);
             memset(h, 0, sizeof(*h));
@@ -673,6 +691,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             h->nstreams = 1;
             p.bricks = (int)v.nbricks;
             h->total_bricks = p.bricks;
+            h->total_z = kBrick * v.bd[2];
             ib[0] = 0;
             ib[1] = p.items;
             bb[0] = 0;
@@ -681,7 +700,8 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         }
         CHECK_ST(arena_upload(c, w2, stream));
         for (auto& p : per) {
-            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters};
+            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab};
+            CHECK_LAUNCH(launch_ztable(L, stream));
             hipEvent_t t0;
             CHECK_ST(timing_begin(c, stream, &t0));
             CHECK_LAUNCH(launch_integrate(L, (p.items + 3) / 4, stream));
@@ -785,6 +805,8 @@ mvf_status destroy_step_graph(mvf_ctx* c)
     if (g.exec) { CHECK_HIP(hipGraphExecDestroy(g.exec)); g.exec = nullptr; }
     if (g.graph) { CHECK_HIP(hipGraphDestroy(g.graph)); g.graph = nullptr; }
     if (g.dev) { CHECK_HIP(hipFree(g.dev)); g.dev = nullptr; }
+    if (g.ztab) { CHECK_HIP(hipFree(g.ztab)); g.ztab = nullptr; }
+    g.ztab_cap = 0;
     g.valid = false;
     return MVF_OK;
 }
@@ -846,8 +868,8 @@ mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg)
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * kCntNum)) != hipSuccess ||
-        (e = hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum)) != hipSuccess ||
+        (e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
+        (e = hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
         (e = hipHostMalloc((void**)&c->arena.host, Arena::kSlots * Arena::kSlotBytes, hipHostMallocDefault)) != hipSuccess ||
         (e = hipMalloc((void**)&c->arena.dev, Arena::kSlots * Arena::kSlotBytes)) != hipSuccess ||
         (e = hipEventCreate(&c->tail)) != hipSuccess)
@@ -881,6 +903,7 @@ mvf_status mvf_destroy(mvf_ctx* c)
         if (s.range) (void)hipFree(s.range);
         if (s.color) (void)hipFree(s.color);
         if (s.rmax) (void)hipFree(s.rmax);
+        if (s.ztab) (void)hipFree(s.ztab);
         if (s.best_t) (void)hipFree(s.best_t);
         if (s.best_id) (void)hipFree(s.best_id);
     }
@@ -929,11 +952,15 @@ mvf_status mvf_get_stats(mvf_ctx* c, mvf_stats* out)
     CHECK_HIP(hipSetDevice(c->device));
     CHECK_ST(mvf_synchronize(c));
     CHECK_ST(drain_timing(c));
-    unsigned long long cnt[kCntNum];
-    CHECK_HIP(hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> cnt((size_t)kCntNum * kCntSlots);
+    CHECK_HIP(hipMemcpy(cnt.data(), c->counters, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     *out = c->stats;
-    out->voxels_updated = cnt[kCntUpdated];
-    out->voxels_band = cnt[kCntBand];
+    out->voxels_updated = 0;
+    out->voxels_band = 0;
+    for (int k = 0; k < kCntSlots; ++k) {
+        out->voxels_updated += cnt[(size_t)k * kCntNum + kCntUpdated];
+        out->voxels_band += cnt[(size_t)k * kCntNum + kCntBand];
+    }
     out->resident_bytes = c->resident_bytes;
     int n = 0;
     for (auto& v : c->vols)
@@ -948,7 +975,7 @@ mvf_status mvf_reset_stats(mvf_ctx* c)
     CHECK_ST(mvf_synchronize(c));
     CHECK_ST(drain_timing(c));
     c->stats = mvf_stats{};
-    CHECK_HIP(hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum));
+    CHECK_HIP(hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum * kCntSlots));
     CHECK_HIP(hipDeviceSynchronize());
     return MVF_OK;
 }
@@ -1286,7 +1313,10 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         max_w = std::max(max_w, frames[i].frame.width);
         max_h = std::max(max_h, frames[i].frame.height);
     }
-    bool same_shape = G.valid && G.n == n && (int)all.size() <= G.max_vols && max_w <= G.max_w && max_h <= G.max_h;
+    int ztotal = 0;
+    for (int id : all) ztotal += kBrick * c->vols[id].bd[2];
+    bool same_shape = G.valid && G.n == n && (int)all.size() <= G.max_vols && max_w <= G.max_w && max_h <= G.max_h &&
+                      ztotal <= G.ztab_cap;
     if (same_shape) {
         for (int i = 0; i < n; ++i)
             if (G.out_w[i] != outs[i].width || G.out_h[i] != outs[i].height) same_shape = false;
@@ -1318,6 +1348,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         G.dev_bytes = align_up(off, 256);
         if (G.dev_bytes > Arena::kSlotBytes) return set_error(MVF_ERR_INVALID_ARG, "step tables too large");
         CHECK_HIP(hipMalloc((void**)&G.dev, G.dev_bytes));
+        G.ztab_cap = std::max(ztotal * 2, 1024);
+        CHECK_HIP(hipMalloc((void**)&G.ztab, (size_t)G.ztab_cap * 3 * sizeof(float)));
         G.integ_blocks = c->n_cus * 8;
         int tiles = 0;
         for (int i = 0; i < n; ++i) tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
@@ -1347,6 +1379,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     int nbr = 0;
     int nv = 0;
     int items = 0;
+    int zt = 0;
     int tiles = 0;
     const int zc = 4;
     lb[0] = 0;
@@ -1386,6 +1419,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             Volume& v = c->vols[ids[j]];
             vt[nv] = make_dev(c, v);
             vt[nv].frame = i;
+            vt[nv].zt_base = zt;
+            zt += kBrick * v.bd[2];
             ib[nv] = items;
             bbase[nv] = nbr;
             nbr += (int)v.nbricks;
@@ -1402,6 +1437,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     h->nvol = nv;
     h->total_bricks = nbr;
     h->total_items = items;
+    h->total_z = zt;
     h->zchunk = zc;
     h->nstreams = n;
     h->total_tiles = tiles;
@@ -1424,8 +1460,9 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         const int32_t* dbb = reinterpret_cast<const int32_t*>(G.dev + G.off_bbase);
         CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         int e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
-        IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters};
-        int e2 = e1 ? e1 : launch_integrate(IL, G.integ_blocks, cs);
+        IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab};
+        int e2 = e1 ? e1 : launch_ztable(IL, cs);
+        if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
         if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs);
         RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th};
         int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);

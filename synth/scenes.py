@@ -332,7 +332,11 @@ def render(scene: Scene, K: Intrinsics, T_wc: np.ndarray,
         rays_c = pixel_rays(K)
     R = T_wc[:, :3]
     C = T_wc[:, 3]
-    d = rays_c.reshape(-1, 3) @ R.T  # world direction, camera z component 1
+    # world direction (camera z component 1).  Products are written out
+    # element-wise: a BLAS call may round differently depending on how it
+    # splits the work over threads, which would make frames irreproducible.
+    rc = rays_c.reshape(-1, 3)
+    d = np.stack([rc[:, 0] * R[a, 0] + rc[:, 1] * R[a, 1] + rc[:, 2] * R[a, 2] for a in range(3)], axis=1)
     n = d.shape[0]
     best = np.full(n, np.inf)
     obj = np.full(n, -1, np.int32)
@@ -348,11 +352,11 @@ def render(scene: Scene, K: Intrinsics, T_wc: np.ndarray,
             best = np.where(m, t, best)
             obj = np.where(m, wall, obj)
     base = 6
-    a2 = np.einsum("ij,ij->i", d, d)
+    a2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
     for si, s in enumerate(scene.spheres):
         oc = C - s.center
-        b = d @ oc
-        c = oc @ oc - s.radius ** 2
+        b = d[:, 0] * oc[0] + d[:, 1] * oc[1] + d[:, 2] * oc[2]
+        c = (oc[0] * oc[0] + oc[1] * oc[1] + oc[2] * oc[2]) - s.radius ** 2
         disc = b * b - a2 * c
         ok = disc >= 0
         sq = np.sqrt(np.where(ok, disc, 0.0))
