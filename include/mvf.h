@@ -81,7 +81,8 @@ typedef struct {
 typedef struct {
     int32_t grid_id;
     int32_t offset[3];  /* h_t: global voxel index of local voxel (0,0,0) */
-    int32_t dims[3];    /* h_r per axis, each in [2, 2048] */
+    int32_t dims[3];    /* h_r per axis, each in [2, 2048]; at most 2^30 voxels
+                           after padding each axis to a multiple of 8 */
     int32_t stream_id;  /* scene this volume belongs to, >= 0 */
 } mvf_volume_desc;
 

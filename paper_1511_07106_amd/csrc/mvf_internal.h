@@ -23,6 +23,17 @@
 //                  brick within dist - 1 of this one is unflagged.  Derived
 //                  from the flags after each integration.
 //   tmp   2 x uint8 per brick: passes of the distance transform.
+//   fmask uint64   per brick: bit z2 * 16 + y2 * 4 + x2 set if some voxel of
+//                  the 2x2x2 sub-block (x2, y2, z2) of the brick may hold
+//                  F <= 2^-100 (same monotone rule as flag, which equals
+//                  fmask != 0).
+//   cmask uint64   per brick: the same bits for cells: bit (x2, y2, z2) set
+//                  if a voxel of [2 x2, 2 x2 + 2] x [2 y2, 2 y2 + 2] x
+//                  [2 z2, 2 z2 + 2] (brick-local, reaching into the +x, +y,
+//                  +z neighbour bricks) may hold F <= 2^-100, i.e. some cell
+//                  whose base voxel lies in that sub-block may have a corner
+//                  F <= 2^-100.  fmask dilated by one sub-block; derived
+//                  after each integration with the distance passes.
 #pragma once
 #include <stdint.h>
 
@@ -40,6 +51,8 @@ struct DevVolume {
     uint8_t* flag;
     uint8_t* dist;
     uint8_t* tmp;            // 2 * nbricks bytes of scratch for the distance passes
+    uint64_t* fmask;         // per brick: sub-block flags
+    uint64_t* cmask;         // per brick: cell sub-block flags
     int32_t dims[3];
     int32_t off[3];
     int32_t bd[3];
@@ -57,7 +70,8 @@ struct DevVolume {
 struct DevFrame {
     const float* range;      // H*W: depth * ray-length factor, 0 = invalid
     const uint32_t* color;   // H*W packed RGB (may be null)
-    float* rmax;             // device scalar: max range of the frame (+mu, for clipping)
+    float* rmax;             // [0]: max range of the frame (for clipping); [1 + b]: per prep block
+    int32_t rmax_parts;      // prep blocks of this frame (ceil(width / 32) * ceil(height / 8))
     int32_t width, height;
     float fx, fy, cx, cy;
     float T[12];
@@ -106,7 +120,7 @@ struct PrepItem {
     float fx, fy, cx, cy;
     float* range;
     uint32_t* color;
-    float* rmax;
+    float* rmax;             // [0] frame's maximum range, [1 + b] maximum of prep block b
 };
 
 // Integration work item: a brick column (8x8 voxel columns) of one volume

@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "mvf_internal.h"
+#include "mvf_masks.h"
 
 namespace mvf {
 
@@ -57,17 +58,9 @@ static __host__ __device__ __forceinline__ size_t brick_index(const int bd[3], i
 // (lambda = |K^-1 [u v 1]|, the same binary32 operations the voxel test
 // uses), 0 for an invalid depth; packed RGB; the frame's maximum range.
 // The range map holds one more element, range[W * H] = 0, read by voxels
-// that project outside the image.
+// that project outside the image.  The maximum range is reduced from
+// per-block maxima by the z-table kernel, which runs before integration.
 // ---------------------------------------------------------------------------
-__global__ void mvf_reset_rmax_kernel(const PrepItem* items, int n)
-{
-    const int i = threadIdx.x;
-    if (i < n) {
-        *items[i].rmax = 0.0f;
-        items[i].range[(size_t)items[i].width * items[i].height] = 0.0f;
-    }
-}
-
 __global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __restrict__ items)
 {
     const PrepItem& it = items[blockIdx.z];
@@ -90,15 +83,19 @@ __global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __r
         }
         it.color[(size_t)v * it.width + u] = c;
     }
-    // block max (non-negative floats order like their bit patterns)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        it.range[(size_t)it.width * it.height] = 0.0f;
+    // block maximum into this block's slot; the z-table kernel reduces the
+    // slots (no atomics on one address)
     float m = R;
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
     __shared__ float wmax[4];
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    const int gx = (it.width + 31) / 32, gy = (it.height + 7) / 8;
+    if (threadIdx.x == 0 && (int)blockIdx.x < gx && (int)blockIdx.y < gy) {
         m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-        if (m > 0.0f) atomicMax((unsigned int*)it.rmax, __float_as_uint(m));
+        it.rmax[1 + blockIdx.y * gx + blockIdx.x] = m;
     }
 }
 
@@ -106,7 +103,6 @@ int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* 
 {
     if (n <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(mvf_reset_rmax_kernel, dim3(1), dim3(64 * ((n + 63) / 64)), 0, s, items, n);
     dim3 grid((max_w + 31) / 32, (max_h + 7) / 8, n);
     hipLaunchKernelGGL(mvf_frame_prep_kernel, grid, dim3(256), 0, s, items);
     return (int)hipGetLastError();
@@ -125,6 +121,8 @@ __global__ __launch_bounds__(256) void mvf_volume_init_kernel(DevVolume v, size_
         if (i < nbricks) {
             v.flag[i] = 0;
             v.dist[i] = kDistCap;
+            v.fmask[i] = 0;
+            v.cmask[i] = 0;
         }
     }
 }
@@ -351,6 +349,7 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
             if (__ballot(any_upd) == 0) continue;
             // phase 3: running average (value path) and weights
             bool flag_here = false;
+            bool fz[kBrick / 2] = {false, false, false, false};
 #pragma unroll
             for (int zz = 0; zz < kBrick; ++zz) {
                 const float phi = fminf(1.0f, sdfv[zz] * V.inv_mu);
@@ -362,11 +361,15 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
                 float r = __builtin_amdgcn_rcpf(den);
                 r = fmaf(r, fmaf(-den, r, 1.0f), r);
                 const float Fn = (w == 0) ? phi : fmaf(Fo[zz], Wf, phi) * r;
+                // plain (cache-allocating) stores: the raycast that follows
+                // reads the updated surface band
                 if (updv[zz]) {
-                    __builtin_nontemporal_store(Fn, &pF[zz * 64]);
-                    __builtin_nontemporal_store((uint16_t)min(w + 1, V.w_max), &pW[zz * 64]);
+                    pF[zz * 64] = Fn;
+                    pW[zz * 64] = (uint16_t)min(w + 1, V.w_max);
                 }
-                flag_here |= updv[zz] & (Fn <= kFlagThreshold);
+                const bool fl = updv[zz] & (Fn <= kFlagThreshold);
+                flag_here |= fl;
+                fz[zz >> 1] |= fl;
             }
             // phase 4: colour in the band |sdf| <= mu (rounded running mean)
             if (has_color && __ballot(any_band) != 0) {
@@ -397,8 +400,16 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
                     }
                 }
             }
-            if (__ballot(flag_here) != 0 && lane == 0)
-                V.flag[brick_index(V.bd, bxi, byi, bz)] = 1;
+            if (__ballot(flag_here) != 0) {
+                uint64_t fm = 0;
+#pragma unroll
+                for (int zp = 0; zp < kBrick / 2; ++zp) fm |= (uint64_t)subblock_bits(__ballot(fz[zp])) << (16 * zp);
+                if (lane == 0) {
+                    const size_t b = brick_index(V.bd, bxi, byi, bz);
+                    V.flag[b] = 1;
+                    atomicOr((unsigned long long*)&V.fmask[b], (unsigned long long)fm);
+                }
+            }
         }
     }
     // counters: the block's total (the wave totals are the same in every
@@ -421,12 +432,26 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
     }
 }
 
-// z table of every volume of the launch (see IntegrateLaunch).
+// z table of every volume of the launch (see IntegrateLaunch), and each
+// frame's maximum range from the frame-preparation block maxima.
 __global__ __launch_bounds__(256) void mvf_ztable_kernel(const LaunchHeader* hdr, const DevVolume* vols,
                                                          const DevFrame* frames, float* ztab)
 {
     const int total = hdr->total_z;
     const int nvol = hdr->nvol;
+    for (int f = blockIdx.x; f < hdr->nstreams; f += gridDim.x) {
+        float* rm = frames[f].rmax;
+        if (!rm) continue;
+        const int np = frames[f].rmax_parts;
+        float m = 0.0f;
+        for (int j = threadIdx.x; j < np; j += blockDim.x) m = fmaxf(m, rm[1 + j]);
+        for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        __shared__ float wmax[4];
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) rm[0] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        __syncthreads();
+    }
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         int lo = 0, hi = nvol - 1;
         while (lo < hi) {
@@ -503,23 +528,51 @@ static __host__ __device__ __forceinline__ bool in_domain(const DevVolume& V, co
            l[1] < (float)(V.dims[1] - 1) && l[2] >= 0.0f && l[2] < (float)(V.dims[2] - 1);
 }
 
+// 32-bit brick-linear addressing: a volume holds at most 2^30 padded
+// voxels, so element and byte offsets of its planes fit in 32 bits.
+static __host__ __device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul24(a, b);
+#else
+    return a * b;
+#endif
+}
+
+static __host__ __device__ __forceinline__ uint32_t brick_index32(const DevVolume& V, int bx, int by, int bz)
+{
+    return mul24(mul24((uint32_t)bx, (uint32_t)V.bd[1]) + (uint32_t)by, (uint32_t)V.bd[2]) + (uint32_t)bz;
+}
+
+static __host__ __device__ __forceinline__ uint32_t voxel_index32(const DevVolume& V, const int i[3])
+{
+    return brick_index32(V, i[0] >> 3, i[1] >> 3, i[2] >> 3) * (uint32_t)kBrickVox +
+           (uint32_t)(((i[2] & 7) << 6) | ((i[1] & 7) << 3) | (i[0] & 7));
+}
+
+// element e of a plane, addressed as base + 32-bit byte offset
+template <class T>
+static __host__ __device__ __forceinline__ T ld_elem(GPTR(const T) base, uint32_t e)
+{
+    return *(GPTR(const T))((GPTR(const uint8_t))base + e * (uint32_t)sizeof(T));
+}
+
 // 8 corner values of the cell with base i (brick-linear addressing)
 static __host__ __device__ __forceinline__ void gather8(const DevVolume& V, const int i[3], float c[8])
 {
-    const size_t base = brick_index(V.bd, i[0] >> 3, i[1] >> 3, i[2] >> 3) * kBrickVox +
-                        (size_t)(((i[2] & 7) << 6) | ((i[1] & 7) << 3) | (i[0] & 7));
-    const size_t sx = ((i[0] & 7) == 7) ? (size_t)V.bd[1] * V.bd[2] * kBrickVox - 7 : 1;
-    const size_t sy = ((i[1] & 7) == 7) ? (size_t)V.bd[2] * kBrickVox - 56 : 8;
-    const size_t sz = ((i[2] & 7) == 7) ? (size_t)(kBrickVox - 448) : 64;
+    const uint32_t base = voxel_index32(V, i);
+    const uint32_t sx = ((i[0] & 7) == 7) ? (uint32_t)V.bd[1] * (uint32_t)V.bd[2] * kBrickVox - 7u : 1u;
+    const uint32_t sy = ((i[1] & 7) == 7) ? (uint32_t)V.bd[2] * kBrickVox - 56u : 8u;
+    const uint32_t sz = ((i[2] & 7) == 7) ? (uint32_t)(kBrickVox - 448) : 64u;
     GPTR(const float) const F = gptr((const float*)V.F);
-    c[0] = F[base];
-    c[1] = F[base + sx];
-    c[2] = F[base + sy];
-    c[3] = F[base + sy + sx];
-    c[4] = F[base + sz];
-    c[5] = F[base + sz + sx];
-    c[6] = F[base + sz + sy];
-    c[7] = F[base + sz + sy + sx];
+    c[0] = ld_elem(F, base);
+    c[1] = ld_elem(F, base + sx);
+    c[2] = ld_elem(F, base + sy);
+    c[3] = ld_elem(F, base + sy + sx);
+    c[4] = ld_elem(F, base + sz);
+    c[5] = ld_elem(F, base + sz + sx);
+    c[6] = ld_elem(F, base + sz + sy);
+    c[7] = ld_elem(F, base + sz + sy + sx);
 }
 
 // trilinear value in the contract's order (x, then y, then z); NaN when a
@@ -533,23 +586,6 @@ static __host__ __device__ __forceinline__ float trilinear(const float c[8], con
     const float c0 = lerp32(c00, c10, f[1]);
     const float c1 = lerp32(c01, c11, f[1]);
     return lerp32(c0, c1, f[2]);
-}
-
-// Evaluate sample with local coordinate l: returns validity, value.
-static __host__ __device__ __forceinline__ bool eval_sample(const DevVolume& V, const float l[3], float& Fk)
-{
-    int i[3];
-    float f[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float fl = floorf(l[a]);
-        i[a] = (int)fl;
-        f[a] = l[a] - fl;
-    }
-    float c[8];
-    gather8(V, i, c);
-    Fk = trilinear(c, f);
-    return !isnan(Fk);
 }
 
 // The 8 corner values of the last cell gathered by a ray; consecutive
@@ -606,22 +642,6 @@ static __host__ __device__ __forceinline__ void ray_k_range(const DevVolume& V, 
     k1 = min(kmax, (int)ceilf(t1 * r.inv_delta) + 2);
 }
 
-// Is some brick holding a corner of the cell with base i flagged?  Also
-// returns the brick box [blo, bhi] that was checked.
-static __host__ __device__ __forceinline__ bool cell_flagged(const DevVolume& V, const int i[3], int blo[3], int bhi[3])
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        blo[a] = i[a] >> 3;
-        bhi[a] = ((i[a] & 7) == 7) ? blo[a] + 1 : blo[a];
-    }
-    for (int bx = blo[0]; bx <= bhi[0]; ++bx)
-        for (int by = blo[1]; by <= bhi[1]; ++by)
-            for (int bz = blo[2]; bz <= bhi[2]; ++bz)
-                if (gptr((const uint8_t*)V.flag)[brick_index(V.bd, bx, by, bz)]) return true;
-    return false;
-}
-
 // March one volume.  Returns true with t* and k when a crossing nearer than
 // (best_t, best_id) exists.
 static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, float delta, int kmax,
@@ -646,6 +666,11 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
     int prev_k = -2;     // index of the last evaluated sample
     bool prev_ok = false;
     float Fprev = 0.0f;
+    GPTR(const uint8_t) const distp = gptr((const uint8_t*)V.dist);
+    GPTR(const uint64_t) const cmaskp = gptr((const uint64_t*)V.cmask);
+    uint32_t dist_b = 0xffffffffu;  // brick whose distance and cell mask are held
+    int dist_D = 0;
+    uint64_t dist_cm = 0;
     CellCache cc;
     cc.i[0] = -1; cc.i[1] = -1; cc.i[2] = -1;
     int k = k0;
@@ -662,31 +687,61 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
         int i[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) i[a] = (int)floorf(l[a]);
-        // empty-space skip: the cube of bricks within dist - 1 of this
-        // sample's brick holds no flagged brick, so no sample whose cell lies
-        // in it can be the far end of a plus-to-minus crossing
-        int blo[3], bhi[3];
-        bool skip;
+        // Empty-space skip.  Samples whose cells have no corner that may
+        // hold F <= 0 (flags are conservative) cannot be the far end of a
+        // plus-to-minus crossing and are skipped while their cells stay in
+        // such a region: the bricks within dist - 1 of this sample's brick,
+        // else clear cell sub-blocks of this brick grown along the ray.
+        // The box [A, B) bounds the cell base coordinate per axis.
+        int A[3], B[3];
+        bool skip = false;
         {
-            const int D = gptr((const uint8_t*)V.dist)[brick_index(V.bd, i[0] >> 3, i[1] >> 3, i[2] >> 3)];
+            const uint32_t bi = brick_index32(V, i[0] >> 3, i[1] >> 3, i[2] >> 3);
+            if (bi != dist_b) {
+                dist_b = bi;
+                dist_D = ld_elem(distp, bi);
+                dist_cm = ld_elem(cmaskp, bi);
+            }
+            const int D = dist_D;
             if (D >= 2) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    blo[a] = (i[a] >> 3) - (D - 1);
-                    bhi[a] = (i[a] >> 3) + (D - 1);
+                    A[a] = 8 * ((i[a] >> 3) - (D - 1));
+                    B[a] = 8 * ((i[a] >> 3) + (D - 1)) + 7;
                 }
                 skip = true;
             } else {
-                skip = D == 1 && !cell_flagged(V, i, blo, bhi);
+                int lo[3], hi[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) lo[a] = hi[a] = (i[a] & 7) >> 1;
+                if ((subblock_box(lo, hi) & dist_cm) == 0) {
+                    skip = true;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        if (dl[a] > 0.0f) {
+                            while (hi[a] < 3) {
+                                ++hi[a];
+                                if (subblock_box(lo, hi) & dist_cm) { --hi[a]; break; }
+                            }
+                        } else if (dl[a] < 0.0f) {
+                            while (lo[a] > 0) {
+                                --lo[a];
+                                if (subblock_box(lo, hi) & dist_cm) { ++lo[a]; break; }
+                            }
+                        }
+                        A[a] = (i[a] & ~7) + 2 * lo[a];
+                        B[a] = (i[a] & ~7) + 2 * hi[a] + 2;
+                    }
+                }
             }
         }
         if (skip) {
-            // samples whose cells stay inside the empty bricks cannot hold F <= 0
+            // samples whose cells stay inside the box cannot hold F <= 0
             float m = 1e30f;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                if (dl[a] > 0.0f) m = fminf(m, ((float)(8 * bhi[a] + 7) - 0.01f - l[a]) * inv_dl[a]);
-                else if (dl[a] < 0.0f) m = fminf(m, (l[a] - ((float)(8 * blo[a]) + 0.01f)) * -inv_dl[a]);
+                if (dl[a] > 0.0f) m = fminf(m, ((float)B[a] - 0.01f - l[a]) * inv_dl[a]);
+                else if (dl[a] < 0.0f) m = fminf(m, (l[a] - ((float)A[a] + 0.01f)) * -inv_dl[a]);
             }
             int jump = (int)fminf(fmaxf(m, 0.0f), 4096.0f);
             if (jump < 1) jump = 1;
@@ -757,7 +812,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
 
 __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
 {
-    const LaunchHeader H = *L.hdr;
+    const LaunchHeader H = *cptr(L.hdr);
     // XCD-aware order: hardware deals blocks round-robin over 8 XCDs; give
     // each XCD a contiguous run of tiles, then each block a contiguous chunk.
     const int nb = gridDim.x;
@@ -768,22 +823,23 @@ __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
     const int t_begin = chunk * per;
     const int t_end = min(t_begin + per, H.total_tiles);
     for (int tile = t_begin; tile < t_end; ++tile) {
+        CPTR(int32_t) const tile_base = cptr(L.tile_base);
         int s = 0;
-        while (s + 1 < H.nstreams && L.tile_base[s + 1] <= tile) ++s;
+        while (s + 1 < H.nstreams && tile_base[s + 1] <= tile) ++s;
         s = wave_uniform(s);
-        const DevFrame& Fr = L.frames[s];
-        const int local = tile - L.tile_base[s];
-        const int tiles_x = (Fr.out_w + L.tile_w - 1) / L.tile_w;
+        const int out_w = cptr(L.frames)[s].out_w, out_h = cptr(L.frames)[s].out_h;
+        const int local = tile - tile_base[s];
+        const int tiles_x = (out_w + L.tile_w - 1) / L.tile_w;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
         const int u = tx * L.tile_w + (int)(threadIdx.x % L.tile_w);
         const int v = ty * L.tile_h + (int)(threadIdx.x / L.tile_w);
-        if (u < Fr.out_w && v < Fr.out_h) raycast_pixel(L, H, s, u, v);
+        if (u < out_w && v < out_h) raycast_pixel(L, H, s, u, v);
     }
 }
 
 static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v)
 {
-    const DevFrame& Fr = L.frames[s];
+    const DevFrame Fr = cptr(L.frames)[s];
     const size_t p = (size_t)v * Fr.out_w + u;
 
     // ray (binary32 contract)
@@ -813,20 +869,20 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
         const int prev = Fr.best_id[p];
         if (prev >= 0) { best_t = Fr.best_t[p]; best_id = prev; }
     }
-    const int l0 = L.list_base[s], l1 = L.list_base[s + 1];
+    const int l0 = cptr(L.list_base)[s], l1 = cptr(L.list_base)[s + 1];
     for (int li = l0; li < l1; ++li) {
-        const DevVolume V = L.vols[L.lists[li]];
+        const DevVolume V = cptr(L.vols)[cptr(L.lists)[li]];
         float ts;
         int ks, cell[3];
         if (march_volume(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell)) {
             best_t = ts;
             best_id = V.id;
-            best_vol = L.lists[li];
+            best_vol = cptr(L.lists)[li];
             best_cell[0] = cell[0]; best_cell[1] = cell[1]; best_cell[2] = cell[2];
         }
     }
     if (best_vol >= 0) {
-        const DevVolume& V = L.vols[best_vol];
+        const DevVolume V = cptr(L.vols)[best_vol];
         float x[3], n[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) x[a] = r.C[a] + (best_t * r.dw[a]);
@@ -856,17 +912,24 @@ int launch_raycast(const RaycastLaunch& L, int blocks, void* stream)
 
 // ---------------------------------------------------------------------------
 // Brick summary: exact recompute of the per-brick "may hold F <= 0" flags
-// (after a volume is written from the host).
+// and sub-block masks (after a volume is written from the host).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void mvf_brick_summary_kernel(DevVolume v, size_t nbricks)
 {
     const int lane = threadIdx.x & 63;
     const size_t brick = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (brick >= nbricks) return;
-    bool any = false;
-    for (int j = lane; j < kBrickVox; j += 64) any |= v.F[brick * kBrickVox + j] <= kFlagThreshold;
-    const unsigned long long m = __ballot(any);
-    if (lane == 0) v.flag[brick] = m ? 1 : 0;
+    const float* F = v.F + brick * kBrickVox + lane;
+    uint64_t fm = 0;
+    for (int zp = 0; zp < kBrick / 2; ++zp) {
+        const bool a = F[(2 * zp) * 64] <= kFlagThreshold;
+        const bool b = F[(2 * zp + 1) * 64] <= kFlagThreshold;
+        fm |= (uint64_t)subblock_bits(__ballot(a | b)) << (16 * zp);
+    }
+    if (lane == 0) {
+        v.flag[brick] = fm ? 1 : 0;
+        v.fmask[brick] = fm;
+    }
 }
 
 int launch_brick_summary(DevVolume v, void* stream)
@@ -883,44 +946,70 @@ int launch_brick_summary(DevVolume v, void* stream)
 // One thread per brick of every volume in the table; three launches (x from
 // the flags into tmp, y into tmp + nbricks, z into dist).
 // ---------------------------------------------------------------------------
+// Distance passes over the bricks of every volume of the table; pass 0 also
+// derives the cell masks from the sub-block flags of each brick and its +x,
+// +y, +z neighbours.  Each volume's bricks start at a multiple of 64 in the
+// launch's brick numbering (brick_base), so a wavefront serves one volume.
 __global__ __launch_bounds__(256) void mvf_brick_distance_kernel(const LaunchHeader* hdr, const DevVolume* vols,
                                                                  const int32_t* brick_base, int pass)
 {
-    const int total = hdr->total_bricks;
-    const int nvol = hdr->nvol;
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+    const int total = cptr(hdr)->total_bricks;
+    const int nvol = cptr(hdr)->nvol;
+    CPTR(int32_t) const bbase = cptr(brick_base);
+    const int stride = gridDim.x * blockDim.x;
+    for (int g0 = blockIdx.x * blockDim.x; g0 < total; g0 += stride) {
+        const int gw = wave_uniform(g0 + (int)(threadIdx.x & ~63u));  // first brick of this wave
         int lo = 0, hi = nvol - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (brick_base[mid] <= g) lo = mid; else hi = mid - 1;
+            if (bbase[mid] <= gw) lo = mid; else hi = mid - 1;
         }
-        const DevVolume& V = vols[lo];
-        const int b = g - brick_base[lo];
-        const size_t nb = (size_t)V.bd[0] * V.bd[1] * V.bd[2];
+        lo = wave_uniform(lo);
+        const DevVolume V = cptr(vols)[lo];
+        const int b = g0 + (int)threadIdx.x - bbase[lo];
+        const int nb = V.bd[0] * V.bd[1] * V.bd[2];
+        if (b >= nb) continue;
         const int bz = b % V.bd[2];
         const int t = b / V.bd[2];
         const int by = t % V.bd[1];
         const int bx = t / V.bd[1];
         int d = kDistCap;
         if (pass == 0) {
+            GPTR(const uint64_t) const fm = gptr((const uint64_t*)V.fmask);
+            uint64_t M[2][2][2];
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const bool in = bx + dx < V.bd[0] && by + dy < V.bd[1] && bz + dz < V.bd[2];
+                        M[dz][dy][dx] = in ? ld_elem(fm, brick_index32(V, bx + dx, by + dy, bz + dz)) : 0ull;
+                    }
+            V.cmask[b] = cell_mask(M);
+            GPTR(const uint8_t) const flag = gptr((const uint8_t*)V.flag);
+            const int sx = V.bd[1] * V.bd[2];
+#pragma unroll
             for (int o = -kDistCap; o <= kDistCap; ++o) {
                 const int x = bx + o;
-                if (x < 0 || x >= V.bd[0]) continue;
-                if (V.flag[brick_index(V.bd, x, by, bz)]) d = min(d, abs(o));
+                if (x >= 0 && x < V.bd[0] && ld_elem(flag, (uint32_t)(b + o * sx))) d = min(d, abs(o));
             }
             V.tmp[b] = (uint8_t)d;
         } else if (pass == 1) {
+            GPTR(const uint8_t) const t0 = gptr((const uint8_t*)V.tmp);
+            const int sy = V.bd[2];
+#pragma unroll
             for (int o = -kDistCap; o <= kDistCap; ++o) {
                 const int y = by + o;
-                if (y < 0 || y >= V.bd[1]) continue;
-                d = min(d, max(abs(o), (int)V.tmp[brick_index(V.bd, bx, y, bz)]));
+                if (y >= 0 && y < V.bd[1]) d = min(d, max(abs(o), (int)ld_elem(t0, (uint32_t)(b + o * sy))));
             }
             V.tmp[nb + b] = (uint8_t)d;
         } else {
+            GPTR(const uint8_t) const t1 = gptr((const uint8_t*)V.tmp + nb);
+#pragma unroll
             for (int o = -kDistCap; o <= kDistCap; ++o) {
                 const int z = bz + o;
-                if (z < 0 || z >= V.bd[2]) continue;
-                d = min(d, max(abs(o), (int)V.tmp[nb + brick_index(V.bd, bx, by, z)]));
+                if (z >= 0 && z < V.bd[2]) d = min(d, max(abs(o), (int)ld_elem(t1, (uint32_t)(b + o))));
             }
             V.dist[b] = (uint8_t)d;
         }

@@ -70,7 +70,7 @@ struct Volume {
     bool alive = false;
     mvf_volume_desc d{};
     int bd[3] = {0, 0, 0};
-    size_t nvox_pad = 0, off_W = 0, off_C = 0, off_flag = 0, off_dist = 0, off_tmp = 0, bytes = 0;
+    size_t nvox_pad = 0, off_W = 0, off_C = 0, off_flag = 0, off_dist = 0, off_tmp = 0, off_fmask = 0, off_cmask = 0, bytes = 0;
     size_t nbricks = 0;
     uint8_t* dev = nullptr;    // device slab while resident
     uint8_t* host = nullptr;   // pinned mirror (allocated on first swap-out)
@@ -91,7 +91,8 @@ struct Scratch {
     int w = 0, h = 0;
     float* range = nullptr;
     uint32_t* color = nullptr;
-    float* rmax = nullptr;
+    float* rmax = nullptr;   // [0] max range, [1 + b] per frame-prep block
+    int rmax_cap = 0;        // floats in rmax
     float* best_t = nullptr;
     int32_t* best_id = nullptr;
     float* ztab = nullptr;  // integration z table (3 floats per entry)
@@ -258,6 +259,8 @@ DevVolume make_dev(mvf_ctx* c, const Volume& v)
     d.flag = v.dev + v.off_flag;
     d.dist = v.dev + v.off_dist;
     d.tmp = v.dev + v.off_tmp;
+    d.fmask = reinterpret_cast<uint64_t*>(v.dev + v.off_fmask);
+    d.cmask = reinterpret_cast<uint64_t*>(v.dev + v.off_cmask);
     for (int a = 0; a < 3; ++a) {
         d.dims[a] = v.d.dims[a];
         d.off[a] = v.d.offset[a];
@@ -519,12 +522,17 @@ double box_distance(mvf_ctx* c, const Volume& v, const float* T)
 mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratch** out)
 {
     Scratch& s = c->scratch[sid];
-    if (w * h > s.w * s.h || !s.rmax) {
+    const int parts = ((w + 31) / 32) * ((h + 7) / 8);
+    if (1 + parts > s.rmax_cap) {
+        if (s.rmax) { CHECK_HIP(hipFree(s.rmax)); s.rmax = nullptr; }
+        CHECK_HIP(hipMalloc((void**)&s.rmax, (size_t)(1 + parts) * sizeof(float)));
+        s.rmax_cap = 1 + parts;
+    }
+    if (w * h > s.w * s.h || !s.range) {
         if (s.range) { CHECK_HIP(hipFree(s.range)); s.range = nullptr; }
         if (s.color) { CHECK_HIP(hipFree(s.color)); s.color = nullptr; }
         if (s.best_t) { CHECK_HIP(hipFree(s.best_t)); s.best_t = nullptr; }
         if (s.best_id) { CHECK_HIP(hipFree(s.best_id)); s.best_id = nullptr; }
-        if (!s.rmax) CHECK_HIP(hipMalloc((void**)&s.rmax, 256));
         const size_t n = (size_t)std::max(w * h, s.w * s.h);
         CHECK_HIP(hipMalloc((void**)&s.range, (n + 64) * sizeof(float)));  // + the zero range behind the image
         CHECK_HIP(hipMalloc((void**)&s.color, n * sizeof(uint32_t)));
@@ -596,6 +604,7 @@ void fill_frame(DevFrame* f, const Scratch* s, int w, int h, const float* T, con
         f->range = s->range;
         f->color = s->color;
         f->rmax = s->rmax;
+        f->rmax_parts = ((w + 31) / 32) * ((h + 7) / 8);
     }
     f->width = w;
     f->height = h;
@@ -690,12 +699,12 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             h->zchunk = zc;
             h->nstreams = 1;
             p.bricks = (int)v.nbricks;
-            h->total_bricks = p.bricks;
+            h->total_bricks = (int)align_up((size_t)p.bricks, 64);
             h->total_z = kBrick * v.bd[2];
             ib[0] = 0;
             ib[1] = p.items;
             bb[0] = 0;
-            bb[1] = p.bricks;
+            bb[1] = h->total_bricks;
             per.push_back(p);
         }
         CHECK_ST(arena_upload(c, w2, stream));
@@ -1017,13 +1026,17 @@ mvf_status mvf_volume_create(mvf_ctx* c, const mvf_volume_desc* d, int32_t* vol_
     v.d = *d;
     for (int a = 0; a < 3; ++a) v.bd[a] = (d->dims[a] + kBrick - 1) / kBrick;
     const size_t nb = (size_t)v.bd[0] * v.bd[1] * v.bd[2];
+    if (nb * kBrickVox > ((size_t)1 << 30))
+        return set_error(MVF_ERR_INVALID_ARG, "volume of %zu padded voxels exceeds 2^30", nb * kBrickVox);
     v.nvox_pad = nb * kBrickVox;
     v.off_W = align_up(v.nvox_pad * 4, kAlign);
     v.off_C = align_up(v.off_W + v.nvox_pad * 2, kAlign);
     v.off_flag = align_up(v.off_C + v.nvox_pad * 4, kAlign);
     v.off_dist = align_up(v.off_flag + nb, kAlign);
     v.off_tmp = align_up(v.off_dist + nb, kAlign);
-    v.bytes = align_up(v.off_tmp + 2 * nb, kAlign);
+    v.off_fmask = align_up(v.off_tmp + 2 * nb, kAlign);
+    v.off_cmask = align_up(v.off_fmask + 8 * nb, kAlign);
+    v.bytes = align_up(v.off_cmask + 8 * nb, kAlign);
     v.nbricks = nb;
     c->vols.push_back(v);
     *vol_id = (int32_t)c->vols.size() - 1;
@@ -1202,10 +1215,10 @@ mvf_status mvf_volume_write(mvf_ctx* c, int32_t id, const float* F, const uint16
             int32_t* bb = w.alloc<int32_t>(2, &dbb);
             memset(h, 0, sizeof(*h));
             h->nvol = 1;
-            h->total_bricks = (int)v->nbricks;
+            h->total_bricks = (int)align_up(v->nbricks, 64);
             *vt = dv;
             bb[0] = 0;
-            bb[1] = (int)v->nbricks;
+            bb[1] = h->total_bricks;
             ast = arena_upload(c, w, nullptr);
             if (ast != MVF_OK) return ast;
             le = launch_brick_distance(dh, dvv, dbb, std::min<int>(1024, ((int)v->nbricks + 255) / 256), nullptr);
@@ -1423,7 +1436,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             zt += kBrick * v.bd[2];
             ib[nv] = items;
             bbase[nv] = nbr;
-            nbr += (int)v.nbricks;
+            nbr += (int)align_up(v.nbricks, 64);  // volumes start on a wavefront
             items += v.bd[0] * v.bd[1] * ((v.bd[2] + zc - 1) / zc);
             ++nv;
         }
