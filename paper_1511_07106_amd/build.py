@@ -20,6 +20,9 @@ LIB = os.path.join(PKG, "libmvf.so")
 ARCH = os.environ.get("MVF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["mvf_kernels.hip", "mvf_runtime.cpp"]
+# self-test of hardware arithmetic the kernels rely on (GPU tests only)
+SELFTEST_SRC = "mvf_selftest.hip"
+SELFTEST_LIB = os.path.join(PKG, "libmvf_selftest.so")
 
 # Numeric contract: no contraction of a*b+c into FMA, IEEE division and
 # square root, denormals kept.  Packed FP32 instructions are disabled.
@@ -57,16 +60,17 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link libmvf.so.  Always recompiles."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    if verbose:
-        print("built", LIB)
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        objs = list(ex.map(_compile, SOURCES + [SELFTEST_SRC]))
+    for lib, lib_objs in ((LIB, objs[:len(SOURCES)]), (SELFTEST_LIB, objs[len(SOURCES):])):
+        tmp = lib + ".tmp%d" % os.getpid()
+        cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *lib_objs]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
+        if verbose:
+            print("built", lib)
     return LIB
 
 
