@@ -120,6 +120,190 @@ def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps):
     return r
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def phase_diffray(mvf, torch, n_poses=16, n_steps=50):
+    """Pose refinement through the differentiable raycast: a 512^3 volume over
+    [-1, 1]^3 fused from 60 noisy 640x480 frames of the small room on its
+    circle; 16 poses perturbed by 2 cm / 2 degrees, 50 gradient steps each
+    against the noise-free analytic depth at the true pose."""
+    from synth import scenes as S
+    from paper_1511_07106_amd.autograd import DiffRaycast, depth_loss
+    n = 512
+    seq = S.small_room_sequence(seed=1, n_frames=60, K=S.K_VGA)
+    K = seq.K.as_array()
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    frames = seq.frames(list(range(60)), threads=16)
+    with mvf.Context() as ctx:
+        gid = ctx.grid((-1.0, -1.0, -1.0), 2.0 / n, 4.0, 128)
+        vid = ctx.volume(gid, (0, 0, 0), (n, n, n))
+        for i, (d, c) in enumerate(frames):
+            ctx.integrate(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev), seq.poses[i], K)
+        ctx.synchronize()
+        F_np, W_np, _ = ctx.read_volume(vid)
+    F = torch.from_numpy(F_np).to(dev)
+    W = torch.from_numpy(W_np.view(np.int16)).to(dev)
+    del F_np, W_np
+    log(f"diffray: fused 60 frames into 512^3 in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(5)
+    pose_idx = [int(x) for x in np.linspace(0, 59, n_poses)]
+    fwd_ms, bwd_ms, err0, err1, rot0, rot1, loss_ratio = [], [], [], [], [], [], []
+
+    def rot_err(A, B):
+        R = A[:, :3].T @ B[:, :3]
+        return float(np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1))))
+
+    with mvf.Context() as ctx:
+        for pi in pose_idx:
+            T_true = seq.poses[pi]
+            target = torch.from_numpy(S.render(seq.scene, seq.K, T_true)[0]).to(dev)
+            T = S.perturb_pose(T_true, rng, 0.02, 2.0)
+            err0.append(float(np.linalg.norm(T[:, 3] - T_true[:, 3])))
+            rot0.append(rot_err(T, T_true))
+            losses = []
+            for it in range(n_steps):
+                xi = torch.zeros(6, dtype=torch.float64, requires_grad=True)
+                a, b = _events(torch)
+                a.record()
+                depth = DiffRaycast.apply(F, xi, W, ctx, (-1.0, -1.0, -1.0), 2.0 / n, T, K, W_IMG, H_IMG)
+                b.record()
+                loss = depth_loss(depth, target)
+                c_, d_ = _events(torch)
+                c_.record()
+                loss.backward()
+                d_.record()
+                torch.cuda.synchronize()
+                fwd_ms.append(a.elapsed_time(b))
+                bwd_ms.append(c_.elapsed_time(d_))
+                losses.append(float(loss))
+                T = mvf.pose_retract(T, -0.5 * xi.grad.numpy())
+            err1.append(float(np.linalg.norm(T[:, 3] - T_true[:, 3])))
+            rot1.append(rot_err(T, T_true))
+            loss_ratio.append(losses[-1] / max(losses[0], 1e-30))
+    return {"poses": n_poses, "steps": n_steps, "image": [W_IMG, H_IMG], "volume": [n, n, n],
+            "forward_ms_median": float(np.median(fwd_ms)), "backward_ms_median": float(np.median(bwd_ms)),
+            "backward_over_forward": float(np.median(bwd_ms) / np.median(fwd_ms)),
+            "trans_err_mm_before": 1e3 * float(np.mean(err0)), "trans_err_mm_after": 1e3 * float(np.mean(err1)),
+            "rot_err_deg_before": float(np.mean(rot0)), "rot_err_deg_after": float(np.mean(rot1)),
+            "loss_ratio_median": float(np.median(loss_ratio)),
+            "poses_improved": int(sum(e1 < e0 for e0, e1 in zip(err0, err1)))}
+
+
+def phase_multi(mvf, torch, n_rooms=32, n_render=3, steps=10, warmup=2):
+    """Many independent scenes: 32 rooms with 1-4 volumes of 128^3..384^3 each
+    (10.4 mm voxels), one 640x480 frame per room per step; the batched step
+    (all rooms in one mvf_step) against the 32 rooms' plain calls."""
+    from synth import scenes as S
+    s = 4.0 / 384
+    rooms = S.multi_room_workload(n_rooms, 100)
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    frames = []
+    for r in rooms:
+        fr = r.frames(list(range(n_render)), threads=16)
+        frames.append([(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev)) for d, c in fr])
+    log(f"multi: rendered {n_rooms * n_render} frames in {time.time() - t0:.1f}s")
+    K = S.K_VGA.as_array()
+    res = {}
+    for mode in ("batched", "plain"):
+        with mvf.Context(timing=False) as ctx:
+            gid = ctx.grid((-2.0, -2.0, -2.0), s, 4.0, 128)
+            nvol = 0
+            vox = 0
+            for i in range(n_rooms):
+                for off, dims in S.room_volumes(1000 + i, s):
+                    ctx.volume(gid, off, dims, stream_id=i)
+                    nvol += 1
+                    vox += dims[0] * dims[1] * dims[2]
+            outs = [{"depth": torch.empty((H_IMG, W_IMG), device=dev),
+                     "vertex": torch.empty((H_IMG, W_IMG, 3), device=dev),
+                     "normal": torch.empty((H_IMG, W_IMG, 3), device=dev),
+                     "hit": torch.empty((H_IMG, W_IMG), dtype=torch.int32, device=dev)} for _ in range(n_rooms)]
+
+            def one(j):
+                fi = j % n_render
+                if mode == "batched":
+                    ctx.step([(i, frames[i][fi][0], frames[i][fi][1], rooms[i].poses[fi], K)
+                              for i in range(n_rooms)], outs)
+                else:
+                    for i in range(n_rooms):
+                        ctx.integrate(frames[i][fi][0], frames[i][fi][1], rooms[i].poses[fi], K, stream_id=i)
+                        ctx.raycast(rooms[i].poses[fi], K, W_IMG, H_IMG, stream_id=i, out=outs[i])
+
+            for j in range(warmup):
+                one(j)
+            torch.cuda.synchronize()
+            ctx.reset_stats()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for j in range(warmup, warmup + steps):
+                one(j)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            st = ctx.stats()
+            res[mode] = {"ms_per_step": 1e3 * wall / steps, "voxel_updates_per_s": st["voxels_updated"] / wall,
+                         "mpix_s": steps * n_rooms * W_IMG * H_IMG / wall / 1e6}
+            res["volumes"] = nvol
+            res["voxels"] = vox
+    res["rooms"] = n_rooms
+    res["batched_vs_plain_speedup"] = res["plain"]["ms_per_step"] / res["batched"]["ms_per_step"]
+    return res
+
+
+def phase_corridor(mvf, torch, n_steps=100, stride=10, d_v=384, n_max=16, budget_gb=8.0):
+    """Dynamic placement down the 20 m corridor: every `stride`-th frame of the
+    2000-frame walk is integrated into the live volumes, raycast, then the
+    endpoint-count placement adds/removes d_v^3 volumes (n_max live, beta 1.5)
+    under an HBM budget, so that volumes swap to and from host memory."""
+    from synth import scenes as S
+    seq = S.corridor_sequence(seed=3, n_frames=2000)
+    K = seq.K.as_array()
+    idx = [i * stride for i in range(n_steps)]
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    fr = seq.frames(idx, threads=16)
+    frames = [(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev)) for d, c in fr]
+    log(f"corridor: rendered {len(idx)} frames in {time.time() - t0:.1f}s")
+    out = {"depth": torch.empty((H_IMG, W_IMG), device=dev),
+           "vertex": torch.empty((H_IMG, W_IMG, 3), device=dev),
+           "normal": torch.empty((H_IMG, W_IMG, 3), device=dev),
+           "hit": torch.empty((H_IMG, W_IMG), dtype=torch.int32, device=dev)}
+    with mvf.Context(budget_bytes=int(budget_gb * (1 << 30)), timing=False) as ctx:
+        gid = ctx.grid((0.0, -1.0, 0.0), 0.00293, 4.0, 128)
+        added = removed = 0
+        hits = []
+        place_ms = []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for j, i in enumerate(idx):
+            d, c = frames[j]
+            ctx.integrate(d, c, seq.poses[i], K)
+            ctx.raycast(seq.poses[i], K, W_IMG, H_IMG, out=out)
+            tp = time.perf_counter()
+            a, r, _ = ctx.placement_update(d, seq.poses[i], K, gid, d_v, n_max, 1.5)
+            place_ms.append(1e3 * (time.perf_counter() - tp))
+            added += len(a)
+            removed += len(r)
+            if j % 10 == 9:
+                hits.append(float((out["depth"] > 0).float().mean()))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        st = ctx.stats()
+    return {"steps": n_steps, "frame_stride": stride, "d_v": d_v, "n_max": n_max, "budget_gb": budget_gb,
+            "ms_per_step": 1e3 * wall / n_steps, "placement_ms_median": float(np.median(place_ms)),
+            "volumes_added": added, "volumes_removed": removed,
+            "swaps_in": st["swaps_in"], "swaps_out": st["swaps_out"],
+            "h2d_gb": st["bytes_h2d"] / 1e9, "d2h_gb": st["bytes_d2h"] / 1e9,
+            "swap_gb_per_s_of_wall": (st["bytes_h2d"] + st["bytes_d2h"]) / 1e9 / wall,
+            "voxel_updates_per_s": st["voxels_updated"] / wall, "hit_fraction_mean": float(np.mean(hits))}
+
+
+EXTRA_PHASES = {"diffray": phase_diffray, "multi": phase_multi, "corridor": phase_corridor}
+
+
 def cpu_baseline(seq_frames, K, budget_s=12.0, max_frames=40):
     """The CPU oracle on a bounded sample of the same workload: whole steps
     (integrate + raycast) into a 512^3 volume, from the first frame, until
@@ -171,7 +355,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--phases", default="single,single_step,tiled,batched")
+    ap.add_argument("--phases", default="single,single_step,tiled,batched",
+                    help="comma list; also diffray, multi, corridor (longer workloads, not in the default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the phases, copy a buffer of this size 5 times (counter calibration)")
     args = ap.parse_args()
@@ -185,16 +370,21 @@ def main():
     mvf._lib.load()
     from synth import scenes as S
     K = S.K_VGA.as_array()
-    n = args.warmup + args.steps
-    seq, frames = render_frames(n)
     dev = torch.device("cuda", 0)
-    dev_frames = [(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev)) for (d, c), _ in frames]
-    poses = [T for _, T in frames]
+    names = args.phases.split(",")
+    frames, dev_frames, poses = [], [], []
+    if any(ph not in EXTRA_PHASES for ph in names) or not args.no_cpu:
+        seq, frames = render_frames(args.warmup + args.steps)
+        dev_frames = [(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev)) for (d, c), _ in frames]
+        poses = [T for _, T in frames]
     torch.cuda.synchronize()
     phases = {}
-    for ph in args.phases.split(","):
+    for ph in names:
         log(f"phase {ph}")
-        phases[ph] = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps)
+        if ph in EXTRA_PHASES:
+            phases[ph] = EXTRA_PHASES[ph](mvf, torch)
+        else:
+            phases[ph] = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps)
         log(json.dumps(phases[ph]))
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -207,8 +397,12 @@ def main():
         del a, b
     # headline: the single 512^3 volume through the graph path; the roofline
     # comes from the plain phase, whose kernels are timed one by one
-    head_ph = phases.get("single_step") or phases.get("single") or next(iter(phases.values()))
-    main_ph = phases.get("single") or head_ph
+    core = {k: v for k, v in phases.items() if k not in EXTRA_PHASES}
+    if not core:
+        print(json.dumps({"phases": phases}), flush=True)
+        return
+    head_ph = core.get("single_step") or core.get("single") or next(iter(core.values()))
+    main_ph = core.get("single") or head_ph
     steps = args.steps
     # roofline of the integration kernel
     upd, band = main_ph["voxels_updated"], main_ph["voxels_band"]

@@ -131,6 +131,14 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libmvf.so not built at {LIB_PATH}; run `python -m paper_1511_07106_amd.build`")
+    # torch ships its own HIP runtime under the same soname; importing torch
+    # first makes libmvf bind to that one, so the process holds a single HIP
+    # runtime (the reverse order leaves torch on a runtime it was not built
+    # against, and it then finds no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, args in SIGNATURES.items():
         fn = getattr(lib, name)

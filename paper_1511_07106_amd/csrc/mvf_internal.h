@@ -183,7 +183,16 @@ struct DiffVolume {
     int32_t off[3];
     float o[3];
     float s, inv_s;
+    // skip summary over 8^3 bricks of the dense volume (x-fastest brick
+    // order), or null: Chebyshev distance in bricks (cap kDistCap) to the
+    // nearest brick holding the base voxel of a cell with an observed corner
+    // F <= 2^-100
+    const uint8_t* dist;
+    int32_t bd[3];
 };
+// Skip summary of a dense volume: work planes of 4 * nbricks bytes, result
+// in dist (nbricks bytes).
+int launch_dense_summary(const DiffVolume& v, uint8_t* work, uint8_t* dist, void* stream);
 int launch_diffray_forward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy,
                            int width, int height, RayParams rp, float* depth, int32_t* record,
                            void* stream);

@@ -1184,8 +1184,9 @@ int launch_placement_count(const float* depth, int depth_pitch, int width, int h
 
 // ---------------------------------------------------------------------------
 // Differentiable raycast on one dense x-fastest volume (F, W).  The forward
-// is the same march (binary32 contract; validity from W) without brick
-// skipping; it records k of the crossing's second sample.  The backward
+// is the same march (binary32 contract; validity from W), skipping bricks by
+// a summary computed for the call; it records k of the crossing's second
+// sample.  The backward
 // recomputes the two bracketing samples from k, and with the structure held
 // fixed scatters dL/dF (16 voxels per pixel, float atomics) and reduces
 // dL/dxi per block into binary64 partials, summed by a second kernel in a
@@ -1256,6 +1257,80 @@ struct PoseArgs {
     float T[12];
 };
 
+// Skip summary of a dense volume.  Pass 0: per brick, some voxel observed
+// with F <= 2^-100 (one wavefront per brick).  Pass 1: the cell flag, some
+// brick of b + {0,1}^3 flagged (a cell with base voxel in b has its corners
+// there).  Passes 2-4: capped Chebyshev distance along x, y, z.
+__global__ __launch_bounds__(256) void mvf_dense_flag_kernel(DiffVolume v, uint8_t* flag, int nb)
+{
+    const int lane = threadIdx.x & 63;
+    const int x = lane & 7, y = lane >> 3;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nb; b += waves) {
+        const int bx = b % v.bd[0], t = b / v.bd[0];
+        const int by = t % v.bd[1], bz = t / v.bd[1];
+        const int gx = 8 * bx + x, gy = 8 * by + y;
+        bool any = false;
+        if (gx < v.dims[0] && gy < v.dims[1]) {
+            for (int z = 8 * bz; z < min(8 * bz + 8, v.dims[2]); ++z) {
+                const size_t id = ((size_t)z * v.dims[1] + gy) * v.dims[0] + gx;
+                any |= (v.W[id] != 0) && (v.F[id] <= kFlagThreshold);
+            }
+        }
+        const unsigned long long m = __ballot(any);
+        if (lane == 0) flag[b] = m ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void mvf_dense_dist_kernel(DiffVolume v, const uint8_t* in, uint8_t* out, int nb,
+                                                             int pass)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+        const int bx = b % v.bd[0], t = b / v.bd[0];
+        const int by = t % v.bd[1], bz = t / v.bd[1];
+        const int sy = v.bd[0], sz = v.bd[0] * v.bd[1];
+        if (pass == 1) {
+            bool f = false;
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx)
+                        if (bx + dx < v.bd[0] && by + dy < v.bd[1] && bz + dz < v.bd[2])
+                            f |= in[b + dx + dy * sy + dz * sz] != 0;
+            out[b] = f ? 1 : 0;
+            continue;
+        }
+        const int pos = pass == 2 ? bx : (pass == 3 ? by : bz);
+        const int len = v.bd[pass - 2];
+        const int stride = pass == 2 ? 1 : (pass == 3 ? sy : sz);
+        int d = kDistCap;
+        for (int o = -kDistCap; o <= kDistCap; ++o) {
+            const int q = pos + o;
+            if (q < 0 || q >= len) continue;
+            const int val = in[b + o * stride];
+            d = pass == 2 ? (val ? min(d, abs(o)) : d) : min(d, max(abs(o), val));
+        }
+        out[b] = (uint8_t)d;
+    }
+}
+
+int launch_dense_summary(const DiffVolume& v, uint8_t* work, uint8_t* dist, void* stream)
+{
+    const int nb = v.bd[0] * v.bd[1] * v.bd[2];
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* flag = work;
+    uint8_t* cflag = work + nb;
+    uint8_t* t0 = work + 2 * (size_t)nb;
+    uint8_t* t1 = work + 3 * (size_t)nb;
+    const int wblocks = (int)std::min<long long>(65536, ((long long)nb + 3) / 4);
+    hipLaunchKernelGGL(mvf_dense_flag_kernel, dim3(wblocks), dim3(256), 0, s, v, flag, nb);
+    const int blocks = (int)std::min<long long>(4096, ((long long)nb + 255) / 256);
+    hipLaunchKernelGGL(mvf_dense_dist_kernel, dim3(blocks), dim3(256), 0, s, v, flag, cflag, nb, 1);
+    hipLaunchKernelGGL(mvf_dense_dist_kernel, dim3(blocks), dim3(256), 0, s, v, cflag, t0, nb, 2);
+    hipLaunchKernelGGL(mvf_dense_dist_kernel, dim3(blocks), dim3(256), 0, s, v, t0, t1, nb, 3);
+    hipLaunchKernelGGL(mvf_dense_dist_kernel, dim3(blocks), dim3(256), 0, s, v, t1, dist, nb, 4);
+    return (int)hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void mvf_diffray_forward_kernel(DiffVolume v, PoseArgs P, float fx, float fy,
                                                                   float cx, float cy, int width, int height,
                                                                   RayParams rp, float* depth, int32_t* record)
@@ -1288,19 +1363,80 @@ __global__ __launch_bounds__(256) void mvf_diffray_forward_kernel(DiffVolume v, 
     if (!none && t0 <= t1) {
         const int k0 = max(1, (int)floorf(t0 / rp.delta) - 2);
         const int k1 = min(rp.kmax, (int)ceilf(t1 / rp.delta) + 2);
+        // per-sample advance in local voxel units (skipping only; the 0.01
+        // voxel shrink of the skip box absorbs rounding)
+        float dl[3], inv_dl[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dl[a] = rp.delta * r.dw[a] * v.inv_s;
+            inv_dl[a] = __builtin_amdgcn_rcpf(dl[a]);
+        }
+        GPTR(const uint8_t) const distp = gptr(v.dist);
+        uint32_t cb = 0xffffffffu;
+        int cD = 0;
+        int prev_k = -2;
         bool prev_ok = false;
         float Fprev = 0.0f;
-        for (int k = k0; k <= k1; ++k) {
+        int k = k0;
+        while (k <= k1) {
+            const float tk = (float)k * rp.delta;
+            if (v.dist) {
+                // samples whose cell base lies in bricks with no cell that
+                // has an observed corner F <= 0 cannot be the far end of a
+                // crossing: skip them while they stay in the clear cube
+                float l[3];
+                bool dom = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float x = r.C[a] + (tk * r.dw[a]);
+                    l[a] = (((x - v.o[a]) * v.inv_s) - 0.5f) - (float)v.off[a];
+                    dom &= l[a] >= 0.0f && l[a] < (float)(v.dims[a] - 1);
+                }
+                if (dom) {
+                    int bi[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) bi[a] = ((int)floorf(l[a])) >> 3;
+                    const uint32_t b = (uint32_t)((bi[2] * v.bd[1] + bi[1]) * v.bd[0] + bi[0]);
+                    if (b != cb) {
+                        cb = b;
+                        cD = ld_elem(distp, b);
+                    }
+                    if (cD >= 1) {
+                        float m = 1e30f;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const float A = (float)(8 * (bi[a] - (cD - 1)));
+                            const float B = (float)(8 * (bi[a] + cD));
+                            if (dl[a] > 0.0f) m = fminf(m, (B - 0.01f - l[a]) * inv_dl[a]);
+                            else if (dl[a] < 0.0f) m = fminf(m, (l[a] - (A + 0.01f)) * -inv_dl[a]);
+                        }
+                        int jump = (int)fminf(fmaxf(m, 0.0f), 4096.0f);
+                        if (jump < 1) jump = 1;
+                        prev_k = -2;
+                        prev_ok = false;
+                        k += jump;
+                        continue;
+                    }
+                }
+            }
+            if (prev_k != k - 1) {
+                DSample P;
+                dense_sample(v, r, (float)(k - 1) * rp.delta, P);
+                prev_ok = P.ok;
+                Fprev = P.F;
+            }
             DSample S;
-            dense_sample(v, r, (float)k * rp.delta, S);
+            dense_sample(v, r, tk, S);
             if (prev_ok && S.ok && Fprev > 0.0f && S.F <= 0.0f) {
                 const float ta = (float)(k - 1) * rp.delta;
                 ts = ta + ((rp.delta * Fprev) / (Fprev - S.F));
                 kfound = k;
                 break;
             }
+            prev_k = k;
             prev_ok = S.ok;
             Fprev = S.F;
+            ++k;
         }
     }
     depth[p] = kfound >= 0 ? ts * dh[2] : 0.0f;

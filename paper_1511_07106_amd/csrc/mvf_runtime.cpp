@@ -180,6 +180,8 @@ struct mvf_ctx {
     static constexpr int kPlaceTable = 8192;
     double* diff_partials = nullptr;
     int diff_partials_n = 0;
+    uint8_t* diff_summary = nullptr;  // dense-volume skip summary: 5 planes of nbricks bytes
+    size_t diff_summary_n = 0;        // nbricks it holds
     StepGraph step;
     hipStream_t capture_stream = nullptr;
 };
@@ -930,6 +932,7 @@ mvf_status mvf_destroy(mvf_ctx* c)
     if (c->place_overflow) (void)hipFree(c->place_overflow);
     if (c->place_T) (void)hipFree(c->place_T);
     if (c->diff_partials) (void)hipFree(c->diff_partials);
+    if (c->diff_summary) (void)hipFree(c->diff_summary);
     if (c->tail) (void)hipEventDestroy(c->tail);
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -1704,6 +1707,8 @@ static mvf_status diff_volume(mvf_ctx* c, const mvf_dense_tsdf* v, DiffVolume* o
     }
     out->s = v->voxel_size;
     out->inv_s = 1.0f / v->voxel_size;
+    out->dist = nullptr;
+    for (int a = 0; a < 3; ++a) out->bd[a] = (v->dims[a] + kBrick - 1) / kBrick;
     (void)c;
     return MVF_OK;
 }
@@ -1723,6 +1728,20 @@ mvf_status mvf_diffray_forward(mvf_ctx* c, const mvf_dense_tsdf* v, const float 
     RayParams rp;
     rp.delta = c->cfg.ray_step * v->voxel_size;
     rp.kmax = (int32_t)std::floor(c->cfg.t_far / rp.delta);
+    // skip summary of the caller's volume, computed for this call
+    const size_t nb = (size_t)dv.bd[0] * dv.bd[1] * dv.bd[2];
+    if (nb > c->diff_summary_n) {
+        if (c->diff_summary) {
+            CHECK_HIP(hipStreamSynchronize(s));
+            CHECK_HIP(hipFree(c->diff_summary));
+            c->diff_summary = nullptr;
+        }
+        CHECK_HIP(hipMalloc((void**)&c->diff_summary, 5 * nb));
+        c->diff_summary_n = nb;
+    }
+    uint8_t* dist = c->diff_summary + 4 * nb;
+    CHECK_LAUNCH(launch_dense_summary(dv, c->diff_summary, dist, s));
+    dv.dist = dist;
     CHECK_LAUNCH(launch_diffray_forward(dv, T_wc, K->fx, K->fy, K->cx, K->cy, width, height, rp, depth, record, s));
     return mark_tail(c, s);
 }

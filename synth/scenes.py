@@ -469,3 +469,33 @@ def corridor_sequence(seed: int = 3, n_frames: int = 2000, noise: bool = True) -
     poses = corridor_trajectory(seed, n_frames)
     scene = corridor_scene(seed)
     return Sequence_(scene, K_VGA, poses, seed, noise)
+
+
+def room_volumes(seed: int, voxel_size: float, room: float = 4.0,
+                 dims_choices=(128, 192, 256, 320, 384), max_volumes: int = 4):
+    """Seeded volume layout of one room for the many-scene batched workload:
+    1..max_volumes cubic volumes with dims drawn from dims_choices, at seeded
+    integer offsets inside the room on a grid whose origin is the room's
+    lower corner.  Returns [(offset (3,), dims (3,))]."""
+    rng = np.random.Generator(np.random.PCG64([seed, 17]))
+    n_room = int(round(room / voxel_size))
+    out = []
+    for _ in range(int(rng.integers(1, max_volumes + 1))):
+        d = int(rng.choice(dims_choices))
+        span = max(1, n_room - d)
+        off = rng.integers(0, span, 3)
+        out.append((tuple(int(x) for x in off), (d, d, d)))
+    return out
+
+
+def multi_room_workload(n_rooms: int = 32, n_frames: int = 100, seed0: int = 1000):
+    """Independent 4 m rooms (3 spheres + 2 boxes each) with handheld paths at
+    640x480, seeds seed0 + i."""
+    out = []
+    for i in range(n_rooms):
+        seed = seed0 + i
+        poses = handheld_trajectory(seed, n_frames)
+        path = np.stack([T[:, 3] for T in poses])
+        scene = room_scene(seed, 3, 2, obj_box=1.5, keep_clear=path, clearance=0.3)
+        out.append(Sequence_(scene, K_VGA, poses, seed, True))
+    return out

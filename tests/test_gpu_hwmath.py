@@ -17,6 +17,7 @@ LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 def test_sqrt_estimate_within_filter_bound():
     if not os.path.exists(LIB):
         raise ImportError(f"{LIB} not built; run paper_1511_07106_amd.build")
+    import torch  # noqa: F401  (one HIP runtime per process: torch's, loaded first)
     lib = C.CDLL(LIB)
     lib.mvf_selftest_sqrt.argtypes = [C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_float)]
     lib.mvf_selftest_sqrt.restype = C.c_int
