@@ -141,6 +141,12 @@ struct IntegrateLaunch {
     float* ztab;
 };
 
+// Lanes that march one ray together in the raycast kernel (P consecutive
+// samples per round of gathers), and the pixel tile of a 64-lane block.
+constexpr int kRayLanes = 4;
+constexpr int kRayTileW = 4;
+constexpr int kRayTileH = 64 / kRayLanes / kRayTileW;
+
 struct RaycastLaunch {
     const LaunchHeader* hdr;
     const DevVolume* vols;      // table

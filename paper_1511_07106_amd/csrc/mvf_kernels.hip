@@ -642,6 +642,76 @@ static __host__ __device__ __forceinline__ void ray_k_range(const DevVolume& V, 
     k1 = min(kmax, (int)ceilf(t1 * r.inv_delta) + 2);
 }
 
+// Empty-space skip.  Samples whose cells have no corner that may hold F <= 0
+// (flags are conservative) cannot be the far end of a plus-to-minus
+// crossing and are skipped while their cells stay in such a region: the
+// bricks within dist - 1 of the sample's brick, else clear cell sub-blocks
+// of its brick grown along the ray.  Returns how many samples, from this
+// one (local coordinate l, cell base i, in the domain), can be skipped, or 0
+// when it must be evaluated.  The jump keeps a 0.01-voxel margin to the box
+// [A, B) of cell base coordinates.
+struct SkipCache {
+    uint32_t b;    // brick whose distance and cell mask are held
+    int D;
+    uint64_t cm;
+};
+
+static __host__ __device__ __forceinline__ int skip_run(const DevVolume& V, const float l[3], const int i[3],
+                                                        const float dl[3], const float inv_dl[3],
+                                                        GPTR(const uint8_t) distp, GPTR(const uint64_t) cmaskp,
+                                                        SkipCache& sc)
+{
+    int A[3], B[3];
+    bool skip = false;
+    const uint32_t bi = brick_index32(V, i[0] >> 3, i[1] >> 3, i[2] >> 3);
+    if (bi != sc.b) {
+        sc.b = bi;
+        sc.D = ld_elem(distp, bi);
+        sc.cm = ld_elem(cmaskp, bi);
+    }
+    const int D = sc.D;
+    if (D >= 2) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            A[a] = 8 * ((i[a] >> 3) - (D - 1));
+            B[a] = 8 * ((i[a] >> 3) + (D - 1)) + 7;
+        }
+        skip = true;
+    } else {
+        int lo[3], hi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) lo[a] = hi[a] = (i[a] & 7) >> 1;
+        if ((subblock_box(lo, hi) & sc.cm) == 0) {
+            skip = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (dl[a] > 0.0f) {
+                    while (hi[a] < 3) {
+                        ++hi[a];
+                        if (subblock_box(lo, hi) & sc.cm) { --hi[a]; break; }
+                    }
+                } else if (dl[a] < 0.0f) {
+                    while (lo[a] > 0) {
+                        --lo[a];
+                        if (subblock_box(lo, hi) & sc.cm) { ++lo[a]; break; }
+                    }
+                }
+                A[a] = (i[a] & ~7) + 2 * lo[a];
+                B[a] = (i[a] & ~7) + 2 * hi[a] + 2;
+            }
+        }
+    }
+    if (!skip) return 0;
+    float m = 1e30f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (dl[a] > 0.0f) m = fminf(m, ((float)B[a] - 0.01f - l[a]) * inv_dl[a]);
+        else if (dl[a] < 0.0f) m = fminf(m, (l[a] - ((float)A[a] + 0.01f)) * -inv_dl[a]);
+    }
+    const int jump = (int)fminf(fmaxf(m, 0.0f), 4096.0f);
+    return jump < 1 ? 1 : jump;
+}
+
 // March one volume.  Returns true with t* and k when a crossing nearer than
 // (best_t, best_id) exists.
 static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, float delta, int kmax,
@@ -668,9 +738,10 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
     float Fprev = 0.0f;
     GPTR(const uint8_t) const distp = gptr((const uint8_t*)V.dist);
     GPTR(const uint64_t) const cmaskp = gptr((const uint64_t*)V.cmask);
-    uint32_t dist_b = 0xffffffffu;  // brick whose distance and cell mask are held
-    int dist_D = 0;
-    uint64_t dist_cm = 0;
+    SkipCache sc;
+    sc.b = 0xffffffffu;
+    sc.D = 0;
+    sc.cm = 0;
     CellCache cc;
     cc.i[0] = -1; cc.i[1] = -1; cc.i[2] = -1;
     int k = k0;
@@ -687,68 +758,14 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
         int i[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) i[a] = (int)floorf(l[a]);
-        // Empty-space skip.  Samples whose cells have no corner that may
-        // hold F <= 0 (flags are conservative) cannot be the far end of a
-        // plus-to-minus crossing and are skipped while their cells stay in
-        // such a region: the bricks within dist - 1 of this sample's brick,
-        // else clear cell sub-blocks of this brick grown along the ray.
-        // The box [A, B) bounds the cell base coordinate per axis.
-        int A[3], B[3];
-        bool skip = false;
         {
-            const uint32_t bi = brick_index32(V, i[0] >> 3, i[1] >> 3, i[2] >> 3);
-            if (bi != dist_b) {
-                dist_b = bi;
-                dist_D = ld_elem(distp, bi);
-                dist_cm = ld_elem(cmaskp, bi);
+            const int jump = skip_run(V, l, i, dl, inv_dl, distp, cmaskp, sc);
+            if (jump) {
+                prev_ok = false;
+                prev_k = -2;
+                k += jump;
+                continue;
             }
-            const int D = dist_D;
-            if (D >= 2) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    A[a] = 8 * ((i[a] >> 3) - (D - 1));
-                    B[a] = 8 * ((i[a] >> 3) + (D - 1)) + 7;
-                }
-                skip = true;
-            } else {
-                int lo[3], hi[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) lo[a] = hi[a] = (i[a] & 7) >> 1;
-                if ((subblock_box(lo, hi) & dist_cm) == 0) {
-                    skip = true;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        if (dl[a] > 0.0f) {
-                            while (hi[a] < 3) {
-                                ++hi[a];
-                                if (subblock_box(lo, hi) & dist_cm) { --hi[a]; break; }
-                            }
-                        } else if (dl[a] < 0.0f) {
-                            while (lo[a] > 0) {
-                                --lo[a];
-                                if (subblock_box(lo, hi) & dist_cm) { ++lo[a]; break; }
-                            }
-                        }
-                        A[a] = (i[a] & ~7) + 2 * lo[a];
-                        B[a] = (i[a] & ~7) + 2 * hi[a] + 2;
-                    }
-                }
-            }
-        }
-        if (skip) {
-            // samples whose cells stay inside the box cannot hold F <= 0
-            float m = 1e30f;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (dl[a] > 0.0f) m = fminf(m, ((float)B[a] - 0.01f - l[a]) * inv_dl[a]);
-                else if (dl[a] < 0.0f) m = fminf(m, (l[a] - ((float)A[a] + 0.01f)) * -inv_dl[a]);
-            }
-            int jump = (int)fminf(fmaxf(m, 0.0f), 4096.0f);
-            if (jump < 1) jump = 1;
-            prev_ok = false;
-            prev_k = -2;
-            k += jump;
-            continue;
         }
         if (prev_k != k - 1) {
             // re-evaluate the previous sample (skipped or never seen)
@@ -776,6 +793,118 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
     }
     return false;
 }
+
+#if defined(__HIP_DEVICE_COMPILE__)
+// March one volume with the P lanes of a group (lane j of the group; all P
+// lanes carry the same ray and take the same path through the loop).  Each
+// round covers a window of P consecutive samples: every lane makes the skip
+// decision of its own sample; if no sample of the window may be the far end
+// of a crossing the group jumps past the longest clear run, otherwise every
+// lane evaluates its sample (one round of gathers for the window) and the
+// first crossing in sample order is taken, exactly as the sequential march
+// would find it.  When the sample before the window was not evaluated the
+// window starts one sample earlier so that it serves as the near end.
+template <int P>
+static __device__ bool march_volume_group(const DevVolume& V, const Ray& r, float delta, int kmax, float best_t,
+                                          int best_id, float& tstar, int& kstar, int cell[3], int j)
+{
+    int k0, k1;
+    ray_k_range(V, r, delta, kmax, k0, k1);
+    if (k0 > k1) return false;
+    {
+        const float t0 = (float)k0 * delta;
+        if (t0 > best_t || (t0 == best_t && V.id > best_id)) return false;
+    }
+    float dl[3], inv_dl[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dl[a] = delta * r.dw[a] * V.inv_s;
+        inv_dl[a] = approx_rcp(dl[a]);
+    }
+    const int gbase = (int)(threadIdx.x & 63u) & ~(P - 1);
+    const uint32_t gm = (1u << P) - 1u;
+    GPTR(const uint8_t) const distp = gptr((const uint8_t*)V.dist);
+    GPTR(const uint64_t) const cmaskp = gptr((const uint64_t*)V.cmask);
+    SkipCache sc;
+    sc.b = 0xffffffffu;
+    sc.D = 0;
+    sc.cm = 0;
+    CellCache cc;
+    cc.i[0] = -1; cc.i[1] = -1; cc.i[2] = -1;
+    int prev_k = -2;
+    bool prev_ok = false;
+    float Fprev = 0.0f;
+    int k = k0;
+    while (k <= k1) {
+        if ((float)(k - 1) * delta > best_t) break;   // nothing nearer can follow
+        const int w0 = (prev_k != k - 1) ? k - 1 : k;
+        const int sidx = w0 + j;
+        const bool far = sidx >= k && sidx <= k1;       // may be the far end of a crossing
+        float l[3];
+        sample_coord(V, r, (float)sidx * delta, l);
+        const bool dom = in_domain(V, l);
+        int i[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) i[a] = (int)floorf(l[a]);
+        int reach = sidx + 1;   // end (exclusive) of the run of samples this lane vouches for
+        bool must = false;
+        if (far && dom) {
+            const int jump = skip_run(V, l, i, dl, inv_dl, distp, cmaskp, sc);
+            if (jump) reach = sidx + jump;
+            else must = true;
+        }
+        const uint32_t must_g = (uint32_t)(__ballot(must) >> gbase) & gm;
+        if (must_g == 0) {
+            // the far-end samples of the window lie in overlapping clear runs
+            int rmax = far ? reach : k + 1;
+#pragma unroll
+            for (int o = 1; o < P; o <<= 1) rmax = max(rmax, __shfl_xor(rmax, o));
+            prev_ok = false;
+            prev_k = -2;
+            k = rmax;
+            continue;
+        }
+        float Fk = 0.0f;
+        bool ok = false;
+        if (dom) ok = eval_sample_cached(V, l, Fk, cc);
+        float Fn = __shfl_up(Fk, 1, P);
+        int okn = __shfl_up((int)ok, 1, P);
+        if (j == 0) { Fn = Fprev; okn = prev_ok; }
+        const bool excl = far && (float)(sidx - 1) * delta > best_t;   // the sequential march stops first
+        const bool cross = far && !excl && okn && ok && Fn > 0.0f && Fk <= 0.0f;
+        const uint32_t cross_g = (uint32_t)(__ballot(cross) >> gbase) & gm;
+        const uint32_t excl_g = (uint32_t)(__ballot(excl) >> gbase) & gm;
+        const int jc = cross_g ? __ffs(cross_g) - 1 : P;
+        const int je = excl_g ? __ffs(excl_g) - 1 : P;
+        if (jc < je) {
+            float ts = 0.0f;
+            int acc = 0;
+            if (j == jc) {
+                const float ta = (float)(sidx - 1) * delta;
+                ts = ta + ((delta * Fn) / (Fn - Fk));
+                acc = (ts < best_t || (ts == best_t && V.id < best_id)) ? 1 : 0;
+            }
+            ts = __shfl(ts, gbase + jc);
+            acc = __shfl(acc, gbase + jc);
+            if (!acc) return false;
+            tstar = ts;
+            kstar = w0 + jc;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) cell[a] = __shfl(i[a], gbase + jc);
+            return true;
+        }
+        if (je < P) return false;
+        // no crossing: the window's last far-end sample becomes the previous one
+        const int last = min(w0 + P - 1, k1);
+        const int jl = last - w0;
+        prev_ok = __shfl((int)ok, gbase + jl) != 0;
+        Fprev = __shfl(Fk, gbase + jl);
+        prev_k = last;
+        k = last + 1;
+    }
+    return false;
+}
+#endif
 
 // unit normal: the gradient, at world point x, of the trilinear interpolant
 // of the given cell (the cell of the crossing's second sample, whose 8
@@ -808,7 +937,10 @@ static __host__ __device__ void surface_normal(const DevVolume& V, const float x
     }
 }
 
-static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v);
+// Pixel (u, v) of stream s; j: lane of the pixel's group (the host build
+// marches sequentially with j = 0).
+static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v,
+                                              int j = 0);
 
 __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
 {
@@ -831,13 +963,15 @@ __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
         const int local = tile - tile_base[s];
         const int tiles_x = (out_w + L.tile_w - 1) / L.tile_w;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
-        const int u = tx * L.tile_w + (int)(threadIdx.x % L.tile_w);
-        const int v = ty * L.tile_h + (int)(threadIdx.x / L.tile_w);
-        if (u < out_w && v < out_h) raycast_pixel(L, H, s, u, v);
+        const int pix = (int)threadIdx.x / kRayLanes;   // kRayLanes lanes per pixel
+        const int u = tx * L.tile_w + pix % L.tile_w;
+        const int v = ty * L.tile_h + pix / L.tile_w;
+        if (u < out_w && v < out_h) raycast_pixel(L, H, s, u, v, (int)threadIdx.x % kRayLanes);
     }
 }
 
-static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v)
+static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v,
+                                              int j)
 {
     const DevFrame Fr = cptr(L.frames)[s];
     const size_t p = (size_t)v * Fr.out_w + u;
@@ -874,13 +1008,19 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
         const DevVolume V = cptr(L.vols)[cptr(L.lists)[li]];
         float ts;
         int ks, cell[3];
-        if (march_volume(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell)) {
+#if defined(__HIP_DEVICE_COMPILE__)
+        const bool found = march_volume_group<kRayLanes>(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell, j);
+#else
+        const bool found = march_volume(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell);
+#endif
+        if (found) {
             best_t = ts;
             best_id = V.id;
             best_vol = cptr(L.lists)[li];
             best_cell[0] = cell[0]; best_cell[1] = cell[1]; best_cell[2] = cell[2];
         }
     }
+    if (j != 0) return;   // the group's first lane writes the pixel
     if (best_vol >= 0) {
         const DevVolume V = cptr(L.vols)[best_vol];
         float x[3], n[3];
@@ -905,7 +1045,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
 int launch_raycast(const RaycastLaunch& L, int blocks, void* stream)
 {
     if (blocks <= 0) return 0;
-    hipLaunchKernelGGL(mvf_raycast_kernel, dim3(blocks), dim3(L.tile_w * L.tile_h), 0,
+    hipLaunchKernelGGL(mvf_raycast_kernel, dim3(blocks), dim3(L.tile_w * L.tile_h * kRayLanes), 0,
                        (hipStream_t)stream, L);
     return (int)hipGetLastError();
 }

@@ -740,7 +740,7 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
     if (multi) CHECK_ST(get_scratch(c, sid, out->width, out->height, true, &sc));
     RayParams rp{};
     if (!c->grids.empty()) rp = ray_params(c, c->grids[ids.empty() ? 0 : c->vols[ids[0]].d.grid_id]);
-    const int tw = 8, th = 8;  // one wavefront per block: free slots refill per wave
+    const int tw = kRayTileW, th = kRayTileH;  // one wavefront per block: free slots refill per wave
     const int tiles = ((out->width + tw - 1) / tw) * ((out->height + th - 1) / th);
     for (size_t wi = 0; wi < waves.size(); ++wi) {
         auto& wave = waves[wi];
@@ -1337,7 +1337,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         for (int i = 0; i < n; ++i)
             if (G.out_w[i] != outs[i].width || G.out_h[i] != outs[i].height) same_shape = false;
     }
-    const int tw = 8, th = 8;  // one wavefront per block: free slots refill per wave
+    const int tw = kRayTileW, th = kRayTileH;  // one wavefront per block: free slots refill per wave
     if (!same_shape) {
         CHECK_ST(destroy_step_graph(c));
         G.n = n;
