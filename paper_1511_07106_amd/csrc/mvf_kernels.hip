@@ -186,7 +186,8 @@ static __device__ __forceinline__ void clip_halfline(float a, float b, float& zl
     }
 }
 
-__global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
+// eight wavefronts per SIMD: the kernel is latency-bound, and its state fits 64 VGPRs
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void mvf_integrate_kernel(IntegrateLaunch L)
 {
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -284,16 +285,6 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
             struct ZRow { float v[3 * kBrick]; };
             const ZRow zr = *(CPTR(ZRow))(ztab + 3 * (V.zt_base + zb));
             const int nz_here = min(kBrick, V.dims[2] - zb);
-            // phase 0: start reading the column's 8 voxels of this brick (the
-            // padded brick always exists) so HBM latency overlaps the
-            // projection arithmetic
-            float Fo[kBrick];
-            uint16_t Wo[kBrick];
-#pragma unroll
-            for (int zz = 0; zz < kBrick; ++zz) {
-                Fo[zz] = __builtin_nontemporal_load(&pF[zz * 64]);
-                Wo[zz] = __builtin_nontemporal_load(&pW[zz * 64]);
-            }
             // phase 1: camera-frame position and nearest pixel of 8 voxels.
             // The pixel coordinates are clamped into the image (a NaN goes
             // to 0); the voxel projects into the image iff clamping left them
@@ -347,7 +338,19 @@ __global__ __launch_bounds__(256) void mvf_integrate_kernel(IntegrateLaunch L)
                 any_band |= bandv[zz];
             }
             if (__ballot(any_upd) == 0) continue;
-            // phase 3: running average (value path) and weights
+            // phase 3: running average (value path) and weights; F and W are
+            // read only in the lanes that update them
+            float Fo[kBrick];
+            uint16_t Wo[kBrick];
+#pragma unroll
+            for (int zz = 0; zz < kBrick; ++zz) {
+                Fo[zz] = 0.0f;
+                Wo[zz] = 0;
+                if (updv[zz]) {
+                    Fo[zz] = __builtin_nontemporal_load(&pF[zz * 64]);
+                    Wo[zz] = __builtin_nontemporal_load(&pW[zz * 64]);
+                }
+            }
             bool flag_here = false;
             bool fz[kBrick / 2] = {false, false, false, false};
 #pragma unroll
