@@ -1478,6 +1478,9 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         int e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
         IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab};
         int e2 = e1 ? e1 : launch_ztable(IL, cs);
+        // one wavefront per work item of the captured volume set (a larger
+        // set later is walked by the kernel's grid-stride loop)
+        G.integ_blocks = std::max(c->n_cus * 8, (items + 3) / 4);
         if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
         if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs);
         RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th};
