@@ -154,7 +154,9 @@ struct RaycastLaunch {
     const int32_t* lists;       // concatenated per-stream lists of table indices, nearest first
     const int32_t* list_base;   // per stream: [list_base[s], list_base[s+1])
     const int32_t* tile_base;   // per stream: first pixel tile; nstreams + 1 entries
-    int32_t tile_w, tile_h;     // pixel tile (tile_w * tile_h == block size)
+    int32_t tile_w, tile_h;     // pixel tile (tile_w * tile_h * kRayLanes == block size)
+    uint32_t* tile_cost;        // per tile: its duration in the last launch (10 ns ticks), or null
+    const int32_t* tile_order;  // tiles in launch order, or null (tile index order)
 };
 
 // Host-side launchers (defined in mvf_kernels.hip).  All return hipError_t
@@ -167,6 +169,9 @@ int launch_ztable(const IntegrateLaunch& L, void* stream);
 // grid smaller than total_items / 4 walks the items.
 int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream);
 int launch_raycast(const RaycastLaunch& L, int blocks, void* stream);
+// Launch order of n raycast tiles from their last durations, longest first
+// (a slow tile started late bounds the launch).
+int launch_tile_order(const uint32_t* cost, int32_t* order, int n, void* stream);
 int launch_brick_summary(DevVolume v, void* stream);
 // Brick distance transform of every volume in the table (3 passes).
 // brick_base: nvol + 1 prefix sums of the volumes' brick counts.

@@ -948,16 +948,12 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
 __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
 {
     const LaunchHeader H = *cptr(L.hdr);
-    // XCD-aware order: hardware deals blocks round-robin over 8 XCDs; give
-    // each XCD a contiguous run of tiles, then each block a contiguous chunk.
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int q = nb >> 3, rr = nb & 7, xcd = b & 7, j = b >> 3;
-    const int chunk = xcd * q + min(xcd, rr) + j;
-    const int per = (H.total_tiles + nb - 1) / nb;
-    const int t_begin = chunk * per;
-    const int t_end = min(t_begin + per, H.total_tiles);
-    for (int tile = t_begin; tile < t_end; ++tile) {
+    // Tiles are taken in the launch order (the slowest tiles of the last
+    // launch first, when an order is given); each block records how long
+    // its tile took.
+    for (int idx = blockIdx.x; idx < H.total_tiles; idx += gridDim.x) {
+        const unsigned long long t_tile = wall_clock64();
+        const int tile = L.tile_order ? cptr(L.tile_order)[idx] : idx;
         CPTR(int32_t) const tile_base = cptr(L.tile_base);
         int s = 0;
         while (s + 1 < H.nstreams && tile_base[s + 1] <= tile) ++s;
@@ -970,7 +966,45 @@ __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
         const int u = tx * L.tile_w + pix % L.tile_w;
         const int v = ty * L.tile_h + pix / L.tile_w;
         if (u < out_w && v < out_h) raycast_pixel(L, H, s, u, v, (int)threadIdx.x % kRayLanes);
+        if (L.tile_cost && threadIdx.x == 0) {
+            const unsigned long long d = wall_clock64() - t_tile;
+            L.tile_cost[tile] = d < 0xffffffffull ? (uint32_t)d : 0xffffffffu;
+        }
     }
+}
+
+// Launch order of the raycast tiles: counting sort of their last durations
+// by octave (log2 of the tick count), longest first.  One block.
+__global__ __launch_bounds__(1024) void mvf_tile_order_kernel(const uint32_t* cost, int32_t* order, int n)
+{
+    __shared__ int hist[33];
+    if (threadIdx.x < 33) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const uint32_t c = cost[t];
+        atomicAdd(&hist[c ? 32 - __clz(c) : 0], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int b = 32; b >= 0; --b) {
+            const int h = hist[b];
+            hist[b] = acc;
+            acc += h;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const uint32_t c = cost[t];
+        order[atomicAdd(&hist[c ? 32 - __clz(c) : 0], 1)] = t;
+    }
+}
+
+int launch_tile_order(const uint32_t* cost, int32_t* order, int n, void* stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(mvf_tile_order_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, cost, order, n);
+    return (int)hipGetLastError();
 }
 
 static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v,

@@ -97,6 +97,9 @@ struct Scratch {
     int32_t* best_id = nullptr;
     float* ztab = nullptr;  // integration z table (3 floats per entry)
     int ztab_cap = 0;
+    uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
+    int32_t* tile_order = nullptr;
+    int tiles_cap = 0;
 };
 
 // Ring of pinned host + device slots for per-launch tables.  A slot is
@@ -147,6 +150,8 @@ struct StepGraph {
     int integ_blocks = 0, ray_blocks = 0;
     float* ztab = nullptr;  // integration z table read by the captured launch
     int ztab_cap = 0;
+    uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
+    int32_t* tile_order = nullptr;
 };
 
 }  // namespace
@@ -184,6 +189,8 @@ struct mvf_ctx {
     size_t diff_summary_n = 0;        // nbricks it holds
     StepGraph step;
     hipStream_t capture_stream = nullptr;
+    hipStream_t capture_side = nullptr;  // second branch of the captured step
+    hipEvent_t cap_fork = nullptr, cap_join = nullptr;
 };
 
 namespace {
@@ -550,6 +557,28 @@ mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratc
     return MVF_OK;
 }
 
+// Per-tile raycast cost and launch-order buffers of n tiles.  The costs
+// start at zero; any content still gives a valid order (a permutation), the
+// order only decides which tiles start first.
+mvf_status alloc_tile_buffers(int n, uint32_t** cost, int32_t** order)
+{
+    CHECK_HIP(hipMalloc((void**)cost, (size_t)n * sizeof(uint32_t)));
+    CHECK_HIP(hipMalloc((void**)order, (size_t)n * sizeof(int32_t)));
+    CHECK_HIP(hipMemset(*cost, 0, (size_t)n * sizeof(uint32_t)));
+    return MVF_OK;
+}
+
+mvf_status get_tile_buffers(Scratch* s, int n)
+{
+    if (n <= s->tiles_cap) return MVF_OK;
+    if (s->tile_cost) { CHECK_HIP(hipFree(s->tile_cost)); s->tile_cost = nullptr; }
+    if (s->tile_order) { CHECK_HIP(hipFree(s->tile_order)); s->tile_order = nullptr; }
+    s->tiles_cap = 0;
+    CHECK_ST(alloc_tile_buffers(n, &s->tile_cost, &s->tile_order));
+    s->tiles_cap = n;
+    return MVF_OK;
+}
+
 mvf_status check_frame(const mvf_frame* f)
 {
     if (!f || !f->depth) return set_error(MVF_ERR_INVALID_ARG, "frame or frame->depth is NULL");
@@ -737,11 +766,12 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
     if (waves.empty()) waves.push_back({});
     const bool multi = waves.size() > 1;
     Scratch* sc = nullptr;
-    if (multi) CHECK_ST(get_scratch(c, sid, out->width, out->height, true, &sc));
+    CHECK_ST(get_scratch(c, sid, out->width, out->height, multi, &sc));
     RayParams rp{};
     if (!c->grids.empty()) rp = ray_params(c, c->grids[ids.empty() ? 0 : c->vols[ids[0]].d.grid_id]);
     const int tw = kRayTileW, th = kRayTileH;  // one wavefront per block: free slots refill per wave
     const int tiles = ((out->width + tw - 1) / tw) * ((out->height + th - 1) / th);
+    CHECK_ST(get_tile_buffers(sc, tiles));
     for (size_t wi = 0; wi < waves.size(); ++wi) {
         auto& wave = waves[wi];
         CHECK_ST(ensure_resident(c, wave, stream));
@@ -788,9 +818,11 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
         h->first_wave = wi == 0 ? 1 : 0;
         h->rp = rp;
         CHECK_ST(arena_upload(c, w, stream));
-        RaycastLaunch L{dh, dvols, dfr, dlists, dlb, dtb, tw, th};
+        // slowest tiles of the stream's last raycast first
+        RaycastLaunch L{dh, dvols, dfr, dlists, dlb, dtb, tw, th, sc->tile_cost, sc->tile_order};
         hipEvent_t t0;
         CHECK_ST(timing_begin(c, stream, &t0));
+        CHECK_LAUNCH(launch_tile_order(sc->tile_cost, sc->tile_order, tiles, stream));
         CHECK_LAUNCH(launch_raycast(L, tiles, stream));
         CHECK_ST(timing_end(c, stream, t0, 1));
         CHECK_ST(arena_release(c, slot, stream));
@@ -817,6 +849,8 @@ mvf_status destroy_step_graph(mvf_ctx* c)
     if (g.graph) { CHECK_HIP(hipGraphDestroy(g.graph)); g.graph = nullptr; }
     if (g.dev) { CHECK_HIP(hipFree(g.dev)); g.dev = nullptr; }
     if (g.ztab) { CHECK_HIP(hipFree(g.ztab)); g.ztab = nullptr; }
+    if (g.tile_cost) { CHECK_HIP(hipFree(g.tile_cost)); g.tile_cost = nullptr; }
+    if (g.tile_order) { CHECK_HIP(hipFree(g.tile_order)); g.tile_order = nullptr; }
     g.ztab_cap = 0;
     g.valid = false;
     return MVF_OK;
@@ -879,6 +913,9 @@ mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg)
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->capture_side, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->cap_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->cap_join, hipEventDisableTiming)) != hipSuccess ||
         (e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
         (e = hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
         (e = hipHostMalloc((void**)&c->arena.host, Arena::kSlots * Arena::kSlotBytes, hipHostMallocDefault)) != hipSuccess ||
@@ -915,6 +952,8 @@ mvf_status mvf_destroy(mvf_ctx* c)
         if (s.color) (void)hipFree(s.color);
         if (s.rmax) (void)hipFree(s.rmax);
         if (s.ztab) (void)hipFree(s.ztab);
+        if (s.tile_cost) (void)hipFree(s.tile_cost);
+        if (s.tile_order) (void)hipFree(s.tile_order);
         if (s.best_t) (void)hipFree(s.best_t);
         if (s.best_id) (void)hipFree(s.best_id);
     }
@@ -936,6 +975,9 @@ mvf_status mvf_destroy(mvf_ctx* c)
     if (c->tail) (void)hipEventDestroy(c->tail);
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->capture_side) (void)hipStreamDestroy(c->capture_side);
+    if (c->cap_fork) (void)hipEventDestroy(c->cap_fork);
+    if (c->cap_join) (void)hipEventDestroy(c->cap_join);
     delete c;
     return MVF_OK;
 }
@@ -1370,6 +1412,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         int tiles = 0;
         for (int i = 0; i < n; ++i) tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
         G.ray_blocks = tiles;
+        CHECK_ST(alloc_tile_buffers(tiles, &G.tile_cost, &G.tile_order));
     }
     // scratch per stream
     std::vector<Scratch*> sc(n);
@@ -1475,7 +1518,14 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         const int32_t* dtb = reinterpret_cast<const int32_t*>(G.dev + G.off_tbase);
         const int32_t* dbb = reinterpret_cast<const int32_t*>(G.dev + G.off_bbase);
         CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        int e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
+        // side branch: the raycast's tile order (slowest tiles of the last
+        // step first), computed while the frames are integrated
+        hipStream_t side = c->capture_side;
+        int e1 = (int)hipEventRecord(c->cap_fork, cs);
+        if (!e1) e1 = (int)hipStreamWaitEvent(side, c->cap_fork, 0);
+        if (!e1) e1 = launch_tile_order(G.tile_cost, G.tile_order, G.ray_blocks, side);
+        if (!e1) e1 = (int)hipEventRecord(c->cap_join, side);
+        if (!e1) e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
         IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab};
         int e2 = e1 ? e1 : launch_ztable(IL, cs);
         // one wavefront per work item of the captured volume set (a larger
@@ -1483,7 +1533,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         G.integ_blocks = std::max(c->n_cus * 8, (items + 3) / 4);
         if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
         if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs);
-        RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th};
+        RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th, G.tile_cost, G.tile_order};
+        if (!e2) e2 = (int)hipStreamWaitEvent(cs, c->cap_join, 0);
         int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
         hipError_t ee = hipStreamEndCapture(cs, &G.graph);
         if (e3) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString((hipError_t)e3));
