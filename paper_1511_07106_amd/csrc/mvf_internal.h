@@ -72,6 +72,8 @@ struct DevFrame {
     const uint32_t* color;   // H*W packed RGB (may be null)
     float* rmax;             // [0]: max range of the frame (for clipping); [1 + b]: per prep block
     int32_t rmax_parts;      // prep blocks of this frame (ceil(width / 32) * ceil(height / 8))
+    const float* tmax;       // maximum range of each 8x8 pixel tile (row-major), or null
+    int32_t tiles_x, tiles_y;
     int32_t width, height;
     float fx, fy, cx, cy;
     float T[12];
@@ -121,6 +123,7 @@ struct PrepItem {
     float* range;
     uint32_t* color;
     float* rmax;             // [0] frame's maximum range, [1 + b] maximum of prep block b
+    float* tmax;             // maximum range of each 8x8 pixel tile, ceil(width / 8) per row
 };
 
 // Integration work item: a brick column (8x8 voxel columns) of one volume
@@ -139,7 +142,12 @@ struct IntegrateLaunch {
     const int32_t* item_base;  // nvol + 1 prefix sums
     unsigned long long* counters;
     float* ztab;
+    // per item, kVisitPerItem bytes: byte j is 1 if brick bz0 + j of the
+    // item may hold a voxel the frame updates (written by the z-table
+    // launch), or null (visit all); needs zchunk <= kVisitPerItem
+    uint8_t* visit;
 };
+constexpr int kVisitPerItem = 4;
 
 // Lanes that march one ray together in the raycast kernel (P consecutive
 // samples per round of gathers), and the pixel tile of a 64-lane block.
@@ -163,8 +171,10 @@ struct RaycastLaunch {
 // as int (0 = success).
 int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream);
 int launch_volume_init(DevVolume v, void* stream);
-// The z table of a launch (must precede launch_integrate on the stream).
-int launch_ztable(const IntegrateLaunch& L, void* stream);
+// The z table of a launch and, when L.visit is set, the items' brick visit
+// masks (cull_blocks blocks of 256 threads walk the items); must precede
+// launch_integrate on the stream.
+int launch_ztable(const IntegrateLaunch& L, int cull_blocks, void* stream);
 // Integration kernel: blocks of 256 threads, 4 items in flight per block; a
 // grid smaller than total_items / 4 walks the items.
 int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream);

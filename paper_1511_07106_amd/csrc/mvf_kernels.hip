@@ -85,17 +85,31 @@ __global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __r
     }
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         it.range[(size_t)it.width * it.height] = 0.0f;
+    // maxima of the block's four 8x8 tiles: a wavefront holds two rows of
+    // 32 pixels, a tile's part of it is 8 consecutive lanes in each half
+    float tm = R;
+    for (int o = 1; o <= 4; o <<= 1) tm = fmaxf(tm, __shfl_xor(tm, o));
+    tm = fmaxf(tm, __shfl_xor(tm, 32));
     // block maximum into this block's slot; the z-table kernel reduces the
     // slots (no atomics on one address)
-    float m = R;
-    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    float m = tm;
+    for (int o = 8; o <= 16; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
     __shared__ float wmax[4];
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __shared__ float tw[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) wmax[wv] = m;
+    if (lane < 32 && (lane & 7) == 0) tw[wv][lane >> 3] = tm;
     __syncthreads();
     const int gx = (it.width + 31) / 32, gy = (it.height + 7) / 8;
     if (threadIdx.x == 0 && (int)blockIdx.x < gx && (int)blockIdx.y < gy) {
         m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
         it.rmax[1 + blockIdx.y * gx + blockIdx.x] = m;
+    }
+    const int tiles_x = (it.width + 7) / 8;
+    const int tx = (int)blockIdx.x * 4 + (int)threadIdx.x;
+    if (it.tmax && threadIdx.x < 4 && tx < tiles_x && (int)blockIdx.y < gy) {
+        const int t = threadIdx.x;
+        it.tmax[blockIdx.y * tiles_x + tx] = fmaxf(fmaxf(tw[0][t], tw[1][t]), fmaxf(tw[2][t], tw[3][t]));
     }
 }
 
@@ -217,6 +231,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
         const int bxi = col - byi * V.bd[0];
         const int bz0 = zc * zchunk;
         const int bz1 = min(bz0 + zchunk, V.bd[2]);
+        // bricks of the item that may hold an updated voxel
+        const uint32_t vis = L.visit ? cptr((const uint32_t*)L.visit)[item] : 0x01010101u;
+        if (vis == 0) continue;
 
         // frame parameters, held in registers for the whole item
         CPTR(DevFrame) const Fp = cptr(L.frames) + V.frame;
@@ -277,7 +294,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
         for (int bz = bz0; bz < bz1; ++bz) {
             const int zb = bz * kBrick;
             const bool mine = zlo < zb + kBrick && zhi > zb;
-            if (__ballot(mine) == 0) continue;
+            if (!((vis >> (8 * (bz - bz0))) & 1u) || __ballot(mine) == 0) continue;
             const size_t base = colbase + (size_t)bz * kBrickVox;
             GPTR(float) const pF = vF + base;
             GPTR(uint16_t) const pW = vW + base;
@@ -435,14 +452,106 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
     }
 }
 
-// z table of every volume of the launch (see IntegrateLaunch), and each
-// frame's maximum range from the frame-preparation block maxima.
-__global__ __launch_bounds__(256) void mvf_ztable_kernel(const LaunchHeader* hdr, const DevVolume* vols,
-                                                         const DevFrame* frames, float* ztab)
+// Whether brick [lo, hi] (the box of its voxel centres, world frame) may
+// hold a voxel that the frame updates.  It may not when it projects outside
+// the image, when the pixels it projects to hold no measurement, or when
+// every voxel centre lies farther from the camera than mu beyond the
+// largest range of those pixels (then R - rho < -mu for each voxel).  The
+// pixels are bounded by the 8x8 tiles under the projected box grown by one
+// pixel (at most 4x4 tiles are read; a larger footprint is visited);
+// margins of 1e-4 m plus 1e-5 of the distance cover the binary32 rounding
+// of the voxel test.  Anything else is visited.
+static __device__ bool brick_may_update(const DevVolume& V, const DevFrame& Fr, const float lo[3], const float hi[3])
 {
-    const int total = hdr->total_z;
+    const float c[3] = {Fr.T[3], Fr.T[7], Fr.T[11]};
+    float d2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float e = fmaxf(fmaxf(lo[a] - c[a], c[a] - hi[a]), 0.0f);
+        d2 += e * e;
+    }
+    const float dmin = sqrtf(d2) * (1.0f - 1e-5f) - 1e-4f;
+    if (!(dmin > V.mu)) return true;
+    float u0 = INFINITY, u1 = -INFINITY, v0 = INFINITY, v1 = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float dx = ((k & 1) ? hi[0] : lo[0]) - c[0];
+        const float dy = ((k & 2) ? hi[1] : lo[1]) - c[1];
+        const float dz = ((k & 4) ? hi[2] : lo[2]) - c[2];
+        const float px = Fr.T[0] * dx + Fr.T[4] * dy + Fr.T[8] * dz;
+        const float py = Fr.T[1] * dx + Fr.T[5] * dy + Fr.T[9] * dz;
+        const float pz = Fr.T[2] * dx + Fr.T[6] * dy + Fr.T[10] * dz;
+        if (!(pz > 0.01f)) return true;
+        const float iz = __builtin_amdgcn_rcpf(pz);  // relative error 2^-22: far inside the margin
+        const float u = Fr.fx * px * iz + Fr.cx;
+        const float v = Fr.fy * py * iz + Fr.cy;
+        u0 = fminf(u0, u); u1 = fmaxf(u1, u);
+        v0 = fminf(v0, v); v1 = fmaxf(v1, v);
+    }
+    const float a0 = fmaxf(floorf(u0 - 0.5f), 0.0f), a1 = fminf(floorf(u1 + 1.5f), (float)(Fr.width - 1));
+    const float b0 = fmaxf(floorf(v0 - 0.5f), 0.0f), b1 = fminf(floorf(v1 + 1.5f), (float)(Fr.height - 1));
+    if (!(a0 <= a1 && b0 <= b1)) return false;  // outside the image
+    const int ta0 = (int)a0 >> 3, tb0 = (int)b0 >> 3;
+    const int nx = ((int)a1 >> 3) - ta0 + 1, ny = ((int)b1 >> 3) - tb0 + 1;
+    if (nx > 4 || ny > 4) return true;
+    float mR = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if ((k & 3) < nx && (k >> 2) < ny) mR = fmaxf(mR, Fr.tmax[(tb0 + (k >> 2)) * Fr.tiles_x + ta0 + (k & 3)]);
+    if (mR == 0.0f) return false;  // no measurement under the brick
+    return !(dmin > mR + V.mu);
+}
+
+// Blocks [0, kZtBlocks): the z table of every volume of the launch (see
+// IntegrateLaunch) and each frame's maximum range from the frame-preparation
+// block maxima.  Blocks beyond: the items' brick visit masks.
+constexpr int kZtBlocks = 16;
+
+__global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
+{
+    const LaunchHeader* hdr = L.hdr;
+    const DevVolume* vols = L.vols;
+    const DevFrame* frames = L.frames;
     const int nvol = hdr->nvol;
-    for (int f = blockIdx.x; f < hdr->nstreams; f += gridDim.x) {
+    if (blockIdx.x >= kZtBlocks) {
+        // one thread per brick of an item (kVisitPerItem per item)
+        const int total = hdr->total_items * kVisitPerItem;
+        const int zchunk = hdr->zchunk;
+        const int stride = (gridDim.x - kZtBlocks) * blockDim.x;
+        for (int t = (blockIdx.x - kZtBlocks) * blockDim.x + threadIdx.x; t < total; t += stride) {
+            const int item = t / kVisitPerItem, j = t - item * kVisitPerItem;
+            int lo = 0, hi = nvol - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.item_base[mid] <= item) lo = mid; else hi = mid - 1;
+            }
+            const DevVolume& V = vols[lo];
+            const DevFrame& Fr = frames[V.frame];
+            const int local = item - L.item_base[lo];
+            const int ncols = V.bd[0] * V.bd[1];
+            const int zc = local / ncols;
+            const int col = local - zc * ncols;
+            const int byi = col / V.bd[0];
+            const int bxi = col - byi * V.bd[0];
+            const int bz = zc * zchunk + j;
+            bool visit = j < zchunk && bz < V.bd[2];
+            if (visit && Fr.tmax) {
+                const int i0[3] = {bxi * kBrick, byi * kBrick, bz * kBrick};
+                float blo[3], bhi[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int i1 = min(i0[a] + kBrick - 1, V.dims[a] - 1);
+                    blo[a] = V.o[a] + (V.s * ((float)(V.off[a] + i0[a]) + 0.5f));
+                    bhi[a] = V.o[a] + (V.s * ((float)(V.off[a] + i1) + 0.5f));
+                }
+                visit = brick_may_update(V, Fr, blo, bhi);
+            }
+            L.visit[t] = visit ? 1 : 0;
+        }
+        return;
+    }
+    const int total = hdr->total_z;
+    for (int f = blockIdx.x; f < hdr->nstreams; f += kZtBlocks) {
         float* rm = frames[f].rmax;
         if (!rm) continue;
         const int np = frames[f].rmax_parts;
@@ -455,7 +564,7 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(const LaunchHeader* hdr
         if (threadIdx.x == 0) rm[0] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
         __syncthreads();
     }
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += kZtBlocks * blockDim.x) {
         int lo = 0, hi = nvol - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -466,16 +575,16 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(const LaunchHeader* hdr
         const int z = i - V.zt_base;
         const float xw_z = V.o[2] + (V.s * ((float)(V.off[2] + z) + 0.5f));
         const float dz = xw_z - Fr.T[11];
-        ztab[3 * i] = Fr.T[8] * dz;
-        ztab[3 * i + 1] = Fr.T[9] * dz;
-        ztab[3 * i + 2] = Fr.T[10] * dz;
+        L.ztab[3 * i] = Fr.T[8] * dz;
+        L.ztab[3 * i + 1] = Fr.T[9] * dz;
+        L.ztab[3 * i + 2] = Fr.T[10] * dz;
     }
 }
 
-int launch_ztable(const IntegrateLaunch& L, void* stream)
+int launch_ztable(const IntegrateLaunch& L, int cull_blocks, void* stream)
 {
-    hipLaunchKernelGGL(mvf_ztable_kernel, dim3(16), dim3(256), 0, (hipStream_t)stream, L.hdr, L.vols, L.frames,
-                       L.ztab);
+    const int blocks = kZtBlocks + (L.visit ? (cull_blocks > 1 ? cull_blocks : 1) : 0);
+    hipLaunchKernelGGL(mvf_ztable_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, L);
     return (int)hipGetLastError();
 }
 

@@ -97,6 +97,10 @@ struct Scratch {
     int32_t* best_id = nullptr;
     float* ztab = nullptr;  // integration z table (3 floats per entry)
     int ztab_cap = 0;
+    float* tmax = nullptr;   // maximum range per 8x8 pixel tile
+    int tmax_cap = 0;
+    uint8_t* visit = nullptr;  // integration: brick visit mask per item
+    int visit_cap = 0;
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
     int32_t* tile_order = nullptr;
     int tiles_cap = 0;
@@ -150,6 +154,8 @@ struct StepGraph {
     int integ_blocks = 0, ray_blocks = 0;
     float* ztab = nullptr;  // integration z table read by the captured launch
     int ztab_cap = 0;
+    uint8_t* visit = nullptr;  // brick visit mask per integration item
+    int visit_cap = 0;
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
     int32_t* tile_order = nullptr;
 };
@@ -537,6 +543,12 @@ mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratc
         CHECK_HIP(hipMalloc((void**)&s.rmax, (size_t)(1 + parts) * sizeof(float)));
         s.rmax_cap = 1 + parts;
     }
+    const int ntiles = ((w + 7) / 8) * ((h + 7) / 8);
+    if (ntiles > s.tmax_cap) {
+        if (s.tmax) { CHECK_HIP(hipFree(s.tmax)); s.tmax = nullptr; }
+        CHECK_HIP(hipMalloc((void**)&s.tmax, (size_t)ntiles * sizeof(float)));
+        s.tmax_cap = ntiles;
+    }
     if (w * h > s.w * s.h || !s.range) {
         if (s.range) { CHECK_HIP(hipFree(s.range)); s.range = nullptr; }
         if (s.color) { CHECK_HIP(hipFree(s.color)); s.color = nullptr; }
@@ -626,7 +638,10 @@ mvf_status drain_timing(mvf_ctx* c)
     return MVF_OK;
 }
 
-int zchunk_for(const Volume&) { return 4; }
+// bricks per integration item along z (the visit masks hold one byte per brick)
+constexpr int kZChunk = 4;
+static_assert(kZChunk <= kVisitPerItem, "visit mask too small for the z chunk");
+int zchunk_for(const Volume&) { return kZChunk; }
 
 void fill_frame(DevFrame* f, const Scratch* s, int w, int h, const float* T, const mvf_intrinsics& K)
 {
@@ -636,6 +651,9 @@ void fill_frame(DevFrame* f, const Scratch* s, int w, int h, const float* T, con
         f->color = s->color;
         f->rmax = s->rmax;
         f->rmax_parts = ((w + 31) / 32) * ((h + 7) / 8);
+        f->tmax = s->tmax;
+        f->tiles_x = (w + 7) / 8;
+        f->tiles_y = (h + 7) / 8;
     }
     f->width = w;
     f->height = h;
@@ -680,6 +698,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
     prep->range = sc->range;
     prep->color = sc->color;
     prep->rmax = sc->rmax;
+    prep->tmax = sc->tmax;
     fill_frame(frame, sc, f->width, f->height, T, K);
     if (!f->rgb) frame->color = nullptr;
     // per-volume tables are filled after residency is known (slab pointers)
@@ -700,6 +719,20 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         }
         CHECK_HIP(hipMalloc((void**)&sc->ztab, (size_t)zmax * 3 * sizeof(float)));
         sc->ztab_cap = zmax;
+    }
+    int max_items = 0;
+    for (int id : ids) {
+        const Volume& v = c->vols[id];
+        max_items = std::max(max_items, v.bd[0] * v.bd[1] * ((v.bd[2] + zchunk_for(v) - 1) / zchunk_for(v)));
+    }
+    if (max_items > sc->visit_cap) {
+        if (sc->visit) {
+            CHECK_HIP(hipStreamSynchronize(stream));
+            CHECK_HIP(hipFree(sc->visit));
+            sc->visit = nullptr;
+        }
+        CHECK_HIP(hipMalloc((void**)&sc->visit, (size_t)max_items * kVisitPerItem));
+        sc->visit_cap = max_items;
     }
     for (auto& wave : waves) {
         CHECK_ST(ensure_resident(c, wave, stream));
@@ -740,8 +773,8 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         }
         CHECK_ST(arena_upload(c, w2, stream));
         for (auto& p : per) {
-            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab};
-            CHECK_LAUNCH(launch_ztable(L, stream));
+            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit};
+            CHECK_LAUNCH(launch_ztable(L, (p.items * kVisitPerItem + 255) / 256, stream));
             hipEvent_t t0;
             CHECK_ST(timing_begin(c, stream, &t0));
             CHECK_LAUNCH(launch_integrate(L, (p.items + 3) / 4, stream));
@@ -849,6 +882,8 @@ mvf_status destroy_step_graph(mvf_ctx* c)
     if (g.graph) { CHECK_HIP(hipGraphDestroy(g.graph)); g.graph = nullptr; }
     if (g.dev) { CHECK_HIP(hipFree(g.dev)); g.dev = nullptr; }
     if (g.ztab) { CHECK_HIP(hipFree(g.ztab)); g.ztab = nullptr; }
+    if (g.visit) { CHECK_HIP(hipFree(g.visit)); g.visit = nullptr; }
+    g.visit_cap = 0;
     if (g.tile_cost) { CHECK_HIP(hipFree(g.tile_cost)); g.tile_cost = nullptr; }
     if (g.tile_order) { CHECK_HIP(hipFree(g.tile_order)); g.tile_order = nullptr; }
     g.ztab_cap = 0;
@@ -952,6 +987,8 @@ mvf_status mvf_destroy(mvf_ctx* c)
         if (s.color) (void)hipFree(s.color);
         if (s.rmax) (void)hipFree(s.rmax);
         if (s.ztab) (void)hipFree(s.ztab);
+        if (s.tmax) (void)hipFree(s.tmax);
+        if (s.visit) (void)hipFree(s.visit);
         if (s.tile_cost) (void)hipFree(s.tile_cost);
         if (s.tile_order) (void)hipFree(s.tile_order);
         if (s.best_t) (void)hipFree(s.best_t);
@@ -1371,10 +1408,14 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         max_w = std::max(max_w, frames[i].frame.width);
         max_h = std::max(max_h, frames[i].frame.height);
     }
-    int ztotal = 0;
-    for (int id : all) ztotal += kBrick * c->vols[id].bd[2];
+    int ztotal = 0, items_total = 0;
+    for (int id : all) {
+        const Volume& v = c->vols[id];
+        ztotal += kBrick * v.bd[2];
+        items_total += v.bd[0] * v.bd[1] * ((v.bd[2] + kZChunk - 1) / kZChunk);
+    }
     bool same_shape = G.valid && G.n == n && (int)all.size() <= G.max_vols && max_w <= G.max_w && max_h <= G.max_h &&
-                      ztotal <= G.ztab_cap;
+                      ztotal <= G.ztab_cap && items_total <= G.visit_cap;
     if (same_shape) {
         for (int i = 0; i < n; ++i)
             if (G.out_w[i] != outs[i].width || G.out_h[i] != outs[i].height) same_shape = false;
@@ -1408,6 +1449,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         CHECK_HIP(hipMalloc((void**)&G.dev, G.dev_bytes));
         G.ztab_cap = std::max(ztotal * 2, 1024);
         CHECK_HIP(hipMalloc((void**)&G.ztab, (size_t)G.ztab_cap * 3 * sizeof(float)));
+        G.visit_cap = std::max(items_total * 2, 1024);
+        CHECK_HIP(hipMalloc((void**)&G.visit, (size_t)G.visit_cap * kVisitPerItem));
         G.integ_blocks = c->n_cus * 8;
         int tiles = 0;
         for (int i = 0; i < n; ++i) tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
@@ -1440,7 +1483,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     int items = 0;
     int zt = 0;
     int tiles = 0;
-    const int zc = 4;
+    const int zc = kZChunk;
     lb[0] = 0;
     tb[0] = 0;
     for (int i = 0; i < n; ++i) {
@@ -1456,6 +1499,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         p.range = sc[i]->range;
         p.color = sc[i]->color;
         p.rmax = sc[i]->rmax;
+        p.tmax = sc[i]->tmax;
         fill_frame(&dfr[i], sc[i], fr.frame.width, fr.frame.height, fr.T_wc, fr.K);
         if (!fr.frame.rgb) dfr[i].color = nullptr;
         dfr[i].depth = outs[i].depth;
@@ -1526,8 +1570,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         if (!e1) e1 = launch_tile_order(G.tile_cost, G.tile_order, G.ray_blocks, side);
         if (!e1) e1 = (int)hipEventRecord(c->cap_join, side);
         if (!e1) e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
-        IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab};
-        int e2 = e1 ? e1 : launch_ztable(IL, cs);
+        IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit};
+        int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items * kVisitPerItem + 255) / 256), cs);
         // one wavefront per work item of the captured volume set (a larger
         // set later is walked by the kernel's grid-stride loop)
         G.integ_blocks = std::max(c->n_cus * 8, (items + 3) / 4);
