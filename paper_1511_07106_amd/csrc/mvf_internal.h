@@ -37,6 +37,14 @@
 #pragma once
 #include <stdint.h>
 
+#ifndef MVF_HD
+#if defined(__HIPCC__)
+#define MVF_HD __host__ __device__ __forceinline__
+#else
+#define MVF_HD inline
+#endif
+#endif
+
 namespace mvf {
 
 constexpr int kBrick = 8;
@@ -154,6 +162,14 @@ constexpr int kVisitPerItem = 4;
 constexpr int kRayLanes = 4;
 constexpr int kRayTileW = 4;
 constexpr int kRayTileH = 64 / kRayLanes / kRayTileW;
+// Raycast launch order: groups of kRayGroup consecutive tiles are ordered by
+// their summed last duration, slowest first.  Blocks are dealt round-robin
+// over the 8 XCDs, so a window of 8 * kRayGroup blocks takes 8 groups, each
+// group's tiles on one XCD (they gather the same bricks).
+constexpr int kRayGroup = 4;
+constexpr int kXcds = 8;
+MVF_HD int ray_groups(int tiles) { return (tiles + kRayGroup - 1) / kRayGroup; }
+MVF_HD int ray_blocks(int tiles) { return (ray_groups(tiles) + kXcds - 1) / kXcds * kXcds * kRayGroup; }
 
 struct RaycastLaunch {
     const LaunchHeader* hdr;
@@ -164,7 +180,7 @@ struct RaycastLaunch {
     const int32_t* tile_base;   // per stream: first pixel tile; nstreams + 1 entries
     int32_t tile_w, tile_h;     // pixel tile (tile_w * tile_h * kRayLanes == block size)
     uint32_t* tile_cost;        // per tile: its duration in the last launch (10 ns ticks), or null
-    const int32_t* tile_order;  // tiles in launch order, or null (tile index order)
+    const int32_t* tile_order;  // tile groups in launch order, or null (index order)
 };
 
 // Host-side launchers (defined in mvf_kernels.hip).  All return hipError_t
@@ -178,9 +194,10 @@ int launch_ztable(const IntegrateLaunch& L, int cull_blocks, void* stream);
 // Integration kernel: blocks of 256 threads, 4 items in flight per block; a
 // grid smaller than total_items / 4 walks the items.
 int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream);
+// Raycast kernel over ray_blocks(total tiles) blocks (or fewer: a grid-stride loop).
 int launch_raycast(const RaycastLaunch& L, int blocks, void* stream);
-// Launch order of n raycast tiles from their last durations, longest first
-// (a slow tile started late bounds the launch).
+// Launch order of the ray_groups(n) groups of n raycast tiles from their
+// last durations, longest first (a slow tile started late bounds the launch).
 int launch_tile_order(const uint32_t* cost, int32_t* order, int n, void* stream);
 int launch_brick_summary(DevVolume v, void* stream);
 // Brick distance transform of every volume in the table (3 passes).

@@ -1057,12 +1057,19 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
 __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
 {
     const LaunchHeader H = *cptr(L.hdr);
-    // Tiles are taken in the launch order (the slowest tiles of the last
-    // launch first, when an order is given); each block records how long
-    // its tile took.
-    for (int idx = blockIdx.x; idx < H.total_tiles; idx += gridDim.x) {
+    // Tile groups are taken in the launch order (the slowest groups of the
+    // last launch first, when an order is given); each block records how
+    // long its tile took.
+    const int ngroups = ray_groups(H.total_tiles);
+    const int slots = ray_blocks(H.total_tiles);
+    for (int idx = blockIdx.x; idx < slots; idx += gridDim.x) {
+        const int win = idx / (kXcds * kRayGroup), r = idx - win * (kXcds * kRayGroup);
+        const int k = win * kXcds + r % kXcds;   // position in the order
+        if (k >= ngroups) continue;
+        const int g = L.tile_order ? cptr(L.tile_order)[k] : k;
+        const int tile = g * kRayGroup + r / kXcds;
+        if (tile >= H.total_tiles) continue;
         const unsigned long long t_tile = wall_clock64();
-        const int tile = L.tile_order ? cptr(L.tile_order)[idx] : idx;
         CPTR(int32_t) const tile_base = cptr(L.tile_base);
         int s = 0;
         while (s + 1 < H.nstreams && tile_base[s + 1] <= tile) ++s;
@@ -1082,30 +1089,54 @@ __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
     }
 }
 
-// Launch order of the raycast tiles: counting sort of their last durations
-// by octave (log2 of the tick count), longest first.  One block.
-__global__ __launch_bounds__(1024) void mvf_tile_order_kernel(const uint32_t* cost, int32_t* order, int n)
+// Launch order of the raycast tile groups: counting sort of their summed
+// last durations by octave, longest first.  One block; lanes of a wavefront
+// that fall into the same octave share one LDS atomic.
+constexpr int kOrderBins = 48;
+
+__global__ __launch_bounds__(1024) void mvf_tile_order_kernel(const uint32_t* cost, int32_t* order, int ntiles)
 {
-    __shared__ int hist[33];
-    if (threadIdx.x < 33) hist[threadIdx.x] = 0;
+    __shared__ int hist[kOrderBins];
+    const int ng = ray_groups(ntiles);
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < kOrderBins) hist[threadIdx.x] = 0;
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        const uint32_t c = cost[t];
-        atomicAdd(&hist[c ? 32 - __clz(c) : 0], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int b = 32; b >= 0; --b) {
-            const int h = hist[b];
-            hist[b] = acc;
-            acc += h;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int g0 = 0; g0 < ng; g0 += blockDim.x) {
+            const int g = g0 + (int)threadIdx.x;
+            int bin = -1;
+            if (g < ng) {
+                uint64_t c = 0;
+#pragma unroll
+                for (int j = 0; j < kRayGroup; ++j)
+                    if (g * kRayGroup + j < ntiles) c += cost[g * kRayGroup + j];
+                bin = c ? min(64 - __clzll(c), kOrderBins - 1) : 0;
+            }
+            unsigned long long todo = __ballot(bin >= 0);
+            while (todo) {
+                const int leader = __ffsll(todo) - 1;
+                const int b = __shfl(bin, leader);
+                const unsigned long long m = __ballot(bin == b);
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&hist[b], (int)__popcll(m));
+                if (pass == 1) {
+                    base = __shfl(base, leader);
+                    if (bin == b) order[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = g;
+                }
+                todo &= ~m;
+            }
         }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        const uint32_t c = cost[t];
-        order[atomicAdd(&hist[c ? 32 - __clz(c) : 0], 1)] = t;
+        __syncthreads();
+        if (pass == 0 && threadIdx.x == 0) {
+            // start of each octave, longest first
+            int acc = 0;
+            for (int b = kOrderBins - 1; b >= 0; --b) {
+                const int h = hist[b];
+                hist[b] = acc;
+                acc += h;
+            }
+        }
+        __syncthreads();
     }
 }
 

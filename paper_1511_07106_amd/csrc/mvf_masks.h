@@ -5,10 +5,12 @@
 #pragma once
 #include <stdint.h>
 
+#ifndef MVF_HD
 #if defined(__HIPCC__)
 #define MVF_HD __host__ __device__ __forceinline__
 #else
 #define MVF_HD inline
+#endif
 #endif
 
 namespace mvf {

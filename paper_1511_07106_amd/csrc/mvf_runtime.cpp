@@ -151,7 +151,7 @@ struct StepGraph {
     size_t dev_bytes = 0;
     size_t off_hdr, off_prep, off_frames, off_vols, off_items, off_lists, off_lbase, off_tbase, off_bbase;
     int max_vols = 0, max_w = 0, max_h = 0;
-    int integ_blocks = 0, ray_blocks = 0;
+    int integ_blocks = 0, ray_tiles = 0, ray_blocks = 0;
     float* ztab = nullptr;  // integration z table read by the captured launch
     int ztab_cap = 0;
     uint8_t* visit = nullptr;  // brick visit mask per integration item
@@ -195,8 +195,6 @@ struct mvf_ctx {
     size_t diff_summary_n = 0;        // nbricks it holds
     StepGraph step;
     hipStream_t capture_stream = nullptr;
-    hipStream_t capture_side = nullptr;  // second branch of the captured step
-    hipEvent_t cap_fork = nullptr, cap_join = nullptr;
 };
 
 namespace {
@@ -856,7 +854,7 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
         hipEvent_t t0;
         CHECK_ST(timing_begin(c, stream, &t0));
         CHECK_LAUNCH(launch_tile_order(sc->tile_cost, sc->tile_order, tiles, stream));
-        CHECK_LAUNCH(launch_raycast(L, tiles, stream));
+        CHECK_LAUNCH(launch_raycast(L, ray_blocks(tiles), stream));
         CHECK_ST(timing_end(c, stream, t0, 1));
         CHECK_ST(arena_release(c, slot, stream));
         c->stats.raycast_launches += 1;
@@ -948,9 +946,6 @@ mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg)
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&c->capture_side, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->cap_fork, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->cap_join, hipEventDisableTiming)) != hipSuccess ||
         (e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
         (e = hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
         (e = hipHostMalloc((void**)&c->arena.host, Arena::kSlots * Arena::kSlotBytes, hipHostMallocDefault)) != hipSuccess ||
@@ -1012,9 +1007,6 @@ mvf_status mvf_destroy(mvf_ctx* c)
     if (c->tail) (void)hipEventDestroy(c->tail);
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
-    if (c->capture_side) (void)hipStreamDestroy(c->capture_side);
-    if (c->cap_fork) (void)hipEventDestroy(c->cap_fork);
-    if (c->cap_join) (void)hipEventDestroy(c->cap_join);
     delete c;
     return MVF_OK;
 }
@@ -1454,7 +1446,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         G.integ_blocks = c->n_cus * 8;
         int tiles = 0;
         for (int i = 0; i < n; ++i) tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
-        G.ray_blocks = tiles;
+        G.ray_tiles = tiles;
+        G.ray_blocks = ray_blocks(tiles);
         CHECK_ST(alloc_tile_buffers(tiles, &G.tile_cost, &G.tile_order));
     }
     // scratch per stream
@@ -1562,14 +1555,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         const int32_t* dtb = reinterpret_cast<const int32_t*>(G.dev + G.off_tbase);
         const int32_t* dbb = reinterpret_cast<const int32_t*>(G.dev + G.off_bbase);
         CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        // side branch: the raycast's tile order (slowest tiles of the last
-        // step first), computed while the frames are integrated
-        hipStream_t side = c->capture_side;
-        int e1 = (int)hipEventRecord(c->cap_fork, cs);
-        if (!e1) e1 = (int)hipStreamWaitEvent(side, c->cap_fork, 0);
-        if (!e1) e1 = launch_tile_order(G.tile_cost, G.tile_order, G.ray_blocks, side);
-        if (!e1) e1 = (int)hipEventRecord(c->cap_join, side);
-        if (!e1) e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
+        int e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
         IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit};
         int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items * kVisitPerItem + 255) / 256), cs);
         // one wavefront per work item of the captured volume set (a larger
@@ -1578,7 +1564,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
         if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs);
         RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th, G.tile_cost, G.tile_order};
-        if (!e2) e2 = (int)hipStreamWaitEvent(cs, c->cap_join, 0);
+        // slowest tile groups of the last step first
+        if (!e2) e2 = launch_tile_order(G.tile_cost, G.tile_order, G.ray_tiles, cs);
         int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
         hipError_t ee = hipStreamEndCapture(cs, &G.graph);
         if (e3) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString((hipError_t)e3));
