@@ -67,10 +67,13 @@ def render_frames(n_frames: int, total: int = 300):
     return seq, [(by[i], seq.poses[i]) for i in idx]
 
 
-def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps):
+def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=False):
+    """Wall-clock run of one phase; with timed=True the library also times
+    every kernel launch with events (a separate run: the events themselves
+    cost a few microseconds per call)."""
     origin = (-EXTENT / 2,) * 3
     s = EXTENT / N_VOX
-    ctx = mvf.Context(timing=True)
+    ctx = mvf.Context(timing=timed)
     gid = ctx.grid(origin, s, 4.0, 128)
     if phase in ("single", "single_step"):
         ctx.volume(gid, (0, 0, 0), (N_VOX,) * 3)
@@ -385,6 +388,14 @@ def main():
             phases[ph] = EXTRA_PHASES[ph](mvf, torch)
         else:
             phases[ph] = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps)
+            if ph in ("single", "tiled"):
+                # per-kernel durations from a second, event-timed run of the same frames
+                t = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps, timed=True)
+                for k in ("integrate_ms", "raycast_ms", "integrate_launches", "raycast_launches",
+                          "integrate_kernel_voxel_updates_per_s", "raycast_kernel_mpix_s"):
+                    if k in t:
+                        phases[ph][k] = t[k]
+                phases[ph]["timed_run_ms_per_step"] = t["ms_per_step"]
         log(json.dumps(phases[ph]))
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4

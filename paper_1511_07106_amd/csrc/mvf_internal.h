@@ -154,6 +154,11 @@ struct IntegrateLaunch {
     // item may hold a voxel the frame updates (written by the z-table
     // launch), or null (visit all); needs zchunk <= kVisitPerItem
     uint8_t* visit;
+    // optional: block 0 computes a raycast tile order (see launch_tile_order)
+    // from these costs instead of integrating; the grid has one more block
+    const uint32_t* tile_cost;
+    int32_t* tile_order;
+    int32_t order_tiles;
 };
 constexpr int kVisitPerItem = 4;
 
@@ -192,7 +197,8 @@ int launch_volume_init(DevVolume v, void* stream);
 // launch_integrate on the stream.
 int launch_ztable(const IntegrateLaunch& L, int cull_blocks, void* stream);
 // Integration kernel: blocks of 256 threads, 4 items in flight per block; a
-// grid smaller than total_items / 4 walks the items.
+// grid smaller than total_items / 4 walks the items (plus block 0 when
+// L.tile_order is set).
 int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream);
 // Raycast kernel over ray_blocks(total tiles) blocks (or fewer: a grid-stride loop).
 int launch_raycast(const RaycastLaunch& L, int blocks, void* stream);

@@ -153,6 +153,75 @@ int launch_volume_init(DevVolume v, void* stream)
 }
 
 // ---------------------------------------------------------------------------
+// Launch order of the raycast tile groups: counting sort of their summed
+// last durations, longest first, by half octaves (the leading two bits).
+// Run by one block of any size: each thread takes kOrderBatch groups per
+// round with all their loads in flight, and lanes of a wavefront that fall
+// into the same bin share one LDS atomic.  The cost array holds
+// ray_groups(n) * kRayGroup entries (zero past n).
+constexpr int kOrderBins = 64;
+constexpr int kOrderBatch = 4;
+
+static __device__ __forceinline__ int cost_bin(uint4 c)
+{
+    const uint64_t t = (uint64_t)c.x + c.y + c.z + c.w;
+    if (t < 2) return (int)t;
+    const int e = 63 - __clzll(t);
+    return min(2 * e + (int)((t >> (e - 1)) & 1), kOrderBins - 1);
+}
+
+static __device__ void tile_order_block(const uint32_t* __restrict__ cost, int32_t* __restrict__ order, int ntiles,
+                                        int* hist)
+{
+    static_assert(kRayGroup == 4, "one uint4 of costs per group");
+    const int ng = ray_groups(ntiles);
+    const int lane = threadIdx.x & 63;
+    const int nt = blockDim.x;
+    const uint4* c4 = reinterpret_cast<const uint4*>(cost);
+    for (int i = threadIdx.x; i < kOrderBins; i += nt) hist[i] = 0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int g0 = 0; g0 < ng; g0 += kOrderBatch * nt) {
+            uint4 c[kOrderBatch];
+#pragma unroll
+            for (int k = 0; k < kOrderBatch; ++k) {
+                const int g = g0 + k * nt + (int)threadIdx.x;
+                c[k] = g < ng ? c4[g] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < kOrderBatch; ++k) {
+                const int g = g0 + k * nt + (int)threadIdx.x;
+                const int bin = g < ng ? cost_bin(c[k]) : -1;
+                unsigned long long todo = __ballot(bin >= 0);
+                while (todo) {
+                    const int leader = __ffsll(todo) - 1;
+                    const int b = __shfl(bin, leader);
+                    const unsigned long long m = __ballot(bin == b);
+                    int base = 0;
+                    if (lane == leader) base = atomicAdd(&hist[b], (int)__popcll(m));
+                    if (pass == 1) {
+                        base = __shfl(base, leader);
+                        if (bin == b) order[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = g;
+                    }
+                    todo &= ~m;
+                }
+            }
+        }
+        __syncthreads();
+        if (pass == 0 && threadIdx.x == 0) {
+            // start of each bin, longest first
+            int acc = 0;
+            for (int b = kOrderBins - 1; b >= 0; --b) {
+                const int h = hist[b];
+                hist[b] = acc;
+                acc += h;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Integration.  One wavefront owns an 8x8 tile of voxel columns (one brick
 // column) and walks z through a chunk of bricks; each lane is one column
 // (Volumetric Integration section: one thread per (x, y), iterating z).  A
@@ -203,17 +272,25 @@ static __device__ __forceinline__ void clip_halfline(float a, float b, float& zl
 // eight wavefronts per SIMD: the kernel is latency-bound, and its state fits 64 VGPRs
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void mvf_integrate_kernel(IntegrateLaunch L)
 {
+    // with a tile order to compute (captured step), block 0 sorts the next
+    // raycast's tile groups while the others integrate
+    const int b0 = L.tile_order ? 1 : 0;
+    if ((int)blockIdx.x < b0) {
+        __shared__ int hist[kOrderBins];
+        tile_order_block(L.tile_cost, L.tile_order, L.order_tiles, hist);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
-    const int total_waves = gridDim.x * wpb;
+    const int total_waves = ((int)gridDim.x - b0) * wpb;
     unsigned n_upd = 0, n_band = 0;  // wave totals
     const int total_items = L.hdr->total_items;
     const int nvol = L.hdr->nvol;
     const int zchunk = L.hdr->zchunk;
     CPTR(float) const ztab = cptr(L.ztab);
 
-    for (int item = wave_uniform(blockIdx.x * wpb + wib); item < total_items; item += total_waves) {
+    for (int item = wave_uniform(((int)blockIdx.x - b0) * wpb + wib); item < total_items; item += total_waves) {
         // volume owning this item
         CPTR(int32_t) const item_base = cptr(L.item_base);
         int lo = 0, hi = nvol - 1;
@@ -446,7 +523,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
             su += cnt_upd[w];
             sb += cnt_band[w];
         }
-        unsigned long long* slot = L.counters + (blockIdx.x % kCntSlots) * kCntNum;
+        unsigned long long* slot = L.counters + ((blockIdx.x - b0) % kCntSlots) * kCntNum;
         if (su) atomicAdd(&slot[kCntUpdated], su);
         if (sb) atomicAdd(&slot[kCntBand], sb);
     }
@@ -1089,55 +1166,10 @@ __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
     }
 }
 
-// Launch order of the raycast tile groups: counting sort of their summed
-// last durations by octave, longest first.  One block; lanes of a wavefront
-// that fall into the same octave share one LDS atomic.
-constexpr int kOrderBins = 48;
-
 __global__ __launch_bounds__(1024) void mvf_tile_order_kernel(const uint32_t* cost, int32_t* order, int ntiles)
 {
     __shared__ int hist[kOrderBins];
-    const int ng = ray_groups(ntiles);
-    const int lane = threadIdx.x & 63;
-    if (threadIdx.x < kOrderBins) hist[threadIdx.x] = 0;
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int g0 = 0; g0 < ng; g0 += blockDim.x) {
-            const int g = g0 + (int)threadIdx.x;
-            int bin = -1;
-            if (g < ng) {
-                uint64_t c = 0;
-#pragma unroll
-                for (int j = 0; j < kRayGroup; ++j)
-                    if (g * kRayGroup + j < ntiles) c += cost[g * kRayGroup + j];
-                bin = c ? min(64 - __clzll(c), kOrderBins - 1) : 0;
-            }
-            unsigned long long todo = __ballot(bin >= 0);
-            while (todo) {
-                const int leader = __ffsll(todo) - 1;
-                const int b = __shfl(bin, leader);
-                const unsigned long long m = __ballot(bin == b);
-                int base = 0;
-                if (lane == leader) base = atomicAdd(&hist[b], (int)__popcll(m));
-                if (pass == 1) {
-                    base = __shfl(base, leader);
-                    if (bin == b) order[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = g;
-                }
-                todo &= ~m;
-            }
-        }
-        __syncthreads();
-        if (pass == 0 && threadIdx.x == 0) {
-            // start of each octave, longest first
-            int acc = 0;
-            for (int b = kOrderBins - 1; b >= 0; --b) {
-                const int h = hist[b];
-                hist[b] = acc;
-                acc += h;
-            }
-        }
-        __syncthreads();
-    }
+    tile_order_block(cost, order, ntiles, hist);
 }
 
 int launch_tile_order(const uint32_t* cost, int32_t* order, int n, void* stream)

@@ -146,6 +146,7 @@ struct StepGraph {
     std::vector<int> widths, heights, out_w, out_h;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy_node = nullptr;  // table upload (first node)
     // persistent device tables read by the captured kernels
     uint8_t* dev = nullptr;
     size_t dev_bytes = 0;
@@ -179,7 +180,8 @@ struct mvf_ctx {
     Arena arena;
     std::vector<TimedPair> timed;
     std::vector<hipEvent_t> event_pool;
-    hipEvent_t tail = nullptr;
+    hipEvent_t tail = nullptr;     // recorded by mark_tail
+    hipEvent_t tail_ev = nullptr;  // the event that marks the end of the last call (tail or an arena event)
     hipStream_t tail_stream = nullptr;
     bool tail_valid = false;
     int n_cus = 256;
@@ -206,20 +208,34 @@ mvf_status get_event(mvf_ctx* c, hipEvent_t* ev)
         c->event_pool.pop_back();
         return MVF_OK;
     }
-    CHECK_HIP(hipEventCreate(ev));
+    // pooled events order device work or time it; none makes device memory
+    // visible to the host, so they skip the system-scope fence (a cache
+    // writeback per record)
+    CHECK_HIP(hipEventCreateWithFlags(ev, hipEventDisableSystemFence));
     return MVF_OK;
 }
 
 // Make `stream` run after everything the previous call enqueued.
 mvf_status order_after_previous(mvf_ctx* c, hipStream_t stream)
 {
-    if (c->tail_valid && c->tail_stream != stream) CHECK_HIP(hipStreamWaitEvent(stream, c->tail, 0));
+    if (c->tail_valid && c->tail_stream != stream) CHECK_HIP(hipStreamWaitEvent(stream, c->tail_ev, 0));
     return MVF_OK;
 }
 
 mvf_status mark_tail(mvf_ctx* c, hipStream_t stream)
 {
     CHECK_HIP(hipEventRecord(c->tail, stream));
+    c->tail_ev = c->tail;
+    c->tail_stream = stream;
+    c->tail_valid = true;
+    return MVF_OK;
+}
+
+// mark_tail with an event just recorded on `stream` behind the call's work
+// (one event record fewer per call)
+mvf_status mark_tail_recorded(mvf_ctx* c, hipStream_t stream, hipEvent_t ev)
+{
+    c->tail_ev = ev;
     c->tail_stream = stream;
     c->tail_valid = true;
     return MVF_OK;
@@ -567,14 +583,16 @@ mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratc
     return MVF_OK;
 }
 
-// Per-tile raycast cost and launch-order buffers of n tiles.  The costs
-// start at zero; any content still gives a valid order (a permutation), the
-// order only decides which tiles start first.
+// Raycast cost per tile (padded to whole groups) and launch order per tile
+// group, for n tiles.  The costs start at zero; any content still gives a
+// valid order (a permutation), the order only decides which tiles start
+// first.
 mvf_status alloc_tile_buffers(int n, uint32_t** cost, int32_t** order)
 {
-    CHECK_HIP(hipMalloc((void**)cost, (size_t)n * sizeof(uint32_t)));
-    CHECK_HIP(hipMalloc((void**)order, (size_t)n * sizeof(int32_t)));
-    CHECK_HIP(hipMemset(*cost, 0, (size_t)n * sizeof(uint32_t)));
+    const size_t nc = (size_t)ray_groups(n) * kRayGroup;  // whole groups (the padding stays 0)
+    CHECK_HIP(hipMalloc((void**)cost, nc * sizeof(uint32_t)));
+    CHECK_HIP(hipMalloc((void**)order, (size_t)ray_groups(n) * sizeof(int32_t)));
+    CHECK_HIP(hipMemset(*cost, 0, nc * sizeof(uint32_t)));
     return MVF_OK;
 }
 
@@ -771,7 +789,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         }
         CHECK_ST(arena_upload(c, w2, stream));
         for (auto& p : per) {
-            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit};
+            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit, nullptr, nullptr, 0};
             CHECK_LAUNCH(launch_ztable(L, (p.items * kVisitPerItem + 255) / 256, stream));
             hipEvent_t t0;
             CHECK_ST(timing_begin(c, stream, &t0));
@@ -878,6 +896,7 @@ mvf_status destroy_step_graph(mvf_ctx* c)
     StepGraph& g = c->step;
     if (g.exec) { CHECK_HIP(hipGraphExecDestroy(g.exec)); g.exec = nullptr; }
     if (g.graph) { CHECK_HIP(hipGraphDestroy(g.graph)); g.graph = nullptr; }
+    g.copy_node = nullptr;
     if (g.dev) { CHECK_HIP(hipFree(g.dev)); g.dev = nullptr; }
     if (g.ztab) { CHECK_HIP(hipFree(g.ztab)); g.ztab = nullptr; }
     if (g.visit) { CHECK_HIP(hipFree(g.visit)); g.visit = nullptr; }
@@ -950,10 +969,12 @@ mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg)
         (e = hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
         (e = hipHostMalloc((void**)&c->arena.host, Arena::kSlots * Arena::kSlotBytes, hipHostMallocDefault)) != hipSuccess ||
         (e = hipMalloc((void**)&c->arena.dev, Arena::kSlots * Arena::kSlotBytes)) != hipSuccess ||
-        (e = hipEventCreate(&c->tail)) != hipSuccess)
+        (e = hipEventCreateWithFlags(&c->tail, hipEventDisableTiming | hipEventDisableSystemFence)) != hipSuccess)
         return fail(set_error(MVF_ERR_HIP, "context setup: %s", hipGetErrorString(e)));
     for (int i = 0; i < Arena::kSlots; ++i)
-        if ((e = hipEventCreate(&c->arena.ev[i])) != hipSuccess)
+        // the host waits on these before rewriting a slot the device has read
+        if ((e = hipEventCreateWithFlags(&c->arena.ev[i], hipEventDisableTiming | hipEventDisableSystemFence)) !=
+            hipSuccess)
             return fail(set_error(MVF_ERR_HIP, "context setup: %s", hipGetErrorString(e)));
     if ((e = hipDeviceSynchronize()) != hipSuccess)
         return fail(set_error(MVF_ERR_HIP, "context setup: %s", hipGetErrorString(e)));
@@ -1015,7 +1036,7 @@ mvf_status mvf_synchronize(mvf_ctx* c)
 {
     if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
     CHECK_HIP(hipSetDevice(c->device));
-    if (c->tail_valid) CHECK_HIP(hipEventSynchronize(c->tail));
+    if (c->tail_valid) CHECK_HIP(hipEventSynchronize(c->tail_ev));
     CHECK_HIP(hipStreamSynchronize(c->copy_stream));
     CHECK_HIP(hipDeviceSynchronize());
     return MVF_OK;
@@ -1539,10 +1560,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     h->total_tiles = tiles;
     h->first_wave = 1;
     h->rp = grid0 >= 0 ? ray_params(c, c->grids[grid0]) : RayParams{1.0f, 0};
-    // upload into the graph's fixed tables (stream-ordered before the replay)
-    CHECK_HIP(hipMemcpyAsync(G.dev, w.host, G.dev_bytes, hipMemcpyHostToDevice, s));
-    CHECK_ST(arena_release(c, slot, s));
-
+    // The graph's first node uploads this image into its fixed tables; the
+    // node's source is pointed at this step's arena slot.
     if (!G.valid) {
         hipStream_t cs = c->capture_stream;
         const LaunchHeader* dh = reinterpret_cast<const LaunchHeader*>(G.dev + G.off_hdr);
@@ -1555,31 +1574,48 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         const int32_t* dtb = reinterpret_cast<const int32_t*>(G.dev + G.off_tbase);
         const int32_t* dbb = reinterpret_cast<const int32_t*>(G.dev + G.off_bbase);
         CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        int e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
-        IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit};
+        int e1 = (int)hipMemcpyAsync(G.dev, w.host, G.dev_bytes, hipMemcpyHostToDevice, cs);
+        if (!e1) e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
+        // integration's block 0 orders the raycast's tile groups (slowest of
+        // the last step first)
+        IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit,
+                           G.tile_cost, G.tile_order, G.ray_tiles};
         int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items * kVisitPerItem + 255) / 256), cs);
         // one wavefront per work item of the captured volume set (a larger
         // set later is walked by the kernel's grid-stride loop)
-        G.integ_blocks = std::max(c->n_cus * 8, (items + 3) / 4);
+        G.integ_blocks = std::max(c->n_cus * 8, (items + 3) / 4) + 1;
         if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
         if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs);
         RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th, G.tile_cost, G.tile_order};
-        // slowest tile groups of the last step first
-        if (!e2) e2 = launch_tile_order(G.tile_cost, G.tile_order, G.ray_tiles, cs);
         int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
         hipError_t ee = hipStreamEndCapture(cs, &G.graph);
         if (e3) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString((hipError_t)e3));
         if (ee != hipSuccess) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString(ee));
         CHECK_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+        size_t nn = 0;
+        CHECK_HIP(hipGraphGetNodes(G.graph, nullptr, &nn));
+        std::vector<hipGraphNode_t> nodes(nn);
+        CHECK_HIP(hipGraphGetNodes(G.graph, nodes.data(), &nn));
+        G.copy_node = nullptr;
+        for (hipGraphNode_t nd : nodes) {
+            hipGraphNodeType ty;
+            CHECK_HIP(hipGraphNodeGetType(nd, &ty));
+            if (ty == hipGraphNodeTypeMemcpy) G.copy_node = nd;
+        }
+        if (!G.copy_node) return set_error(MVF_ERR_HIP, "step capture: no table upload node");
         G.valid = true;
+    } else {
+        CHECK_HIP(hipGraphExecMemcpyNodeSetParams1D(G.exec, G.copy_node, G.dev, w.host, G.dev_bytes,
+                                                    hipMemcpyHostToDevice));
     }
     hipEvent_t t0;
     CHECK_ST(timing_begin(c, s, &t0));
     CHECK_HIP(hipGraphLaunch(G.exec, s));
     CHECK_ST(timing_end(c, s, t0, 2));
+    CHECK_ST(arena_release(c, slot, s));  // reused once the replay that reads it is done
     c->stats.step_launches += 1;
     for (int i = 0; i < n; ++i) c->stats.pixels_raycast += (uint64_t)outs[i].width * outs[i].height;
-    return mark_tail(c, s);
+    return mark_tail_recorded(c, s, c->arena.ev[slot]);
 }
 
 // ---- placement ------------------------------------------------------------------
