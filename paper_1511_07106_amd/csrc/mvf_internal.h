@@ -93,6 +93,13 @@ struct DevFrame {
     float* best_t;           // per-pixel running best (multi-wave raycast)
     int32_t* best_id;
     int32_t out_w, out_h;
+    // raycast range bounds per 8x8 output-pixel cell (cells_x * cells_y,
+    // row-major), or null: the nearest and farthest camera distance of any
+    // sample the march may have to evaluate; a cell no brick reaches holds
+    // (inf, 0).  Written by launch_ray_bounds_merge.
+    float* rb_lo;
+    float* rb_hi;
+    int32_t cells_x, cells_y;
 };
 
 struct RayParams {
@@ -119,6 +126,24 @@ struct LaunchHeader {
     int32_t first_wave;    // raycast: 1 = start from no hit, 0 = merge with best_t/best_id
     RayParams rp;
     int32_t total_z;       // entries of the integration z table (sum of 8 * bd[2])
+    int32_t rb_parity;     // raycast range bounds: which half of RayBounds::counts this launch fills
+};
+
+// Footprint of one brick in the raycast range bounds: cells [x0, x1] x
+// [y0, y1] of its volume's frame and the camera distances [dn, df] of its box.
+struct RayBoundEntry {
+    uint16_t x0, x1, y0, y1;
+    float dn, df;
+};
+
+// Range-bound footprints of a launch.  Volume v of the table appends to
+// entries + brick_base[v] (room for all its bricks) and counts its entries
+// in counts[rb_parity * cap + v]; the merge reads them and clears the other
+// half for the next launch.
+struct RayBounds {
+    RayBoundEntry* entries;
+    uint32_t* counts;          // 2 * cap, zero before first use
+    int32_t cap;               // volume slots per half (>= nvol)
 };
 
 // Frame preparation input for one stream.
@@ -167,6 +192,8 @@ constexpr int kVisitPerItem = 4;
 constexpr int kRayLanes = 4;
 constexpr int kRayTileW = 4;
 constexpr int kRayTileH = 64 / kRayLanes / kRayTileW;
+constexpr int kBoundCell = 8;   // output pixels per side of a raycast range-bound cell
+static_assert(kBoundCell % kRayTileW == 0 && kBoundCell % kRayTileH == 0, "a ray tile lies in one bound cell");
 // Raycast launch order: groups of kRayGroup consecutive tiles are ordered by
 // their summed last duration, slowest first.  Blocks are dealt round-robin
 // over the 8 XCDs, so a window of 8 * kRayGroup blocks takes 8 groups, each
@@ -207,9 +234,21 @@ int launch_raycast(const RaycastLaunch& L, int blocks, void* stream);
 int launch_tile_order(const uint32_t* cost, int32_t* order, int n, void* stream);
 int launch_brick_summary(DevVolume v, void* stream);
 // Brick distance transform of every volume in the table (3 passes).
-// brick_base: nvol + 1 prefix sums of the volumes' brick counts.
+// brick_base: nvol + 1 prefix sums of the volumes' brick counts (each a
+// multiple of 64).  With frames and rb.entries set, the last pass also
+// collects the range-bound footprints (as launch_ray_bounds_collect).
 int launch_brick_distance(const LaunchHeader* hdr, const DevVolume* vols, const int32_t* brick_base,
-                          int blocks, void* stream);
+                          int blocks, void* stream, const DevFrame* frames = nullptr, RayBounds rb = RayBounds{});
+// Range-bound footprints of the bricks of every volume of the table whose
+// cell mask is not empty, for the volume's frame.
+int launch_ray_bounds_collect(const LaunchHeader* hdr, const DevVolume* vols, const int32_t* brick_base,
+                              const DevFrame* frames, RayBounds rb, int blocks, void* stream);
+// Range bounds of every cell of each stream's frame from the footprints of
+// the stream's volumes (lists / list_base as in RaycastLaunch); clears the
+// other half of rb.counts.  max_cells_x/y: largest cell grid of the frames.
+int launch_ray_bounds_merge(const LaunchHeader* hdr, const DevFrame* frames, const int32_t* lists,
+                            const int32_t* list_base, const int32_t* brick_base, RayBounds rb, int nstreams,
+                            int max_cells_x, int max_cells_y, void* stream);
 int launch_to_canonical(DevVolume v, float* F, uint16_t* W, uint32_t* C, void* stream);
 int launch_from_canonical(DevVolume v, const float* F, const uint16_t* W, const uint32_t* C,
                           void* stream);

@@ -689,6 +689,7 @@ struct Ray {
     float dw[3];
     float inv_dw[3];   // approximate 1/dw (conservative uses only)
     float inv_delta;   // approximate 1/delta
+    float t_lo, t_hi;  // every sample that may end a crossing lies in [t_lo, t_hi]
 };
 
 static __host__ __device__ __forceinline__ float approx_rcp(float x)
@@ -807,10 +808,88 @@ static __host__ __device__ __forceinline__ bool eval_sample_cached(const DevVolu
 
 // Conservative sample range [k0, k1] of the ray inside V's domain box grown
 // by one voxel, plus two samples each side.
+// Raycast range bounds.  Every sample the march must evaluate (a possible
+// far end of a crossing) lies in a brick whose cell mask is not empty, at a
+// local coordinate in the brick's box [8 b, 8 b + 8).  Each such brick
+// records the distance range of that box (grown by 0.1 voxel) from the
+// camera centre and the 8x8-pixel cells its projection can reach (grown by
+// one pixel; all cells when the box reaches behind the camera); a merge
+// folds these footprints into per-cell ranges, and a ray marches only
+// within the range of its cell (a cell no brick reaches is empty).
+static __device__ bool brick_footprint(const DevVolume& V, const DevFrame& Fr, int bx, int by, int bz,
+                                       RayBoundEntry& e)
+{
+    const int ib[3] = {bx, by, bz};
+    const float c[3] = {Fr.T[3], Fr.T[7], Fr.T[11]};
+    float lo[3], hi[3];
+    float dn2 = 0.0f, df2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = V.o[a] + V.s * ((float)(V.off[a] + kBrick * ib[a]) + 0.4f);
+        hi[a] = V.o[a] + V.s * ((float)(V.off[a] + kBrick * ib[a] + kBrick) + 0.6f);
+        const float en = fmaxf(fmaxf(lo[a] - c[a], c[a] - hi[a]), 0.0f);
+        const float ef = fmaxf(fabsf(lo[a] - c[a]), fabsf(hi[a] - c[a]));
+        dn2 += en * en;
+        df2 += ef * ef;
+    }
+    e.dn = fmaxf(sqrtf(dn2) * (1.0f - 1e-5f) - 1e-4f, 0.0f);
+    e.df = sqrtf(df2) * (1.0f + 1e-5f) + 1e-4f;
+    float u0 = INFINITY, u1 = -INFINITY, v0 = INFINITY, v1 = -INFINITY;
+    bool behind = false, front = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float dx = ((k & 1) ? hi[0] : lo[0]) - c[0];
+        const float dy = ((k & 2) ? hi[1] : lo[1]) - c[1];
+        const float dz = ((k & 4) ? hi[2] : lo[2]) - c[2];
+        const float px = Fr.T[0] * dx + Fr.T[4] * dy + Fr.T[8] * dz;
+        const float py = Fr.T[1] * dx + Fr.T[5] * dy + Fr.T[9] * dz;
+        const float pz = Fr.T[2] * dx + Fr.T[6] * dy + Fr.T[10] * dz;
+        behind |= !(pz > 1e-3f);
+        front |= pz > -1e-3f;
+        const float iz = __builtin_amdgcn_rcpf(pz);
+        const float u = Fr.fx * px * iz + Fr.cx;
+        const float v = Fr.fy * py * iz + Fr.cy;
+        u0 = fminf(u0, u); u1 = fmaxf(u1, u);
+        v0 = fminf(v0, v); v1 = fmaxf(v1, v);
+    }
+    // every ray sample lies in front of the camera (z > 0): a box wholly
+    // behind it is seen by no ray, one across the camera plane by any
+    if (!front) return false;
+    if (behind) {
+        e.x0 = 0; e.x1 = (uint16_t)(Fr.cells_x - 1);
+        e.y0 = 0; e.y1 = (uint16_t)(Fr.cells_y - 1);
+        return true;
+    }
+    const float a0 = fmaxf(floorf(u0 - 1.0f), 0.0f), a1 = fminf(ceilf(u1 + 1.0f), (float)(Fr.out_w - 1));
+    const float b0 = fmaxf(floorf(v0 - 1.0f), 0.0f), b1 = fminf(ceilf(v1 + 1.0f), (float)(Fr.out_h - 1));
+    if (!(a0 <= a1 && b0 <= b1)) return false;   // no pixel of the image sees the box
+    e.x0 = (uint16_t)((int)a0 / kBoundCell); e.x1 = (uint16_t)((int)a1 / kBoundCell);
+    e.y0 = (uint16_t)((int)b0 / kBoundCell); e.y1 = (uint16_t)((int)b1 / kBoundCell);
+    return true;
+}
+
+// Footprint of brick (bx, by, bz) of volume v appended to the volume's list
+// (if its cell mask is not empty).  Called by every active lane of a
+// wavefront whose lanes all serve volume v; one counter atomic per wavefront.
+static __device__ void collect_footprint(const DevVolume& V, const DevFrame& Fr, int v, uint32_t b, int bx, int by,
+                                         int bz, const int32_t* brick_base, const LaunchHeader* hdr, RayBounds rb)
+{
+    RayBoundEntry e;
+    const bool has = Fr.rb_lo && V.cmask[b] != 0ull && brick_footprint(V, Fr, bx, by, bz, e);
+    const unsigned long long m = __ballot(has);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll(m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&rb.counts[hdr->rb_parity * rb.cap + v], (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader);
+    if (has) rb.entries[brick_base[v] + base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = e;
+}
+
 static __host__ __device__ __forceinline__ void ray_k_range(const DevVolume& V, const Ray& r, float delta, int kmax,
                                                    int& k0, int& k1)
 {
-    float t0 = 0.0f, t1 = (float)kmax * delta;
+    float t0 = fmaxf(0.0f, r.t_lo), t1 = fminf((float)kmax * delta, r.t_hi);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float lo = V.o[a] + V.s * ((float)V.off[a] + 0.5f) - V.s;
@@ -1203,6 +1282,14 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
             r.inv_dw[a] = approx_rcp(r.dw[a]);
         }
         r.inv_delta = approx_rcp(H.rp.delta);
+        // the range bounds of the pixel's cell and of the whole image
+        r.t_lo = 0.0f;
+        r.t_hi = pinf();
+        if (Fr.rb_lo) {
+            const int cell = (v / kBoundCell) * Fr.cells_x + u / kBoundCell;
+            r.t_lo = Fr.rb_lo[cell];
+            r.t_hi = Fr.rb_hi[cell];
+        }
     }
     float best_t = pinf();
     int best_id = 0x7fffffff;
@@ -1300,7 +1387,8 @@ int launch_brick_summary(DevVolume v, void* stream)
 // +y, +z neighbours.  Each volume's bricks start at a multiple of 64 in the
 // launch's brick numbering (brick_base), so a wavefront serves one volume.
 __global__ __launch_bounds__(256) void mvf_brick_distance_kernel(const LaunchHeader* hdr, const DevVolume* vols,
-                                                                 const int32_t* brick_base, int pass)
+                                                                 const int32_t* brick_base, int pass,
+                                                                 const DevFrame* frames, RayBounds rb)
 {
     const int total = cptr(hdr)->total_bricks;
     const int nvol = cptr(hdr)->nvol;
@@ -1361,17 +1449,111 @@ __global__ __launch_bounds__(256) void mvf_brick_distance_kernel(const LaunchHea
                 if (z >= 0 && z < V.bd[2]) d = min(d, max(abs(o), (int)ld_elem(t1, (uint32_t)(b + o))));
             }
             V.dist[b] = (uint8_t)d;
+            if (frames && rb.entries) collect_footprint(V, frames[V.frame], lo, (uint32_t)b, bx, by, bz, brick_base, hdr, rb);
         }
     }
 }
 
 int launch_brick_distance(const LaunchHeader* hdr, const DevVolume* vols, const int32_t* brick_base, int blocks,
-                          void* stream)
+                          void* stream, const DevFrame* frames, RayBounds rb)
 {
     if (blocks <= 0) return 0;
     for (int pass = 0; pass < 3; ++pass)
         hipLaunchKernelGGL(mvf_brick_distance_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, hdr, vols,
-                           brick_base, pass);
+                           brick_base, pass, pass == 2 ? frames : nullptr, rb);
+    return (int)hipGetLastError();
+}
+
+// Range-bound footprints of every brick of the table (one thread per brick,
+// a wavefront within one volume as in the distance passes).
+__global__ __launch_bounds__(256) void mvf_ray_bounds_collect_kernel(const LaunchHeader* hdr, const DevVolume* vols,
+                                                                     const int32_t* brick_base,
+                                                                     const DevFrame* frames, RayBounds rb)
+{
+    const int total = hdr->total_bricks;
+    const int nvol = hdr->nvol;
+    for (int g0 = blockIdx.x * blockDim.x; g0 < total; g0 += gridDim.x * blockDim.x) {
+        const int gw = wave_uniform(g0 + (int)(threadIdx.x & ~63u));
+        int lo = 0, hi = nvol - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (brick_base[mid] <= gw) lo = mid; else hi = mid - 1;
+        }
+        lo = wave_uniform(lo);
+        const DevVolume& V = vols[lo];
+        const int b = g0 + (int)threadIdx.x - brick_base[lo];
+        const int nb = V.bd[0] * V.bd[1] * V.bd[2];
+        if (b >= nb) continue;
+        const int bz = b % V.bd[2];
+        const int t = b / V.bd[2];
+        collect_footprint(V, frames[V.frame], lo, (uint32_t)b, t / V.bd[1], t % V.bd[1], bz, brick_base, hdr, rb);
+    }
+}
+
+int launch_ray_bounds_collect(const LaunchHeader* hdr, const DevVolume* vols, const int32_t* brick_base,
+                              const DevFrame* frames, RayBounds rb, int blocks, void* stream)
+{
+    if (blocks <= 0) return 0;
+    hipLaunchKernelGGL(mvf_ray_bounds_collect_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, hdr, vols,
+                       brick_base, frames, rb);
+    return (int)hipGetLastError();
+}
+
+// Block (x, y, s): cells [8x, 8x + 8) x [8y, 8y + 8) of stream s, folded in
+// LDS from every footprint of the stream's volumes.  Block (0, 0, 0) also
+// clears the other half of the counts.
+__global__ __launch_bounds__(256) void mvf_ray_bounds_merge_kernel(const LaunchHeader* hdr, const DevFrame* frames,
+                                                                   const int32_t* lists, const int32_t* list_base,
+                                                                   const int32_t* brick_base, RayBounds rb)
+{
+    const int par = hdr->rb_parity;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
+        for (int i = threadIdx.x; i < rb.cap; i += blockDim.x) rb.counts[(1 - par) * rb.cap + i] = 0;
+    const int s = blockIdx.z;
+    if (s >= hdr->nstreams) return;
+    const DevFrame& Fr = frames[s];
+    const int cx0 = blockIdx.x * 8, cy0 = blockIdx.y * 8;
+    if (!Fr.rb_lo || cx0 >= Fr.cells_x || cy0 >= Fr.cells_y) return;
+    __shared__ uint32_t lo[64], hi[64];
+    if (threadIdx.x < 64) {
+        lo[threadIdx.x] = 0x7f800000u;   // +inf
+        hi[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    for (int li = list_base[s]; li < list_base[s + 1]; ++li) {
+        const int v = lists[li];
+        const uint32_t n = rb.counts[par * rb.cap + v];
+        const RayBoundEntry* E = rb.entries + brick_base[v];
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const RayBoundEntry e = E[i];
+            const int x0 = max((int)e.x0, cx0), x1 = min((int)e.x1, cx0 + 7);
+            const int y0 = max((int)e.y0, cy0), y1 = min((int)e.y1, cy0 + 7);
+            for (int y = y0; y <= y1; ++y)
+                for (int x = x0; x <= x1; ++x) {
+                    const int k = (y - cy0) * 8 + (x - cx0);
+                    atomicMin(&lo[k], __float_as_uint(e.dn));   // distances are >= 0: bit order is value order
+                    atomicMax(&hi[k], __float_as_uint(e.df));
+                }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int x = cx0 + (threadIdx.x & 7), y = cy0 + (threadIdx.x >> 3);
+        if (x < Fr.cells_x && y < Fr.cells_y) {
+            Fr.rb_lo[y * Fr.cells_x + x] = __uint_as_float(lo[threadIdx.x]);
+            Fr.rb_hi[y * Fr.cells_x + x] = __uint_as_float(hi[threadIdx.x]);
+        }
+    }
+}
+
+int launch_ray_bounds_merge(const LaunchHeader* hdr, const DevFrame* frames, const int32_t* lists,
+                            const int32_t* list_base, const int32_t* brick_base, RayBounds rb, int nstreams,
+                            int max_cells_x, int max_cells_y, void* stream)
+{
+    if (nstreams <= 0) return 0;
+    const dim3 grid((max_cells_x + 7) / 8, (max_cells_y + 7) / 8, nstreams);
+    hipLaunchKernelGGL(mvf_ray_bounds_merge_kernel, grid, dim3(256), 0, (hipStream_t)stream, hdr, frames, lists,
+                       list_base, brick_base, rb);
     return (int)hipGetLastError();
 }
 
@@ -1600,6 +1782,8 @@ static __device__ __forceinline__ void make_ray(int u, int v, float fx, float fy
         r.dw[a] = ((T[4 * a + 0] * dh[0]) + (T[4 * a + 1] * dh[1])) + (T[4 * a + 2] * dh[2]);
         r.C[a] = T[4 * a + 3];
     }
+    r.t_lo = 0.0f;
+    r.t_hi = INFINITY;
 }
 
 struct PoseArgs {

@@ -104,6 +104,14 @@ struct Scratch {
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
     int32_t* tile_order = nullptr;
     int tiles_cap = 0;
+    float* rb_lo = nullptr;  // raycast range bounds per 8x8 output-pixel cell
+    float* rb_hi = nullptr;
+    int rb_cap = 0;
+    RayBoundEntry* rb_entries = nullptr;  // plain raycast: footprints of a launch's bricks
+    int rb_entries_cap = 0;
+    uint32_t* rb_counts = nullptr;        // 2 halves of rb_counts_cap volume slots
+    int rb_counts_cap = 0;
+    int rb_parity = 0;
 };
 
 // Ring of pinned host + device slots for per-launch tables.  A slot is
@@ -157,6 +165,11 @@ struct StepGraph {
     int ztab_cap = 0;
     uint8_t* visit = nullptr;  // brick visit mask per integration item
     int visit_cap = 0;
+    RayBoundEntry* rb_entries = nullptr;  // raycast range-bound footprints (one per brick)
+    int rb_entries_cap = 0;
+    uint32_t* rb_counts = nullptr;        // 2 * max_vols
+    int rb_parity = 0;
+    int max_cells_x = 0, max_cells_y = 0;
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
     int32_t* tile_order = nullptr;
 };
@@ -607,6 +620,50 @@ mvf_status get_tile_buffers(Scratch* s, int n)
     return MVF_OK;
 }
 
+// Range-bound cells for a w x h raycast output (written by every merge
+// before the raycast reads them).
+mvf_status get_bound_buffers(Scratch* s, int w, int h)
+{
+    const int n = ((w + kBoundCell - 1) / kBoundCell) * ((h + kBoundCell - 1) / kBoundCell);
+    if (n <= s->rb_cap) return MVF_OK;
+    if (s->rb_lo) { CHECK_HIP(hipFree(s->rb_lo)); s->rb_lo = nullptr; }
+    if (s->rb_hi) { CHECK_HIP(hipFree(s->rb_hi)); s->rb_hi = nullptr; }
+    s->rb_cap = 0;
+    CHECK_HIP(hipMalloc((void**)&s->rb_lo, (size_t)n * sizeof(float)));
+    CHECK_HIP(hipMalloc((void**)&s->rb_hi, (size_t)n * sizeof(float)));
+    s->rb_cap = n;
+    return MVF_OK;
+}
+
+// Footprint list for `bricks` (64-aligned per volume) and zeroed counts for
+// `vols` volume slots.
+mvf_status get_footprint_buffers(RayBoundEntry** entries, int* entries_cap, uint32_t** counts, int* counts_cap,
+                                 int bricks, int vols)
+{
+    if (bricks > *entries_cap) {
+        if (*entries) { CHECK_HIP(hipFree(*entries)); *entries = nullptr; }
+        *entries_cap = 0;
+        CHECK_HIP(hipMalloc((void**)entries, (size_t)bricks * sizeof(RayBoundEntry)));
+        *entries_cap = bricks;
+    }
+    if (counts_cap && vols > *counts_cap) {
+        if (*counts) { CHECK_HIP(hipFree(*counts)); *counts = nullptr; }
+        *counts_cap = 0;
+        CHECK_HIP(hipMalloc((void**)counts, (size_t)2 * vols * sizeof(uint32_t)));
+        CHECK_HIP(hipMemset(*counts, 0, (size_t)2 * vols * sizeof(uint32_t)));
+        *counts_cap = vols;
+    }
+    return MVF_OK;
+}
+
+void set_bounds(DevFrame* f, const Scratch* s, int w, int h)
+{
+    f->rb_lo = s->rb_lo;
+    f->rb_hi = s->rb_hi;
+    f->cells_x = (w + kBoundCell - 1) / kBoundCell;
+    f->cells_y = (h + kBoundCell - 1) / kBoundCell;
+}
+
 mvf_status check_frame(const mvf_frame* f)
 {
     if (!f || !f->depth) return set_error(MVF_ERR_INVALID_ARG, "frame or frame->depth is NULL");
@@ -821,6 +878,7 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
     const int tw = kRayTileW, th = kRayTileH;  // one wavefront per block: free slots refill per wave
     const int tiles = ((out->width + tw - 1) / tw) * ((out->height + th - 1) / th);
     CHECK_ST(get_tile_buffers(sc, tiles));
+    CHECK_ST(get_bound_buffers(sc, out->width, out->height));
     for (size_t wi = 0; wi < waves.size(); ++wi) {
         auto& wave = waves[wi];
         CHECK_ST(ensure_resident(c, wave, stream));
@@ -856,6 +914,19 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
             fr->best_t = sc->best_t;
             fr->best_id = sc->best_id;
         }
+        set_bounds(fr, sc, out->width, out->height);
+        // footprint regions: the wave's bricks, 64-aligned per volume
+        int32_t* dbb;
+        int32_t* bb = w.alloc<int32_t>(wave.size() + 1, &dbb);
+        if (!bb) return set_error(MVF_ERR_INVALID_ARG, "arena overflow");
+        int nbr = 0;
+        for (size_t j = 0; j < wave.size(); ++j) {
+            bb[j] = nbr;
+            nbr += (int)align_up(c->vols[wave[j]].nbricks, 64);
+        }
+        bb[wave.size()] = nbr;
+        CHECK_ST(get_footprint_buffers(&sc->rb_entries, &sc->rb_entries_cap, &sc->rb_counts, &sc->rb_counts_cap,
+                                       std::max(nbr, 64), std::max<int>((int)wave.size(), 16)));
         lb[0] = 0;
         lb[1] = (int32_t)wave.size();
         tb[0] = 0;
@@ -866,11 +937,17 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
         h->total_tiles = tiles;
         h->first_wave = wi == 0 ? 1 : 0;
         h->rp = rp;
+        h->total_bricks = nbr;
+        h->rb_parity = sc->rb_parity;
+        sc->rb_parity ^= 1;
         CHECK_ST(arena_upload(c, w, stream));
         // slowest tiles of the stream's last raycast first
         RaycastLaunch L{dh, dvols, dfr, dlists, dlb, dtb, tw, th, sc->tile_cost, sc->tile_order};
         hipEvent_t t0;
         CHECK_ST(timing_begin(c, stream, &t0));
+        const RayBounds RB{sc->rb_entries, sc->rb_counts, sc->rb_counts_cap};
+        CHECK_LAUNCH(launch_ray_bounds_collect(dh, dvols, dbb, dfr, RB, std::min(1024, (nbr + 255) / 256), stream));
+        CHECK_LAUNCH(launch_ray_bounds_merge(dh, dfr, dlists, dlb, dbb, RB, 1, fr->cells_x, fr->cells_y, stream));
         CHECK_LAUNCH(launch_tile_order(sc->tile_cost, sc->tile_order, tiles, stream));
         CHECK_LAUNCH(launch_raycast(L, ray_blocks(tiles), stream));
         CHECK_ST(timing_end(c, stream, t0, 1));
@@ -901,6 +978,9 @@ mvf_status destroy_step_graph(mvf_ctx* c)
     if (g.ztab) { CHECK_HIP(hipFree(g.ztab)); g.ztab = nullptr; }
     if (g.visit) { CHECK_HIP(hipFree(g.visit)); g.visit = nullptr; }
     g.visit_cap = 0;
+    if (g.rb_entries) { CHECK_HIP(hipFree(g.rb_entries)); g.rb_entries = nullptr; }
+    if (g.rb_counts) { CHECK_HIP(hipFree(g.rb_counts)); g.rb_counts = nullptr; }
+    g.rb_entries_cap = 0;
     if (g.tile_cost) { CHECK_HIP(hipFree(g.tile_cost)); g.tile_cost = nullptr; }
     if (g.tile_order) { CHECK_HIP(hipFree(g.tile_order)); g.tile_order = nullptr; }
     g.ztab_cap = 0;
@@ -1005,6 +1085,10 @@ mvf_status mvf_destroy(mvf_ctx* c)
         if (s.ztab) (void)hipFree(s.ztab);
         if (s.tmax) (void)hipFree(s.tmax);
         if (s.visit) (void)hipFree(s.visit);
+        if (s.rb_lo) (void)hipFree(s.rb_lo);
+        if (s.rb_hi) (void)hipFree(s.rb_hi);
+        if (s.rb_entries) (void)hipFree(s.rb_entries);
+        if (s.rb_counts) (void)hipFree(s.rb_counts);
         if (s.tile_cost) (void)hipFree(s.tile_cost);
         if (s.tile_order) (void)hipFree(s.tile_order);
         if (s.best_t) (void)hipFree(s.best_t);
@@ -1421,14 +1505,15 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         max_w = std::max(max_w, frames[i].frame.width);
         max_h = std::max(max_h, frames[i].frame.height);
     }
-    int ztotal = 0, items_total = 0;
+    int ztotal = 0, items_total = 0, bricks_total = 0;
     for (int id : all) {
         const Volume& v = c->vols[id];
         ztotal += kBrick * v.bd[2];
         items_total += v.bd[0] * v.bd[1] * ((v.bd[2] + kZChunk - 1) / kZChunk);
+        bricks_total += (int)align_up(v.nbricks, 64);
     }
     bool same_shape = G.valid && G.n == n && (int)all.size() <= G.max_vols && max_w <= G.max_w && max_h <= G.max_h &&
-                      ztotal <= G.ztab_cap && items_total <= G.visit_cap;
+                      ztotal <= G.ztab_cap && items_total <= G.visit_cap && bricks_total <= G.rb_entries_cap;
     if (same_shape) {
         for (int i = 0; i < n; ++i)
             if (G.out_w[i] != outs[i].width || G.out_h[i] != outs[i].height) same_shape = false;
@@ -1464,6 +1549,14 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         CHECK_HIP(hipMalloc((void**)&G.ztab, (size_t)G.ztab_cap * 3 * sizeof(float)));
         G.visit_cap = std::max(items_total * 2, 1024);
         CHECK_HIP(hipMalloc((void**)&G.visit, (size_t)G.visit_cap * kVisitPerItem));
+        int counts_cap = 0;
+        CHECK_ST(get_footprint_buffers(&G.rb_entries, &G.rb_entries_cap, &G.rb_counts, &counts_cap,
+                                       std::max(bricks_total * 2, 1024), G.max_vols));
+        G.max_cells_x = G.max_cells_y = 0;
+        for (int i = 0; i < n; ++i) {
+            G.max_cells_x = std::max(G.max_cells_x, (outs[i].width + kBoundCell - 1) / kBoundCell);
+            G.max_cells_y = std::max(G.max_cells_y, (outs[i].height + kBoundCell - 1) / kBoundCell);
+        }
         G.integ_blocks = c->n_cus * 8;
         int tiles = 0;
         for (int i = 0; i < n; ++i) tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
@@ -1474,7 +1567,10 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     // scratch per stream
     std::vector<Scratch*> sc(n);
     for (int i = 0; i < n; ++i)
+    {
         CHECK_ST(get_scratch(c, frames[i].stream_id, frames[i].frame.width, frames[i].frame.height, false, &sc[i]));
+        CHECK_ST(get_bound_buffers(sc[i], outs[i].width, outs[i].height));
+    }
 
     // host image of the tables, uploaded to G.dev before the graph runs
     int slot;
@@ -1515,6 +1611,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         p.rmax = sc[i]->rmax;
         p.tmax = sc[i]->tmax;
         fill_frame(&dfr[i], sc[i], fr.frame.width, fr.frame.height, fr.T_wc, fr.K);
+        set_bounds(&dfr[i], sc[i], outs[i].width, outs[i].height);
         if (!fr.frame.rgb) dfr[i].color = nullptr;
         dfr[i].depth = outs[i].depth;
         dfr[i].vertex = outs[i].vertex;
@@ -1560,6 +1657,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     h->total_tiles = tiles;
     h->first_wave = 1;
     h->rp = grid0 >= 0 ? ray_params(c, c->grids[grid0]) : RayParams{1.0f, 0};
+    h->rb_parity = G.rb_parity;
+    G.rb_parity ^= 1;
     // The graph's first node uploads this image into its fixed tables; the
     // node's source is pointed at this step's arena slot.
     if (!G.valid) {
@@ -1585,7 +1684,11 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         // set later is walked by the kernel's grid-stride loop)
         G.integ_blocks = std::max(c->n_cus * 8, (items + 3) / 4) + 1;
         if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
-        if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs);
+        // the last distance pass also collects the raycast range-bound
+        // footprints; the merge folds them per cell
+        const RayBounds RB{G.rb_entries, G.rb_counts, G.max_vols};
+        if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs, dframes, RB);
+        if (!e2) e2 = launch_ray_bounds_merge(dh, dframes, dlists, dlb, dbb, RB, n, G.max_cells_x, G.max_cells_y, cs);
         RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th, G.tile_cost, G.tile_order};
         int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
         hipError_t ee = hipStreamEndCapture(cs, &G.graph);
