@@ -1426,27 +1426,46 @@ __global__ __launch_bounds__(256) void mvf_brick_distance_kernel(const LaunchHea
             V.cmask[b] = cell_mask(M);
             GPTR(const uint8_t) const flag = gptr((const uint8_t*)V.flag);
             const int sx = V.bd[1] * V.bd[2];
+            // all loads first (in-range addresses), then the minimum
+            uint8_t f[2 * kDistCap + 1];
+#pragma unroll
+            for (int o = -kDistCap; o <= kDistCap; ++o) {
+                const int x = min(max(bx + o, 0), V.bd[0] - 1);
+                f[o + kDistCap] = ld_elem(flag, (uint32_t)(b + (x - bx) * sx));
+            }
 #pragma unroll
             for (int o = -kDistCap; o <= kDistCap; ++o) {
                 const int x = bx + o;
-                if (x >= 0 && x < V.bd[0] && ld_elem(flag, (uint32_t)(b + o * sx))) d = min(d, abs(o));
+                if (x >= 0 && x < V.bd[0] && f[o + kDistCap]) d = min(d, abs(o));
             }
             V.tmp[b] = (uint8_t)d;
         } else if (pass == 1) {
             GPTR(const uint8_t) const t0 = gptr((const uint8_t*)V.tmp);
             const int sy = V.bd[2];
+            uint8_t f[2 * kDistCap + 1];
+#pragma unroll
+            for (int o = -kDistCap; o <= kDistCap; ++o) {
+                const int y = min(max(by + o, 0), V.bd[1] - 1);
+                f[o + kDistCap] = ld_elem(t0, (uint32_t)(b + (y - by) * sy));
+            }
 #pragma unroll
             for (int o = -kDistCap; o <= kDistCap; ++o) {
                 const int y = by + o;
-                if (y >= 0 && y < V.bd[1]) d = min(d, max(abs(o), (int)ld_elem(t0, (uint32_t)(b + o * sy))));
+                if (y >= 0 && y < V.bd[1]) d = min(d, max(abs(o), (int)f[o + kDistCap]));
             }
             V.tmp[nb + b] = (uint8_t)d;
         } else {
             GPTR(const uint8_t) const t1 = gptr((const uint8_t*)V.tmp + nb);
+            uint8_t f[2 * kDistCap + 1];
+#pragma unroll
+            for (int o = -kDistCap; o <= kDistCap; ++o) {
+                const int z = min(max(bz + o, 0), V.bd[2] - 1);
+                f[o + kDistCap] = ld_elem(t1, (uint32_t)(b + (z - bz)));
+            }
 #pragma unroll
             for (int o = -kDistCap; o <= kDistCap; ++o) {
                 const int z = bz + o;
-                if (z >= 0 && z < V.bd[2]) d = min(d, max(abs(o), (int)ld_elem(t1, (uint32_t)(b + o))));
+                if (z >= 0 && z < V.bd[2]) d = min(d, max(abs(o), (int)f[o + kDistCap]));
             }
             V.dist[b] = (uint8_t)d;
             if (frames && rb.entries) collect_footprint(V, frames[V.frame], lo, (uint32_t)b, bx, by, bz, brick_base, hdr, rb);
@@ -1502,7 +1521,7 @@ int launch_ray_bounds_collect(const LaunchHeader* hdr, const DevVolume* vols, co
 // Block (x, y, s): cells [8x, 8x + 8) x [8y, 8y + 8) of stream s, folded in
 // LDS from every footprint of the stream's volumes.  Block (0, 0, 0) also
 // clears the other half of the counts.
-__global__ __launch_bounds__(256) void mvf_ray_bounds_merge_kernel(const LaunchHeader* hdr, const DevFrame* frames,
+__global__ __launch_bounds__(1024) void mvf_ray_bounds_merge_kernel(const LaunchHeader* hdr, const DevFrame* frames,
                                                                    const int32_t* lists, const int32_t* list_base,
                                                                    const int32_t* brick_base, RayBounds rb)
 {
@@ -1524,16 +1543,27 @@ __global__ __launch_bounds__(256) void mvf_ray_bounds_merge_kernel(const LaunchH
         const int v = lists[li];
         const uint32_t n = rb.counts[par * rb.cap + v];
         const RayBoundEntry* E = rb.entries + brick_base[v];
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const RayBoundEntry e = E[i];
-            const int x0 = max((int)e.x0, cx0), x1 = min((int)e.x1, cx0 + 7);
-            const int y0 = max((int)e.y0, cy0), y1 = min((int)e.y1, cy0 + 7);
-            for (int y = y0; y <= y1; ++y)
-                for (int x = x0; x <= x1; ++x) {
-                    const int k = (y - cy0) * 8 + (x - cx0);
-                    atomicMin(&lo[k], __float_as_uint(e.dn));   // distances are >= 0: bit order is value order
-                    atomicMax(&hi[k], __float_as_uint(e.df));
-                }
+        // four entries per thread per round, their loads in flight together
+        for (uint32_t i0 = 0; i0 < n; i0 += 4 * blockDim.x) {
+            RayBoundEntry e[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t i = i0 + q * blockDim.x + threadIdx.x;
+                if (i < n) e[q] = E[i];
+                else e[q].x0 = 1, e[q].x1 = 0;   // empty
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int x0 = max((int)e[q].x0, cx0), x1 = min((int)e[q].x1, cx0 + 7);
+                const int y0 = max((int)e[q].y0, cy0), y1 = min((int)e[q].y1, cy0 + 7);
+                if (x0 > x1) continue;
+                for (int y = y0; y <= y1; ++y)
+                    for (int x = x0; x <= x1; ++x) {
+                        const int k = (y - cy0) * 8 + (x - cx0);
+                        atomicMin(&lo[k], __float_as_uint(e[q].dn));   // distances are >= 0: bit order is value order
+                        atomicMax(&hi[k], __float_as_uint(e[q].df));
+                    }
+            }
         }
     }
     __syncthreads();
@@ -1552,7 +1582,7 @@ int launch_ray_bounds_merge(const LaunchHeader* hdr, const DevFrame* frames, con
 {
     if (nstreams <= 0) return 0;
     const dim3 grid((max_cells_x + 7) / 8, (max_cells_y + 7) / 8, nstreams);
-    hipLaunchKernelGGL(mvf_ray_bounds_merge_kernel, grid, dim3(256), 0, (hipStream_t)stream, hdr, frames, lists,
+    hipLaunchKernelGGL(mvf_ray_bounds_merge_kernel, grid, dim3(1024), 0, (hipStream_t)stream, hdr, frames, lists,
                        list_base, brick_base, rb);
     return (int)hipGetLastError();
 }
