@@ -226,9 +226,12 @@ int launch_ztable(const IntegrateLaunch& L, int cull_blocks, void* stream);
 // Integration kernel: blocks of 256 threads, 4 items in flight per block; a
 // grid smaller than total_items / 4 walks the items (plus block 0 when
 // L.tile_order is set).
-int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream);
+// With ev_start/ev_stop (hipEvent_t) the kernel's own dispatch records them.
+int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream, void* ev_start = nullptr,
+                     void* ev_stop = nullptr);
 // Raycast kernel over ray_blocks(total tiles) blocks (or fewer: a grid-stride loop).
-int launch_raycast(const RaycastLaunch& L, int blocks, void* stream);
+int launch_raycast(const RaycastLaunch& L, int blocks, void* stream, void* ev_start = nullptr,
+                   void* ev_stop = nullptr);
 // Launch order of the ray_groups(n) groups of n raycast tiles from their
 // last durations, longest first (a slow tile started late bounds the launch).
 int launch_tile_order(const uint32_t* cost, int32_t* order, int n, void* stream);

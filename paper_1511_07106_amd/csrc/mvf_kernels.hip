@@ -4,6 +4,7 @@
 // decision path reproduces the binary32 contract of the CPU reference
 // bit for bit.  Paper: Salvato, Finman, Leonard, arXiv 1511.07106.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <math.h>
 #include <stdint.h>
 
@@ -665,10 +666,14 @@ int launch_ztable(const IntegrateLaunch& L, int cull_blocks, void* stream)
     return (int)hipGetLastError();
 }
 
-int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream)
+int launch_integrate(const IntegrateLaunch& L, int blocks, void* stream, void* ev_start, void* ev_stop)
 {
     if (blocks <= 0) return 0;
-    hipLaunchKernelGGL(mvf_integrate_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, L);
+    if (ev_start)
+        hipExtLaunchKernelGGL(mvf_integrate_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                              (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, L);
+    else
+        hipLaunchKernelGGL(mvf_integrate_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, L);
     return (int)hipGetLastError();
 }
 
@@ -1338,11 +1343,15 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
     }
 }
 
-int launch_raycast(const RaycastLaunch& L, int blocks, void* stream)
+int launch_raycast(const RaycastLaunch& L, int blocks, void* stream, void* ev_start, void* ev_stop)
 {
     if (blocks <= 0) return 0;
-    hipLaunchKernelGGL(mvf_raycast_kernel, dim3(blocks), dim3(L.tile_w * L.tile_h * kRayLanes), 0,
-                       (hipStream_t)stream, L);
+    if (ev_start)
+        hipExtLaunchKernelGGL(mvf_raycast_kernel, dim3(blocks), dim3(L.tile_w * L.tile_h * kRayLanes), 0,
+                              (hipStream_t)stream, (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, L);
+    else
+        hipLaunchKernelGGL(mvf_raycast_kernel, dim3(blocks), dim3(L.tile_w * L.tile_h * kRayLanes), 0,
+                           (hipStream_t)stream, L);
     return (int)hipGetLastError();
 }
 

@@ -685,6 +685,22 @@ mvf_status timing_begin(mvf_ctx* c, hipStream_t stream, hipEvent_t* a)
     return MVF_OK;
 }
 
+// Event pair for a kernel launch that records them itself (timing only).
+mvf_status timing_pair(mvf_ctx* c, hipEvent_t* a, hipEvent_t* b)
+{
+    *a = *b = nullptr;
+    if (!(c->cfg.flags & MVF_FLAG_TIMING)) return MVF_OK;
+    CHECK_ST(get_event(c, a));
+    CHECK_ST(get_event(c, b));
+    return MVF_OK;
+}
+
+mvf_status timing_push(mvf_ctx* c, hipEvent_t a, hipEvent_t b, int kind)
+{
+    if (a) c->timed.push_back(TimedPair{a, b, kind});
+    return MVF_OK;
+}
+
 mvf_status timing_end(mvf_ctx* c, hipStream_t stream, hipEvent_t a, int kind)
 {
     if (!a) return MVF_OK;
@@ -848,10 +864,11 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         for (auto& p : per) {
             IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit, nullptr, nullptr, 0};
             CHECK_LAUNCH(launch_ztable(L, (p.items * kVisitPerItem + 255) / 256, stream));
-            hipEvent_t t0;
-            CHECK_ST(timing_begin(c, stream, &t0));
-            CHECK_LAUNCH(launch_integrate(L, (p.items + 3) / 4, stream));
-            CHECK_ST(timing_end(c, stream, t0, 0));
+            // with timing, the kernel's dispatch records the event pair
+            hipEvent_t t0, t1;
+            CHECK_ST(timing_pair(c, &t0, &t1));
+            CHECK_LAUNCH(launch_integrate(L, (p.items + 3) / 4, stream, t0, t1));
+            CHECK_ST(timing_push(c, t0, t1, 0));
             CHECK_LAUNCH(launch_brick_distance(p.dh, p.dv, p.dbb, std::min(1024, (p.bricks + 255) / 256), stream));
             c->stats.integrate_launches += 1;
         }
@@ -943,14 +960,14 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
         CHECK_ST(arena_upload(c, w, stream));
         // slowest tiles of the stream's last raycast first
         RaycastLaunch L{dh, dvols, dfr, dlists, dlb, dtb, tw, th, sc->tile_cost, sc->tile_order};
-        hipEvent_t t0;
-        CHECK_ST(timing_begin(c, stream, &t0));
+        hipEvent_t t0, t1;
+        CHECK_ST(timing_pair(c, &t0, &t1));
         const RayBounds RB{sc->rb_entries, sc->rb_counts, sc->rb_counts_cap};
         CHECK_LAUNCH(launch_ray_bounds_collect(dh, dvols, dbb, dfr, RB, std::min(1024, (nbr + 255) / 256), stream));
         CHECK_LAUNCH(launch_ray_bounds_merge(dh, dfr, dlists, dlb, dbb, RB, 1, fr->cells_x, fr->cells_y, stream));
         CHECK_LAUNCH(launch_tile_order(sc->tile_cost, sc->tile_order, tiles, stream));
-        CHECK_LAUNCH(launch_raycast(L, ray_blocks(tiles), stream));
-        CHECK_ST(timing_end(c, stream, t0, 1));
+        CHECK_LAUNCH(launch_raycast(L, ray_blocks(tiles), stream, t0, t1));
+        CHECK_ST(timing_push(c, t0, t1, 1));
         CHECK_ST(arena_release(c, slot, stream));
         c->stats.raycast_launches += 1;
     }
