@@ -29,6 +29,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -67,13 +68,20 @@ def render_frames(n_frames: int, total: int = 300):
     return seq, [(by[i], seq.poses[i]) for i in idx]
 
 
-def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=False):
+TUNE_STEPS = 24 + 2   # the autotuner's candidate runs (8 x 3) and two more
+
+
+def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=False, tune_cache=None,
+              tune=False):
     """Wall-clock run of one phase; with timed=True the library also times
     every kernel launch with events (a separate run: the events themselves
-    cost a few microseconds per call)."""
+    cost a few microseconds per call).  Batched phases take their launch
+    schedule from tune_cache (written by a tuning run with tune=True)."""
     origin = (-EXTENT / 2,) * 3
     s = EXTENT / N_VOX
     ctx = mvf.Context(timing=timed)
+    if tune_cache:
+        ctx.autotune("tune" if tune else "cached", tune_cache)
     gid = ctx.grid(origin, s, 4.0, 128)
     if phase in ("single", "single_step"):
         ctx.volume(gid, (0, 0, 0), (N_VOX,) * 3)
@@ -97,6 +105,13 @@ def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=Fals
             ctx.integrate(d, c, poses[i], K)
             ctx.raycast(poses[i], K, W_IMG, H_IMG, out=out)
 
+    if tune:
+        for i in range(TUNE_STEPS):
+            one(i % len(dev_frames))
+        torch.cuda.synchronize()
+        sched = ctx.schedule()
+        ctx.close()
+        return sched
     for i in range(warmup):
         one(i)
     torch.cuda.synchronize()
@@ -109,11 +124,14 @@ def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=Fals
     wall = time.perf_counter() - t0
     st = ctx.stats()
     hit_frac = float((out["depth"] > 0).float().mean())
+    sched = ctx.schedule() if phase in ("batched", "single_step") else None
     ctx.close()
     r = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "voxels_updated": st["voxels_updated"],
          "voxels_band": st["voxels_band"], "integrate_ms": st["integrate_ms"], "raycast_ms": st["raycast_ms"],
          "step_ms": st["step_ms"], "integrate_launches": st["integrate_launches"],
          "raycast_launches": st["raycast_launches"], "hit_fraction_last": hit_frac}
+    if sched:
+        r["schedule"] = sched
     r["voxel_updates_per_s"] = st["voxels_updated"] / wall
     r["raycast_mpix_s"] = steps * W_IMG * H_IMG / wall / 1e6
     if st["integrate_ms"] > 0:
@@ -387,7 +405,15 @@ def main():
         if ph in EXTRA_PHASES:
             phases[ph] = EXTRA_PHASES[ph](mvf, torch)
         else:
-            phases[ph] = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps)
+            cache = None
+            if ph in ("single_step", "batched"):
+                # the batched form's autotuner picks the launch schedule on a
+                # separate context first (untimed)
+                cache = os.path.join(tempfile.mkdtemp(prefix="mvf_tune_"), "schedules.jsonl")
+                run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps, tune_cache=cache,
+                          tune=True)
+            phases[ph] = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps,
+                                   tune_cache=cache)
             if ph in ("single", "tiled"):
                 # per-kernel durations from a second, event-timed run of the same frames
                 t = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps, timed=True)

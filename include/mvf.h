@@ -222,6 +222,43 @@ typedef struct {
 mvf_status mvf_step(mvf_ctx* ctx, int32_t n, const mvf_stream_frame* frames,
                     const mvf_raycast_out* outs, void* stream);
 
+/* Launch schedule of mvf_step (no part of the paper's method: the batched
+ * form's own tuning).  Every schedule gives the same results bit for bit.
+ *   zchunk            bricks per integration work item along z: 1, 2, 4 or 8
+ *   persistent        0: one integration wavefront per work item;
+ *                     1: 8 wavefronts per SIMD walking the items
+ *   ray_lanes         lanes that march one ray together: 2, 4 or 8 (pixel
+ *                     tiles 8x4, 4x4, 4x2)
+ * Default {4, 0, 4}. */
+typedef struct {
+    int32_t zchunk;
+    int32_t persistent;
+    int32_t ray_lanes;
+    int32_t reserved;   /* 0 */
+} mvf_schedule;
+
+/* Fix the schedule of later mvf_step calls (and switch autotuning off).
+ * MVF_ERR_INVALID_ARG for a value outside the lists above. */
+mvf_status mvf_set_schedule(mvf_ctx* ctx, const mvf_schedule* sched);
+/* The schedule the last mvf_step call ran with (the default before any). */
+mvf_status mvf_get_schedule(mvf_ctx* ctx, mvf_schedule* out);
+
+#define MVF_AUTOTUNE_OFF 0      /* fixed schedule (mvf_set_schedule or the default) */
+#define MVF_AUTOTUNE_TUNE 1     /* tune shapes the cache does not hold */
+#define MVF_AUTOTUNE_CACHED 2   /* use the cache; the default schedule for other shapes */
+/* Autotuning of mvf_step.  A step shape is the stream count, the output
+ * sizes, the number of volumes and their brick dimensions.  In TUNE mode
+ * the first steps of a new shape run each candidate schedule three times
+ * (timed with HIP events on the call's stream; the step's results are
+ * unaffected) and the shape keeps the fastest by median; a candidate's
+ * first run also pays its graph capture.  cache_path (may be NULL: memory
+ * only) is a JSON-lines file read now (missing file: empty cache) and
+ * appended to whenever a shape is tuned; one line per shape:
+ * {"key": "...", "zchunk": z, "persistent": p, "ray_lanes": l, "ms": t}.
+ * The string is copied.  MVF_ERR_INVALID_ARG for an unknown mode, a line
+ * that does not parse or a schedule outside the lists. */
+mvf_status mvf_autotune(mvf_ctx* ctx, int32_t mode, const char* cache_path);
+
 /* ---- placement (Dynamic Mapping for SLAM; Insertion and Removal) -------- */
 
 typedef struct {

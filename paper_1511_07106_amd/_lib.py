@@ -21,6 +21,9 @@ MVF_ERR_STATE = 6
 MVF_ERR_UNSUPPORTED = 7
 MVF_FLAG_TIMING = 1
 MVF_EVICT_SWAP_OUT = 1
+MVF_AUTOTUNE_OFF = 0
+MVF_AUTOTUNE_TUNE = 1
+MVF_AUTOTUNE_CACHED = 2
 
 
 class mvf_config(C.Structure):
@@ -66,6 +69,11 @@ class mvf_stream_frame(C.Structure):
                 ("K", mvf_intrinsics)]
 
 
+class mvf_schedule(C.Structure):
+    _fields_ = [("zchunk", C.c_int32), ("persistent", C.c_int32), ("ray_lanes", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class mvf_placement_params(C.Structure):
     _fields_ = [("grid_id", C.c_int32), ("d_v", C.c_int32), ("n_max", C.c_int32), ("beta", C.c_float)]
 
@@ -108,6 +116,9 @@ SIGNATURES = {
     "mvf_integrate": [P, I32, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics), P],
     "mvf_raycast": [P, I32, PF, C.POINTER(mvf_intrinsics), C.POINTER(mvf_raycast_out), P],
     "mvf_step": [P, I32, C.POINTER(mvf_stream_frame), C.POINTER(mvf_raycast_out), P],
+    "mvf_set_schedule": [P, C.POINTER(mvf_schedule)],
+    "mvf_get_schedule": [P, C.POINTER(mvf_schedule)],
+    "mvf_autotune": [P, I32, C.c_char_p],
     "mvf_placement_update": [P, I32, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics),
                              C.POINTER(mvf_placement_params), C.POINTER(mvf_placement_result), P],
     "mvf_placement_count": [P, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics), I32, I32, PI32, PI32,

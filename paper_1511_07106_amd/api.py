@@ -238,6 +238,24 @@ class Context:
             oarr[i] = self._out_struct(outs[i], w, h)
         L.check(self.lib.mvf_step(self.h, n, arr, oarr, _stream(stream)), "mvf_step")
 
+    def set_schedule(self, zchunk: int = 4, persistent: int = 0, ray_lanes: int = 4) -> None:
+        """Fix the launch schedule of step() (switches autotuning off)."""
+        sc = L.mvf_schedule(int(zchunk), int(persistent), int(ray_lanes), 0)
+        L.check(self.lib.mvf_set_schedule(self.h, C.byref(sc)), "mvf_set_schedule")
+
+    def schedule(self) -> Dict[str, int]:
+        """The schedule the last step() ran with."""
+        sc = L.mvf_schedule()
+        L.check(self.lib.mvf_get_schedule(self.h, C.byref(sc)), "mvf_get_schedule")
+        return {"zchunk": sc.zchunk, "persistent": sc.persistent, "ray_lanes": sc.ray_lanes}
+
+    def autotune(self, mode: str = "tune", cache_path: Optional[str] = None) -> None:
+        """mode: 'off', 'tune' (time the candidate schedules on the first
+        steps of each new shape) or 'cached' (use cache_path only)."""
+        m = {"off": L.MVF_AUTOTUNE_OFF, "tune": L.MVF_AUTOTUNE_TUNE, "cached": L.MVF_AUTOTUNE_CACHED}[mode]
+        path = cache_path.encode() if cache_path else None
+        L.check(self.lib.mvf_autotune(self.h, m, path), "mvf_autotune")
+
     # -- placement -----------------------------------------------------------
     def placement_count(self, depth, T, K, grid_id: int, d_v: int, max_cells: int = 8192, stream=None):
         f = self._frame(depth, None)

@@ -185,15 +185,15 @@ struct IntegrateLaunch {
     int32_t* tile_order;
     int32_t order_tiles;
 };
-constexpr int kVisitPerItem = 4;
+constexpr int kVisitPerItem = 8;
 
 // Lanes that march one ray together in the raycast kernel (P consecutive
-// samples per round of gathers), and the pixel tile of a 64-lane block.
+// samples per round of gathers: 2, 4 or 8), and the pixel tile of a
+// 64-lane block for each (8x4, 4x4, 4x2).  kRayLanes is the default.
 constexpr int kRayLanes = 4;
-constexpr int kRayTileW = 4;
-constexpr int kRayTileH = 64 / kRayLanes / kRayTileW;
-constexpr int kBoundCell = 8;   // output pixels per side of a raycast range-bound cell
-static_assert(kBoundCell % kRayTileW == 0 && kBoundCell % kRayTileH == 0, "a ray tile lies in one bound cell");
+MVF_HD int ray_tile_w(int lanes) { return lanes == 2 ? 8 : 4; }
+MVF_HD int ray_tile_h(int lanes) { return 64 / lanes / ray_tile_w(lanes); }
+constexpr int kBoundCell = 8;   // output pixels per side of a raycast range-bound cell (a ray tile lies in one)
 // Raycast launch order: groups of kRayGroup consecutive tiles are ordered by
 // their summed last duration, slowest first.  Blocks are dealt round-robin
 // over the 8 XCDs, so a window of 8 * kRayGroup blocks takes 8 groups, each
@@ -210,7 +210,8 @@ struct RaycastLaunch {
     const int32_t* lists;       // concatenated per-stream lists of table indices, nearest first
     const int32_t* list_base;   // per stream: [list_base[s], list_base[s+1])
     const int32_t* tile_base;   // per stream: first pixel tile; nstreams + 1 entries
-    int32_t tile_w, tile_h;     // pixel tile (tile_w * tile_h * kRayLanes == block size)
+    int32_t tile_w, tile_h;     // pixel tile: ray_tile_w(lanes) x ray_tile_h(lanes)
+    int32_t lanes;              // lanes per ray (2, 4 or 8)
     uint32_t* tile_cost;        // per tile: its duration in the last launch (10 ns ticks), or null
     const int32_t* tile_order;  // tile groups in launch order, or null (index order)
 };

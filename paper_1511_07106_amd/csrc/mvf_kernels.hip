@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
         const int bz0 = zc * zchunk;
         const int bz1 = min(bz0 + zchunk, V.bd[2]);
         // bricks of the item that may hold an updated voxel
-        const uint32_t vis = L.visit ? cptr((const uint32_t*)L.visit)[item] : 0x01010101u;
+        const uint64_t vis = L.visit ? cptr((const uint64_t*)L.visit)[item] : 0x0101010101010101ull;
         if (vis == 0) continue;
 
         // frame parameters, held in registers for the whole item
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
         for (int bz = bz0; bz < bz1; ++bz) {
             const int zb = bz * kBrick;
             const bool mine = zlo < zb + kBrick && zhi > zb;
-            if (!((vis >> (8 * (bz - bz0))) & 1u) || __ballot(mine) == 0) continue;
+            if (!((vis >> (8 * (bz - bz0))) & 1ull) || __ballot(mine) == 0) continue;
             const size_t base = colbase + (size_t)bz * kBrickVox;
             GPTR(float) const pF = vF + base;
             GPTR(uint16_t) const pW = vW + base;
@@ -1212,9 +1212,11 @@ static __host__ __device__ void surface_normal(const DevVolume& V, const float x
 
 // Pixel (u, v) of stream s; j: lane of the pixel's group (the host build
 // marches sequentially with j = 0).
+template <int P>
 static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v,
                                               int j = 0);
 
+template <int P>
 __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
 {
     const LaunchHeader H = *cptr(L.hdr);
@@ -1239,10 +1241,10 @@ __global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
         const int local = tile - tile_base[s];
         const int tiles_x = (out_w + L.tile_w - 1) / L.tile_w;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
-        const int pix = (int)threadIdx.x / kRayLanes;   // kRayLanes lanes per pixel
+        const int pix = (int)threadIdx.x / P;   // P lanes per pixel
         const int u = tx * L.tile_w + pix % L.tile_w;
         const int v = ty * L.tile_h + pix / L.tile_w;
-        if (u < out_w && v < out_h) raycast_pixel(L, H, s, u, v, (int)threadIdx.x % kRayLanes);
+        if (u < out_w && v < out_h) raycast_pixel<P>(L, H, s, u, v, (int)threadIdx.x % P);
         if (L.tile_cost && threadIdx.x == 0) {
             const unsigned long long d = wall_clock64() - t_tile;
             L.tile_cost[tile] = d < 0xffffffffull ? (uint32_t)d : 0xffffffffu;
@@ -1263,6 +1265,7 @@ int launch_tile_order(const uint32_t* cost, int32_t* order, int n, void* stream)
     return (int)hipGetLastError();
 }
 
+template <int P>
 static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const LaunchHeader& H, int s, int u, int v,
                                               int j)
 {
@@ -1310,7 +1313,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
         float ts;
         int ks, cell[3];
 #if defined(__HIP_DEVICE_COMPILE__)
-        const bool found = march_volume_group<kRayLanes>(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell, j);
+        const bool found = march_volume_group<P>(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell, j);
 #else
         const bool found = march_volume(V, r, H.rp.delta, H.rp.kmax, best_t, best_id, ts, ks, cell);
 #endif
@@ -1343,15 +1346,27 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
     }
 }
 
+template <int P>
+static void launch_raycast_p(const RaycastLaunch& L, int blocks, hipStream_t stream, hipEvent_t a, hipEvent_t b)
+{
+    if (a)
+        hipExtLaunchKernelGGL(mvf_raycast_kernel<P>, dim3(blocks), dim3(64), 0, stream, a, b, 0, L);
+    else
+        hipLaunchKernelGGL(mvf_raycast_kernel<P>, dim3(blocks), dim3(64), 0, stream, L);
+}
+
 int launch_raycast(const RaycastLaunch& L, int blocks, void* stream, void* ev_start, void* ev_stop)
 {
     if (blocks <= 0) return 0;
-    if (ev_start)
-        hipExtLaunchKernelGGL(mvf_raycast_kernel, dim3(blocks), dim3(L.tile_w * L.tile_h * kRayLanes), 0,
-                              (hipStream_t)stream, (hipEvent_t)ev_start, (hipEvent_t)ev_stop, 0, L);
-    else
-        hipLaunchKernelGGL(mvf_raycast_kernel, dim3(blocks), dim3(L.tile_w * L.tile_h * kRayLanes), 0,
-                           (hipStream_t)stream, L);
+    if (ray_tile_w(L.lanes) != L.tile_w || ray_tile_h(L.lanes) != L.tile_h) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a = (hipEvent_t)ev_start, b = (hipEvent_t)ev_stop;
+    switch (L.lanes) {
+    case 2: launch_raycast_p<2>(L, blocks, s, a, b); break;
+    case 4: launch_raycast_p<4>(L, blocks, s, a, b); break;
+    case 8: launch_raycast_p<8>(L, blocks, s, a, b); break;
+    default: return (int)hipErrorInvalidValue;
+    }
     return (int)hipGetLastError();
 }
 

@@ -170,6 +170,7 @@ struct StepGraph {
     uint32_t* rb_counts = nullptr;        // 2 * max_vols
     int rb_parity = 0;
     int max_cells_x = 0, max_cells_y = 0;
+    mvf_schedule sched{4, 0, kRayLanes, 0};  // schedule the graph was captured with
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
     int32_t* tile_order = nullptr;
 };
@@ -198,6 +199,18 @@ struct mvf_ctx {
     hipStream_t tail_stream = nullptr;
     bool tail_valid = false;
     int n_cus = 256;
+    // step schedule and its autotuner
+    mvf_schedule fixed_sched{4, 0, kRayLanes, 0};
+    mvf_schedule last_sched{4, 0, kRayLanes, 0};
+    int tune_mode = MVF_AUTOTUNE_OFF;
+    std::string tune_path;
+    std::map<std::string, std::pair<mvf_schedule, double>> tune_cache;  // shape -> (schedule, ms)
+    struct Tuning {
+        std::string key;
+        std::vector<mvf_schedule> cands;
+        int next = 0;                                   // launches issued so far
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // per launch
+    } tuning;
     // placement bookkeeping: per stream, cell -> volume id (volumes created by placement)
     std::map<int, std::map<std::vector<int>, int>> placed;
     unsigned long long* place_table = nullptr;
@@ -892,7 +905,7 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
     CHECK_ST(get_scratch(c, sid, out->width, out->height, multi, &sc));
     RayParams rp{};
     if (!c->grids.empty()) rp = ray_params(c, c->grids[ids.empty() ? 0 : c->vols[ids[0]].d.grid_id]);
-    const int tw = kRayTileW, th = kRayTileH;  // one wavefront per block: free slots refill per wave
+    const int tw = ray_tile_w(kRayLanes), th = ray_tile_h(kRayLanes);  // one wavefront per block
     const int tiles = ((out->width + tw - 1) / tw) * ((out->height + th - 1) / th);
     CHECK_ST(get_tile_buffers(sc, tiles));
     CHECK_ST(get_bound_buffers(sc, out->width, out->height));
@@ -959,7 +972,7 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
         sc->rb_parity ^= 1;
         CHECK_ST(arena_upload(c, w, stream));
         // slowest tiles of the stream's last raycast first
-        RaycastLaunch L{dh, dvols, dfr, dlists, dlb, dtb, tw, th, sc->tile_cost, sc->tile_order};
+        RaycastLaunch L{dh, dvols, dfr, dlists, dlb, dtb, tw, th, kRayLanes, sc->tile_cost, sc->tile_order};
         hipEvent_t t0, t1;
         CHECK_ST(timing_pair(c, &t0, &t1));
         const RayBounds RB{sc->rb_entries, sc->rb_counts, sc->rb_counts_cap};
@@ -1002,6 +1015,161 @@ mvf_status destroy_step_graph(mvf_ctx* c)
     if (g.tile_order) { CHECK_HIP(hipFree(g.tile_order)); g.tile_order = nullptr; }
     g.ztab_cap = 0;
     g.valid = false;
+    return MVF_OK;
+}
+
+// ---- step schedules and their autotuner -------------------------------------
+
+constexpr int kTuneReps = 3;
+
+bool valid_schedule(const mvf_schedule& s)
+{
+    return (s.zchunk == 1 || s.zchunk == 2 || s.zchunk == 4 || s.zchunk == 8) && (s.persistent == 0 || s.persistent == 1) &&
+           (s.ray_lanes == 2 || s.ray_lanes == 4 || s.ray_lanes == 8);
+}
+
+bool same_schedule(const mvf_schedule& a, const mvf_schedule& b)
+{
+    return a.zchunk == b.zchunk && a.persistent == b.persistent && a.ray_lanes == b.ray_lanes;
+}
+
+// Candidates tried for a new shape: every z chunk with both integration
+// grids at 4 lanes per ray, then the other lane counts at the default.
+std::vector<mvf_schedule> tune_candidates()
+{
+    std::vector<mvf_schedule> c;
+    for (int z : {2, 4, 8})
+        for (int p : {0, 1}) c.push_back(mvf_schedule{z, p, kRayLanes, 0});
+    for (int l : {2, 8}) c.push_back(mvf_schedule{4, 0, l, 0});
+    return c;
+}
+
+// Shape of a step: stream count, output sizes, and the brick dimensions of
+// its volumes (as a sorted multiset).
+std::string step_key(mvf_ctx* c, int n, const mvf_raycast_out* outs, const std::vector<int>& all)
+{
+    std::string k = "n" + std::to_string(n) + ":";
+    for (int i = 0; i < n; ++i) k += std::to_string(outs[i].width) + "x" + std::to_string(outs[i].height) + ",";
+    std::map<std::string, int> dims;
+    for (int id : all) {
+        const Volume& v = c->vols[id];
+        dims[std::to_string(v.bd[0]) + "x" + std::to_string(v.bd[1]) + "x" + std::to_string(v.bd[2])] += 1;
+    }
+    k += "|";
+    for (auto& d : dims) k += d.first + "*" + std::to_string(d.second) + ",";
+    return k;
+}
+
+mvf_status read_tune_cache(mvf_ctx* c, const std::string& path)
+{
+    FILE* f = fopen(path.c_str(), "r");
+    if (!f) return MVF_OK;   // no cache yet
+    char line[4096];
+    int ln = 0;
+    mvf_status st = MVF_OK;
+    while (fgets(line, sizeof line, f)) {
+        ++ln;
+        std::string L(line);
+        if (L.find_first_not_of(" \t\r\n") == std::string::npos) continue;
+        auto field = [&](const char* name, std::string* sval, double* dval) {
+            const std::string pat = std::string("\"") + name + "\":";
+            size_t p = L.find(pat);
+            if (p == std::string::npos) return false;
+            p += pat.size();
+            while (p < L.size() && L[p] == ' ') ++p;
+            if (sval) {
+                if (p >= L.size() || L[p] != '"') return false;
+                const size_t e = L.find('"', p + 1);
+                if (e == std::string::npos) return false;
+                *sval = L.substr(p + 1, e - p - 1);
+                return true;
+            }
+            char* end = nullptr;
+            *dval = strtod(L.c_str() + p, &end);
+            return end != L.c_str() + p;
+        };
+        std::string key;
+        double z, pe, la, ms = 0.0;
+        if (!field("key", &key, nullptr) || !field("zchunk", nullptr, &z) || !field("persistent", nullptr, &pe) ||
+            !field("ray_lanes", nullptr, &la)) {
+            st = set_error(MVF_ERR_INVALID_ARG, "autotune cache %s line %d does not parse", path.c_str(), ln);
+            break;
+        }
+        field("ms", nullptr, &ms);
+        const mvf_schedule sc{(int32_t)z, (int32_t)pe, (int32_t)la, 0};
+        if (!valid_schedule(sc)) {
+            st = set_error(MVF_ERR_INVALID_ARG, "autotune cache %s line %d: schedule out of range", path.c_str(), ln);
+            break;
+        }
+        c->tune_cache[key] = std::make_pair(sc, ms);
+    }
+    fclose(f);
+    return st;
+}
+
+void append_tune_cache(mvf_ctx* c, const std::string& key, const mvf_schedule& sc, double ms)
+{
+    if (c->tune_path.empty()) return;
+    FILE* f = fopen(c->tune_path.c_str(), "a");
+    if (!f) return;   // the cache is an optimisation: an unwritable path keeps the result in memory only
+    fprintf(f, "{\"key\": \"%s\", \"zchunk\": %d, \"persistent\": %d, \"ray_lanes\": %d, \"ms\": %.5f}\n",
+            key.c_str(), sc.zchunk, sc.persistent, sc.ray_lanes, ms);
+    fclose(f);
+}
+
+// Schedule for a step of shape `key`; *tuning set when this launch is a
+// timed candidate run.
+mvf_schedule pick_schedule(mvf_ctx* c, const std::string& key, bool* tuning)
+{
+    *tuning = false;
+    if (c->tune_mode == MVF_AUTOTUNE_OFF) return c->fixed_sched;
+    auto it = c->tune_cache.find(key);
+    if (it != c->tune_cache.end()) return it->second.first;
+    if (c->tune_mode == MVF_AUTOTUNE_CACHED) return mvf_schedule{4, 0, kRayLanes, 0};
+    mvf_ctx::Tuning& T = c->tuning;
+    if (T.key != key) {
+        for (auto& e : T.ev) {
+            c->event_pool.push_back(e.first);
+            c->event_pool.push_back(e.second);
+        }
+        T = mvf_ctx::Tuning{};
+        T.key = key;
+        T.cands = tune_candidates();
+    }
+    *tuning = true;
+    return T.cands[(size_t)(T.next / kTuneReps) % T.cands.size()];
+}
+
+// After the last timed launch of a shape: the fastest candidate by median
+// becomes the shape's schedule.
+mvf_status finish_tuning(mvf_ctx* c)
+{
+    mvf_ctx::Tuning& T = c->tuning;
+    if (T.next < (int)T.cands.size() * kTuneReps) return MVF_OK;
+    CHECK_HIP(hipEventSynchronize(T.ev.back().second));
+    int best = 0;
+    double best_ms = 1e300;
+    for (size_t ci = 0; ci < T.cands.size(); ++ci) {
+        std::vector<float> ms;
+        for (int r = 0; r < kTuneReps; ++r) {
+            const auto& e = T.ev[ci * kTuneReps + r];
+            float t = 0.0f;
+            CHECK_HIP(hipEventElapsedTime(&t, e.first, e.second));
+            ms.push_back(t);
+        }
+        std::sort(ms.begin(), ms.end());
+        if (ms[kTuneReps / 2] < best_ms) {
+            best_ms = ms[kTuneReps / 2];
+            best = (int)ci;
+        }
+    }
+    c->tune_cache[T.key] = std::make_pair(T.cands[best], best_ms);
+    append_tune_cache(c, T.key, T.cands[best], best_ms);
+    for (auto& e : T.ev) {
+        c->event_pool.push_back(e.first);
+        c->event_pool.push_back(e.second);
+    }
+    T = mvf_ctx::Tuning{};
     return MVF_OK;
 }
 
@@ -1116,6 +1284,10 @@ mvf_status mvf_destroy(mvf_ctx* c)
         (void)hipEventDestroy(t.b);
     }
     for (auto ev : c->event_pool) (void)hipEventDestroy(ev);
+    for (auto& e : c->tuning.ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
     for (int i = 0; i < Arena::kSlots; ++i)
         if (c->arena.ev[i]) (void)hipEventDestroy(c->arena.ev[i]);
     if (c->arena.host) (void)hipHostFree(c->arena.host);
@@ -1516,6 +1688,9 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
                          (unsigned long long)total);
     CHECK_ST(ensure_resident(c, all, s));
 
+    bool tuning = false;
+    const std::string key = step_key(c, n, outs, all);
+    const mvf_schedule sch = pick_schedule(c, key, &tuning);
     StepGraph& G = c->step;
     int max_w = 0, max_h = 0;
     for (int i = 0; i < n; ++i) {
@@ -1526,18 +1701,20 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     for (int id : all) {
         const Volume& v = c->vols[id];
         ztotal += kBrick * v.bd[2];
-        items_total += v.bd[0] * v.bd[1] * ((v.bd[2] + kZChunk - 1) / kZChunk);
+        items_total += v.bd[0] * v.bd[1] * ((v.bd[2] + sch.zchunk - 1) / sch.zchunk);
         bricks_total += (int)align_up(v.nbricks, 64);
     }
     bool same_shape = G.valid && G.n == n && (int)all.size() <= G.max_vols && max_w <= G.max_w && max_h <= G.max_h &&
-                      ztotal <= G.ztab_cap && items_total <= G.visit_cap && bricks_total <= G.rb_entries_cap;
+                      ztotal <= G.ztab_cap && items_total <= G.visit_cap && bricks_total <= G.rb_entries_cap &&
+                      same_schedule(sch, G.sched);
     if (same_shape) {
         for (int i = 0; i < n; ++i)
             if (G.out_w[i] != outs[i].width || G.out_h[i] != outs[i].height) same_shape = false;
     }
-    const int tw = kRayTileW, th = kRayTileH;  // one wavefront per block: free slots refill per wave
+    const int tw = ray_tile_w(sch.ray_lanes), th = ray_tile_h(sch.ray_lanes);  // one wavefront per block
     if (!same_shape) {
         CHECK_ST(destroy_step_graph(c));
+        G.sched = sch;
         G.n = n;
         G.max_vols = std::max<int>((int)all.size() * 2, 16);
         G.max_w = max_w;
@@ -1610,7 +1787,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     int items = 0;
     int zt = 0;
     int tiles = 0;
-    const int zc = kZChunk;
+    const int zc = sch.zchunk;
     lb[0] = 0;
     tb[0] = 0;
     for (int i = 0; i < n; ++i) {
@@ -1699,14 +1876,14 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items * kVisitPerItem + 255) / 256), cs);
         // one wavefront per work item of the captured volume set (a larger
         // set later is walked by the kernel's grid-stride loop)
-        G.integ_blocks = std::max(c->n_cus * 8, (items + 3) / 4) + 1;
+        G.integ_blocks = (sch.persistent ? c->n_cus * 8 : std::max(c->n_cus * 8, (items + 3) / 4)) + 1;
         if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
         // the last distance pass also collects the raycast range-bound
         // footprints; the merge folds them per cell
         const RayBounds RB{G.rb_entries, G.rb_counts, G.max_vols};
         if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs, dframes, RB);
         if (!e2) e2 = launch_ray_bounds_merge(dh, dframes, dlists, dlb, dbb, RB, n, G.max_cells_x, G.max_cells_y, cs);
-        RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th, G.tile_cost, G.tile_order};
+        RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th, sch.ray_lanes, G.tile_cost, G.tile_order};
         int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
         hipError_t ee = hipStreamEndCapture(cs, &G.graph);
         if (e3) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString((hipError_t)e3));
@@ -1730,12 +1907,54 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
     }
     hipEvent_t t0;
     CHECK_ST(timing_begin(c, s, &t0));
+    hipEvent_t tune_a = nullptr, tune_b = nullptr;
+    if (tuning) {
+        CHECK_ST(get_event(c, &tune_a));
+        CHECK_ST(get_event(c, &tune_b));
+        CHECK_HIP(hipEventRecord(tune_a, s));
+    }
     CHECK_HIP(hipGraphLaunch(G.exec, s));
+    if (tuning) {
+        CHECK_HIP(hipEventRecord(tune_b, s));
+        c->tuning.ev.push_back(std::make_pair(tune_a, tune_b));
+        c->tuning.next += 1;
+    }
     CHECK_ST(timing_end(c, s, t0, 2));
+    c->last_sched = sch;
     CHECK_ST(arena_release(c, slot, s));  // reused once the replay that reads it is done
+    if (tuning) CHECK_ST(finish_tuning(c));
     c->stats.step_launches += 1;
     for (int i = 0; i < n; ++i) c->stats.pixels_raycast += (uint64_t)outs[i].width * outs[i].height;
     return mark_tail_recorded(c, s, c->arena.ev[slot]);
+}
+
+mvf_status mvf_set_schedule(mvf_ctx* c, const mvf_schedule* sched)
+{
+    if (!c || !sched) return set_error(MVF_ERR_INVALID_ARG, "ctx or schedule is NULL");
+    if (!valid_schedule(*sched) || sched->reserved != 0)
+        return set_error(MVF_ERR_INVALID_ARG, "schedule {%d, %d, %d} out of range", sched->zchunk, sched->persistent,
+                         sched->ray_lanes);
+    c->fixed_sched = *sched;
+    c->tune_mode = MVF_AUTOTUNE_OFF;
+    return MVF_OK;
+}
+
+mvf_status mvf_get_schedule(mvf_ctx* c, mvf_schedule* out)
+{
+    if (!c || !out) return set_error(MVF_ERR_INVALID_ARG, "ctx or out is NULL");
+    *out = c->last_sched;
+    return MVF_OK;
+}
+
+mvf_status mvf_autotune(mvf_ctx* c, int32_t mode, const char* cache_path)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    if (mode != MVF_AUTOTUNE_OFF && mode != MVF_AUTOTUNE_TUNE && mode != MVF_AUTOTUNE_CACHED)
+        return set_error(MVF_ERR_INVALID_ARG, "autotune mode %d", mode);
+    c->tune_path = cache_path ? cache_path : "";
+    if (!c->tune_path.empty()) CHECK_ST(read_tune_cache(c, c->tune_path));
+    c->tune_mode = mode;
+    return MVF_OK;
 }
 
 // ---- placement ------------------------------------------------------------------

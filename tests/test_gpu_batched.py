@@ -78,3 +78,78 @@ def test_step_equals_plain(mvf, n_streams):
         for a, b in zip(fa, fb):
             for k in a:
                 np.testing.assert_array_equal(a[k].view(np.uint8), b[k].view(np.uint8))
+
+
+def _run_steps(mvf, seqs, layouts, n_frames, configure=None):
+    import torch
+    origin, s = (-1.0, -1.0, -1.0), 2.0 / 64
+    K = seqs[0].K.as_array()
+    w, h = seqs[0].K.width, seqs[0].K.height
+    n = len(seqs)
+    with mvf.Context() as ctx:
+        if configure:
+            configure(ctx)
+        gid = ctx.grid(origin, s)
+        ids = [[ctx.volume(gid, off, dims, stream_id=i) for off, dims in layouts[i]] for i in range(n)]
+        maps, scheds = [], []
+        for f in range(n_frames):
+            frames = []
+            for i, seq in enumerate(seqs):
+                d, c = seq.frame(f % 12)
+                frames.append((i, t(d), t(c), seq.poses[f % 12], K))
+            outs = [{"depth": torch.empty((h, w), device="cuda"), "vertex": torch.empty((h, w, 3), device="cuda"),
+                     "normal": torch.empty((h, w, 3), device="cuda"),
+                     "hit": torch.empty((h, w), dtype=torch.int32, device="cuda")} for _ in range(n)]
+            ctx.step(frames, outs)
+            scheds.append(ctx.schedule())
+            maps.append([{k: v.cpu().numpy() for k, v in o.items()} for o in outs])
+        vols = [[ctx.read_volume(v) for v in per] for per in ids]
+    return maps, vols, scheds
+
+
+def _assert_same(a, b):
+    (m0, v0, _), (m1, v1, _) = a, b
+    for x, y in zip(v0, v1):
+        for p, q in zip(x, y):
+            for u, v in zip(p, q):
+                np.testing.assert_array_equal(u.view(np.uint8), v.view(np.uint8))
+    for fa, fb in zip(m0, m1):
+        for x, y in zip(fa, fb):
+            for k in x:
+                np.testing.assert_array_equal(x[k].view(np.uint8), y[k].view(np.uint8))
+
+
+@pytest.mark.parametrize("sched", [(1, 0, 4), (2, 1, 4), (8, 0, 4), (8, 1, 2), (4, 1, 8)])
+def test_every_schedule_gives_the_same_bits(mvf, sched):
+    """Schedules change the work decomposition only: z chunk, integration
+    grid and lanes per ray leave every output and voxel bit-identical."""
+    seqs, layouts = _scenes(3)
+    log(f"schedule {sched} vs default")
+    ref = _run_steps(mvf, seqs, layouts, 6)
+    got = _run_steps(mvf, seqs, layouts, 6, lambda ctx: ctx.set_schedule(*sched))
+    assert all(s == {"zchunk": sched[0], "persistent": sched[1], "ray_lanes": sched[2]} for s in got[2])
+    _assert_same(ref, got)
+
+
+def test_autotune_tunes_caches_and_keeps_results(mvf, tmp_path):
+    """TUNE mode runs each candidate three times on the first steps of a new
+    shape, then keeps the fastest and appends it to the cache; CACHED mode
+    reads it back.  Results equal the default schedule's throughout."""
+    seqs, layouts = _scenes(2)
+    path = str(tmp_path / "tune.jsonl")
+    log("autotune: 8 candidates x 3 runs + 4 steps")
+    ref = _run_steps(mvf, seqs, layouts, 28)
+    got = _run_steps(mvf, seqs, layouts, 28, lambda ctx: ctx.autotune("tune", path))
+    _assert_same(ref, got)
+    lines = open(path).read().strip().splitlines()
+    assert len(lines) == 1
+    import json
+    rec = json.loads(lines[0])
+    chosen = {k: rec[k] for k in ("zchunk", "persistent", "ray_lanes")}
+    assert rec["ms"] > 0
+    # the tuning steps ran the candidates in order, then the chosen one stays
+    assert got[2][0] == {"zchunk": 2, "persistent": 0, "ray_lanes": 4}
+    assert all(s == chosen for s in got[2][24:])
+    cached = _run_steps(mvf, seqs, layouts, 2, lambda ctx: ctx.autotune("cached", path))
+    assert all(s == chosen for s in cached[2])
+    assert len(open(path).read().strip().splitlines()) == 1
