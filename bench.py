@@ -229,8 +229,12 @@ def phase_multi(mvf, torch, n_rooms=32, n_render=3, steps=10, warmup=2):
     log(f"multi: rendered {n_rooms * n_render} frames in {time.time() - t0:.1f}s")
     K = S.K_VGA.as_array()
     res = {}
-    for mode in ("batched", "plain"):
+    cache = os.path.join(tempfile.mkdtemp(prefix="mvf_tune_"), "schedules.jsonl")
+    for mode in ("tune", "batched", "plain"):
         with mvf.Context(timing=False) as ctx:
+            if mode != "plain":
+                # the batched form's schedule: tuned on a separate context first
+                ctx.autotune("tune" if mode == "tune" else "cached", cache)
             gid = ctx.grid((-2.0, -2.0, -2.0), s, 4.0, 128)
             nvol = 0
             vox = 0
@@ -246,7 +250,7 @@ def phase_multi(mvf, torch, n_rooms=32, n_render=3, steps=10, warmup=2):
 
             def one(j):
                 fi = j % n_render
-                if mode == "batched":
+                if mode != "plain":
                     ctx.step([(i, frames[i][fi][0], frames[i][fi][1], rooms[i].poses[fi], K)
                               for i in range(n_rooms)], outs)
                 else:
@@ -254,6 +258,12 @@ def phase_multi(mvf, torch, n_rooms=32, n_render=3, steps=10, warmup=2):
                         ctx.integrate(frames[i][fi][0], frames[i][fi][1], rooms[i].poses[fi], K, stream_id=i)
                         ctx.raycast(rooms[i].poses[fi], K, W_IMG, H_IMG, stream_id=i, out=outs[i])
 
+            if mode == "tune":
+                for j in range(TUNE_STEPS):
+                    one(j)
+                torch.cuda.synchronize()
+                res["schedule"] = ctx.schedule()
+                continue
             for j in range(warmup):
                 one(j)
             torch.cuda.synchronize()
