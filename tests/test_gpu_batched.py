@@ -153,3 +153,24 @@ def test_autotune_tunes_caches_and_keeps_results(mvf, tmp_path):
     cached = _run_steps(mvf, seqs, layouts, 2, lambda ctx: ctx.autotune("cached", path))
     assert all(s == chosen for s in cached[2])
     assert len(open(path).read().strip().splitlines()) == 1
+
+
+def test_autotune_rejects_bad_arguments(mvf, tmp_path):
+    """Errors of the schedule API: an unknown mode, a cache line that does
+    not parse, a schedule outside the lists."""
+    from paper_1511_07106_amd import _lib as L
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"key": "n1:", "zchunk": 4}\n')
+    out_of_range = tmp_path / "range.jsonl"
+    out_of_range.write_text('{"key": "n1:", "zchunk": 3, "persistent": 0, "ray_lanes": 4, "ms": 1.0}\n')
+    with mvf.Context() as ctx:
+        for call in (lambda: ctx.lib.mvf_autotune(ctx.h, 7, None),
+                     lambda: ctx.lib.mvf_autotune(ctx.h, 1, str(bad).encode()),
+                     lambda: ctx.lib.mvf_autotune(ctx.h, 2, str(out_of_range).encode())):
+            assert call() == L.MVF_ERR_INVALID_ARG
+        with pytest.raises(L.MvfError):
+            ctx.set_schedule(3, 0, 4)
+        with pytest.raises(L.MvfError):
+            ctx.set_schedule(4, 0, 16)
+        ctx.autotune("cached", str(tmp_path / "missing.jsonl"))   # a missing file is an empty cache
+        assert ctx.schedule() == {"zchunk": 4, "persistent": 0, "ray_lanes": 4}
