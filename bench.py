@@ -68,7 +68,7 @@ def render_frames(n_frames: int, total: int = 300):
     return seq, [(by[i], seq.poses[i]) for i in idx]
 
 
-TUNE_STEPS = 24 + 2   # the autotuner's candidate runs (8 x 3) and two more
+TUNE_STEPS = 32 + 2   # the autotuner's candidate runs (8 x 4) and two more
 
 
 def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=False, tune_cache=None,
@@ -80,8 +80,8 @@ def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=Fals
     origin = (-EXTENT / 2,) * 3
     s = EXTENT / N_VOX
     ctx = mvf.Context(timing=timed)
-    if tune_cache:
-        ctx.autotune("tune" if tune else "cached", tune_cache)
+    if tune_cache and not tune:
+        ctx.autotune("cached", tune_cache)
     gid = ctx.grid(origin, s, 4.0, 128)
     if phase in ("single", "single_step"):
         ctx.volume(gid, (0, 0, 0), (N_VOX,) * 3)
@@ -106,7 +106,11 @@ def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=Fals
             ctx.raycast(poses[i], K, W_IMG, H_IMG, out=out)
 
     if tune:
-        for i in range(TUNE_STEPS):
+        # tune on the frames the timed run sees, after the same warm-up
+        for i in range(warmup):
+            one(i)
+        ctx.autotune("tune", tune_cache)
+        for i in range(warmup, warmup + TUNE_STEPS):
             one(i % len(dev_frames))
         torch.cuda.synchronize()
         sched = ctx.schedule()

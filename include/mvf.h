@@ -248,10 +248,12 @@ mvf_status mvf_get_schedule(mvf_ctx* ctx, mvf_schedule* out);
 #define MVF_AUTOTUNE_CACHED 2   /* use the cache; the default schedule for other shapes */
 /* Autotuning of mvf_step.  A step shape is the stream count, the output
  * sizes, the number of volumes and their brick dimensions.  In TUNE mode
- * the first steps of a new shape run each candidate schedule three times
- * (timed with HIP events on the call's stream; the step's results are
- * unaffected) and the shape keeps the fastest by median; a candidate's
- * first run also pays its graph capture.  cache_path (may be NULL: memory
+ * the first 32 steps of a new shape run each of 8 candidate schedules four
+ * times in a row (timed with HIP events on the call's stream; the step's
+ * results are unaffected) and the shape keeps the fastest by the median of
+ * the last three runs (the first pays the graph capture).  Tune on
+ * representative frames: the fastest schedule depends on how much of the
+ * volumes the frames see.  cache_path (may be NULL: memory
  * only) is a JSON-lines file read now (missing file: empty cache) and
  * appended to whenever a shape is tuned; one line per shape:
  * {"key": "...", "zchunk": z, "persistent": p, "ray_lanes": l, "ms": t}.

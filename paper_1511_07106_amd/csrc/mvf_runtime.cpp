@@ -1020,7 +1020,9 @@ mvf_status destroy_step_graph(mvf_ctx* c)
 
 // ---- step schedules and their autotuner -------------------------------------
 
-constexpr int kTuneReps = 3;
+// runs per candidate; the first (which pays the graph capture and starts the
+// raycast tile order afresh) is not counted
+constexpr int kTuneReps = 4;
 
 bool valid_schedule(const mvf_schedule& s)
 {
@@ -1151,15 +1153,16 @@ mvf_status finish_tuning(mvf_ctx* c)
     double best_ms = 1e300;
     for (size_t ci = 0; ci < T.cands.size(); ++ci) {
         std::vector<float> ms;
-        for (int r = 0; r < kTuneReps; ++r) {
+        for (int r = 1; r < kTuneReps; ++r) {
             const auto& e = T.ev[ci * kTuneReps + r];
             float t = 0.0f;
             CHECK_HIP(hipEventElapsedTime(&t, e.first, e.second));
             ms.push_back(t);
         }
         std::sort(ms.begin(), ms.end());
-        if (ms[kTuneReps / 2] < best_ms) {
-            best_ms = ms[kTuneReps / 2];
+        const float med = ms[ms.size() / 2];
+        if (med < best_ms) {
+            best_ms = med;
             best = (int)ci;
         }
     }

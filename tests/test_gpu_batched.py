@@ -132,14 +132,14 @@ def test_every_schedule_gives_the_same_bits(mvf, sched):
 
 
 def test_autotune_tunes_caches_and_keeps_results(mvf, tmp_path):
-    """TUNE mode runs each candidate three times on the first steps of a new
+    """TUNE mode runs each candidate four times on the first steps of a new
     shape, then keeps the fastest and appends it to the cache; CACHED mode
     reads it back.  Results equal the default schedule's throughout."""
     seqs, layouts = _scenes(2)
     path = str(tmp_path / "tune.jsonl")
-    log("autotune: 8 candidates x 3 runs + 4 steps")
-    ref = _run_steps(mvf, seqs, layouts, 28)
-    got = _run_steps(mvf, seqs, layouts, 28, lambda ctx: ctx.autotune("tune", path))
+    log("autotune: 8 candidates x 4 runs + 4 steps")
+    ref = _run_steps(mvf, seqs, layouts, 36)
+    got = _run_steps(mvf, seqs, layouts, 36, lambda ctx: ctx.autotune("tune", path))
     _assert_same(ref, got)
     lines = open(path).read().strip().splitlines()
     assert len(lines) == 1
@@ -149,7 +149,7 @@ def test_autotune_tunes_caches_and_keeps_results(mvf, tmp_path):
     assert rec["ms"] > 0
     # the tuning steps ran the candidates in order, then the chosen one stays
     assert got[2][0] == {"zchunk": 2, "persistent": 0, "ray_lanes": 4}
-    assert all(s == chosen for s in got[2][24:])
+    assert all(s == chosen for s in got[2][32:])
     cached = _run_steps(mvf, seqs, layouts, 2, lambda ctx: ctx.autotune("cached", path))
     assert all(s == chosen for s in cached[2])
     assert len(open(path).read().strip().splitlines()) == 1
