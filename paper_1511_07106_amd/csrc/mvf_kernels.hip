@@ -956,19 +956,10 @@ static __host__ __device__ __forceinline__ int skip_run(const DevVolume& V, cons
         for (int a = 0; a < 3; ++a) lo[a] = hi[a] = (i[a] & 7) >> 1;
         if ((subblock_box(lo, hi) & sc.cm) == 0) {
             skip = true;
+            // grown over clear sub-blocks along the ray (x, then y, then z)
+            grow_clear_box(sc.cm, lo, hi, dl);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                if (dl[a] > 0.0f) {
-                    while (hi[a] < 3) {
-                        ++hi[a];
-                        if (subblock_box(lo, hi) & sc.cm) { --hi[a]; break; }
-                    }
-                } else if (dl[a] < 0.0f) {
-                    while (lo[a] > 0) {
-                        --lo[a];
-                        if (subblock_box(lo, hi) & sc.cm) { ++lo[a]; break; }
-                    }
-                }
                 A[a] = (i[a] & ~7) + 2 * lo[a];
                 B[a] = (i[a] & ~7) + 2 * hi[a] + 2;
             }

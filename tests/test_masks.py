@@ -26,6 +26,8 @@ def lib():
     L.t_subblock_box.restype = C.c_uint64
     L.t_cell_mask.argtypes = [C.POINTER(C.c_uint64)]
     L.t_cell_mask.restype = C.c_uint64
+    L.t_grow_clear_box.argtypes = [C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_float)]
+    L.t_grow_clear_box.restype = None
     return L
 
 
@@ -129,3 +131,50 @@ def test_fmask_and_cell_mask_cover_flagged_corners(lib):
                     if fl[z:z + 2, y:y + 2, x:x + 2].any():
                         X, Y, Z = x // 2, y // 2, z // 2
                         assert (int(cm[X // 4, Y // 4, Z // 4]) >> ((Z % 4) * 16 + (Y % 4) * 4 + X % 4)) & 1
+
+
+def _box_bits(lo, hi):
+    m = 0
+    for z in range(lo[2], hi[2] + 1):
+        for y in range(lo[1], hi[1] + 1):
+            for x in range(lo[0], hi[0] + 1):
+                m |= bit((x, y, z))
+    return m
+
+
+def test_grow_clear_box_matches_stepwise_growth(lib):
+    """The raycast's skip box: from a clear sub-block, grown along x, then y,
+    then z towards the ray direction one sub-block at a time while it stays
+    clear (brute force here) -- the helper reaches the same box directly."""
+    rng = np.random.default_rng(5)
+    n = 0
+    for trial in range(3000):
+        dens = (0.02, 0.1, 0.3)[trial % 3]
+        cm = 0
+        for b in range(64):
+            if rng.random() < dens:
+                cm |= 1 << b
+        s = [int(v) for v in rng.integers(0, 4, 3)]
+        if cm & bit(s):
+            continue
+        d = [float(rng.choice([-1.0, 0.0, 1.0])) for _ in range(3)]
+        lo, hi = list(s), list(s)
+        for a in range(3):
+            if d[a] > 0:
+                while hi[a] < 3:
+                    hi[a] += 1
+                    if cm & _box_bits(lo, hi):
+                        hi[a] -= 1
+                        break
+            elif d[a] < 0:
+                while lo[a] > 0:
+                    lo[a] -= 1
+                    if cm & _box_bits(lo, hi):
+                        lo[a] += 1
+                        break
+        clo, chi = (C.c_int * 3)(*s), (C.c_int * 3)(*s)
+        lib.t_grow_clear_box(cm, clo, chi, (C.c_float * 3)(*d))
+        assert (list(clo), list(chi)) == (lo, hi), (hex(cm), s, d)
+        assert cm & _box_bits(lo, hi) == 0
+        n += 1
+    assert n > 1000
