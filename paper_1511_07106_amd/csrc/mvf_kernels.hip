@@ -811,6 +811,24 @@ static __host__ __device__ __forceinline__ bool eval_sample_cached(const DevVolu
     return !isnan(Fk);
 }
 
+// The same without the cache (the group march: a lane's successive samples
+// are a window apart, rarely in one cell).
+static __device__ __forceinline__ bool eval_sample(const DevVolume& V, const float l[3], float& Fk)
+{
+    int i[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float fl = floorf(l[a]);
+        i[a] = (int)fl;
+        f[a] = l[a] - fl;
+    }
+    float c[8];
+    gather8(V, i, c);
+    Fk = trilinear(c, f);
+    return !isnan(Fk);
+}
+
 // Conservative sample range [k0, k1] of the ray inside V's domain box grown
 // by one voxel, plus two samples each side.
 // Raycast range bounds.  Every sample the march must evaluate (a possible
@@ -1093,8 +1111,6 @@ static __device__ bool march_volume_group(const DevVolume& V, const Ray& r, floa
     sc.b = 0xffffffffu;
     sc.D = 0;
     sc.cm = 0;
-    CellCache cc;
-    cc.i[0] = -1; cc.i[1] = -1; cc.i[2] = -1;
     int prev_k = -2;
     bool prev_ok = false;
     float Fprev = 0.0f;
@@ -1130,7 +1146,7 @@ static __device__ bool march_volume_group(const DevVolume& V, const Ray& r, floa
         }
         float Fk = 0.0f;
         bool ok = false;
-        if (dom) ok = eval_sample_cached(V, l, Fk, cc);
+        if (dom) ok = eval_sample(V, l, Fk);
         float Fn = __shfl_up(Fk, 1, P);
         int okn = __shfl_up((int)ok, 1, P);
         if (j == 0) { Fn = Fprev; okn = prev_ok; }
