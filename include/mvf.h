@@ -178,6 +178,17 @@ mvf_status mvf_volume_read(mvf_ctx* ctx, int32_t vol_id, float* F, uint16_t* W, 
  * to their empty value. */
 mvf_status mvf_volume_write(mvf_ctx* ctx, int32_t vol_id, const float* F, const uint16_t* W,
                             const uint8_t* rgba);
+/* Synchronising.  Copy the volume's brick summaries to host buffers of
+ * nb = bx * by * bz bytes each, where (bx, by, bz) = ceil(dims / 8), in
+ * brick order (index (x * by + y) * bz + z, z fastest).  flag: 1 if some
+ * voxel of the 8^3 brick may hold F <= 2^-100 (set when an update writes
+ * such a value, never cleared except by mvf_volume_write), else 0.  dist:
+ * the Chebyshev distance in bricks to the nearest flagged brick, capped at
+ * 12, as of the last integration or write.  These are the exact-skip
+ * structures of the raycast (the zero crossing can only lie in a cell with
+ * a corner F <= 0, Raycasting section); a diagnostic for tests.  Either
+ * pointer may be NULL. */
+mvf_status mvf_volume_brick_summary(mvf_ctx* ctx, int32_t vol_id, uint8_t* flag, uint8_t* dist);
 /* The descriptor a volume was created with (also for volumes the
  * placement step created). */
 mvf_status mvf_volume_describe(mvf_ctx* ctx, int32_t vol_id, mvf_volume_desc* out);

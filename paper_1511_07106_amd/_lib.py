@@ -110,6 +110,7 @@ SIGNATURES = {
     "mvf_volume_swap_in": [P, I32, P],
     "mvf_volume_swap_out": [P, I32, P],
     "mvf_volume_read": [P, I32, P, P, P],
+    "mvf_volume_brick_summary": [P, I32, P, P],
     "mvf_volume_write": [P, I32, P, P, P],
     "mvf_volume_query": [P, I32, PI32, C.POINTER(C.c_uint64), PI32],
     "mvf_volume_describe": [P, I32, C.POINTER(mvf_volume_desc)],

@@ -165,6 +165,16 @@ class Context:
                 "mvf_volume_read")
         return F, W, Cc
 
+    def brick_summary(self, vid: int):
+        """(flag, dist) uint8 arrays of shape (bx, by, bz) = ceil(dims / 8):
+        the raycast's exact-skip flags and capped Chebyshev distances."""
+        nb = [(d + 7) // 8 for d in self.dims(vid)]
+        flag = np.zeros(nb, np.uint8)
+        dist = np.zeros(nb, np.uint8)
+        L.check(self.lib.mvf_volume_brick_summary(self.h, int(vid), flag.ctypes.data_as(C.c_void_p),
+                                                  dist.ctypes.data_as(C.c_void_p)), "mvf_volume_brick_summary")
+        return flag, dist
+
     def write_volume(self, vid: int, F=None, W=None, rgba=None) -> None:
         nx, ny, nz = self.dims(vid)
         arrs = []

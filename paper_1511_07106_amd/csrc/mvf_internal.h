@@ -22,7 +22,11 @@
 //                  flagged brick, capped at kDistCap (0 = flagged); every
 //                  brick within dist - 1 of this one is unflagged.  Derived
 //                  from the flags after each integration.
-//   tmp   2 x uint8 per brick: passes of the distance transform.
+//   colm  uint64   per brick column (bx, by) and 64 bricks of it along z:
+//                  word (bx * bd[1] + by) * col_words(bd[2]) + (bz >> 6),
+//                  bit bz & 63 equal to the brick's flag (maintained with
+//                  the flags; the distance transform reads only these),
+//                  then one word that is always zero.
 //   fmask uint64   per brick: bit z2 * 16 + y2 * 4 + x2 set if some voxel of
 //                  the 2x2x2 sub-block (x2, y2, z2) of the brick may hold
 //                  F <= 2^-100 (same monotone rule as flag, which equals
@@ -52,13 +56,16 @@ constexpr int kBrickVox = 512;
 constexpr float kFlagThreshold = 0x1p-100f;
 constexpr int kDistCap = 12;
 
+// 64-bit words per brick column of the colm flag bits
+MVF_HD int col_words(int bd2) { return (bd2 + 63) >> 6; }
+
 struct DevVolume {
     float* F;
     uint16_t* W;
     uint32_t* C;
     uint8_t* flag;
     uint8_t* dist;
-    uint8_t* tmp;            // 2 * nbricks bytes of scratch for the distance passes
+    uint64_t* colm;          // per brick column: flags as bits along z
     uint64_t* fmask;         // per brick: sub-block flags
     uint64_t* cmask;         // per brick: cell sub-block flags
     int32_t dims[3];

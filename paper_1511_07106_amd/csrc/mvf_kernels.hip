@@ -129,6 +129,7 @@ int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* 
 __global__ __launch_bounds__(256) void mvf_volume_init_kernel(DevVolume v, size_t nvox, size_t nbricks)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t ncolw = (size_t)v.bd[0] * v.bd[1] * col_words(v.bd[2]);  // <= nbricks
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox; i += stride) {
         v.F[i] = __uint_as_float(0x7fc00000u);
         v.W[i] = 0;
@@ -139,6 +140,7 @@ __global__ __launch_bounds__(256) void mvf_volume_init_kernel(DevVolume v, size_
             v.fmask[i] = 0;
             v.cmask[i] = 0;
         }
+        if (i <= ncolw) v.colm[i] = 0;  // word ncolw stays zero (read for absent neighbours)
     }
 }
 
@@ -501,11 +503,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
             if (__ballot(flag_here) != 0) {
                 uint64_t fm = 0;
 #pragma unroll
-                for (int zp = 0; zp < kBrick / 2; ++zp) fm |= (uint64_t)subblock_bits(__ballot(fz[zp])) << (16 * zp);
+                for (int zp = 0; zp < kBrick / 2; ++zp)
+                    fm |= (uint64_t)subblock_bits(__ballot(fz[zp])) << (16 * zp);
                 if (lane == 0) {
                     const size_t b = brick_index(V.bd, bxi, byi, bz);
                     V.flag[b] = 1;
                     atomicOr((unsigned long long*)&V.fmask[b], (unsigned long long)fm);
+                    const size_t cw = (size_t)(bxi * V.bd[1] + byi) * col_words(V.bd[2]) + (bz >> 6);
+                    atomicOr((unsigned long long*)&V.colm[cw], 1ull << (bz & 63));
                 }
             }
         }
@@ -894,11 +899,11 @@ static __device__ bool brick_footprint(const DevVolume& V, const DevFrame& Fr, i
 // Footprint of brick (bx, by, bz) of volume v appended to the volume's list
 // (if its cell mask is not empty).  Called by every active lane of a
 // wavefront whose lanes all serve volume v; one counter atomic per wavefront.
-static __device__ void collect_footprint(const DevVolume& V, const DevFrame& Fr, int v, uint32_t b, int bx, int by,
+static __device__ void collect_footprint(const DevVolume& V, const DevFrame& Fr, int v, uint64_t cm, int bx, int by,
                                          int bz, const int32_t* brick_base, const LaunchHeader* hdr, RayBounds rb)
 {
     RayBoundEntry e;
-    const bool has = Fr.rb_lo && V.cmask[b] != 0ull && brick_footprint(V, Fr, bx, by, bz, e);
+    const bool has = Fr.rb_lo && cm != 0ull && brick_footprint(V, Fr, bx, by, bz, e);
     const unsigned long long m = __ballot(has);
     if (m == 0) return;
     const int lane = threadIdx.x & 63;
@@ -1399,107 +1404,181 @@ __global__ __launch_bounds__(256) void mvf_brick_summary_kernel(DevVolume v, siz
     }
 }
 
+// Column flag words after a full flag recompute: one wavefront per word,
+// lane l taking the flag of brick 64 w + l of the column.
+__global__ __launch_bounds__(256) void mvf_column_flags_kernel(DevVolume v, int ncolw)
+{
+    const int lane = threadIdx.x & 63;
+    const int nw = col_words(v.bd[2]);
+    const int step = (int)(gridDim.x * (blockDim.x >> 6));
+    for (int cw = wave_uniform((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6))); cw < ncolw; cw += step) {
+        const int col = cw / nw, w = cw - col * nw;
+        const int bz = 64 * w + lane;
+        const bool f = bz < v.bd[2] && v.flag[(size_t)col * v.bd[2] + bz] != 0;
+        const unsigned long long m = __ballot(f);
+        if (lane == 0) v.colm[cw] = m;
+    }
+}
+
 int launch_brick_summary(DevVolume v, void* stream)
 {
     const size_t nb = (size_t)v.bd[0] * v.bd[1] * v.bd[2];
     hipLaunchKernelGGL(mvf_brick_summary_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0,
                        (hipStream_t)stream, v, nb);
+    const int ncolw = v.bd[0] * v.bd[1] * col_words(v.bd[2]);
+    hipLaunchKernelGGL(mvf_column_flags_kernel, dim3((unsigned)std::min((ncolw + 3) / 4, 65535)), dim3(256), 0,
+                       (hipStream_t)stream, v, ncolw);
     return (int)hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Brick distance transform: Chebyshev distance (in bricks, capped) from each
-// brick to the nearest flagged brick of its volume, separably over x, y, z.
-// One thread per brick of every volume in the table; three launches (x from
-// the flags into tmp, y into tmp + nbricks, z into dist).
+// Brick distance transform: Chebyshev distance (in bricks, capped at
+// kDistCap) from each brick to the nearest flagged brick of its volume; the
+// cell masks from the sub-block flags of each brick and its +x, +y, +z
+// neighbours; with range bounds, the bricks' footprints.  One launch for
+// every volume of the table, one wavefront (and block) per word of a brick
+// column: lane l stands for brick 64 w + l along z.
+//
+// A brick is within distance k of a flagged brick iff its bit is set in the
+// z-dilation by k of C_k, the OR of the column words within Chebyshev
+// distance k in (x, y).  Separably: lane j < 2 kDistCap + 1 takes the
+// neighbour row dy = j - kDistCap and ORs its words along x outwards,
+// giving X_k(dy) = OR over |dx| <= k for every k; lane k <= kDistCap ORs
+// X_k(dy) over |dy| <= k into C_k and dilates it along z; every lane then
+// tests its bit in each dilation.  Columns of more than 64 bricks also carry
+// the words below and above (the dilation reaches kDistCap < 64 bits into
+// them).
 // ---------------------------------------------------------------------------
-// Distance passes over the bricks of every volume of the table; pass 0 also
-// derives the cell masks from the sub-block flags of each brick and its +x,
-// +y, +z neighbours.  Each volume's bricks start at a multiple of 64 in the
-// launch's brick numbering (brick_base), so a wavefront serves one volume.
-__global__ __launch_bounds__(256) void mvf_brick_distance_kernel(const LaunchHeader* hdr, const DevVolume* vols,
-                                                                 const int32_t* brick_base, int pass,
-                                                                 const DevFrame* frames, RayBounds rb)
+constexpr int kDistSide = 2 * kDistCap + 1;
+
+// Bits of word `cur` set within distance k along z of a set bit of the
+// window prev | cur | next (k < 64).
+static __device__ __forceinline__ uint64_t dilate_z(uint64_t prev, uint64_t cur, uint64_t next, int k)
 {
-    const int total = cptr(hdr)->total_bricks;
-    const int nvol = cptr(hdr)->nvol;
-    CPTR(int32_t) const bbase = cptr(brick_base);
-    const int stride = gridDim.x * blockDim.x;
-    for (int g0 = blockIdx.x * blockDim.x; g0 < total; g0 += stride) {
-        const int gw = wave_uniform(g0 + (int)(threadIdx.x & ~63u));  // first brick of this wave
-        int lo = 0, hi = nvol - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (bbase[mid] <= gw) lo = mid; else hi = mid - 1;
+    uint64_t d = cur;
+#pragma unroll
+    for (int s = 1; s <= kDistCap; ++s)
+        if (s <= k) d |= (cur << s) | (prev >> (64 - s)) | (cur >> s) | (next << (64 - s));
+    return d;
+}
+
+struct DistShared {
+    uint64_t x[3][kDistCap + 1][kDistSide];  // X_k of each neighbour row, per word offset -1, 0, +1
+    uint64_t d[kDistCap + 1];                // z-dilations of C_k
+};
+
+// Orders this wavefront's shared-memory writes before its later reads of
+// them by other lanes (the wavefront's LDS operations complete in order).
+static __device__ __forceinline__ void wave_lds_sync()
+{
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+template <bool Multi>
+static __device__ __forceinline__ void brick_distance_word(const DevVolume& V, int v, int cw, int lane,
+                                                           DistShared& sh, const DevFrame* frames, RayBounds rb,
+                                                           const int32_t* brick_base, const LaunchHeader* hdr)
+{
+    const int nw = col_words(V.bd[2]);
+    const int ncw = V.bd[0] * V.bd[1] * nw;
+    const int col = cw / nw, w = cw - col * nw;
+    const int by = col % V.bd[1], bx = col / V.bd[1];
+    const int bz = 64 * w + lane;
+    const bool valid = bz < V.bd[2];
+    const uint32_t b = (uint32_t)col * (uint32_t)V.bd[2] + (uint32_t)min(bz, V.bd[2] - 1);
+    // cell mask from the sub-block flags of the brick and its +x, +y, +z
+    // neighbours (loads issued first, used at the end)
+    GPTR(const uint64_t) const fm = gptr((const uint64_t*)V.fmask);
+    uint64_t M[2][2][2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const bool in = valid && bx + dx < V.bd[0] && by + dy < V.bd[1] && bz + dz < V.bd[2];
+                M[dz][dy][dx] = ld_elem(fm, in ? brick_index32(V, bx + dx, by + dy, bz + dz) : b);
+                M[dz][dy][dx] = in ? M[dz][dy][dx] : 0ull;
+            }
+    // word ncw of colm is always zero: out-of-range neighbours read it
+    GPTR(const uint64_t) const colm = gptr((const uint64_t*)V.colm);
+    constexpr int kOffsets = Multi ? 3 : 1;
+    if (lane < kDistSide) {
+        const int y = by + lane - kDistCap;
+        const bool row_in = y >= 0 && y < V.bd[1];
+        const uint32_t row = (uint32_t)(row_in ? y : 0);
+#pragma unroll
+        for (int oi = 0; oi < kOffsets; ++oi) {
+            const int o = Multi ? oi - 1 : 0;
+            const bool word_in = row_in && w + o >= 0 && w + o < nw;
+            uint64_t m[kDistSide];
+#pragma unroll
+            for (int i = 0; i < kDistSide; ++i) {
+                const int x = bx + i - kDistCap;
+                const bool in = word_in && x >= 0 && x < V.bd[0];
+                m[i] = ld_elem(colm, in ? ((uint32_t)x * (uint32_t)V.bd[1] + row) * (uint32_t)nw + (uint32_t)(w + o)
+                                        : (uint32_t)ncw);
+            }
+            uint64_t X = m[kDistCap];
+            sh.x[oi][0][lane] = X;
+#pragma unroll
+            for (int k = 1; k <= kDistCap; ++k) {
+                X |= m[kDistCap - k] | m[kDistCap + k];
+                sh.x[oi][k][lane] = X;
+            }
         }
-        lo = wave_uniform(lo);
-        const DevVolume V = cptr(vols)[lo];
-        const int b = g0 + (int)threadIdx.x - bbase[lo];
-        const int nb = V.bd[0] * V.bd[1] * V.bd[2];
-        if (b >= nb) continue;
-        const int bz = b % V.bd[2];
-        const int t = b / V.bd[2];
-        const int by = t % V.bd[1];
-        const int bx = t / V.bd[1];
-        int d = kDistCap;
-        if (pass == 0) {
-            GPTR(const uint64_t) const fm = gptr((const uint64_t*)V.fmask);
-            uint64_t M[2][2][2];
+    }
+    wave_lds_sync();
+    if (lane <= kDistCap) {
+        const int k = lane;
+        uint64_t c[3] = {0ull, 0ull, 0ull};
 #pragma unroll
-            for (int dz = 0; dz < 2; ++dz)
+        for (int oi = 0; oi < kOffsets; ++oi)
 #pragma unroll
-                for (int dy = 0; dy < 2; ++dy)
+            for (int j = 0; j < kDistSide; ++j)
+                if (j >= kDistCap - k && j <= kDistCap + k) c[oi] |= sh.x[oi][k][j];
+        sh.d[k] = Multi ? dilate_z(c[0], c[1], c[2], k) : dilate_z(0ull, c[0], 0ull, k);
+    }
+    wave_lds_sync();
+    int d = kDistCap;
 #pragma unroll
-                    for (int dx = 0; dx < 2; ++dx) {
-                        const bool in = bx + dx < V.bd[0] && by + dy < V.bd[1] && bz + dz < V.bd[2];
-                        M[dz][dy][dx] = in ? ld_elem(fm, brick_index32(V, bx + dx, by + dy, bz + dz)) : 0ull;
-                    }
-            V.cmask[b] = cell_mask(M);
-            GPTR(const uint8_t) const flag = gptr((const uint8_t*)V.flag);
-            const int sx = V.bd[1] * V.bd[2];
-            // all loads first (in-range addresses), then the minimum
-            uint8_t f[2 * kDistCap + 1];
-#pragma unroll
-            for (int o = -kDistCap; o <= kDistCap; ++o) {
-                const int x = min(max(bx + o, 0), V.bd[0] - 1);
-                f[o + kDistCap] = ld_elem(flag, (uint32_t)(b + (x - bx) * sx));
-            }
-#pragma unroll
-            for (int o = -kDistCap; o <= kDistCap; ++o) {
-                const int x = bx + o;
-                if (x >= 0 && x < V.bd[0] && f[o + kDistCap]) d = min(d, abs(o));
-            }
-            V.tmp[b] = (uint8_t)d;
-        } else if (pass == 1) {
-            GPTR(const uint8_t) const t0 = gptr((const uint8_t*)V.tmp);
-            const int sy = V.bd[2];
-            uint8_t f[2 * kDistCap + 1];
-#pragma unroll
-            for (int o = -kDistCap; o <= kDistCap; ++o) {
-                const int y = min(max(by + o, 0), V.bd[1] - 1);
-                f[o + kDistCap] = ld_elem(t0, (uint32_t)(b + (y - by) * sy));
-            }
-#pragma unroll
-            for (int o = -kDistCap; o <= kDistCap; ++o) {
-                const int y = by + o;
-                if (y >= 0 && y < V.bd[1]) d = min(d, max(abs(o), (int)f[o + kDistCap]));
-            }
-            V.tmp[nb + b] = (uint8_t)d;
-        } else {
-            GPTR(const uint8_t) const t1 = gptr((const uint8_t*)V.tmp + nb);
-            uint8_t f[2 * kDistCap + 1];
-#pragma unroll
-            for (int o = -kDistCap; o <= kDistCap; ++o) {
-                const int z = min(max(bz + o, 0), V.bd[2] - 1);
-                f[o + kDistCap] = ld_elem(t1, (uint32_t)(b + (z - bz)));
-            }
-#pragma unroll
-            for (int o = -kDistCap; o <= kDistCap; ++o) {
-                const int z = bz + o;
-                if (z >= 0 && z < V.bd[2]) d = min(d, max(abs(o), (int)f[o + kDistCap]));
-            }
-            V.dist[b] = (uint8_t)d;
-            if (frames && rb.entries) collect_footprint(V, frames[V.frame], lo, (uint32_t)b, bx, by, bz, brick_base, hdr, rb);
+    for (int k = kDistCap; k >= 0; --k)
+        if ((sh.d[k] >> lane) & 1ull) d = k;
+    wave_lds_sync();  // sh is rewritten for the wavefront's next word
+    const uint64_t cm = valid ? cell_mask(M) : 0ull;
+    if (valid) {
+        V.cmask[b] = cm;
+        V.dist[b] = (uint8_t)d;
+    }
+    if (frames && rb.entries) collect_footprint(V, frames[V.frame], v, cm, bx, by, bz, brick_base, hdr, rb);
+}
+
+// four wavefronts per block, each with its own shared memory
+__global__ __launch_bounds__(256) void mvf_brick_distance_kernel(const LaunchHeader* hdr, const DevVolume* vols,
+                                                                 const int32_t* brick_base, const DevFrame* frames,
+                                                                 RayBounds rb)
+{
+    __shared__ DistShared shared[4];
+    const int lane = threadIdx.x & 63;
+    DistShared& sh = shared[threadIdx.x >> 6];
+    const int nvol = cptr(hdr)->nvol;
+    const int waves = (int)(gridDim.x * 4);
+    const int wave = wave_uniform((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    // the column words of all volumes, numbered volume by volume, are dealt
+    // to the wavefronts in turn; acc = words before volume v, modulo waves
+    int acc = 0;
+    for (int v = 0; v < nvol; ++v) {
+        CPTR(DevVolume) const Vp = cptr(vols) + v;
+        const int nw = col_words(Vp->bd[2]);
+        const int ncw = Vp->bd[0] * Vp->bd[1] * nw;
+        int first = (wave - acc) % waves;
+        if (first < 0) first += waves;
+        acc = (int)(((long long)acc + ncw) % waves);
+        if (first >= ncw) continue;
+        const DevVolume V = *Vp;
+        for (int cw = first; cw < ncw; cw += waves) {
+            if (nw == 1) brick_distance_word<false>(V, v, cw, lane, sh, frames, rb, brick_base, hdr);
+            else brick_distance_word<true>(V, v, cw, lane, sh, frames, rb, brick_base, hdr);
         }
     }
 }
@@ -1508,9 +1587,8 @@ int launch_brick_distance(const LaunchHeader* hdr, const DevVolume* vols, const 
                           void* stream, const DevFrame* frames, RayBounds rb)
 {
     if (blocks <= 0) return 0;
-    for (int pass = 0; pass < 3; ++pass)
-        hipLaunchKernelGGL(mvf_brick_distance_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, hdr, vols,
-                           brick_base, pass, pass == 2 ? frames : nullptr, rb);
+    hipLaunchKernelGGL(mvf_brick_distance_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, hdr, vols,
+                       brick_base, frames, rb);
     return (int)hipGetLastError();
 }
 
@@ -1536,7 +1614,7 @@ __global__ __launch_bounds__(256) void mvf_ray_bounds_collect_kernel(const Launc
         if (b >= nb) continue;
         const int bz = b % V.bd[2];
         const int t = b / V.bd[2];
-        collect_footprint(V, frames[V.frame], lo, (uint32_t)b, t / V.bd[1], t % V.bd[1], bz, brick_base, hdr, rb);
+        collect_footprint(V, frames[V.frame], lo, V.cmask[b], t / V.bd[1], t % V.bd[1], bz, brick_base, hdr, rb);
     }
 }
 

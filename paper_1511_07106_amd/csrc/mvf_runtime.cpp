@@ -70,7 +70,7 @@ struct Volume {
     bool alive = false;
     mvf_volume_desc d{};
     int bd[3] = {0, 0, 0};
-    size_t nvox_pad = 0, off_W = 0, off_C = 0, off_flag = 0, off_dist = 0, off_tmp = 0, off_fmask = 0, off_cmask = 0, bytes = 0;
+    size_t nvox_pad = 0, off_W = 0, off_C = 0, off_flag = 0, off_dist = 0, off_colm = 0, off_fmask = 0, off_cmask = 0, bytes = 0;
     size_t nbricks = 0;
     uint8_t* dev = nullptr;    // device slab while resident
     uint8_t* host = nullptr;   // pinned mirror (allocated on first swap-out)
@@ -313,7 +313,7 @@ DevVolume make_dev(mvf_ctx* c, const Volume& v)
     d.C = reinterpret_cast<uint32_t*>(v.dev + v.off_C);
     d.flag = v.dev + v.off_flag;
     d.dist = v.dev + v.off_dist;
-    d.tmp = v.dev + v.off_tmp;
+    d.colm = reinterpret_cast<uint64_t*>(v.dev + v.off_colm);
     d.fmask = reinterpret_cast<uint64_t*>(v.dev + v.off_fmask);
     d.cmask = reinterpret_cast<uint64_t*>(v.dev + v.off_cmask);
     for (int a = 0; a < 3; ++a) {
@@ -1404,8 +1404,8 @@ mvf_status mvf_volume_create(mvf_ctx* c, const mvf_volume_desc* d, int32_t* vol_
     v.off_C = align_up(v.off_W + v.nvox_pad * 2, kAlign);
     v.off_flag = align_up(v.off_C + v.nvox_pad * 4, kAlign);
     v.off_dist = align_up(v.off_flag + nb, kAlign);
-    v.off_tmp = align_up(v.off_dist + nb, kAlign);
-    v.off_fmask = align_up(v.off_tmp + 2 * nb, kAlign);
+    v.off_colm = align_up(v.off_dist + nb, kAlign);
+    v.off_fmask = align_up(v.off_colm + 8 * ((size_t)v.bd[0] * v.bd[1] * col_words(v.bd[2]) + 1), kAlign);
     v.off_cmask = align_up(v.off_fmask + 8 * nb, kAlign);
     v.bytes = align_up(v.off_cmask + 8 * nb, kAlign);
     v.nbricks = nb;
@@ -1495,6 +1495,29 @@ mvf_status mvf_volume_query(mvf_ctx* c, int32_t id, int32_t* resident, uint64_t*
     if (resident) *resident = v->state == State::Device ? 1 : 0;
     if (bytes) *bytes = v->bytes;
     if (active) *active = v->active ? 1 : 0;
+    return MVF_OK;
+}
+
+mvf_status mvf_volume_brick_summary(mvf_ctx* c, int32_t id, uint8_t* flag, uint8_t* dist)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    CHECK_HIP(hipSetDevice(c->device));
+    CHECK_ST(mvf_synchronize(c));
+    const size_t nb = v->nbricks;
+    if (v->state == State::Empty) {
+        if (flag) memset(flag, 0, nb);
+        if (dist) memset(dist, kDistCap, nb);
+        return MVF_OK;
+    }
+    if (v->state == State::Host) {
+        if (flag) memcpy(flag, v->host + v->off_flag, nb);
+        if (dist) memcpy(dist, v->host + v->off_dist, nb);
+        return MVF_OK;
+    }
+    if (flag) CHECK_HIP(hipMemcpy(flag, v->dev + v->off_flag, nb, hipMemcpyDeviceToHost));
+    if (dist) CHECK_HIP(hipMemcpy(dist, v->dev + v->off_dist, nb, hipMemcpyDeviceToHost));
     return MVF_OK;
 }
 

@@ -1,0 +1,118 @@
+"""Brick summaries behind the raycast's exact skipping: after integration,
+a volume write and a batched step, every brick's distance equals the
+Chebyshev distance (in bricks, capped at 12) to the nearest flagged brick,
+computed here by brute force from the flags (scipy's chessboard distance
+transform), and every brick holding a voxel with W > 0 and F <= 2^-100 is
+flagged."""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from synth import scenes as S
+from tests.util import dev, log, t
+
+pytestmark = pytest.mark.gpu
+
+CAP = 12
+THRESH = np.float32(2.0 ** -100)
+
+
+@pytest.fixture(scope="module")
+def mvf():
+    import paper_1511_07106_amd as mvf
+    return mvf
+
+
+def _brute_dist(flag):
+    if not flag.any():
+        return np.full(flag.shape, CAP, np.uint8)
+    d = ndimage.distance_transform_cdt(flag == 0, metric="chessboard")
+    return np.minimum(d, CAP).astype(np.uint8)
+
+
+def _bricks_with_low_F(F, W, nb):
+    """(bx, by, bz) mask of bricks holding a voxel with W > 0 and F <= 2^-100;
+    F, W in canonical (z, y, x) layout."""
+    nz, ny, nx = F.shape
+    low = (W > 0) & (F <= THRESH)
+    pad = np.zeros((nb[2] * 8, nb[1] * 8, nb[0] * 8), bool)
+    pad[:nz, :ny, :nx] = low
+    b = pad.reshape(nb[2], 8, nb[1], 8, nb[0], 8).any(axis=(1, 3, 5))  # (bz, by, bx)
+    return b.transpose(2, 1, 0)
+
+
+def _check(ctx, vid, need_flag=True):
+    flag, dist = ctx.brick_summary(vid)
+    want = _brute_dist(flag)
+    bad = np.argwhere(dist != want)
+    assert bad.size == 0, f"{len(bad)} bricks differ, first {bad[:3].tolist()}: {dist[tuple(bad[0])]} vs {want[tuple(bad[0])]}"
+    if need_flag:
+        F, W, _ = ctx.read_volume(vid)
+        low = _bricks_with_low_F(F, W, flag.shape)
+        assert not (low & (flag == 0)).any(), "a brick with F <= 2^-100 is not flagged"
+    return flag, dist
+
+
+def test_summary_after_integration(mvf):
+    log("brick summary after integrating 128^3 small room, 10 frames")
+    seq = S.small_room_sequence(seed=1)
+    K = seq.K.as_array()
+    with mvf.Context() as ctx:
+        gid = ctx.grid((-1.0, -1.0, -1.0), 2.0 / 128, 4.0, 128)
+        vid = ctx.volume(gid, (0, 0, 0), (128, 128, 128))
+        # a ragged second volume of the same grid
+        vid2 = ctx.volume(gid, (5, -3, 11), (37, 90, 45))
+        for i in range(10):
+            d, c = seq.frame(i)
+            ctx.integrate(t(d), t(c), seq.poses[i], K)
+        flag, dist = _check(ctx, vid)
+        assert 0 < flag.sum() < flag.size and (dist == 1).any() and (dist >= 4).any()
+        _check(ctx, vid2)
+        log(f"flagged {int(flag.sum())} of {flag.size} bricks")
+
+
+def test_summary_after_write_multiword_columns(mvf):
+    """Columns of more than 64 bricks (138 along z): flags planted at the
+    64-brick word boundaries and in the volume's corners."""
+    dims = (24, 16, 1100)
+    log(f"brick summary after write, dims {dims}")
+    nx, ny, nz = dims
+    F = np.ones((nz, ny, nx), np.float32)
+    W = np.ones((nz, ny, nx), np.uint16)
+    W[:, :, 20:] = 0
+    for bz in (0, 63, 64, 65, 127, 128, 137):
+        z = min(bz * 8 + 3, nz - 1)
+        F[z, 9, 2] = -0.5
+    F[1099, 15, 15] = 0.0
+    F[500, 0, 23] = -1.0  # W == 0 there: not a surface voxel
+    with mvf.Context() as ctx:
+        gid = ctx.grid((0.0, 0.0, 0.0), 0.01, 4.0, 128)
+        vid = ctx.volume(gid, (0, 0, 0), dims)
+        ctx.write_volume(vid, F=F, W=W)
+        flag, dist = _check(ctx, vid)
+        assert flag.shape == (3, 2, 138)
+        assert flag.sum() == 8
+        assert flag[1, 1, 137] == 1 and flag[2, 0, 62] == 0
+
+
+@pytest.mark.parametrize("zchunk", [2, 4])
+def test_summary_after_batched_step(mvf, zchunk):
+    """The step's fused launches over several volumes of different shapes
+    (columns of 33 and 80 bricks) in one table."""
+    seq = S.small_room_sequence(seed=3)
+    K = seq.K.as_array()
+    import torch
+    specs = [((-8, -8, -8), (264, 100, 264)), ((0, 0, 0), (64, 64, 640)), ((40, 12, 3), (21, 70, 9))]
+    log(f"brick summary after batched steps, zchunk {zchunk}")
+    with mvf.Context() as ctx:
+        ctx.set_schedule(zchunk=zchunk)
+        gid = ctx.grid((-1.0, -1.0, -1.0), 2.0 / 128, 4.0, 128)
+        vids = [ctx.volume(gid, off, dims) for off, dims in specs]
+        w, h = seq.K.width, seq.K.height
+        out = {"depth": torch.empty((h, w), dtype=torch.float32, device=dev())}
+        for i in range(6):
+            d, c = seq.frame(i)
+            ctx.step([(0, t(d), t(c), seq.poses[i], K)], [out])
+        torch.cuda.synchronize()
+        for v in vids:
+            _check(ctx, v)
