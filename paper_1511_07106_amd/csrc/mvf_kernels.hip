@@ -1432,163 +1432,223 @@ int launch_brick_summary(DevVolume v, void* stream)
 }
 
 // ---------------------------------------------------------------------------
-// Brick distance transform: Chebyshev distance (in bricks, capped at
-// kDistCap) from each brick to the nearest flagged brick of its volume; the
-// cell masks from the sub-block flags of each brick and its +x, +y, +z
-// neighbours; with range bounds, the bricks' footprints.  One launch for
-// every volume of the table, one wavefront (and block) per word of a brick
-// column: lane l stands for brick 64 w + l along z.
+// Brick distance transform and cell masks: one launch for every volume of
+// the table, two kinds of wavefronts.
 //
-// A brick is within distance k of a flagged brick iff its bit is set in the
-// z-dilation by k of C_k, the OR of the column words within Chebyshev
-// distance k in (x, y).  Separably: lane j < 2 kDistCap + 1 takes the
-// neighbour row dy = j - kDistCap and ORs its words along x outwards,
-// giving X_k(dy) = OR over |dx| <= k for every k; lane k <= kDistCap ORs
-// X_k(dy) over |dy| <= k into C_k and dilates it along z; every lane then
-// tests its bit in each dilation.  Columns of more than 64 bricks also carry
-// the words below and above (the dilation reaches kDistCap < 64 bits into
-// them).
+// Distance lines (the first kDistWaves wavefronts): one per (bx, chunk of
+// kDistRows columns along y, 64-brick word w of the columns).  Lane l holds
+// the row y = y0 - kDistCap + l and ORs that row's column words along x
+// outwards, X_k = OR over |dx| <= k; C_k, the OR of X_k over the lanes
+// within k, covers the columns within Chebyshev distance k in (x, y); a
+// brick of the word is within distance k of a flagged brick iff its bit is
+// set in the z-dilation of C_k by k.  The capped distances of the word's 64
+// bricks are kept as four bit planes (bit z of plane i = bit i of brick z's
+// distance) and written by the middle kDistRows lanes.  Columns of more than
+// 64 bricks also take the words below and above (the dilation reaches
+// kDistCap < 64 bits into them).
+//
+// Bricks (the other wavefronts): one thread per brick, 64 consecutive
+// bricks of one volume per wavefront (brick_base): the cell mask from the
+// sub-block flags of the brick and its +x, +y, +z neighbours and, with range
+// bounds, the brick's footprint.
 // ---------------------------------------------------------------------------
 constexpr int kDistSide = 2 * kDistCap + 1;
+constexpr int kDistRows = 64 - 2 * kDistCap;  // output columns of a distance line
+constexpr int kDistWaves = 256;               // wavefronts of the distance lines
 
-// Bits of word `cur` set within distance k along z of a set bit of the
-// window prev | cur | next (k < 64).
-static __device__ __forceinline__ uint64_t dilate_z(uint64_t prev, uint64_t cur, uint64_t next, int k)
+// Dilation by r (r < 16) in shift steps of 1, 2, 4 and the rest: a step s
+// with s <= c + 1 widens the covered offsets [-c, c] to [-(c + s), c + s]
+// without a gap (shifts of 8 and 2 alone would cover only 0, 2, 6, 8, 10).
+template <class Step>
+static __device__ __forceinline__ void covering_steps(int r, Step step)
 {
-    uint64_t d = cur;
+    int c = 0;
 #pragma unroll
-    for (int s = 1; s <= kDistCap; ++s)
-        if (s <= k) d |= (cur << s) | (prev >> (64 - s)) | (cur >> s) | (next << (64 - s));
-    return d;
+    for (int s = 1; s <= 8; s <<= 1) {
+        if (c < r) {
+            const int st = min(s, r - c);
+            step(st);
+            c += st;
+        }
+    }
 }
 
-struct DistShared {
-    uint64_t x[3][kDistCap + 1][kDistSide];  // X_k of each neighbour row, per word offset -1, 0, +1
-    uint64_t d[kDistCap + 1];                // z-dilations of C_k
-};
-
-// Orders this wavefront's shared-memory writes before its later reads of
-// them by other lanes (the wavefront's LDS operations complete in order).
-static __device__ __forceinline__ void wave_lds_sync()
+// OR of x over the lanes within r; lanes beyond the wavefront add nothing.
+static __device__ __forceinline__ uint64_t lane_dilate(uint64_t x, int r)
 {
-    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    covering_steps(r, [&](int st) { x |= __shfl_up(x, st) | __shfl_down(x, st); });
+    return x;
+}
+
+// The bits of the window prev | cur | next within r (r <= kDistCap) of a set
+// bit; prev and next keep the bits that can still reach cur.
+static __device__ __forceinline__ void z_dilate(uint64_t& prev, uint64_t& cur, uint64_t& next, int r)
+{
+    covering_steps(r, [&](int st) {
+        const uint64_t p = prev, c = cur, n = next;
+        cur = c | (c << st) | (c >> st) | (p >> (64 - st)) | (n << (64 - st));
+        prev = p | (p << st) | (p >> st) | (c << (64 - st));
+        next = n | (n << st) | (n >> st) | (c >> (64 - st));
+    });
+}
+
+// Bits 0..3 of x to the low bit of each byte.
+static __device__ __forceinline__ uint32_t spread4(uint32_t x)
+{
+    x &= 0xfu;
+    return (x | (x << 7) | (x << 14) | (x << 21)) & 0x01010101u;
 }
 
 template <bool Multi>
-static __device__ __forceinline__ void brick_distance_word(const DevVolume& V, int v, int cw, int lane,
-                                                           DistShared& sh, const DevFrame* frames, RayBounds rb,
-                                                           const int32_t* brick_base, const LaunchHeader* hdr)
+static __device__ void distance_line(const DevVolume& V, int bx, int y0, int w, int lane)
 {
     const int nw = col_words(V.bd[2]);
     const int ncw = V.bd[0] * V.bd[1] * nw;
-    const int col = cw / nw, w = cw - col * nw;
-    const int by = col % V.bd[1], bx = col / V.bd[1];
-    const int bz = 64 * w + lane;
-    const bool valid = bz < V.bd[2];
-    const uint32_t b = (uint32_t)col * (uint32_t)V.bd[2] + (uint32_t)min(bz, V.bd[2] - 1);
-    // cell mask from the sub-block flags of the brick and its +x, +y, +z
-    // neighbours (loads issued first, used at the end)
-    GPTR(const uint64_t) const fm = gptr((const uint64_t*)V.fmask);
-    uint64_t M[2][2][2];
-#pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-                const bool in = valid && bx + dx < V.bd[0] && by + dy < V.bd[1] && bz + dz < V.bd[2];
-                M[dz][dy][dx] = ld_elem(fm, in ? brick_index32(V, bx + dx, by + dy, bz + dz) : b);
-                M[dz][dy][dx] = in ? M[dz][dy][dx] : 0ull;
-            }
-    // word ncw of colm is always zero: out-of-range neighbours read it
     GPTR(const uint64_t) const colm = gptr((const uint64_t*)V.colm);
-    constexpr int kOffsets = Multi ? 3 : 1;
-    if (lane < kDistSide) {
-        const int y = by + lane - kDistCap;
-        const bool row_in = y >= 0 && y < V.bd[1];
-        const uint32_t row = (uint32_t)(row_in ? y : 0);
+    const int y = y0 - kDistCap + lane;
+    const bool row_in = y >= 0 && y < V.bd[1];
+    const uint32_t row = (uint32_t)(row_in ? y : 0);
+    // word ncw of colm is always zero: out-of-range neighbours read it
+    auto word = [&](int x, int ww) -> uint64_t {
+        const bool in = row_in && x >= 0 && x < V.bd[0] && ww >= 0 && ww < nw;
+        return ld_elem(colm, in ? ((uint32_t)x * (uint32_t)V.bd[1] + row) * (uint32_t)nw + (uint32_t)ww
+                                : (uint32_t)ncw);
+    };
+    uint64_t Xp = 0, X = 0, Xn = 0;
+    uint64_t p0 = 0, p1 = 0, p2 = ~0ull, p3 = ~0ull, found = 0;  // kDistCap = 12 = 0b1100 until found
+    static_assert(kDistCap == 12, "bit planes start at the cap");
+    // distance k: C_k dilated along z, the bricks it reaches first get k
+    auto ring = [&](int k) {
+        uint64_t c = lane_dilate(X, k);
+        uint64_t cp = Multi ? lane_dilate(Xp, k) : 0ull;
+        uint64_t cn = Multi ? lane_dilate(Xn, k) : 0ull;
+        z_dilate(cp, c, cn, k);
+        const uint64_t fresh = c & ~found;
+        found |= c;
+        p0 = (k & 1) ? (p0 | fresh) : (p0 & ~fresh);
+        p1 = (k & 2) ? (p1 | fresh) : (p1 & ~fresh);
+        p2 = (k & 4) ? (p2 | fresh) : (p2 & ~fresh);
+        p3 = (k & 8) ? (p3 | fresh) : (p3 & ~fresh);
+    };
+    if (Multi) {
+        // three words a row: loaded as the rings grow (a rare shape)
+#pragma unroll 1
+        for (int k = 0; k <= kDistCap; ++k) {
+            X |= word(bx - k, w) | word(bx + k, w);
+            Xp |= word(bx - k, w - 1) | word(bx + k, w - 1);
+            Xn |= word(bx - k, w + 1) | word(bx + k, w + 1);
+            ring(k);
+        }
+    } else {
+        uint64_t m[kDistSide];
 #pragma unroll
-        for (int oi = 0; oi < kOffsets; ++oi) {
-            const int o = Multi ? oi - 1 : 0;
-            const bool word_in = row_in && w + o >= 0 && w + o < nw;
-            uint64_t m[kDistSide];
+        for (int i = 0; i < kDistSide; ++i) m[i] = word(bx + i - kDistCap, w);
 #pragma unroll
-            for (int i = 0; i < kDistSide; ++i) {
-                const int x = bx + i - kDistCap;
-                const bool in = word_in && x >= 0 && x < V.bd[0];
-                m[i] = ld_elem(colm, in ? ((uint32_t)x * (uint32_t)V.bd[1] + row) * (uint32_t)nw + (uint32_t)(w + o)
-                                        : (uint32_t)ncw);
-            }
-            uint64_t X = m[kDistCap];
-            sh.x[oi][0][lane] = X;
-#pragma unroll
-            for (int k = 1; k <= kDistCap; ++k) {
-                X |= m[kDistCap - k] | m[kDistCap + k];
-                sh.x[oi][k][lane] = X;
-            }
+        for (int k = 0; k <= kDistCap; ++k) {
+            X |= m[kDistCap - k] | m[kDistCap + k];
+            ring(k);
         }
     }
-    wave_lds_sync();
-    if (lane <= kDistCap) {
-        const int k = lane;
-        uint64_t c[3] = {0ull, 0ull, 0ull};
+    if (lane < kDistCap || lane >= kDistCap + kDistRows || !row_in) return;
+    const int nz = min(64, V.bd[2] - 64 * w);
+    const uint32_t b0 = ((uint32_t)bx * (uint32_t)V.bd[1] + row) * (uint32_t)V.bd[2] + 64u * (uint32_t)w;
+    const bool aligned = (V.bd[2] & 3) == 0;
 #pragma unroll
-        for (int oi = 0; oi < kOffsets; ++oi)
+    for (int j = 0; j < 64; j += 4) {
+        if (j >= nz) break;
+        const uint32_t v = spread4((uint32_t)(p0 >> j)) | (spread4((uint32_t)(p1 >> j)) << 1) |
+                           (spread4((uint32_t)(p2 >> j)) << 2) | (spread4((uint32_t)(p3 >> j)) << 3);
+        if (aligned) {
+            *(uint32_t*)(V.dist + b0 + j) = v;  // nz is a multiple of 4 here
+        } else {
 #pragma unroll
-            for (int j = 0; j < kDistSide; ++j)
-                if (j >= kDistCap - k && j <= kDistCap + k) c[oi] |= sh.x[oi][k][j];
-        sh.d[k] = Multi ? dilate_z(c[0], c[1], c[2], k) : dilate_z(0ull, c[0], 0ull, k);
+            for (int q = 0; q < 4; ++q)
+                if (j + q < nz) V.dist[b0 + j + q] = (uint8_t)(v >> (8 * q));
+        }
     }
-    wave_lds_sync();
-    int d = kDistCap;
-#pragma unroll
-    for (int k = kDistCap; k >= 0; --k)
-        if ((sh.d[k] >> lane) & 1ull) d = k;
-    wave_lds_sync();  // sh is rewritten for the wavefront's next word
-    const uint64_t cm = valid ? cell_mask(M) : 0ull;
-    if (valid) {
-        V.cmask[b] = cm;
-        V.dist[b] = (uint8_t)d;
-    }
-    if (frames && rb.entries) collect_footprint(V, frames[V.frame], v, cm, bx, by, bz, brick_base, hdr, rb);
 }
 
-// four wavefronts per block, each with its own shared memory
-__global__ __launch_bounds__(256) void mvf_brick_distance_kernel(const LaunchHeader* hdr, const DevVolume* vols,
-                                                                 const int32_t* brick_base, const DevFrame* frames,
-                                                                 RayBounds rb)
+// at most 96 VGPRs: five wavefronts per SIMD still hold every brick wavefront of
+// a 512^3 volume at once
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void mvf_brick_distance_kernel(
+    const LaunchHeader* hdr, const DevVolume* vols, const int32_t* brick_base, const DevFrame* frames, RayBounds rb)
 {
-    __shared__ DistShared shared[4];
     const int lane = threadIdx.x & 63;
-    DistShared& sh = shared[threadIdx.x >> 6];
+    const int wave = wave_uniform((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
     const int nvol = cptr(hdr)->nvol;
-    const int waves = (int)(gridDim.x * 4);
-    const int wave = wave_uniform((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    // the column words of all volumes, numbered volume by volume, are dealt
-    // to the wavefronts in turn; acc = words before volume v, modulo waves
-    int acc = 0;
-    for (int v = 0; v < nvol; ++v) {
-        CPTR(DevVolume) const Vp = cptr(vols) + v;
-        const int nw = col_words(Vp->bd[2]);
-        const int ncw = Vp->bd[0] * Vp->bd[1] * nw;
-        int first = (wave - acc) % waves;
-        if (first < 0) first += waves;
-        acc = (int)(((long long)acc + ncw) % waves);
-        if (first >= ncw) continue;
-        const DevVolume V = *Vp;
-        for (int cw = first; cw < ncw; cw += waves) {
-            if (nw == 1) brick_distance_word<false>(V, v, cw, lane, sh, frames, rb, brick_base, hdr);
-            else brick_distance_word<true>(V, v, cw, lane, sh, frames, rb, brick_base, hdr);
+    if (wave < kDistWaves) {
+        // the lines of all volumes, numbered volume by volume, are dealt to
+        // the distance wavefronts in turn; acc = lines before volume v,
+        // modulo kDistWaves
+        int acc = 0;
+        for (int v = 0; v < nvol; ++v) {
+            CPTR(DevVolume) const Vp = cptr(vols) + v;
+            const int nw = col_words(Vp->bd[2]);
+            const int nyc = (Vp->bd[1] + kDistRows - 1) / kDistRows;
+            const int nl = Vp->bd[0] * nyc * nw;
+            int first = (wave - acc) % kDistWaves;
+            if (first < 0) first += kDistWaves;
+            acc = (int)(((long long)acc + nl) % kDistWaves);
+            if (first >= nl) continue;
+            const DevVolume V = *Vp;
+            for (int t = first; t < nl; t += kDistWaves) {
+                const int w = t % nw, r = t / nw;
+                const int yc = r % nyc, bx = r / nyc;
+                if (nw == 1) distance_line<false>(V, bx, yc * kDistRows, w, lane);
+                else distance_line<true>(V, bx, yc * kDistRows, w, lane);
+            }
         }
+        return;
+    }
+    const int total = cptr(hdr)->total_bricks;
+    const int bwaves = (int)(gridDim.x * (blockDim.x >> 6)) - kDistWaves;
+    CPTR(int32_t) const bbase = cptr(brick_base);
+    for (int g = wave - kDistWaves; g * 64 < total; g += bwaves) {
+        const int gw = g * 64;
+        int lo = 0, hi = nvol - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (bbase[mid] <= gw) lo = mid; else hi = mid - 1;
+        }
+        lo = wave_uniform(lo);
+        const DevVolume V = cptr(vols)[lo];
+        const int nb = V.bd[0] * V.bd[1] * V.bd[2];
+        const int b = gw + lane - bbase[lo];
+        const bool valid = b < nb;
+        const int bc = valid ? b : 0;
+        const int bz = bc % V.bd[2];
+        const int t = bc / V.bd[2];
+        const int by = t % V.bd[1];
+        const int bx = t / V.bd[1];
+        uint64_t cm = 0;
+        if (valid) {
+            GPTR(const uint64_t) const fm = gptr((const uint64_t*)V.fmask);
+            uint64_t M[2][2][2];
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const bool in = bx + dx < V.bd[0] && by + dy < V.bd[1] && bz + dz < V.bd[2];
+                        M[dz][dy][dx] = ld_elem(fm, in ? brick_index32(V, bx + dx, by + dy, bz + dz) : (uint32_t)b);
+                        M[dz][dy][dx] = in ? M[dz][dy][dx] : 0ull;
+                    }
+            cm = cell_mask(M);
+            V.cmask[b] = cm;
+        }
+        if (frames && rb.entries) collect_footprint(V, frames[V.frame], lo, cm, bx, by, bz, brick_base, hdr, rb);
     }
 }
 
+// blocks: wavefront groups of four for the bricks; the distance lines get
+// kDistWaves more wavefronts
 int launch_brick_distance(const LaunchHeader* hdr, const DevVolume* vols, const int32_t* brick_base, int blocks,
                           void* stream, const DevFrame* frames, RayBounds rb)
 {
     if (blocks <= 0) return 0;
-    hipLaunchKernelGGL(mvf_brick_distance_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, hdr, vols,
-                       brick_base, frames, rb);
+    hipLaunchKernelGGL(mvf_brick_distance_kernel, dim3(blocks + kDistWaves / 4), dim3(256), 0, (hipStream_t)stream,
+                       hdr, vols, brick_base, frames, rb);
     return (int)hipGetLastError();
 }
 
