@@ -81,10 +81,16 @@ struct Volume {
     bool host_pending = false;
 };
 
+// Swaps move a slab in chunks of kSwapChunk bytes, each with its own event,
+// so that a swap-in into a slab still being swapped out copies chunk k as
+// soon as the download of chunk k is done: the two directions of the host
+// link then run at once.
+constexpr size_t kSwapChunk = (size_t)64 << 20;
+
 struct Slab {
     uint8_t* ptr;
     size_t bytes;
-    hipEvent_t free_after;   // slab may be reused once this event completes
+    std::vector<hipEvent_t> chunk_done;  // download of chunk k finished (on d2h_stream); the last: all
 };
 
 struct Scratch {
@@ -180,7 +186,9 @@ struct StepGraph {
 struct mvf_ctx {
     mvf_config cfg{};
     int device = 0;
-    hipStream_t copy_stream = nullptr;
+    hipStream_t d2h_stream = nullptr;  // swap-out copies
+    hipStream_t h2d_stream = nullptr;  // swap-in copies
+    hipEvent_t h2d_last = nullptr;     // after the latest swap-in copies (swap-outs wait for it)
     std::vector<Grid> grids;
     std::vector<Volume> vols;
     std::map<int, Scratch> scratch;
@@ -340,8 +348,8 @@ mvf_status release_pool(mvf_ctx* c, uint64_t need_room)
     while (!c->pool.empty() && c->resident_bytes + c->pooled_bytes + need_room > c->budget) {
         Slab s = c->pool.front();
         c->pool.erase(c->pool.begin());
-        CHECK_HIP(hipEventSynchronize(s.free_after));
-        c->event_pool.push_back(s.free_after);
+        CHECK_HIP(hipEventSynchronize(s.chunk_done.back()));
+        for (hipEvent_t e : s.chunk_done) c->event_pool.push_back(e);
         CHECK_HIP(hipFree(s.ptr));
         c->pooled_bytes -= s.bytes;
     }
@@ -361,22 +369,29 @@ mvf_status swap_out(mvf_ctx* c, Volume& v, hipStream_t stream, bool keep_slab_po
     hipEvent_t used;
     CHECK_ST(get_event(c, &used));
     CHECK_HIP(hipEventRecord(used, stream));
-    CHECK_HIP(hipStreamWaitEvent(c->copy_stream, used, 0));
+    CHECK_HIP(hipStreamWaitEvent(c->d2h_stream, used, 0));
     c->event_pool.push_back(used);  // recorded; safe to reuse after the wait is enqueued
-    CHECK_HIP(hipMemcpyAsync(v.host, v.dev, v.bytes, hipMemcpyDeviceToHost, c->copy_stream));
+    // the mirror may still be the source of a swap-in copy
+    CHECK_HIP(hipStreamWaitEvent(c->d2h_stream, c->h2d_last, 0));
+    std::vector<hipEvent_t> chunks;
+    for (size_t off = 0; off < v.bytes; off += kSwapChunk) {
+        const size_t n = std::min(kSwapChunk, v.bytes - off);
+        CHECK_HIP(hipMemcpyAsync(v.host + off, v.dev + off, n, hipMemcpyDeviceToHost, c->d2h_stream));
+        hipEvent_t e;
+        CHECK_ST(get_event(c, &e));
+        CHECK_HIP(hipEventRecord(e, c->d2h_stream));
+        chunks.push_back(e);
+    }
     if (!v.host_ready) CHECK_HIP(hipEventCreate(&v.host_ready));
-    CHECK_HIP(hipEventRecord(v.host_ready, c->copy_stream));
+    CHECK_HIP(hipEventRecord(v.host_ready, c->d2h_stream));
     v.host_pending = true;
-    hipEvent_t done;
-    CHECK_ST(get_event(c, &done));
-    CHECK_HIP(hipEventRecord(done, c->copy_stream));
     c->resident_bytes -= v.bytes;
     if (keep_slab_pooled) {
-        c->pool.push_back(Slab{v.dev, v.bytes, done});
+        c->pool.push_back(Slab{v.dev, v.bytes, std::move(chunks)});
         c->pooled_bytes += v.bytes;
     } else {
-        CHECK_HIP(hipEventSynchronize(done));
-        c->event_pool.push_back(done);
+        CHECK_HIP(hipEventSynchronize(chunks.back()));
+        for (hipEvent_t e : chunks) c->event_pool.push_back(e);
         CHECK_HIP(hipFree(v.dev));
     }
     v.dev = nullptr;
@@ -386,17 +401,23 @@ mvf_status swap_out(mvf_ctx* c, Volume& v, hipStream_t stream, bool keep_slab_po
     return MVF_OK;
 }
 
-// Obtain a slab of v.bytes for v, usable on `stream`.
-mvf_status get_slab(mvf_ctx* c, Volume& v, hipStream_t stream)
+// Obtain a slab of v.bytes for v.  With `pending` null the slab is usable
+// on `stream`; otherwise the events of a download still filling from it are
+// handed over (chunk k free once event k completes) and the caller orders
+// its own copies after them.
+mvf_status get_slab(mvf_ctx* c, Volume& v, hipStream_t stream, std::vector<hipEvent_t>* pending)
 {
     for (size_t i = 0; i < c->pool.size(); ++i) {
         if (c->pool[i].bytes == v.bytes) {
             Slab s = c->pool[i];
             c->pool.erase(c->pool.begin() + i);
             c->pooled_bytes -= s.bytes;
-            CHECK_HIP(hipStreamWaitEvent(stream, s.free_after, 0));
-            CHECK_HIP(hipStreamWaitEvent(c->copy_stream, s.free_after, 0));
-            c->event_pool.push_back(s.free_after);
+            if (pending) {
+                *pending = std::move(s.chunk_done);
+            } else {
+                CHECK_HIP(hipStreamWaitEvent(stream, s.chunk_done.back(), 0));
+                for (hipEvent_t e : s.chunk_done) c->event_pool.push_back(e);
+            }
             v.dev = s.ptr;
             return MVF_OK;
         }
@@ -455,16 +476,27 @@ mvf_status ensure_resident(mvf_ctx* c, const std::vector<int>& need, hipStream_t
         Volume& v = c->vols[id];
         v.last_use = ++c->tick;
         if (v.state == State::Device) continue;
-        CHECK_ST(get_slab(c, v, stream));
+        std::vector<hipEvent_t> pending;
+        CHECK_ST(get_slab(c, v, stream, v.state == State::Host ? &pending : nullptr));
         c->resident_bytes += v.bytes;
         if (v.state == State::Host) {
-            // stream-ordered after earlier work on the caller's stream
+            // stream-ordered after earlier work on the caller's stream and
+            // after the download that wrote the mirror
             hipEvent_t before;
             CHECK_ST(get_event(c, &before));
             CHECK_HIP(hipEventRecord(before, stream));
-            CHECK_HIP(hipStreamWaitEvent(c->copy_stream, before, 0));
+            CHECK_HIP(hipStreamWaitEvent(c->h2d_stream, before, 0));
             c->event_pool.push_back(before);
-            CHECK_HIP(hipMemcpyAsync(v.dev, v.host, v.bytes, hipMemcpyHostToDevice, c->copy_stream));
+            if (v.host_pending) CHECK_HIP(hipStreamWaitEvent(c->h2d_stream, v.host_ready, 0));
+            // chunk k after the slab's previous download of chunk k (same
+            // slab size, same chunks)
+            size_t k = 0;
+            for (size_t off = 0; off < v.bytes; off += kSwapChunk, ++k) {
+                if (k < pending.size()) CHECK_HIP(hipStreamWaitEvent(c->h2d_stream, pending[k], 0));
+                CHECK_HIP(hipMemcpyAsync(v.dev + off, v.host + off, std::min(kSwapChunk, v.bytes - off),
+                                         hipMemcpyHostToDevice, c->h2d_stream));
+            }
+            for (hipEvent_t e : pending) c->event_pool.push_back(e);
             c->stats.bytes_h2d += v.bytes;
             c->stats.swaps_in += 1;
             copied = true;
@@ -474,11 +506,8 @@ mvf_status ensure_resident(mvf_ctx* c, const std::vector<int>& need, hipStream_t
         v.state = State::Device;
     }
     if (copied) {
-        hipEvent_t done;
-        CHECK_ST(get_event(c, &done));
-        CHECK_HIP(hipEventRecord(done, c->copy_stream));
-        CHECK_HIP(hipStreamWaitEvent(stream, done, 0));
-        c->event_pool.push_back(done);
+        CHECK_HIP(hipEventRecord(c->h2d_last, c->h2d_stream));
+        CHECK_HIP(hipStreamWaitEvent(stream, c->h2d_last, 0));
     }
     return MVF_OK;
 }
@@ -1231,7 +1260,9 @@ mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg)
         return st;
     };
     hipError_t e;
-    if ((e = hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking)) != hipSuccess ||
+    if ((e = hipStreamCreateWithFlags(&c->d2h_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->h2d_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->h2d_last, hipEventDisableTiming | hipEventDisableSystemFence)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
         (e = hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntNum * kCntSlots)) != hipSuccess ||
@@ -1263,7 +1294,7 @@ mvf_status mvf_destroy(mvf_ctx* c)
     }
     for (auto& s : c->pool) {
         (void)hipFree(s.ptr);
-        (void)hipEventDestroy(s.free_after);
+        for (hipEvent_t e : s.chunk_done) (void)hipEventDestroy(e);
     }
     for (auto& kv : c->scratch) {
         Scratch& s = kv.second;
@@ -1302,7 +1333,9 @@ mvf_status mvf_destroy(mvf_ctx* c)
     if (c->diff_partials) (void)hipFree(c->diff_partials);
     if (c->diff_summary) (void)hipFree(c->diff_summary);
     if (c->tail) (void)hipEventDestroy(c->tail);
-    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    if (c->d2h_stream) (void)hipStreamDestroy(c->d2h_stream);
+    if (c->h2d_stream) (void)hipStreamDestroy(c->h2d_stream);
+    if (c->h2d_last) (void)hipEventDestroy(c->h2d_last);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
     return MVF_OK;
@@ -1313,7 +1346,8 @@ mvf_status mvf_synchronize(mvf_ctx* c)
     if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
     CHECK_HIP(hipSetDevice(c->device));
     if (c->tail_valid) CHECK_HIP(hipEventSynchronize(c->tail_ev));
-    CHECK_HIP(hipStreamSynchronize(c->copy_stream));
+    CHECK_HIP(hipStreamSynchronize(c->d2h_stream));
+    CHECK_HIP(hipStreamSynchronize(c->h2d_stream));
     CHECK_HIP(hipDeviceSynchronize());
     return MVF_OK;
 }

@@ -50,16 +50,17 @@ def test_swap_round_trip(mvf):
         assert st["swaps_out"] == 1 and st["swaps_in"] == 1 and st["bytes_h2d"] == nbytes
 
 
-@pytest.mark.parametrize("budget_volumes", [1, 3])
-def test_budget_identity(mvf, budget_volumes):
-    """Eight 33^3 subvolumes fused and raycast with room for only
+@pytest.mark.parametrize("n,budget_volumes", [(64, 1), (64, 3), (416, 1), (416, 3)])
+def test_budget_identity(mvf, n, budget_volumes):
+    """Eight (n/2 + 1)^3 subvolumes fused and raycast with room for only
     `budget_volumes` of them on the device (waves + swaps) give the same bits
-    as with no budget."""
+    as with no budget.  At n = 416 a slab (209^3, about 93 MB) is copied in
+    two chunks, and a swap-in into the slab of the volume just swapped out
+    overlaps that volume's download chunk by chunk."""
     seq = S.small_room_sequence(seed=1)
     K = seq.K.as_array()
-    n = 64
     origin, s = (-1.0, -1.0, -1.0), 2.0 / n
-    log(f"budget identity, room for {budget_volumes} of 8 volumes")
+    log(f"budget identity, n {n}, room for {budget_volumes} of 8 volumes")
     results = []
     for limited in (False, True):
         with mvf.Context() as ctx:
