@@ -312,7 +312,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
         const int bz0 = zc * zchunk;
         const int bz1 = min(bz0 + zchunk, V.bd[2]);
         // bricks of the item that may hold an updated voxel
-        const uint64_t vis = L.visit ? cptr((const uint64_t*)L.visit)[item] : 0x0101010101010101ull;
+        // bytes from zchunk on are not written by the visit pass
+        const uint64_t vis = L.visit ? cptr((const uint64_t*)L.visit)[item] &
+                                           (zchunk >= kVisitPerItem ? ~0ull : (1ull << (8 * zchunk)) - 1ull)
+                                     : 0x0101010101010101ull;
         if (vis == 0) continue;
 
         // frame parameters, held in registers for the whole item
@@ -597,28 +600,29 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
     const DevFrame* frames = L.frames;
     const int nvol = hdr->nvol;
     if (blockIdx.x >= kZtBlocks) {
-        // one thread per brick of an item (kVisitPerItem per item)
-        const int total = hdr->total_items * kVisitPerItem;
+        // one thread per brick of an item (zchunk per item; the item's
+        // bytes from zchunk on are never read)
         const int zchunk = hdr->zchunk;
+        const int total = hdr->total_items * zchunk;
         const int stride = (gridDim.x - kZtBlocks) * blockDim.x;
-        for (int t = (blockIdx.x - kZtBlocks) * blockDim.x + threadIdx.x; t < total; t += stride) {
-            const int item = t / kVisitPerItem, j = t - item * kVisitPerItem;
+        for (int t0 = (blockIdx.x - kZtBlocks) * blockDim.x; t0 < total; t0 += stride) {
+            const int t = min(t0 + (int)threadIdx.x, total - 1);
+            const int item = t / zchunk, j = t - item * zchunk;
             int lo = 0, hi = nvol - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (L.item_base[mid] <= item) lo = mid; else hi = mid - 1;
             }
-            const DevVolume& V = vols[lo];
-            const DevFrame& Fr = frames[V.frame];
-            const int local = item - L.item_base[lo];
-            const int ncols = V.bd[0] * V.bd[1];
-            const int zc = local / ncols;
-            const int col = local - zc * ncols;
-            const int byi = col / V.bd[0];
-            const int bxi = col - byi * V.bd[0];
-            const int bz = zc * zchunk + j;
-            bool visit = j < zchunk && bz < V.bd[2];
-            if (visit && Fr.tmax) {
+            auto test = [&](const DevVolume& V, const DevFrame& Fr) {
+                const int local = item - L.item_base[lo];
+                const int ncols = V.bd[0] * V.bd[1];
+                const int zc = local / ncols;
+                const int col = local - zc * ncols;
+                const int byi = col / V.bd[0];
+                const int bxi = col - byi * V.bd[0];
+                const int bz = zc * zchunk + j;
+                if (bz >= V.bd[2]) return false;
+                if (!Fr.tmax) return true;
                 const int i0[3] = {bxi * kBrick, byi * kBrick, bz * kBrick};
                 float blo[3], bhi[3];
 #pragma unroll
@@ -627,9 +631,19 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
                     blo[a] = V.o[a] + (V.s * ((float)(V.off[a] + i0[a]) + 0.5f));
                     bhi[a] = V.o[a] + (V.s * ((float)(V.off[a] + i1) + 0.5f));
                 }
-                visit = brick_may_update(V, Fr, blo, bhi);
+                return brick_may_update(V, Fr, blo, bhi);
+            };
+            // a wavefront whose bricks share one volume reads the volume
+            // and frame tables with scalar loads
+            const int lo0 = wave_uniform(lo);
+            bool visit;
+            if (__ballot(lo != lo0) == 0) {
+                const DevVolume V = cptr(vols)[lo0];
+                visit = test(V, cptr(frames)[V.frame]);
+            } else {
+                visit = test(vols[lo], frames[vols[lo].frame]);
             }
-            L.visit[t] = visit ? 1 : 0;
+            if (t0 + (int)threadIdx.x < total) L.visit[(size_t)item * kVisitPerItem + j] = visit ? 1 : 0;
         }
         return;
     }

@@ -905,7 +905,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         CHECK_ST(arena_upload(c, w2, stream));
         for (auto& p : per) {
             IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit, nullptr, nullptr, 0};
-            CHECK_LAUNCH(launch_ztable(L, (p.items * kVisitPerItem + 255) / 256, stream));
+            CHECK_LAUNCH(launch_ztable(L, (p.items * kZChunk + 255) / 256, stream));
             // with timing, the kernel's dispatch records the event pair
             hipEvent_t t0, t1;
             CHECK_ST(timing_pair(c, &t0, &t1));
@@ -1933,7 +1933,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         // the last step first)
         IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit,
                            G.tile_cost, G.tile_order, G.ray_tiles};
-        int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items * kVisitPerItem + 255) / 256), cs);
+        int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items * zc + 255) / 256), cs);
         // one wavefront per work item of the captured volume set (a larger
         // set later is walked by the kernel's grid-stride loop)
         G.integ_blocks = (sch.persistent ? c->n_cus * 8 : std::max(c->n_cus * 8, (items + 3) / 4)) + 1;
