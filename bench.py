@@ -68,7 +68,7 @@ def render_frames(n_frames: int, total: int = 300):
     return seq, [(by[i], seq.poses[i]) for i in idx]
 
 
-TUNE_STEPS = 32 + 2   # the autotuner's candidate runs (8 x 4) and two more
+TUNE_STEPS = 60 + 2   # the autotuner's runs (15 blocks of 4: the reference between the 7 others) and two more
 
 
 def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=False, tune_cache=None,

@@ -259,10 +259,12 @@ mvf_status mvf_get_schedule(mvf_ctx* ctx, mvf_schedule* out);
 #define MVF_AUTOTUNE_CACHED 2   /* use the cache; the default schedule for other shapes */
 /* Autotuning of mvf_step.  A step shape is the stream count, the output
  * sizes, the number of volumes and their brick dimensions.  In TUNE mode
- * the first 32 steps of a new shape run each of 8 candidate schedules four
- * times in a row (timed with HIP events on the call's stream; the step's
- * results are unaffected) and the shape keeps the fastest by the median of
- * the last three runs (the first pays the graph capture).  Tune on
+ * the first 60 steps of a new shape run blocks of four steps, the default
+ * schedule between each two of the 7 other candidates (timed with HIP events
+ * on the call's stream; the step's results are unaffected); each block
+ * counts by the median of its last three runs (the first pays the graph
+ * capture), and the shape keeps the candidate fastest relative to the mean
+ * of the default blocks around it.  Tune on
  * representative frames: the fastest schedule depends on how much of the
  * volumes the frames see.  cache_path (may be NULL: memory
  * only) is a JSON-lines file read now (missing file: empty cache) and

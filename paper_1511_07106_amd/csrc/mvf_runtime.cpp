@@ -1049,9 +1049,18 @@ mvf_status destroy_step_graph(mvf_ctx* c)
 
 // ---- step schedules and their autotuner -------------------------------------
 
-// runs per candidate; the first (which pays the graph capture and starts the
-// raycast tile order afresh) is not counted
+// runs per block of one schedule; the first (which pays the graph capture and
+// starts the raycast tile order afresh) is not counted.  The blocks alternate
+// between the reference schedule (the first candidate, the default) and the
+// other candidates in turn: ref, c1, ref, c2, ..., ref.  A candidate is scored
+// by its median over the mean of the two reference medians around it, so that
+// the frames' cost, which drifts as the map fills, cancels locally.
 constexpr int kTuneReps = 4;
+
+int tune_blocks(int ncand) { return 2 * ncand - 1; }
+
+// candidate run by block b
+int tune_block_cand(int b) { return (b & 1) ? (b + 1) / 2 : 0; }
 
 bool valid_schedule(const mvf_schedule& s)
 {
@@ -1064,14 +1073,16 @@ bool same_schedule(const mvf_schedule& a, const mvf_schedule& b)
     return a.zchunk == b.zchunk && a.persistent == b.persistent && a.ray_lanes == b.ray_lanes;
 }
 
-// Candidates tried for a new shape: every z chunk with both integration
-// grids at 4 lanes per ray, then the other lane counts at the default.
+// Candidates tried for a new shape: the default first (the reference), then
+// every other z chunk and integration grid at 4 lanes per ray, then the other
+// lane counts at the default.
 std::vector<mvf_schedule> tune_candidates()
 {
-    std::vector<mvf_schedule> c;
+    std::vector<mvf_schedule> c{mvf_schedule{kZChunk, 0, kRayLanes, 0}};
     for (int z : {2, 4, 8})
-        for (int p : {0, 1}) c.push_back(mvf_schedule{z, p, kRayLanes, 0});
-    for (int l : {2, 8}) c.push_back(mvf_schedule{4, 0, l, 0});
+        for (int p : {0, 1})
+            if (!(z == kZChunk && p == 0)) c.push_back(mvf_schedule{z, p, kRayLanes, 0});
+    for (int l : {2, 8}) c.push_back(mvf_schedule{kZChunk, 0, l, 0});
     return c;
 }
 
@@ -1168,7 +1179,8 @@ mvf_schedule pick_schedule(mvf_ctx* c, const std::string& key, bool* tuning)
         T.cands = tune_candidates();
     }
     *tuning = true;
-    return T.cands[(size_t)(T.next / kTuneReps) % T.cands.size()];
+    const int b = (T.next / kTuneReps) % tune_blocks((int)T.cands.size());
+    return T.cands[(size_t)tune_block_cand(b)];
 }
 
 // After the last timed launch of a shape: the fastest candidate by median
@@ -1176,23 +1188,32 @@ mvf_schedule pick_schedule(mvf_ctx* c, const std::string& key, bool* tuning)
 mvf_status finish_tuning(mvf_ctx* c)
 {
     mvf_ctx::Tuning& T = c->tuning;
-    if (T.next < (int)T.cands.size() * kTuneReps) return MVF_OK;
+    const int nc = (int)T.cands.size(), nb = tune_blocks(nc);
+    if (T.next < nb * kTuneReps) return MVF_OK;
     CHECK_HIP(hipEventSynchronize(T.ev.back().second));
-    int best = 0;
-    double best_ms = 1e300;
-    for (size_t ci = 0; ci < T.cands.size(); ++ci) {
+    std::vector<double> med(nb);
+    for (int b = 0; b < nb; ++b) {
         std::vector<float> ms;
         for (int r = 1; r < kTuneReps; ++r) {
-            const auto& e = T.ev[ci * kTuneReps + r];
+            const auto& e = T.ev[(size_t)(b * kTuneReps + r)];
             float t = 0.0f;
             CHECK_HIP(hipEventElapsedTime(&t, e.first, e.second));
             ms.push_back(t);
         }
         std::sort(ms.begin(), ms.end());
-        const float med = ms[ms.size() / 2];
-        if (med < best_ms) {
-            best_ms = med;
-            best = (int)ci;
+        med[b] = ms[ms.size() / 2];
+    }
+    // the reference scores 1; candidate j (block 2j - 1) against the
+    // reference blocks 2j - 2 and 2j around it
+    int best = 0;
+    double best_score = 1.0, best_ms = med[0];
+    for (int j = 1; j < nc; ++j) {
+        const double ref = 0.5 * (med[2 * j - 2] + med[2 * j]);
+        const double score = med[2 * j - 1] / ref;
+        if (score < best_score) {
+            best_score = score;
+            best = j;
+            best_ms = med[2 * j - 1];
         }
     }
     c->tune_cache[T.key] = std::make_pair(T.cands[best], best_ms);

@@ -92,10 +92,13 @@ def _run_steps(mvf, seqs, layouts, n_frames, configure=None):
         gid = ctx.grid(origin, s)
         ids = [[ctx.volume(gid, off, dims, stream_id=i) for off, dims in layouts[i]] for i in range(n)]
         maps, scheds = [], []
+        rendered = {}
         for f in range(n_frames):
             frames = []
             for i, seq in enumerate(seqs):
-                d, c = seq.frame(f % 12)
+                if (i, f % 12) not in rendered:
+                    rendered[(i, f % 12)] = seq.frame(f % 12)
+                d, c = rendered[(i, f % 12)]
                 frames.append((i, t(d), t(c), seq.poses[f % 12], K))
             outs = [{"depth": torch.empty((h, w), device="cuda"), "vertex": torch.empty((h, w, 3), device="cuda"),
                      "normal": torch.empty((h, w, 3), device="cuda"),
@@ -132,14 +135,16 @@ def test_every_schedule_gives_the_same_bits(mvf, sched):
 
 
 def test_autotune_tunes_caches_and_keeps_results(mvf, tmp_path):
-    """TUNE mode runs each candidate four times on the first steps of a new
-    shape, then keeps the fastest and appends it to the cache; CACHED mode
-    reads it back.  Results equal the default schedule's throughout."""
+    """TUNE mode runs blocks of four steps on the first steps of a new shape,
+    the default schedule between each two of the other candidates, keeps the
+    fastest relative to the default blocks around it and appends it to the
+    cache; CACHED mode reads it back.  Results equal the default schedule's
+    throughout."""
     seqs, layouts = _scenes(2)
     path = str(tmp_path / "tune.jsonl")
-    log("autotune: 8 candidates x 4 runs + 4 steps")
-    ref = _run_steps(mvf, seqs, layouts, 36)
-    got = _run_steps(mvf, seqs, layouts, 36, lambda ctx: ctx.autotune("tune", path))
+    log("autotune: 15 blocks x 4 runs + 4 steps")
+    ref = _run_steps(mvf, seqs, layouts, 64)
+    got = _run_steps(mvf, seqs, layouts, 64, lambda ctx: ctx.autotune("tune", path))
     _assert_same(ref, got)
     lines = open(path).read().strip().splitlines()
     assert len(lines) == 1
@@ -147,9 +152,13 @@ def test_autotune_tunes_caches_and_keeps_results(mvf, tmp_path):
     rec = json.loads(lines[0])
     chosen = {k: rec[k] for k in ("zchunk", "persistent", "ray_lanes")}
     assert rec["ms"] > 0
-    # the tuning steps ran the candidates in order, then the chosen one stays
-    assert got[2][0] == {"zchunk": 2, "persistent": 0, "ray_lanes": 4}
-    assert all(s == chosen for s in got[2][32:])
+    # the tuning steps alternated the default with the others, then the
+    # chosen one stays
+    default = {"zchunk": 4, "persistent": 0, "ray_lanes": 4}
+    assert all(got[2][4 * b] == default for b in range(0, 15, 2))
+    assert got[2][4] == {"zchunk": 2, "persistent": 0, "ray_lanes": 4}
+    assert got[2][56] == default and got[2][52] == {"zchunk": 4, "persistent": 0, "ray_lanes": 8}
+    assert all(s == chosen for s in got[2][60:])
     cached = _run_steps(mvf, seqs, layouts, 2, lambda ctx: ctx.autotune("cached", path))
     assert all(s == chosen for s in cached[2])
     assert len(open(path).read().strip().splitlines()) == 1
