@@ -851,24 +851,31 @@ static __device__ __forceinline__ bool eval_sample(const DevVolume& V, const flo
 // Conservative sample range [k0, k1] of the ray inside V's domain box grown
 // by one voxel, plus two samples each side.
 // Raycast range bounds.  Every sample the march must evaluate (a possible
-// far end of a crossing) lies in a brick whose cell mask is not empty, at a
-// local coordinate in the brick's box [8 b, 8 b + 8).  Each such brick
-// records the distance range of that box (grown by 0.1 voxel) from the
-// camera centre and the 8x8-pixel cells its projection can reach (grown by
-// one pixel; all cells when the box reaches behind the camera); a merge
-// folds these footprints into per-cell ranges, and a ray marches only
+// far end of a crossing) lies in a cell with a corner that may hold F <= 0:
+// a cell whose base voxel lies in a sub-block set in its brick's cell mask,
+// at local coordinates in [8 b + 2 s0, 8 b + 2 s1 + 2) along each axis for
+// the set sub-blocks s0 .. s1 (the near end of a crossing is one sample
+// before; rays keep two samples of margin).  Each brick with a non-empty
+// cell mask records the distance range of that box (grown by 0.1 voxel)
+// from the camera centre and the 8x8-pixel cells its projection can reach
+// (grown by one pixel; all cells when the box reaches behind the camera); a
+// merge folds these footprints into per-cell ranges, and a ray marches only
 // within the range of its cell (a cell no brick reaches is empty).
-static __device__ bool brick_footprint(const DevVolume& V, const DevFrame& Fr, int bx, int by, int bz,
+static __device__ bool brick_footprint(const DevVolume& V, const DevFrame& Fr, int bx, int by, int bz, uint64_t cm,
                                        RayBoundEntry& e)
 {
     const int ib[3] = {bx, by, bz};
     const float c[3] = {Fr.T[3], Fr.T[7], Fr.T[11]};
+    // the box of the cell mask's sub-blocks (cm != 0), in voxel-centre
+    // coordinates
+    const uint32_t occ[3] = {occupancy_x(cm), occupancy_y(cm), occupancy_z(cm)};
     float lo[3], hi[3];
     float dn2 = 0.0f, df2 = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        lo[a] = V.o[a] + V.s * ((float)(V.off[a] + kBrick * ib[a]) + 0.4f);
-        hi[a] = V.o[a] + V.s * ((float)(V.off[a] + kBrick * ib[a] + kBrick) + 0.6f);
+        const int s0 = __builtin_ctz(occ[a]), s1 = 31 - __builtin_clz(occ[a]);
+        lo[a] = V.o[a] + V.s * ((float)(V.off[a] + kBrick * ib[a] + 2 * s0) + 0.4f);
+        hi[a] = V.o[a] + V.s * ((float)(V.off[a] + kBrick * ib[a] + 2 * s1 + 2) + 0.6f);
         const float en = fmaxf(fmaxf(lo[a] - c[a], c[a] - hi[a]), 0.0f);
         const float ef = fmaxf(fabsf(lo[a] - c[a]), fabsf(hi[a] - c[a]));
         dn2 += en * en;
@@ -917,7 +924,7 @@ static __device__ void collect_footprint(const DevVolume& V, const DevFrame& Fr,
                                          int bz, const int32_t* brick_base, const LaunchHeader* hdr, RayBounds rb)
 {
     RayBoundEntry e;
-    const bool has = Fr.rb_lo && cm != 0ull && brick_footprint(V, Fr, bx, by, bz, e);
+    const bool has = Fr.rb_lo && cm != 0ull && brick_footprint(V, Fr, bx, by, bz, cm, e);
     const unsigned long long m = __ballot(has);
     if (m == 0) return;
     const int lane = threadIdx.x & 63;
