@@ -68,7 +68,7 @@ def render_frames(n_frames: int, total: int = 300):
     return seq, [(by[i], seq.poses[i]) for i in idx]
 
 
-TUNE_STEPS = 60 + 2   # the autotuner's runs (15 blocks of 4: the reference between the 7 others) and two more
+TUNE_STEPS = 120 + 2  # the autotuner's runs (15 blocks of 8: the reference between the 7 others) and two more
 
 
 def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=False, tune_cache=None,
@@ -409,7 +409,9 @@ def main():
     names = args.phases.split(",")
     frames, dev_frames, poses = [], [], []
     if any(ph not in EXTRA_PHASES for ph in names) or not args.no_cpu:
-        seq, frames = render_frames(args.warmup + args.steps)
+        # the tuning runs see the frames after the warm-up too: render enough
+        # for both
+        seq, frames = render_frames(args.warmup + max(args.steps, TUNE_STEPS))
         dev_frames = [(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev)) for (d, c), _ in frames]
         poses = [T for _, T in frames]
     torch.cuda.synchronize()

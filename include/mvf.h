@@ -259,12 +259,12 @@ mvf_status mvf_get_schedule(mvf_ctx* ctx, mvf_schedule* out);
 #define MVF_AUTOTUNE_CACHED 2   /* use the cache; the default schedule for other shapes */
 /* Autotuning of mvf_step.  A step shape is the stream count, the output
  * sizes, the number of volumes and their brick dimensions.  In TUNE mode
- * the first 60 steps of a new shape run blocks of four steps, the default
+ * the first 120 steps of a new shape run blocks of eight steps, the default
  * schedule between each two of the 7 other candidates (timed with HIP events
  * on the call's stream; the step's results are unaffected); each block
- * counts by the median of its last three runs (the first pays the graph
- * capture), and the shape keeps the candidate fastest relative to the mean
- * of the default blocks around it.  Tune on
+ * counts by the mean of its last seven runs without their highest and lowest
+ * (the first pays the graph capture), and the shape keeps the candidate
+ * fastest relative to the mean of the default blocks around it.  Tune on
  * representative frames: the fastest schedule depends on how much of the
  * volumes the frames see.  cache_path (may be NULL: memory
  * only) is a JSON-lines file read now (missing file: empty cache) and

@@ -1050,12 +1050,13 @@ mvf_status destroy_step_graph(mvf_ctx* c)
 // ---- step schedules and their autotuner -------------------------------------
 
 // runs per block of one schedule; the first (which pays the graph capture and
-// starts the raycast tile order afresh) is not counted.  The blocks alternate
+// starts the raycast tile order afresh) is not counted, and a block scores
+// the mean of the others without their highest and lowest.  The blocks alternate
 // between the reference schedule (the first candidate, the default) and the
 // other candidates in turn: ref, c1, ref, c2, ..., ref.  A candidate is scored
-// by its median over the mean of the two reference medians around it, so that
+// by its score over the mean of the two reference scores around it, so that
 // the frames' cost, which drifts as the map fills, cancels locally.
-constexpr int kTuneReps = 4;
+constexpr int kTuneReps = 8;
 
 int tune_blocks(int ncand) { return 2 * ncand - 1; }
 
@@ -1201,7 +1202,9 @@ mvf_status finish_tuning(mvf_ctx* c)
             ms.push_back(t);
         }
         std::sort(ms.begin(), ms.end());
-        med[b] = ms[ms.size() / 2];
+        double sum = 0.0;
+        for (size_t i = 1; i + 1 < ms.size(); ++i) sum += ms[i];
+        med[b] = sum / (double)(ms.size() - 2);
     }
     // the reference scores 1; candidate j (block 2j - 1) against the
     // reference blocks 2j - 2 and 2j around it

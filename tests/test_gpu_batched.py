@@ -135,16 +135,16 @@ def test_every_schedule_gives_the_same_bits(mvf, sched):
 
 
 def test_autotune_tunes_caches_and_keeps_results(mvf, tmp_path):
-    """TUNE mode runs blocks of four steps on the first steps of a new shape,
+    """TUNE mode runs blocks of eight steps on the first steps of a new shape,
     the default schedule between each two of the other candidates, keeps the
     fastest relative to the default blocks around it and appends it to the
     cache; CACHED mode reads it back.  Results equal the default schedule's
     throughout."""
     seqs, layouts = _scenes(2)
     path = str(tmp_path / "tune.jsonl")
-    log("autotune: 15 blocks x 4 runs + 4 steps")
-    ref = _run_steps(mvf, seqs, layouts, 64)
-    got = _run_steps(mvf, seqs, layouts, 64, lambda ctx: ctx.autotune("tune", path))
+    log("autotune: 15 blocks x 8 runs + 4 steps")
+    ref = _run_steps(mvf, seqs, layouts, 124)
+    got = _run_steps(mvf, seqs, layouts, 124, lambda ctx: ctx.autotune("tune", path))
     _assert_same(ref, got)
     lines = open(path).read().strip().splitlines()
     assert len(lines) == 1
@@ -155,10 +155,10 @@ def test_autotune_tunes_caches_and_keeps_results(mvf, tmp_path):
     # the tuning steps alternated the default with the others, then the
     # chosen one stays
     default = {"zchunk": 4, "persistent": 0, "ray_lanes": 4}
-    assert all(got[2][4 * b] == default for b in range(0, 15, 2))
-    assert got[2][4] == {"zchunk": 2, "persistent": 0, "ray_lanes": 4}
-    assert got[2][56] == default and got[2][52] == {"zchunk": 4, "persistent": 0, "ray_lanes": 8}
-    assert all(s == chosen for s in got[2][60:])
+    assert all(got[2][8 * b] == default for b in range(0, 15, 2))
+    assert got[2][8] == {"zchunk": 2, "persistent": 0, "ray_lanes": 4}
+    assert got[2][112] == default and got[2][104] == {"zchunk": 4, "persistent": 0, "ray_lanes": 8}
+    assert all(s == chosen for s in got[2][120:])
     cached = _run_steps(mvf, seqs, layouts, 2, lambda ctx: ctx.autotune("cached", path))
     assert all(s == chosen for s in cached[2])
     assert len(open(path).read().strip().splitlines()) == 1
