@@ -34,6 +34,8 @@ def test_swap_round_trip(mvf):
             d, c = seq.frame(i)
             ctx.integrate(t(d), t(c), seq.poses[i], K)
         F1, W1, C1 = ctx.read_volume(vid)
+        flag1, dist1 = ctx.brick_summary(vid)
+        assert flag1.any()
         ctx.swap_out(vid)
         resident, nbytes, active = ctx.query(vid)
         assert not resident and active and nbytes >= 64 ** 3 * 10
@@ -41,11 +43,17 @@ def test_swap_round_trip(mvf):
         np.testing.assert_array_equal(F2.view(np.uint32), F1.view(np.uint32))
         np.testing.assert_array_equal(W2, W1)
         np.testing.assert_array_equal(C2, C1)
+        flag2, dist2 = ctx.brick_summary(vid)  # the summaries travel with the slab
+        np.testing.assert_array_equal(flag2, flag1)
+        np.testing.assert_array_equal(dist2, dist1)
         ctx.swap_in(vid)
         assert ctx.query(vid)[0]
         F3, W3, C3 = ctx.read_volume(vid)
         np.testing.assert_array_equal(F3.view(np.uint32), F1.view(np.uint32))
         np.testing.assert_array_equal(W3, W1)
+        flag3, dist3 = ctx.brick_summary(vid)
+        np.testing.assert_array_equal(flag3, flag1)
+        np.testing.assert_array_equal(dist3, dist1)
         st = ctx.stats()
         assert st["swaps_out"] == 1 and st["swaps_in"] == 1 and st["bytes_h2d"] == nbytes
 

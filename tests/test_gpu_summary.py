@@ -116,3 +116,14 @@ def test_summary_after_batched_step(mvf, zchunk):
         torch.cuda.synchronize()
         for v in vids:
             _check(ctx, v)
+
+
+def test_summary_of_a_volume_never_resident(mvf):
+    """A volume that was never made resident reads as unflagged, at the cap."""
+    log("brick summary of an empty volume")
+    with mvf.Context() as ctx:
+        gid = ctx.grid((0.0, 0.0, 0.0), 0.01, 4.0, 128)
+        vid = ctx.volume(gid, (0, 0, 0), (20, 9, 70), place=False)
+        flag, dist = ctx.brick_summary(vid)
+        assert flag.shape == (3, 2, 9)
+        assert not flag.any() and (dist == CAP).all()
