@@ -294,6 +294,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
     CPTR(float) const ztab = cptr(L.ztab);
 
     for (int item = wave_uniform(((int)blockIdx.x - b0) * wpb + wib); item < total_items; item += total_waves) {
+        // bricks of the item that may hold an updated voxel, first: about
+        // two thirds of the items of a frame have none and stop here (bytes
+        // from zchunk on are not written by the visit pass)
+        const uint64_t vis = L.visit ? cptr((const uint64_t*)L.visit)[item] &
+                                           (zchunk >= kVisitPerItem ? ~0ull : (1ull << (8 * zchunk)) - 1ull)
+                                     : 0x0101010101010101ull;
+        if (vis == 0) continue;
         // volume owning this item
         CPTR(int32_t) const item_base = cptr(L.item_base);
         int lo = 0, hi = nvol - 1;
@@ -311,12 +318,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
         const int bxi = col - byi * V.bd[0];
         const int bz0 = zc * zchunk;
         const int bz1 = min(bz0 + zchunk, V.bd[2]);
-        // bricks of the item that may hold an updated voxel
-        // bytes from zchunk on are not written by the visit pass
-        const uint64_t vis = L.visit ? cptr((const uint64_t*)L.visit)[item] &
-                                           (zchunk >= kVisitPerItem ? ~0ull : (1ull << (8 * zchunk)) - 1ull)
-                                     : 0x0101010101010101ull;
-        if (vis == 0) continue;
 
         // frame parameters, held in registers for the whole item
         CPTR(DevFrame) const Fp = cptr(L.frames) + V.frame;
