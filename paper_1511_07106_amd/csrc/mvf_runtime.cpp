@@ -110,6 +110,8 @@ struct Scratch {
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
     int32_t* tile_order = nullptr;
     int tiles_cap = 0;
+    int last_tiles = 0;         // tiles of the stream's last raycast (0: none yet)
+    int order_ready_tiles = 0;  // an integration ordered that many tiles for the next raycast
     float* rb_lo = nullptr;  // raycast range bounds per 8x8 output-pixel cell
     float* rb_hi = nullptr;
     int rb_cap = 0;
@@ -865,6 +867,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         CHECK_HIP(hipMalloc((void**)&sc->visit, (size_t)max_items * kVisitPerItem));
         sc->visit_cap = max_items;
     }
+    bool order_pending = sc->tile_cost && sc->last_tiles > 0;  // once per call
     for (auto& wave : waves) {
         CHECK_ST(ensure_resident(c, wave, stream));
         int slot2;
@@ -903,13 +906,22 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             per.push_back(p);
         }
         CHECK_ST(arena_upload(c, w2, stream));
-        for (auto& p : per) {
-            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit, nullptr, nullptr, 0};
+        for (size_t pi = 0; pi < per.size(); ++pi) {
+            const Per& p = per[pi];
+            // the first launch's block 0 orders the tiles of the stream's
+            // next raycast from the last one's durations (the raycast then
+            // skips its own ordering launch)
+            const bool order = pi == 0 && order_pending;
+            order_pending = false;
+            IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit,
+                              order ? sc->tile_cost : nullptr, order ? sc->tile_order : nullptr,
+                              order ? sc->last_tiles : 0};
+            if (order) sc->order_ready_tiles = sc->last_tiles;
             CHECK_LAUNCH(launch_ztable(L, (p.items * kZChunk + 255) / 256, stream));
             // with timing, the kernel's dispatch records the event pair
             hipEvent_t t0, t1;
             CHECK_ST(timing_pair(c, &t0, &t1));
-            CHECK_LAUNCH(launch_integrate(L, (p.items + 3) / 4, stream, t0, t1));
+            CHECK_LAUNCH(launch_integrate(L, (p.items + 3) / 4 + (order ? 1 : 0), stream, t0, t1));
             CHECK_ST(timing_push(c, t0, t1, 0));
             CHECK_LAUNCH(launch_brick_distance(p.dh, p.dv, p.dbb, std::min(1024, (p.bricks + 255) / 256), stream));
             c->stats.integrate_launches += 1;
@@ -938,6 +950,10 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
     const int tiles = ((out->width + tw - 1) / tw) * ((out->height + th - 1) / th);
     CHECK_ST(get_tile_buffers(sc, tiles));
     CHECK_ST(get_bound_buffers(sc, out->width, out->height));
+    // an order the integration computed holds for this many tiles only
+    const bool ordered = sc->order_ready_tiles == tiles && sc->last_tiles == tiles;
+    sc->order_ready_tiles = 0;
+    sc->last_tiles = tiles;
     for (size_t wi = 0; wi < waves.size(); ++wi) {
         auto& wave = waves[wi];
         CHECK_ST(ensure_resident(c, wave, stream));
@@ -1007,7 +1023,7 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
         const RayBounds RB{sc->rb_entries, sc->rb_counts, sc->rb_counts_cap};
         CHECK_LAUNCH(launch_ray_bounds_collect(dh, dvols, dbb, dfr, RB, std::min(1024, (nbr + 255) / 256), stream));
         CHECK_LAUNCH(launch_ray_bounds_merge(dh, dfr, dlists, dlb, dbb, RB, 1, fr->cells_x, fr->cells_y, stream));
-        CHECK_LAUNCH(launch_tile_order(sc->tile_cost, sc->tile_order, tiles, stream));
+        if (!(ordered && wi == 0)) CHECK_LAUNCH(launch_tile_order(sc->tile_cost, sc->tile_order, tiles, stream));
         CHECK_LAUNCH(launch_raycast(L, ray_blocks(tiles), stream, t0, t1));
         CHECK_ST(timing_push(c, t0, t1, 1));
         CHECK_ST(arena_release(c, slot, stream));
