@@ -37,7 +37,7 @@
 //                  +z neighbour bricks) may hold F <= 2^-100, i.e. some cell
 //                  whose base voxel lies in that sub-block may have a corner
 //                  F <= 2^-100.  fmask dilated by one sub-block; derived
-//                  after each integration with the distance passes.
+//                  after each integration with the distance transform.
 #pragma once
 #include <stdint.h>
 
@@ -129,7 +129,7 @@ struct LaunchHeader {
     int32_t zchunk;        // bricks per integration item along z
     int32_t nstreams;      // frames in the frame table
     int32_t total_tiles;   // raycast pixel tiles over all streams
-    int32_t total_bricks;  // bricks over all volumes of the table (distance passes)
+    int32_t total_bricks;  // bricks over all volumes of the table (distance transform)
     int32_t first_wave;    // raycast: 1 = start from no hit, 0 = merge with best_t/best_id
     RayParams rp;
     int32_t total_z;       // entries of the integration z table (sum of 8 * bd[2])

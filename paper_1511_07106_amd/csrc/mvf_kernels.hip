@@ -1675,7 +1675,7 @@ int launch_brick_distance(const LaunchHeader* hdr, const DevVolume* vols, const 
 }
 
 // Range-bound footprints of every brick of the table (one thread per brick,
-// a wavefront within one volume as in the distance passes).
+// a wavefront within one volume as in the distance transform).
 __global__ __launch_bounds__(256) void mvf_ray_bounds_collect_kernel(const LaunchHeader* hdr, const DevVolume* vols,
                                                                      const int32_t* brick_base,
                                                                      const DevFrame* frames, RayBounds rb)
