@@ -43,6 +43,17 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def build_variant(defines: Dict[str, int], out_dir: str) -> C.CDLL:
+    """Compile the oracle with preprocessor ``defines`` into ``out_dir`` and
+    load it.  Only for tests that plant an alternative reading (or a mistake)
+    in the oracle to show that a pin rejects it."""
+    tag = "_".join(f"{k}{v}" for k, v in sorted(defines.items()))
+    path = os.path.join(out_dir, f"liboracle_{tag}.so")
+    subprocess.run(["gcc", *CFLAGS, *[f"-D{k}={v}" for k, v in defines.items()], "-o", path, _SRC, "-lm"],
+                   check=True)
+    return C.CDLL(path)
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -128,9 +139,10 @@ def integrate(vol: OVolume, grid: OGrid, depth: np.ndarray, rgb: Optional[np.nda
 
 def raycast(vols: Sequence[OVolume], grid: OGrid, K, T, width: int, height: int,
             step: float = 0.5, t_far: float = 10.0,
-            F32: Optional[Sequence[np.ndarray]] = None) -> Dict[str, np.ndarray]:
+            F32: Optional[Sequence[np.ndarray]] = None, oracle_lib=None) -> Dict[str, np.ndarray]:
     """Raycast one view through all volumes.  ``F32`` optionally gives the
-    binary32 TSDF planes to read (default: each volume's F rounded to f32)."""
+    binary32 TSDF planes to read (default: each volume's F rounded to f32).
+    ``oracle_lib``: a variant build from ``build_variant`` (tests only)."""
     n = len(vols)
     if F32 is not None:
         if isinstance(F32, np.ndarray) or len(F32) != n:
@@ -151,7 +163,7 @@ def raycast(vols: Sequence[OVolume], grid: OGrid, K, T, width: int, height: int,
     out = dict(depth=np.zeros(P), vertex=np.zeros((P, 3)), normal=np.zeros((P, 3)),
                hit=np.zeros(P, np.int32), k=np.zeros(P, np.int32), tstar=np.zeros(P, np.float32),
                cells=np.zeros((P, 9), np.int32), ambiguous=np.zeros(P, np.uint8))
-    r = lib().orc_raycast(C.c_int(n), _p(dims), _p(offs), _p(Fcat), _p(Wcat), _p(base),
+    r = (oracle_lib or lib()).orc_raycast(C.c_int(n), _p(dims), _p(offs), _p(Fcat), _p(Wcat), _p(base),
                           _p(grid.arr4()), C.c_float(step), C.c_float(t_far), _p(_f32(K)),
                           _p(_f32(np.asarray(T).reshape(12))), C.c_int(width), C.c_int(height),
                           _p(out["depth"]), _p(out["vertex"]), _p(out["normal"]), _p(out["hit"]),

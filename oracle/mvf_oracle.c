@@ -34,6 +34,15 @@
 #define ORC_AMBIG_F 1e-5f       /* |F| below this makes a sign test ambiguous */
 #define ORC_AMBIG_DF 1e-3f      /* F_a - F_b below this makes t* ill conditioned */
 
+/* Cell whose trilinear patch gives the raycast normal.  1 (the reading
+ * taken): the cell of the crossing's second sample, evaluated at the
+ * vertex.  0 (the first sample's cell) and 2 (the vertex's own cell, clamped
+ * into the volume) are alternative readings, compiled only by the test that
+ * shows its pin tells the three apart. */
+#ifndef ORC_NORMAL_CELL
+#define ORC_NORMAL_CELL 1
+#endif
+
 static inline int64_t vidx(const int32_t* dims, int x, int y, int z) {
     return ((int64_t)z * dims[1] + y) * dims[0] + x;
 }
@@ -394,14 +403,6 @@ int orc_raycast(int nvol, const int32_t* dims, const int32_t* offs,
             const orc_vol vol = { dims + 3 * best, offs + 3 * best, Fcat + base[best], Wcat + base[best] };
             hit_k[p] = hb.k;
             tstar32[p] = hb.tstar;
-            /* the normal is taken from the cell of the crossing's second sample,
-             * whose 8 voxels are all observed */
-            int cv[3] = { hb.cell_b[0], hb.cell_b[1], hb.cell_b[2] };
-            for (int a = 0; a < 3; ++a) {
-                cells[9 * p + a] = hb.cell_a[a];
-                cells[9 * p + 3 + a] = hb.cell_b[a];
-                cells[9 * p + 6 + a] = cv[a];
-            }
             /* binary64 outputs with the structure fixed */
             double dh64[3], dw64[3];
             pixel_ray64(u, v, K, T64, dh64, dw64);
@@ -409,12 +410,32 @@ int orc_raycast(int nvol, const int32_t* dims, const int32_t* offs,
             const double ts = eval_crossing64(&vol, grid, (double)delta, C64, dw64, hb.k,
                                               hb.cell_a, hb.cell_b, NULL, NULL);
             depth[p] = ts * dh64[2];
-            double f[3], g[3];
+            double lv[3];
             for (int a = 0; a < 3; ++a) {
                 const double x = C64[a] + ts * dw64[a];
                 vertex[3 * p + a] = x;
-                f[a] = (x - grid[a]) / (double)grid[3] - 0.5 - (double)vol.off[a] - (double)cv[a];
+                lv[a] = (x - grid[a]) / (double)grid[3] - 0.5 - (double)vol.off[a];
             }
+            /* the normal is the gradient of the trilinear patch of the cell of
+             * the crossing's second sample, whose 8 voxels are all observed,
+             * evaluated at the vertex (which may lie just outside that cell:
+             * the patch is then extended linearly in each coordinate) */
+            int cv[3];
+            for (int a = 0; a < 3; ++a) {
+#if ORC_NORMAL_CELL == 0
+                cv[a] = hb.cell_a[a];
+#elif ORC_NORMAL_CELL == 2
+                int c = (int)floor(lv[a]);
+                cv[a] = c < 0 ? 0 : (c > vol.dims[a] - 2 ? vol.dims[a] - 2 : c);
+#else
+                cv[a] = hb.cell_b[a];
+#endif
+                cells[9 * p + a] = hb.cell_a[a];
+                cells[9 * p + 3 + a] = hb.cell_b[a];
+                cells[9 * p + 6 + a] = cv[a];
+            }
+            double f[3], g[3];
+            for (int a = 0; a < 3; ++a) f[a] = lv[a] - (double)cv[a];
             sample64(&vol, cv, f, g, NULL);
             const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
             for (int a = 0; a < 3; ++a) normal[3 * p + a] = gn > 0.0 ? g[a] / gn : NAN;

@@ -221,3 +221,113 @@ def test_step_must_be_below_one_voxel():
     with pytest.raises(ValueError):
         O.raycast([vol], grid, np.array([10, 10, 2, 2], np.float32), S.look_at([0, 0, -1], [0, 0, 0]),
                   4, 4, step=1.0)
+
+
+# -- the normal's cell (the Raycasting section takes the normal as the
+# derivative of the TSDF at the zero crossing; the reading: the gradient of
+# the trilinear patch of the cell holding the crossing's second sample,
+# evaluated at the vertex) -------------------------------------------------
+
+_KINK = dict(a=0.011, b=-0.007, s1=-0.05, s2=-0.4, plane=32, z0=31.7)
+
+
+def _kink_field(gx, gy, gz):
+    """Lattice values piecewise linear along z with a kink at the voxel plane
+    gz = plane: slope s1 below it, s2 above, zero of the lower piece at z0
+    (on the volume's axis).  Trilinear interpolation of such values is
+    linear inside every cell, so a cell's gradient is the closed form
+    (a, b, slope of its z interval) in voxel units."""
+    k = _KINK
+    h = np.where(gz <= k["plane"], k["s1"] * (gz - k["plane"]), k["s2"] * (gz - k["plane"]))
+    return k["a"] * (gx - 32) + k["b"] * (gy - 32) + h + (-k["s1"]) * (k["plane"] - k["z0"])
+
+
+def _kink_setup():
+    grid = O.OGrid((-1.0, -1.0, -1.0), 1.0 / 32, 4.0)
+    vol = O.OVolume.empty((64, 64, 64))
+    gz, gy, gx = np.meshgrid(np.arange(64.0), np.arange(64.0), np.arange(64.0), indexing="ij")
+    vol.F[:] = _kink_field(gx, gy, gz)
+    vol.W[:] = 1
+    # camera below the kink looking up through it at a slant, so rays cross
+    # the plane at every phase of the sample lattice
+    T = S.look_at([0.11, -0.07, -0.55], [-0.05, 0.04, 0.3], up=(0, 1, 0))
+    K = np.array([70.0, 70.0, 47.5, 35.5], np.float32)
+    return grid, vol, T, K, 96, 72
+
+
+def _kink_expected(grid, vol, T, K, w, h, step=0.5):
+    """Per pixel, from the geometry alone (binary64): the first sample pair
+    (k - 1, k) with a plus-to-minus change of the field, the z cells of the
+    two samples and of the vertex on the chord between them, and the
+    normal of the second sample's cell.  Pixels whose decisive values lie
+    within rounding of a cell boundary or of zero are marked unsure."""
+    k_ = _KINK
+    s = grid.voxel_size
+    dh, dw = _rays_world(K, w, h, T)
+    C = np.asarray(T)[:, 3]
+    delta = step * s
+    ks = np.arange(1, int(2.0 / delta))
+    x = C[None, None, None, :] + (ks[None, None, :, None] * delta) * dw[:, :, None, :]
+    l = (x - np.asarray(grid.origin)) / s - 0.5
+    inside = np.all((l >= 0) & (l < 63), axis=-1)
+    lz = l[..., 2]
+    cz = np.floor(lz)
+    slope = np.where(cz < k_["plane"], k_["s1"], k_["s2"])
+    # linear inside each cell: value at the cell base plus slope * fraction
+    base = np.where(cz < k_["plane"], k_["s1"] * (cz - k_["plane"]), k_["s2"] * (cz - k_["plane"]))
+    Fv = (k_["a"] * (l[..., 0] - 32) + k_["b"] * (l[..., 1] - 32) + base + slope * (lz - cz)
+          + (-k_["s1"]) * (k_["plane"] - k_["z0"]))
+    pos = inside[..., :-1] & inside[..., 1:] & (Fv[..., :-1] > 0) & (Fv[..., 1:] <= 0)
+    anyx = pos.any(-1)
+    j = np.argmax(pos, axis=-1)  # pair (j, j + 1) of ks
+    take = lambda a, o: np.take_along_axis(a, (j + o)[..., None], -1)[..., 0]
+    Fa, Fb = take(Fv, 0), take(Fv, 1)
+    za, zb = take(lz, 0), take(lz, 1)
+    zv = za + (zb - za) * Fa / (Fa - Fb)
+    nrm = np.stack([np.full(zb.shape, k_["a"]), np.full(zb.shape, k_["b"]),
+                    np.where(np.floor(zb) < k_["plane"], k_["s1"], k_["s2"])], -1)
+    nrm /= np.linalg.norm(nrm, axis=-1, keepdims=True)
+    frac = lambda z: np.abs(z - np.round(z))
+    unsure = (frac(za) < 1e-4) | (frac(zb) < 1e-4) | (frac(zv) < 1e-4) | (np.abs(Fa) < 1e-4) | (np.abs(Fb) < 1e-4)
+    return dict(hit=anyx, cell_a=np.floor(za), cell_b=np.floor(zb), cell_v=np.floor(zv), normal=nrm,
+                unsure=unsure)
+
+
+def _kink_check(rc, ex):
+    """Normal error of each sure hit pixel against the closed form."""
+    hit = rc["hit"] >= 0
+    sure = ex["hit"] & ~ex["unsure"]
+    assert np.array_equal(hit[sure], ex["hit"][sure])
+    return np.abs(rc["normal"] - ex["normal"]).max(-1), sure
+
+
+def test_normal_cell_pinned_by_a_kinked_field():
+    """Where the sample pair straddles the kink, the three candidate cells
+    (first sample's, second sample's, vertex's own) have gradients that
+    differ by a closed-form amount; the oracle's normal must be the second
+    sample's, including where the vertex lies outside that cell (the patch
+    extended linearly)."""
+    grid, vol, T, K, w, h = _kink_setup()
+    rc = O.raycast([vol], grid, K, T, w, h)
+    ex = _kink_expected(grid, vol, T, K, w, h)
+    err, sure = _kink_check(rc, ex)
+    straddle = sure & (ex["cell_a"] != ex["cell_b"])
+    outside = straddle & (ex["cell_v"] != ex["cell_b"])
+    assert straddle.sum() > 300 and outside.sum() > 100, (straddle.sum(), outside.sum())
+    # the candidates differ by far more than the tolerance
+    n1 = np.array([_KINK["a"], _KINK["b"], _KINK["s1"]]); n1 /= np.linalg.norm(n1)
+    n2 = np.array([_KINK["a"], _KINK["b"], _KINK["s2"]]); n2 /= np.linalg.norm(n2)
+    assert np.abs(n1 - n2).max() > 0.1
+    assert err[sure].max() < 1e-5, err[sure].max()
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_kink_pin_rejects_other_cells(tmp_path, variant):
+    """The same pin fails for an oracle built with the first sample's cell
+    (0) or the vertex's own cell (2) for the normal."""
+    lib = O.build_variant({"ORC_NORMAL_CELL": variant}, str(tmp_path))
+    grid, vol, T, K, w, h = _kink_setup()
+    rc = O.raycast([vol], grid, K, T, w, h, oracle_lib=lib)
+    ex = _kink_expected(grid, vol, T, K, w, h)
+    err, sure = _kink_check(rc, ex)
+    assert (err[sure] > 0.1).sum() > 100
