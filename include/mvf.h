@@ -344,8 +344,28 @@ mvf_status mvf_diffray_backward(mvf_ctx* ctx, const mvf_dense_tsdf* v, const flo
                                 const mvf_intrinsics* K, int32_t width, int32_t height,
                                 const float* grad_depth, const int32_t* record,
                                 float* grad_F, double* grad_xi, void* stream);
+/* mvf_diffray_backward without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results;
+ * the per-block pose partials go to a static device array of the library
+ * (768 KiB per GPU, held until the process ends) instead of a buffer the
+ * context allocates.  Limit: ceil(width / 16) * ceil(height / 16) <= 16384
+ * (e.g. 2048 x 2048); larger images return MVF_ERR_INVALID_ARG.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (other
+ * streams, other contexts or threads) race and must be serialised by the
+ * caller. */
+mvf_status mvf_diffray_backward_noalloc(mvf_ctx* ctx, const mvf_dense_tsdf* v, const float T_wc[12],
+                                        const mvf_intrinsics* K, int32_t width, int32_t height,
+                                        const float* grad_depth, const int32_t* record,
+                                        float* grad_F, double* grad_xi, void* stream);
 /* Host-only: T_out = T Exp(xi) for xi = (rho, omega) (binary64 3x4). */
 mvf_status mvf_pose_retract(const double T[12], const double xi[6], double T_out[12]);
+/* Host-only: the right Jacobian J (6x6 row-major, binary64) of Exp at xi:
+ * T Exp(xi + d) = T Exp(xi) Exp(J d) to first order in d.  A gradient g
+ * with respect to the right perturbation at T Exp(xi) (what
+ * mvf_diffray_backward returns) is a gradient with respect to xi itself
+ * after g <- J^T g. */
+mvf_status mvf_pose_right_jacobian(const double xi[6], double J[36]);
 
 #ifdef __cplusplus
 }

@@ -128,7 +128,10 @@ SIGNATURES = {
     "mvf_diffray_forward": [P, C.POINTER(mvf_dense_tsdf), PF, C.POINTER(mvf_intrinsics), I32, I32, P, P, P],
     "mvf_diffray_backward": [P, C.POINTER(mvf_dense_tsdf), PF, C.POINTER(mvf_intrinsics), I32, I32, P, P, P,
                              P, P],
+    "mvf_diffray_backward_noalloc": [P, C.POINTER(mvf_dense_tsdf), PF, C.POINTER(mvf_intrinsics), I32, I32, P, P,
+                                     P, P, P],
     "mvf_pose_retract": [PD, PD, PD],
+    "mvf_pose_right_jacobian": [PD, PD],
 }
 STRING_FUNCS = {"mvf_status_string": [I32], "mvf_last_error": [], "mvf_version": []}
 

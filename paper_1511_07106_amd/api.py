@@ -315,17 +315,21 @@ class Context:
         return depth, record
 
     def diffray_backward(self, F, W, origin, voxel_size, T, K, grad_depth, record, grad_F=None,
-                         offset=(0, 0, 0), stream=None):
+                         offset=(0, 0, 0), stream=None, grad_xi=None, noalloc=False):
+        """dL/dxi (6 doubles on the device; written into ``grad_xi`` when
+        given) and dL/dF accumulated into ``grad_F``.  ``noalloc`` calls
+        mvf_diffray_backward_noalloc, which allocates no device memory."""
         torch = _torch()
         h, w = record.shape
-        gxi = torch.zeros(6, dtype=torch.float64, device=F.device)
+        gxi = torch.zeros(6, dtype=torch.float64, device=F.device) if grad_xi is None else grad_xi
         v = self._dense(F, W, origin, voxel_size, offset)
         gd = grad_depth.contiguous()
-        L.check(self.lib.mvf_diffray_backward(
+        name = "mvf_diffray_backward_noalloc" if noalloc else "mvf_diffray_backward"
+        L.check(getattr(self.lib, name)(
             self.h, C.byref(v), _pose(T), C.byref(_K(K)), int(w), int(h),
             _dev_ptr(gd, torch.float32, (h, w), "grad_depth"), _dev_ptr(record, torch.int32, (h, w), "record"),
             _dev_ptr(grad_F, torch.float32, name="grad_F") if grad_F is not None else None,
-            C.c_void_p(gxi.data_ptr()), _stream(stream)), "mvf_diffray_backward")
+            _dev_ptr(gxi, torch.float64, (6,), "grad_xi"), _stream(stream)), name)
         return gxi
 
 
@@ -358,3 +362,13 @@ def pose_retract(T, xi) -> np.ndarray:
     L.check(lib.mvf_pose_retract(Ta.ctypes.data_as(L.PD), xa.ctypes.data_as(L.PD), out.ctypes.data_as(L.PD)),
             "mvf_pose_retract")
     return out.reshape(3, 4)
+
+
+def pose_right_jacobian(xi) -> np.ndarray:
+    """J (6x6) with T Exp(xi + d) = T Exp(xi) Exp(J d) to first order."""
+    lib = L.load()
+    xa = np.ascontiguousarray(np.asarray(xi, np.float64).reshape(6))
+    out = np.zeros(36)
+    L.check(lib.mvf_pose_right_jacobian(xa.ctypes.data_as(L.PD), out.ctypes.data_as(L.PD)),
+            "mvf_pose_right_jacobian")
+    return out.reshape(6, 6)

@@ -5,7 +5,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .api import Context, pose_retract
+from .api import Context, pose_retract, pose_right_jacobian
 
 
 class DiffRaycast(torch.autograd.Function):
@@ -14,8 +14,9 @@ class DiffRaycast(torch.autograd.Function):
     F: (nz, ny, nx) float32 TSDF on the device (truncation units), W: weights
     of the same shape (uint16/int16; 0 = unobserved), xi: 6-vector (rho,
     omega) of the right pose perturbation T = T0 Exp(xi).  The backward gives
-    dL/dF and dL/dxi, the latter taken as the right perturbation at T (which
-    is d/dxi at xi = 0).  The crossing found by the forward is held fixed.
+    dL/dF and dL/dxi: the kernel's gradient g for a right perturbation at T
+    is mapped through the right Jacobian of Exp at xi (dL/dxi = J_r(xi)^T g,
+    equal to g at xi = 0).  The crossing found by the forward is held fixed.
     """
 
     @staticmethod
@@ -25,6 +26,7 @@ class DiffRaycast(torch.autograd.Function):
         ctx.save_for_backward(F, W, record)
         ctx.mvf = mvf
         ctx.params = (origin, voxel_size, T, K)
+        ctx.jr = pose_right_jacobian(xi.detach().double().cpu().numpy())
         ctx.xi_dtype = xi.dtype
         ctx.xi_device = xi.device
         ctx.mark_non_differentiable(record)
@@ -37,7 +39,11 @@ class DiffRaycast(torch.autograd.Function):
         grad_F = torch.zeros_like(F) if ctx.needs_input_grad[0] else None
         gxi = ctx.mvf.diffray_backward(F.detach(), W, origin, voxel_size, T, K,
                                        grad_depth.float().contiguous(), record, grad_F)
-        gxi = gxi.to(device=ctx.xi_device, dtype=ctx.xi_dtype) if ctx.needs_input_grad[1] else None
+        if ctx.needs_input_grad[1]:
+            g = gxi.cpu().numpy() @ ctx.jr  # J_r^T g
+            gxi = torch.from_numpy(g).to(device=ctx.xi_device, dtype=ctx.xi_dtype)
+        else:
+            gxi = None
         return grad_F, gxi, None, None, None, None, None, None, None, None
 
 

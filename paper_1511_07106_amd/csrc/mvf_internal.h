@@ -295,5 +295,14 @@ int launch_diffray_backward(DiffVolume v, const float* T, float fx, float fy, fl
                             const int32_t* record, float* grad_F, double* partials,
                             int n_partials, double* grad_xi, void* stream);
 int diffray_partials_needed(int width, int height);
+// Allocation-free backward: a static device array holds the pose partials of
+// at most kDiffScratchBlocks 16x16-pixel blocks (768 KiB per GPU).
+constexpr int kDiffScratchBlocks = 16384;
+constexpr int kMaxDevices = 64;
+// Take the current device's address of the static array (once per device;
+// the device must be current).  0 on success, else a hipError_t.
+int diffray_scratch_init(int device);
+// That address, or null before diffray_scratch_init(device) succeeded.
+double* diffray_scratch(int device);
 
 }  // namespace mvf

@@ -8,6 +8,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "mvf_internal.h"
 #include "mvf_masks.h"
 
@@ -2310,6 +2312,36 @@ __global__ void mvf_reduce_partials_kernel(const double* partials, int nblocks, 
 int diffray_partials_needed(int width, int height)
 {
     return ((width + 15) / 16) * ((height + 15) / 16);
+}
+
+// Static scratch of the allocation-free backward: the binary64 pose partials
+// of up to kDiffScratchBlocks 16x16-pixel blocks.  Every block of a launch
+// writes its own 6 entries before the reduction reads them, so nothing needs
+// clearing between calls.  Each GPU holds its own copy, at its own address.
+static __device__ __align__(256) double scratch[6 * kDiffScratchBlocks];
+
+// Device addresses of `scratch`, one per device, taken once with that device
+// current.  In host code the array's name is only a stand-in for the symbol.
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+int diffray_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return 0;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+    return 0;
+}
+
+double* diffray_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 int launch_diffray_backward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy, int width,

@@ -1315,6 +1315,10 @@ mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg)
         if ((e = hipEventCreateWithFlags(&c->arena.ev[i], hipEventDisableTiming | hipEventDisableSystemFence)) !=
             hipSuccess)
             return fail(set_error(MVF_ERR_HIP, "context setup: %s", hipGetErrorString(e)));
+    // device address of the allocation-free backward's static scratch (once
+    // per device, with the device current)
+    if (int se = diffray_scratch_init(c0.device))
+        return fail(set_error(MVF_ERR_HIP, "static scratch address: %s", hipGetErrorString((hipError_t)se)));
     if ((e = hipDeviceSynchronize()) != hipSuccess)
         return fail(set_error(MVF_ERR_HIP, "context setup: %s", hipGetErrorString(e)));
     *out = c;
@@ -2306,16 +2310,34 @@ mvf_status mvf_diffray_forward(mvf_ctx* c, const mvf_dense_tsdf* v, const float 
     return mark_tail(c, s);
 }
 
+// Argument checks shared by the two backward entry points.
+static mvf_status diffray_backward_args(mvf_ctx* c, const mvf_dense_tsdf* v, const float T_wc[12],
+                                        const mvf_intrinsics* K, int32_t width, int32_t height,
+                                        const float* grad_depth, const int32_t* record, const double* grad_xi,
+                                        DiffVolume* dv)
+{
+    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
+    CHECK_ST(diff_volume(c, v, dv));
+    if (!T_wc || !finite_pose(T_wc) || !valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "bad pose or intrinsics");
+    if (width <= 0 || height <= 0 || width > 16384 || height > 16384 || !grad_depth || !record || !grad_xi)
+        return set_error(MVF_ERR_INVALID_ARG, "bad gradient buffers");
+    return MVF_OK;
+}
+
+static RayParams diff_ray_params(mvf_ctx* c, const mvf_dense_tsdf* v)
+{
+    RayParams rp;
+    rp.delta = c->cfg.ray_step * v->voxel_size;
+    rp.kmax = (int32_t)std::floor(c->cfg.t_far / rp.delta);
+    return rp;
+}
+
 mvf_status mvf_diffray_backward(mvf_ctx* c, const mvf_dense_tsdf* v, const float T_wc[12], const mvf_intrinsics* K,
                                 int32_t width, int32_t height, const float* grad_depth, const int32_t* record,
                                 float* grad_F, double* grad_xi, void* stream)
 {
-    if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
     DiffVolume dv;
-    CHECK_ST(diff_volume(c, v, &dv));
-    if (!T_wc || !finite_pose(T_wc) || !valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "bad pose or intrinsics");
-    if (width <= 0 || height <= 0 || width > 16384 || height > 16384 || !grad_depth || !record || !grad_xi)
-        return set_error(MVF_ERR_INVALID_ARG, "bad gradient buffers");
+    CHECK_ST(diffray_backward_args(c, v, T_wc, K, width, height, grad_depth, record, grad_xi, &dv));
     CHECK_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     CHECK_ST(order_after_previous(c, s));
@@ -2328,11 +2350,30 @@ mvf_status mvf_diffray_backward(mvf_ctx* c, const mvf_dense_tsdf* v, const float
         CHECK_HIP(hipMalloc((void**)&c->diff_partials, sizeof(double) * 6 * need));
         c->diff_partials_n = need;
     }
-    RayParams rp;
-    rp.delta = c->cfg.ray_step * v->voxel_size;
-    rp.kmax = (int32_t)std::floor(c->cfg.t_far / rp.delta);
-    CHECK_LAUNCH(launch_diffray_backward(dv, T_wc, K->fx, K->fy, K->cx, K->cy, width, height, rp, grad_depth, record,
-                                         grad_F, c->diff_partials, c->diff_partials_n, grad_xi, s));
+    CHECK_LAUNCH(launch_diffray_backward(dv, T_wc, K->fx, K->fy, K->cx, K->cy, width, height, diff_ray_params(c, v),
+                                         grad_depth, record, grad_F, c->diff_partials, c->diff_partials_n, grad_xi, s));
+    return mark_tail(c, s);
+}
+
+mvf_status mvf_diffray_backward_noalloc(mvf_ctx* c, const mvf_dense_tsdf* v, const float T_wc[12],
+                                        const mvf_intrinsics* K, int32_t width, int32_t height,
+                                        const float* grad_depth, const int32_t* record, float* grad_F,
+                                        double* grad_xi, void* stream)
+{
+    DiffVolume dv;
+    CHECK_ST(diffray_backward_args(c, v, T_wc, K, width, height, grad_depth, record, grad_xi, &dv));
+    const int need = diffray_partials_needed(width, height);
+    if (need > kDiffScratchBlocks)
+        return set_error(MVF_ERR_INVALID_ARG,
+                         "a %dx%d image needs %d partial blocks of 16x16 pixels; the static scratch holds %d",
+                         width, height, need, kDiffScratchBlocks);
+    CHECK_HIP(hipSetDevice(c->device));
+    double* partials = diffray_scratch(c->device);
+    if (!partials) return set_error(MVF_ERR_STATE, "static scratch of device %d not set up", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    CHECK_LAUNCH(launch_diffray_backward(dv, T_wc, K->fx, K->fy, K->cx, K->cy, width, height, diff_ray_params(c, v),
+                                         grad_depth, record, grad_F, partials, kDiffScratchBlocks, grad_xi, s));
     return mark_tail(c, s);
 }
 
@@ -2373,6 +2414,74 @@ mvf_status mvf_pose_retract(const double T[12], const double xi[6], double T_out
         out[4 * i + 3] = T[4 * i] * t[0] + T[4 * i + 1] * t[1] + T[4 * i + 2] * t[2] + T[4 * i + 3];
     }
     memcpy(T_out, out, sizeof(out));
+    return MVF_OK;
+}
+
+// Right Jacobian of Exp on SE(3) with xi = (rho, omega): Exp(xi + d) =
+// Exp(xi) Exp(J d) to first order in d.  J_r(xi) is the left Jacobian at
+// -xi, [[J(w), Q(rho, w)], [0, J(w)]] with J the SO(3) left Jacobian
+// (the V of Exp) and Q the closed-form coupling block (Barfoot, State
+// Estimation for Robotics, SE(3) kinematics); series below 1e-2 rad.
+mvf_status mvf_pose_right_jacobian(const double xi[6], double J_out[36])
+{
+    if (!xi || !J_out) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    double r[3], w[3];
+    for (int i = 0; i < 3; ++i) {
+        r[i] = -xi[i];
+        w[i] = -xi[3 + i];
+    }
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const double th = std::sqrt(th2);
+    double b1, a1, a2, a3;
+    if (th < 1e-2) {
+        const double t4 = th2 * th2;
+        b1 = 0.5 - th2 / 24.0 + t4 / 720.0;
+        a1 = 1.0 / 6.0 - th2 / 120.0 + t4 / 5040.0;
+        a2 = 1.0 / 24.0 - th2 / 720.0 + t4 / 40320.0;
+        a3 = 1.0 / 120.0 - th2 / 2520.0;
+    } else {
+        const double sn = std::sin(th), cs = std::cos(th);
+        b1 = (1.0 - cs) / th2;
+        a1 = (th - sn) / (th2 * th);
+        a2 = (th2 + 2.0 * cs - 2.0) / (2.0 * th2 * th2);
+        a3 = (2.0 * th - 3.0 * sn + th * cs) / (2.0 * th2 * th2 * th);
+    }
+    typedef double M3[9];
+    auto hat = [](const double v[3], double* m) {
+        const double t[9] = {0, -v[2], v[1], v[2], 0, -v[0], -v[1], v[0], 0};
+        memcpy(m, t, sizeof(t));
+    };
+    auto mul = [](const double* a, const double* b, double* out) {
+        double t[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) t[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+        memcpy(out, t, sizeof(t));
+    };
+    M3 W, P, WW, WP, PW, WPW, WWP, PWW, WPWW, WWPW, Jw, Q;
+    hat(w, W);
+    hat(r, P);
+    mul(W, W, WW);
+    mul(W, P, WP);
+    mul(P, W, PW);
+    mul(WP, W, WPW);
+    mul(WW, P, WWP);
+    mul(P, WW, PWW);
+    mul(WPW, W, WPWW);
+    mul(WW, PW, WWPW);
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i % 4 == 0) ? 1.0 : 0.0;
+        Jw[i] = I + b1 * W[i] + a1 * WW[i];
+        Q[i] = 0.5 * P[i] + a1 * (WP[i] + PW[i] + WPW[i]) + a2 * (WWP[i] + PWW[i] - 3.0 * WPW[i]) +
+               a3 * (WPWW[i] + WWPW[i]);
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double v = 0.0;
+            if (i < 3 && j < 3) v = Jw[3 * i + j];
+            else if (i < 3) v = Q[3 * i + (j - 3)];
+            else if (j >= 3) v = Jw[3 * (i - 3) + (j - 3)];
+            J_out[6 * i + j] = v;
+        }
     return MVF_OK;
 }
 

@@ -128,3 +128,28 @@ def test_pose_retract_matches_oracle_exponential():
         T = O.compose(np.eye(3, 4), O.se3_exp(rng.normal(size=6)))
         xi = rng.normal(size=6) * rng.choice([1e-12, 1e-3, 0.5])
         np.testing.assert_allclose(mvf.pose_retract(T, xi), O.compose(T, O.se3_exp(xi)), atol=1e-12)
+
+
+@pytest.mark.parametrize("scale", [1e-6, 3e-3, 0.4, 1.2])
+def test_pose_right_jacobian_first_order(scale):
+    """T Exp(xi + d) = T Exp(xi) Exp(J d) + O(|d|^2): the residual of the
+    first-order step shrinks with |d|^2, while the identity (what the right
+    perturbation gradient equals only at xi = 0) leaves an O(|d| |xi|) one."""
+    from paper_1511_07106_amd.api import pose_retract, pose_right_jacobian
+    rng = np.random.default_rng(int(scale * 1e6) % 1000)
+    I34 = np.hstack([np.eye(3), np.zeros((3, 1))])
+    for _ in range(5):
+        xi = rng.normal(size=6) * scale
+        xi[:3] += rng.normal(size=3) * 0.5  # translation part of ordinary size
+        J = pose_right_jacobian(xi)
+        base = pose_retract(I34, xi)
+        res = {}
+        for h in (1e-4, 1e-5):
+            d = rng.normal(size=6) * h
+            lhs = pose_retract(I34, xi + d)
+            rhs = pose_retract(base, J @ d)
+            res[h] = np.abs(lhs - rhs).max()
+            wrong = np.abs(lhs - pose_retract(base, d)).max()
+            if scale >= 3e-3 and h == 1e-4:
+                assert wrong > 50 * res[h], (wrong, res[h])
+        assert res[1e-4] < 1e-7 and res[1e-5] < 1e-9, res

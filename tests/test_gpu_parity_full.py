@@ -1,0 +1,354 @@
+"""Oracle parity at the shapes the benchmark times (Comparison to
+KinectFusion; Memory Passing):
+
+- the captured step (mvf_step, one graph replay per frame) on one 512^3
+  volume over the 3 m large room, 640x480, under several launch schedules
+  and under the schedule the autotuner picks;
+- the 8 x 257^3 tiling at offsets {0, 255}^3 through the plain calls and
+  through the step;
+- runs under a device budget of one and of three volumes;
+- the differentiable raycast on a 512^3 volume at 640x480;
+- the exactly representable boundary cases of the integration contract.
+
+Volumes: W and colour bit-exact, F within 1e-5 truncation units.  Raycast
+maps are compared with the oracle raycast of the device's own TSDF (same
+binary32 values, so validity and hit volume must agree exactly; depth
+within 1e-4 m, vertex 2e-4 m, normal 2e-3), and, end to end, with the oracle
+raycast of the oracle's TSDF off the pixels the oracle flags ambiguous
+(the fraction is printed)."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import scenes as S
+from tests.util import check_raycast, dev, log, t
+
+pytestmark = pytest.mark.gpu
+
+FRAMES = [0, 1, 2, 3, 4, 150]
+N, EXTENT = 512, 3.0
+W_IMG, H_IMG = 640, 480
+
+
+@pytest.fixture(scope="module")
+def mvf():
+    import paper_1511_07106_amd as mvf
+    return mvf
+
+
+@pytest.fixture(scope="module")
+def large():
+    """Large-room frames and the oracle's 512^3 volume after the first five
+    frames (a snapshot) and after all six."""
+    seq = S.large_room_sequence(seed=2)
+    frames = seq.frames(FRAMES, threads=16)
+    og = O.OGrid((-EXTENT / 2,) * 3, EXTENT / N, 4.0, 128)
+    ov = O.OVolume.empty((N, N, N))
+    K = seq.K.as_array()
+    snap = None
+    for j, (i, (d, c)) in enumerate(zip(FRAMES, frames)):
+        O.integrate(ov, og, d, c, K, seq.poses[i])
+        if j == 4:
+            snap = O.OVolume(ov.dims, ov.offset, ov.F.copy(), ov.W.copy(), ov.Cc.copy())
+    return seq, frames, og, snap, ov
+
+
+def _outs():
+    import torch
+    return {"depth": torch.empty((H_IMG, W_IMG), device=dev()),
+            "vertex": torch.empty((H_IMG, W_IMG, 3), device=dev()),
+            "normal": torch.empty((H_IMG, W_IMG, 3), device=dev()),
+            "hit": torch.empty((H_IMG, W_IMG), dtype=torch.int32, device=dev())}
+
+
+def _np(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _cmp_volume(F, W, Cc, ov, sl=np.s_[:, :, :]):
+    """Device planes vs the oracle volume (optionally a slice of it)."""
+    np.testing.assert_array_equal(W, ov.W[sl])
+    np.testing.assert_array_equal(Cc, ov.Cc[sl])
+    err = float(np.abs(F.astype(np.float64) - ov.F[sl]).max())
+    assert err <= 1e-5, f"max |dF| = {err}"
+    return err
+
+
+def _end_to_end(g, ovs, og, K, T, ids):
+    """Device maps vs the oracle raycast of the oracle's own TSDF: validity
+    and hit volume exact off ambiguous pixels, depth within 1e-4 m.
+    Returns the ambiguous fraction."""
+    rc = O.raycast(ovs, og, K, T, W_IMG, H_IMG)
+    amb = rc["ambiguous"].astype(bool)
+    hit_g, hit_o = g["hit"] >= 0, rc["hit"] >= 0
+    bad = (hit_g != hit_o) & ~amb
+    assert not bad.any(), f"validity differs off ambiguous pixels on {int(bad.sum())} pixels"
+    mapped = np.where(hit_o, np.asarray(ids)[np.maximum(rc["hit"], 0)], -1)
+    assert np.array_equal(g["hit"][~amb], mapped[~amb])
+    both = hit_g & hit_o & ~amb
+    dd = np.abs(g["depth"].astype(np.float64) - rc["depth"])[both]
+    assert dd.max() <= 1e-4, dd.max()
+    return float(amb.mean())
+
+
+SCHEDULES = [(4, 0, 4), (8, 0, 4), (8, 1, 2), (2, 0, 8), "autotuned"]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: s if isinstance(s, str) else "z%dp%dl%d" % s)
+def test_step_512_large_room(mvf, large, sched):
+    seq, frames, og, snap, ov = large
+    K = seq.K.as_array()
+    dframes = [(t(d), t(c)) for d, c in frames]
+    cache = None
+    if sched == "autotuned":
+        # tune on a separate context over the same frames (cycled), then run
+        # the parity context from the cache the tuner wrote
+        cache = os.path.join(tempfile.mkdtemp(), "tune.jsonl")
+        log("step 512^3 large room: autotuning on a separate context")
+        with mvf.Context() as ctx:
+            gid = ctx.grid(og.origin, og.voxel_size, 4.0, 128)
+            ctx.volume(gid, (0, 0, 0), (N, N, N))
+            o = _outs()
+            ctx.autotune("tune", cache)
+            for r in range(130):
+                j = r % len(FRAMES)
+                ctx.step([(0, *dframes[j], seq.poses[FRAMES[j]], K)], [o])
+            ctx.synchronize()
+            tuned = ctx.schedule()
+    log(f"step 512^3 large room, schedule {sched}")
+    with mvf.Context() as ctx:
+        gid = ctx.grid(og.origin, og.voxel_size, 4.0, 128)
+        vid = ctx.volume(gid, (0, 0, 0), (N, N, N))
+        if cache:
+            ctx.autotune("cached", cache)
+        else:
+            ctx.set_schedule(*sched)
+        for j, i in enumerate(FRAMES):
+            out = _outs()
+            ctx.step([(0, *dframes[j], seq.poses[i], K)], [out])
+            if j in (4, 5):
+                g = _np(out)
+                F, W, Cc = ctx.read_volume(vid)
+                ref = snap if j == 4 else ov
+                err = _cmp_volume(F, W, Cc, ref)
+                # the same TSDF bits on both sides: validity exact everywhere
+                dev_vol = O.OVolume(ref.dims, ref.offset, ref.F, W, Cc)
+                rc = O.raycast([dev_vol], og, K, seq.poses[i], W_IMG, H_IMG, F32=[F])
+                n = check_raycast(g, rc, [vid])
+                assert n > 100000
+                amb = _end_to_end(g, [ref], og, K, seq.poses[i], [vid])
+                print(f"[parity] step 512^3 sched {sched} frame {i}: max|dF| {err:.2e}, hits {n}, "
+                      f"ambiguous fraction {amb:.2e}", flush=True)
+                assert amb < 1e-3
+        if cache:
+            assert ctx.schedule() == tuned
+
+
+@pytest.mark.parametrize("mode", ["plain", "step"])
+def test_tiled_8x257_large_room(mvf, large, mode):
+    """Eight 257^3 tiles at offsets {0, 255}^3 hold exactly the oracle's
+    voxels (the oracle computes each voxel from its global index alone, and
+    its tiled-equals-single identity is pinned on the CPU), and their shared
+    raycast equals the oracle's multi-volume raycast."""
+    seq, frames, og, snap, ov = large
+    K = seq.K.as_array()
+    h = N // 2
+    offs = [(ox, oy, oz) for oz in (0, h - 1) for oy in (0, h - 1) for ox in (0, h - 1)]
+    log(f"tiled 8 x 257^3 large room via {mode}")
+    with mvf.Context() as ctx:
+        gid = ctx.grid(og.origin, og.voxel_size, 4.0, 128)
+        ids = [ctx.volume(gid, o, (h + 1,) * 3) for o in offs]
+        out = _outs()
+        for j, i in enumerate(FRAMES):
+            d, c = t(frames[j][0]), t(frames[j][1])
+            if mode == "step":
+                ctx.step([(0, d, c, seq.poses[i], K)], [out])
+            else:
+                ctx.integrate(d, c, seq.poses[i], K)
+                ctx.raycast(seq.poses[i], K, W_IMG, H_IMG, out=out)
+        g = _np(out)
+        tiles, F32s = [], []
+        for vid, (ox, oy, oz) in zip(ids, offs):
+            F, W, Cc = ctx.read_volume(vid)
+            sl = np.s_[oz:oz + h + 1, oy:oy + h + 1, ox:ox + h + 1]
+            _cmp_volume(F, W, Cc, ov, sl)
+            tiles.append(O.OVolume((h + 1,) * 3, (ox, oy, oz), ov.F[sl], W, Cc))
+            F32s.append(F)
+        T = seq.poses[FRAMES[-1]]
+        rc = O.raycast(tiles, og, K, T, W_IMG, H_IMG, F32=F32s)
+        n = check_raycast(g, rc, ids)
+        assert n > 100000
+        # and the depth map equals the single volume's oracle raycast
+        rc1 = O.raycast([ov], og, K, T, W_IMG, H_IMG)
+        amb = rc1["ambiguous"].astype(bool)
+        np.testing.assert_array_equal(g["hit"][~amb] >= 0, rc1["hit"][~amb] >= 0)
+        print(f"[parity] tiled 8 x 257^3 via {mode}: hits {n}, ambiguous fraction {amb.mean():.2e}", flush=True)
+
+
+@pytest.mark.parametrize("n,budget_volumes", [(64, 1), (64, 3), (416, 1)])
+def test_budget_runs_vs_oracle(mvf, n, budget_volumes):
+    """Eight (n/2 + 1)^3 subvolumes fused and raycast with room for only
+    `budget_volumes` of them on the device (waves and swaps, the paper's
+    memory passing) against the oracle's eight volumes."""
+    seq = S.small_room_sequence(seed=1)
+    K = seq.K.as_array()
+    og = O.OGrid((-1.0, -1.0, -1.0), 2.0 / n, 4.0, 128)
+    half = n // 2
+    offs = [(ox, oy, oz) for oz in (0, half - 1) for oy in (0, half - 1) for ox in (0, half - 1)]
+    ovs = [O.OVolume.empty((half + 1,) * 3, o) for o in offs]
+    log(f"budget run vs oracle, n {n}, room for {budget_volumes} of 8 volumes")
+    with mvf.Context() as ctx:
+        gid = ctx.grid(og.origin, og.voxel_size, 4.0, 128)
+        ids = [ctx.volume(gid, o, (half + 1,) * 3) for o in offs]
+        ctx.set_budget(budget_volumes * ctx.query(ids[0])[1])
+        for i in range(10):
+            d, c = seq.frame(i)
+            for v in ovs:
+                O.integrate(v, og, d, c, K, seq.poses[i])
+            ctx.integrate(t(d), t(c), seq.poses[i], K)
+            if i in (3, 9):
+                g = _np(ctx.raycast(seq.poses[i], K, 320, 240))
+                devs = [ctx.read_volume(v) for v in ids]
+                for (F, W, Cc), v in zip(devs, ovs):
+                    _cmp_volume(F, W, Cc, v)
+                dvs = [O.OVolume(v.dims, v.offset, v.F, W, Cc) for (F, W, Cc), v in zip(devs, ovs)]
+                rc = O.raycast(dvs, og, K, seq.poses[i], 320, 240, F32=[x[0] for x in devs])
+                assert check_raycast(g, rc, ids) > 10000
+        st = ctx.stats()
+        assert st["swaps_out"] > 0 and st["swaps_in"] > 0
+
+
+def test_diffray_512_vga(mvf):
+    """The differentiable raycast at 512^3 over 2 m and 640x480 (the small
+    room fused from 60 noisy frames on the circle): forward record exact and
+    depth within 1e-4 m; backward pose and voxel gradients against the
+    binary64 oracle gradient, on two perturbed poses."""
+    import torch
+    seq = S.small_room_sequence(seed=1, n_frames=60, K=S.K_VGA)
+    K = seq.K.as_array()
+    n = 512
+    og = O.OGrid((-1.0, -1.0, -1.0), 2.0 / n, 4.0, 128)
+    log("diffray 512^3 640x480: fusing 60 frames on the device")
+    with mvf.Context() as ctx:
+        gid = ctx.grid(og.origin, og.voxel_size, 4.0, 128)
+        vid = ctx.volume(gid, (0, 0, 0), (n, n, n))
+        for i, (d, c) in enumerate(seq.frames(range(60), threads=16)):
+            ctx.integrate(t(d), t(c), seq.poses[i], K)
+        F_np, W_np, _ = ctx.read_volume(vid)
+    ov = O.OVolume((n, n, n), (0, 0, 0), F_np.astype(np.float64), W_np, np.zeros(W_np.shape + (4,), np.uint8))
+    F = t(F_np)
+    W = torch.from_numpy(W_np.view(np.int16).copy()).to(dev())
+    rng = np.random.default_rng(55)
+    with mvf.Context() as ctx:
+        for p in (7, 33):
+            T = S.perturb_pose(seq.poses[p], rng, 0.02, 2.0)
+            T32 = np.asarray(T, np.float32).astype(np.float64)
+            log(f"diffray 512^3 640x480 pose {p}")
+            depth, record = ctx.diffray_forward(F, W, og.origin, og.voxel_size, T32, K, W_IMG, H_IMG)
+            rc = O.raycast([ov], og, K, T32, W_IMG, H_IMG, F32=[F_np])
+            rec = record.cpu().numpy()
+            np.testing.assert_array_equal(rec, rc["k"])
+            hit = rec >= 0
+            assert hit.mean() > 0.3
+            dd = np.abs(depth.cpu().numpy().astype(np.float64) - rc["depth"])[hit]
+            assert dd.max() <= 1e-4, dd.max()
+            gd = rng.normal(size=(H_IMG, W_IMG)).astype(np.float32) * hit
+            grad_F = torch.zeros_like(F)
+            gxi = ctx.diffray_backward(F, W, og.origin, og.voxel_size, T32, K, t(gd), record, grad_F)
+            g_ref, gF_ref = O.depth_grad(ov, og, K, T32, W_IMG, H_IMG, O.structure(rc), gd.astype(np.float64),
+                                         F32=F_np)
+            g = gxi.cpu().numpy()
+            assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) <= 1e-3, (g, g_ref)
+            gF = grad_F.cpu().numpy().astype(np.float64)
+            assert np.abs(gF - gF_ref).max() <= 1e-3 * np.abs(gF_ref).max()
+            del grad_F, gF, gF_ref
+
+
+# -- exactly representable boundary cases (the oracle pins them on the CPU
+# with closed forms; here the device must reproduce them bit for bit) ------
+
+S64 = 1.0 / 64.0
+
+
+def _axis_case(mvf, depths, rgbs=None, w_max=128, nz=64, z0=0):
+    """Camera looking down world +z through the centre of voxel column
+    (40, -20); every quantity exactly representable.  Returns the device
+    and oracle (8, 8, nz) volumes after the given frames."""
+    tz = -0.2578125
+    og = O.OGrid((0.0, 0.0, 0.0), S64, 4.0, w_max)
+    T = np.zeros((3, 4))
+    T[:, :3] = np.eye(3)
+    T[:, 3] = [S64 * 40.5, S64 * -19.5, tz]
+    K = np.array([100.0, 100.0, 16.0, 12.0], np.float32)
+    ov = O.OVolume.empty((8, 8, nz), (36, -24, z0))
+    with mvf.Context() as ctx:
+        gid = ctx.grid(og.origin, og.voxel_size, 4.0, w_max)
+        vid = ctx.volume(gid, ov.offset, ov.dims)
+        for j, Z in enumerate(depths):
+            d = np.full((24, 32), Z, np.float32)
+            c = None if rgbs is None else np.tile(np.asarray(rgbs[j], np.uint8), (24, 32, 1))
+            O.integrate(ov, og, d, c, K, T)
+            ctx.integrate(t(d), None if c is None else t(c), T, K)
+        F, W, Cc = ctx.read_volume(vid)
+    return F, W, Cc, ov, og
+
+
+def _axis_sdf(Z0, nz=64, z0=0):
+    gz = z0 + np.arange(nz)
+    return Z0 - (S64 * (gz + 0.5) + 0.2578125)
+
+
+def test_boundary_truncation_edge_bit_exact(mvf):
+    """The voxel with sdf = -mu exactly is updated, the one just behind is
+    not; F = min(1, sdf/mu) on the optical axis, bit for bit."""
+    log("boundary: sdf = -mu on the device")
+    F, W, Cc, ov, og = _axis_case(mvf, [0.5])
+    sdf = _axis_sdf(0.5)
+    mu = og.mu
+    assert np.any(sdf == -mu)
+    np.testing.assert_array_equal(W, ov.W)
+    np.testing.assert_array_equal(F.astype(np.float64), ov.F)
+    col_W = W[:, 4, 4]
+    np.testing.assert_array_equal(col_W, (sdf >= -mu).astype(np.uint16))
+    np.testing.assert_array_equal(F[:, 4, 4].astype(np.float64), np.where(sdf >= -mu, np.minimum(1.0, sdf / mu), 0.0))
+
+
+def test_boundary_colour_band_and_half_rounding(mvf):
+    """Colour enters at |sdf| <= mu including both edges; the running mean
+    rounds halves up: (10, 200, 77) then (11, 101, 254) gives (11, 151, 166)."""
+    log("boundary: colour band edges and .5 rounding on the device")
+    F, W, Cc, ov, og = _axis_case(mvf, [0.5, 0.5], rgbs=[(10, 200, 77), (11, 101, 254)])
+    sdf = _axis_sdf(0.5)
+    mu = og.mu
+    band = np.abs(sdf) <= mu
+    assert np.any(sdf == mu) and np.any(sdf == -mu)
+    np.testing.assert_array_equal(Cc, ov.Cc)
+    np.testing.assert_array_equal(W, ov.W)
+    col = Cc[:, 4, 4]
+    np.testing.assert_array_equal(col[band], np.tile([11, 151, 166, 2], (band.sum(), 1)))
+    np.testing.assert_array_equal(col[~band], 0)
+    # fuse-twice of identical depth leaves F unchanged bit for bit
+    F1, *_ = _axis_case(mvf, [0.5])
+    np.testing.assert_array_equal(F.view(np.uint32), F1.view(np.uint32))
+
+
+def test_boundary_weight_cap_and_running_mean(mvf):
+    """w_max = 3 over six frames of changing depth: W saturates at 3 and F is
+    the oracle's running mean (value path within 1e-5, decisions exact)."""
+    log("boundary: weight cap 3 on the device")
+    depths = [0.5, 0.53125, 0.46875, 0.5625, 0.515625, 0.5]
+    F, W, Cc, ov, og = _axis_case(mvf, depths, w_max=3)
+    np.testing.assert_array_equal(W, ov.W)
+    assert W.max() == 3
+    assert np.abs(F.astype(np.float64) - ov.F).max() <= 1e-5
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, np.nan, np.inf, -np.inf])
+def test_boundary_invalid_depth(mvf, bad):
+    log(f"boundary: invalid depth {bad} on the device")
+    F, W, Cc, ov, og = _axis_case(mvf, [bad])
+    assert W.max() == 0 and ov.W.max() == 0
+    assert np.all(F == 0)
