@@ -9,7 +9,7 @@ with 12 seeded spheres/boxes on a seeded 0.5 m/s handheld path at 30 fps
 every active volume, raycast of the frame's pose.  Inputs are rendered on
 the host and resident in device memory before the timed region.
 
-Phases:
+Phases (all run by default):
   single       one 512^3 volume over a 3 m cube (5.86 mm voxels), plain
                mvf_integrate + mvf_raycast calls (each kernel timed with HIP
                events: the roofline figures come from here)
@@ -19,8 +19,21 @@ Phases:
                per-volume calls
   batched      the same 8 volumes through mvf_step (one persistent launch each
                for integration and raycast, replayed as a HIP graph)
+  probe        roofline probe (not a workload of the paper): one 512^3 volume
+               wholly inside the view in front of a far plane, so that every
+               voxel is updated in every frame (1.6 GB of TSDF traffic per
+               frame, far above the 256 MB Infinity Cache)
+  small        128^3 over 2 m, ten 320x240 frames of the small room, through
+               mvf_step and through the plain calls (absolute units only: the
+               21 MB volume stays in the Infinity Cache)
+  multi        32 independent rooms, 1-4 uneven volumes of 128^3..384^3 each,
+               distinct 640x480 frames of each room's 100-frame path; the
+               batched step against the rooms' plain calls
+  corridor     dynamic placement down a 20 m corridor under an 8 GB budget
+  diffray      pose refinement through the differentiable raycast at 512^3
 
 Prints one JSON line.  python bench.py [--steps K] [--warmup W] [--gpus 1]
+[--phases a,b,...] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -149,6 +162,98 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
+def phase_probe(mvf, torch, steps=60, warmup=5):
+    """Roofline probe: one 512^3 volume over 3 m seen from 3.6 m in front of
+    its near face (wholly inside the 640x480 view), and a depth map of a
+    fronto-parallel plane 7.5 m away behind it: every voxel is in front of
+    the surface and within the view, so all 134 M voxels are updated (F and
+    W read and written) in every frame and no colour band exists."""
+    dev = torch.device("cuda", 0)
+    s = EXTENT / N_VOX
+    T = np.zeros((3, 4))
+    T[:, :3] = np.eye(3)
+    T[:, 3] = [0.0, 0.0, -EXTENT / 2 - 3.6]
+    depth = torch.full((H_IMG, W_IMG), 7.5, dtype=torch.float32, device=dev)
+    rgb = torch.zeros((H_IMG, W_IMG, 3), dtype=torch.uint8, device=dev)
+    K = np.array([525.0, 525.0, 319.5, 239.5], np.float32)
+    res = {}
+    for timed in (False, True):
+        with mvf.Context(timing=timed) as ctx:
+            gid = ctx.grid((-EXTENT / 2,) * 3, s, 4.0, 128)
+            ctx.volume(gid, (0, 0, 0), (N_VOX,) * 3)
+            for _ in range(warmup):
+                ctx.integrate(depth, rgb, T, K)
+            torch.cuda.synchronize()
+            ctx.reset_stats()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.integrate(depth, rgb, T, K)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = ctx.stats()
+        if not timed:
+            res["ms_per_frame"] = 1e3 * wall / steps
+            res["voxel_updates_per_frame"] = st["voxels_updated"] / steps
+            res["voxel_updates_per_s"] = st["voxels_updated"] / wall
+        else:
+            avg_s = st["integrate_ms"] * 1e-3 / max(1, st["integrate_launches"])
+            bytes_launch = (B_UPDATED * st["voxels_updated"] + B_BAND * st["voxels_band"]) / steps \
+                + B_PIXEL * W_IMG * H_IMG
+            res["integrate_avg_launch_ms"] = avg_s * 1e3
+            res["algorithmic_bytes_per_launch"] = bytes_launch
+            res["achieved_gb_s"] = bytes_launch / avg_s / 1e9
+            res["frac"] = res["achieved_gb_s"] / HBM_PEAK_GBS
+    res["all_voxels_updated"] = res["voxel_updates_per_frame"] == float(N_VOX ** 3)
+    return res
+
+
+def phase_small(mvf, torch, reps=6, warmup=1):
+    """The plain single-volume case: 128^3 over [-1, 1]^3 (15.6 mm voxels),
+    the ten 320x240 frames of the small room (3 spheres) on its 1 m circle;
+    each step integrates one frame and raycasts its view.  The ten frames are
+    replayed `reps` times after `warmup` passes (each pass fuses them again),
+    through mvf_step (a graph replay per frame) and through the plain calls."""
+    from synth import scenes as S
+    seq = S.small_room_sequence(seed=1)
+    K = seq.K.as_array()
+    w, h = seq.K.width, seq.K.height
+    dev = torch.device("cuda", 0)
+    fr = [(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev)) for d, c in seq.frames(range(10), threads=10)]
+    res = {"volume": [128, 128, 128], "image": [w, h], "frames": 10}
+    for path in ("step", "plain"):
+        with mvf.Context() as ctx:
+            gid = ctx.grid((-1.0,) * 3, 2.0 / 128, 4.0, 128)
+            ctx.volume(gid, (0, 0, 0), (128,) * 3)
+            out = {"depth": torch.empty((h, w), device=dev), "vertex": torch.empty((h, w, 3), device=dev),
+                   "normal": torch.empty((h, w, 3), device=dev),
+                   "hit": torch.empty((h, w), dtype=torch.int32, device=dev)}
+
+            def one(i):
+                d, c = fr[i]
+                if path == "step":
+                    ctx.step([(0, d, c, seq.poses[i], K)], [out])
+                else:
+                    ctx.integrate(d, c, seq.poses[i], K)
+                    ctx.raycast(seq.poses[i], K, w, h, out=out)
+
+            for _ in range(warmup):
+                for i in range(10):
+                    one(i)
+            torch.cuda.synchronize()
+            ctx.reset_stats()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                for i in range(10):
+                    one(i)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = ctx.stats()
+        n = 10 * reps
+        res[path] = {"ms_per_step": 1e3 * wall / n, "voxel_updates_per_s": st["voxels_updated"] / wall,
+                     "raycast_mpix_s": n * w * h / wall / 1e6}
+    return res
+
+
 def phase_diffray(mvf, torch, n_poses=16, n_steps=50):
     """Pose refinement through the differentiable raycast: a 512^3 volume over
     [-1, 1]^3 fused from 60 noisy 640x480 frames of the small room on its
@@ -217,23 +322,29 @@ def phase_diffray(mvf, torch, n_poses=16, n_steps=50):
             "poses_improved": int(sum(e1 < e0 for e0, e1 in zip(err0, err1)))}
 
 
-def phase_multi(mvf, torch, n_rooms=32, n_render=3, steps=10, warmup=2):
+def phase_multi(mvf, torch, n_rooms=32, n_frames=100, warmup=10):
     """Many independent scenes: 32 rooms with 1-4 volumes of 128^3..384^3 each
-    (10.4 mm voxels), one 640x480 frame per room per step; the batched step
-    (all rooms in one mvf_step) against the 32 rooms' plain calls."""
+    (10.4 mm voxels), each room streaming the distinct 640x480 frames of its
+    own 100-frame handheld path (rendered into device memory); one step takes
+    one frame of every room.  The batched step (all rooms in one mvf_step,
+    autotuned schedule) against the 32 rooms' plain per-volume calls, over
+    frames warmup..n_frames-1 of every path after the first `warmup`."""
     from synth import scenes as S
+    from synth.device_render import DeviceRenderer
     s = 4.0 / 384
-    rooms = S.multi_room_workload(n_rooms, 100)
+    rooms = S.multi_room_workload(n_rooms, n_frames)
     dev = torch.device("cuda", 0)
     t0 = time.time()
     frames = []
     for r in rooms:
-        fr = r.frames(list(range(n_render)), threads=16)
-        frames.append([(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev)) for d, c in fr])
-    log(f"multi: rendered {n_rooms * n_render} frames in {time.time() - t0:.1f}s")
+        rd = DeviceRenderer(r.scene, r.K, dev, noise_seed=r.seed)
+        frames.append([rd.frame(r.poses[i], i) for i in range(n_frames)])
+    torch.cuda.synchronize()
+    log(f"multi: rendered {n_rooms * n_frames} frames on the device in {time.time() - t0:.1f}s")
     K = S.K_VGA.as_array()
     res = {}
     cache = os.path.join(tempfile.mkdtemp(prefix="mvf_tune_"), "schedules.jsonl")
+    steps = n_frames - warmup
     for mode in ("tune", "batched", "plain"):
         with mvf.Context(timing=False) as ctx:
             if mode != "plain":
@@ -253,7 +364,7 @@ def phase_multi(mvf, torch, n_rooms=32, n_render=3, steps=10, warmup=2):
                      "hit": torch.empty((H_IMG, W_IMG), dtype=torch.int32, device=dev)} for _ in range(n_rooms)]
 
             def one(j):
-                fi = j % n_render
+                fi = j % n_frames
                 if mode != "plain":
                     ctx.step([(i, frames[i][fi][0], frames[i][fi][1], rooms[i].poses[fi], K)
                               for i in range(n_rooms)], outs)
@@ -274,7 +385,7 @@ def phase_multi(mvf, torch, n_rooms=32, n_render=3, steps=10, warmup=2):
             ctx.reset_stats()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            for j in range(warmup, warmup + steps):
+            for j in range(warmup, n_frames):
                 one(j)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t1
@@ -283,7 +394,10 @@ def phase_multi(mvf, torch, n_rooms=32, n_render=3, steps=10, warmup=2):
                          "mpix_s": steps * n_rooms * W_IMG * H_IMG / wall / 1e6}
             res["volumes"] = nvol
             res["voxels"] = vox
+    del frames
     res["rooms"] = n_rooms
+    res["frames_per_room"] = n_frames
+    res["timed_steps"] = steps
     res["batched_vs_plain_speedup"] = res["plain"]["ms_per_step"] / res["batched"]["ms_per_step"]
     return res
 
@@ -336,30 +450,55 @@ def phase_corridor(mvf, torch, n_steps=100, stride=10, d_v=384, n_max=16, budget
             "voxel_updates_per_s": st["voxels_updated"] / wall, "hit_fraction_mean": float(np.mean(hits))}
 
 
-EXTRA_PHASES = {"diffray": phase_diffray, "multi": phase_multi, "corridor": phase_corridor}
+EXTRA_PHASES = {"probe": phase_probe, "small": phase_small, "multi": phase_multi, "corridor": phase_corridor,
+                "diffray": phase_diffray}
+DEFAULT_PHASES = "single,single_step,tiled,batched,probe,small,multi,corridor,diffray"
 
 
-def cpu_baseline(seq_frames, K, budget_s=12.0, max_frames=40):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seq_frames, K, budget_s=12.0, max_frames=40, threads=None):
     """The CPU oracle on a bounded sample of the same workload: whole steps
     (integrate + raycast) into a 512^3 volume, from the first frame, until
-    budget_s of CPU time has passed (at least 2 steps)."""
+    budget_s of wall time has passed (at least 2 steps), on `threads` host
+    threads (default: all the oracle's OpenMP threads)."""
     import oracle as O
+    lib = O.lib()
+    all_threads = int(lib.orc_threads())
+    lib.orc_set_threads(threads or all_threads)
+    used = int(lib.orc_threads())
     og = O.OGrid((-EXTENT / 2,) * 3, EXTENT / N_VOX, 4.0, 128)
     ov = O.OVolume.empty((N_VOX,) * 3)
     upd = 0
     n = 0
+    t_int = t_ray = 0.0
     t0 = time.perf_counter()
     for (d, c), T in seq_frames[:max_frames]:
+        a = time.perf_counter()
         st = O.integrate(ov, og, d, c, K, T)
+        b = time.perf_counter()
         upd += st[1]
         O.raycast([ov], og, K, T, W_IMG, H_IMG)
+        t_int += b - a
+        t_ray += time.perf_counter() - b
         n += 1
         if n >= 2 and time.perf_counter() - t0 > budget_s:
             break
     wall = time.perf_counter() - t0
-    return {"value": upd / wall, "unit": "voxel-updates/s", "cores": int(O.lib().orc_threads()),
-            "kind": "oracle", "sample": f"first {n} frames of the timed sequence, integrate + raycast each, into "
-                                         f"the 512^3 volume; {upd} voxel updates in {wall:.1f} s"}
+    lib.orc_set_threads(all_threads)
+    return {"value": upd / wall, "unit": "voxel-updates/s", "cores": used, "kind": "oracle",
+            "integrate_voxel_updates_per_s": upd / t_int, "raycast_mpix_s": n * W_IMG * H_IMG / t_ray / 1e6,
+            "cpu_model": cpu_model(),
+            "sample": f"first {n} frames of the timed sequence, integrate + raycast each, into the 512^3 "
+                      f"volume on {used} thread(s); {upd} voxel updates in {wall:.1f} s"}
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "integrate_kernel_large_room_512_pmc.md")
@@ -384,14 +523,45 @@ def traffic_from_profile():
         return None
 
 
+def config_summary(phases):
+    """The key figures of every workload, by the configuration it stands for."""
+    out = {}
+    g = phases.get
+    if g("small"):
+        out["small_room_128"] = {"step": g("small")["step"], "plain": g("small")["plain"]}
+    if g("single_step") or g("single"):
+        e = {}
+        for k in ("single_step", "single"):
+            if g(k):
+                e[k] = {x: g(k)[x] for x in ("ms_per_step", "voxel_updates_per_s", "raycast_mpix_s")}
+        out["large_room_512"] = e
+    if g("tiled") or g("batched"):
+        e = {}
+        for k in ("tiled", "batched"):
+            if g(k):
+                e[k] = {x: g(k)[x] for x in ("ms_per_step", "voxel_updates_per_s", "raycast_mpix_s")}
+        if g("tiled") and g("batched"):
+            e["batched_vs_plain_speedup"] = g("tiled")["ms_per_step"] / g("batched")["ms_per_step"]
+        out["large_room_8x257"] = e
+    if g("corridor"):
+        out["corridor"] = g("corridor")
+    if g("multi"):
+        m = g("multi")
+        out["multi_room_32"] = {k: m[k] for k in ("batched", "plain", "batched_vs_plain_speedup", "volumes")}
+    if g("diffray"):
+        out["diffray_512"] = g("diffray")
+    if g("probe"):
+        out["roofline_probe_512"] = g("probe")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--phases", default="single,single_step,tiled,batched",
-                    help="comma list; also diffray, multi, corridor (longer workloads, not in the default)")
+    ap.add_argument("--phases", default=DEFAULT_PHASES, help="comma list of phases (default: all)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the phases, copy a buffer of this size 5 times (counter calibration)")
     args = ap.parse_args()
@@ -470,6 +640,11 @@ def main():
             "traffic": traffic_from_profile(),
             "kernel": "mvf_integrate_kernel", "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": main_ph["integrate_ms"] / launches if main_ph["integrate_ms"] else None}
+    if "probe" in phases:
+        pr = phases["probe"]
+        roof["probe_full_frustum"] = {"achieved": pr["achieved_gb_s"], "frac": pr["frac"],
+                                      "algorithmic_bytes_per_launch": pr["algorithmic_bytes_per_launch"],
+                                      "avg_launch_ms": pr["integrate_avg_launch_ms"]}
     res = {
         "metric": METRIC,
         "value": head_ph["voxel_updates_per_s"],
@@ -498,9 +673,15 @@ def main():
         res["batched_vs_plain_speedup"] = phases["tiled"]["ms_per_step"] / phases["batched"]["ms_per_step"]
     if "single" in phases and "single_step" in phases:
         res["single_step_vs_plain_speedup"] = phases["single"]["ms_per_step"] / phases["single_step"]["ms_per_step"]
+    res["configs"] = config_summary(phases)
     if not args.no_cpu:
-        log("cpu baseline")
+        log("cpu baseline (all threads)")
         res["cpu_baseline"] = cpu_baseline(frames, K)
+        log("cpu baseline (one thread)")
+        one = cpu_baseline(frames, K, budget_s=12.0, threads=1)
+        res["cpu_baseline"]["single_thread"] = {k: one[k] for k in
+                                                ("value", "integrate_voxel_updates_per_s", "raycast_mpix_s",
+                                                 "cores", "sample")}
     print(json.dumps(res), flush=True)
 
 

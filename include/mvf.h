@@ -227,9 +227,12 @@ typedef struct {
  * raycast every stream at its frame's pose into outs[i], for all n streams
  * at once: one persistent integration launch and one persistent raycast
  * launch over a device volume table, captured once into a HIP graph and
- * replayed.  Results equal the plain calls bit for bit.  All active
- * volumes of the streams must fit the budget together (else
- * MVF_ERR_BUDGET; use the plain calls). */
+ * replayed.  Results equal the plain calls bit for bit.  When the active
+ * in-view volumes of the streams do not fit the budget together they are
+ * processed in waves that do (swapping volumes in and out, Memory Passing
+ * section), one graph replay per wave, the raycast of each wave merged
+ * with the earlier ones per pixel; MVF_ERR_BUDGET only when one volume
+ * alone exceeds the budget.  Steps split into waves are not autotuned. */
 mvf_status mvf_step(mvf_ctx* ctx, int32_t n, const mvf_stream_frame* frames,
                     const mvf_raycast_out* outs, void* stream);
 

@@ -591,6 +591,9 @@ int orc_placement_cells(const float* depth, int width, int height,
 #ifdef _OPENMP
 #include <omp.h>
 int orc_threads(void) { return omp_get_max_threads(); }
+/* Threads the parallel loops use from now on (n >= 1). */
+void orc_set_threads(int n) { omp_set_num_threads(n < 1 ? 1 : n); }
 #else
 int orc_threads(void) { return 1; }
+void orc_set_threads(int n) { (void)n; }
 #endif

@@ -134,6 +134,7 @@ struct LaunchHeader {
     RayParams rp;
     int32_t total_z;       // entries of the integration z table (sum of 8 * bd[2])
     int32_t rb_parity;     // raycast range bounds: which half of RayBounds::counts this launch fills
+    int32_t list_parity;   // integration: which of the two visited-item counts this launch uses
 };
 
 // Footprint of one brick in the raycast range bounds: cells [x0, x1] x
@@ -191,6 +192,13 @@ struct IntegrateLaunch {
     const uint32_t* tile_cost;
     int32_t* tile_order;
     int32_t order_tiles;
+    // visited items, compacted (needs visit): the z-table launch appends
+    // every item with a visited brick to list (room for total_items) and
+    // counts them in list_count[hdr->list_parity]; integration walks the
+    // list.  The z-table launch also zeroes list_count[list_parity ^ 1] for
+    // the next launch, so the two counts must be zero before first use.
+    int32_t* list;
+    uint32_t* list_count;
 };
 constexpr int kVisitPerItem = 8;
 

@@ -290,15 +290,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
     const int wpb = blockDim.x >> 6;
     const int total_waves = ((int)gridDim.x - b0) * wpb;
     unsigned n_upd = 0, n_band = 0;  // wave totals
-    const int total_items = L.hdr->total_items;
     const int nvol = L.hdr->nvol;
     const int zchunk = L.hdr->zchunk;
     CPTR(float) const ztab = cptr(L.ztab);
+    // with a list, only the items that have a visited brick (about a third
+    // of a frame's items) get a wavefront
+    const int n_work = L.list ? (int)cptr(L.list_count)[L.hdr->list_parity] : L.hdr->total_items;
 
-    for (int item = wave_uniform(((int)blockIdx.x - b0) * wpb + wib); item < total_items; item += total_waves) {
-        // bricks of the item that may hold an updated voxel, first: about
-        // two thirds of the items of a frame have none and stop here (bytes
-        // from zchunk on are not written by the visit pass)
+    for (int w = wave_uniform(((int)blockIdx.x - b0) * wpb + wib); w < n_work; w += total_waves) {
+        const int item = L.list ? cptr(L.list)[w] : w;
+        // bricks of the item that may hold an updated voxel (bytes from
+        // zchunk on are not written by the visit pass)
         const uint64_t vis = L.visit ? cptr((const uint64_t*)L.visit)[item] &
                                            (zchunk >= kVisitPerItem ? ~0ull : (1ull << (8 * zchunk)) - 1ull)
                                      : 0x0101010101010101ull;
@@ -521,23 +523,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
             }
         }
     }
-    // counters: the block's total (the wave totals are the same in every
-    // lane), one atomic per block into one of kCntSlots copies
-    __shared__ unsigned cnt_upd[4], cnt_band[4];
-    if (lane == 0) {
-        cnt_upd[wib & 3] = n_upd;
-        cnt_band[wib & 3] = n_band;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && L.counters) {
-        unsigned long long su = 0, sb = 0;
-        for (int w = 0; w < wpb && w < 4; ++w) {
-            su += cnt_upd[w];
-            sb += cnt_band[w];
-        }
-        unsigned long long* slot = L.counters + ((blockIdx.x - b0) % kCntSlots) * kCntNum;
-        if (su) atomicAdd(&slot[kCntUpdated], su);
-        if (sb) atomicAdd(&slot[kCntBand], sb);
+    // counters: the wave's totals (the same in every lane), one atomic each
+    // into one of kCntSlots copies; no block barrier, so a wavefront that
+    // finishes early frees its slot at once
+    if (lane == 0 && L.counters && (n_upd | n_band)) {
+        unsigned long long* slot = L.counters + ((((int)blockIdx.x - b0) * wpb + wib) % kCntSlots) * kCntNum;
+        if (n_upd) atomicAdd(&slot[kCntUpdated], (unsigned long long)n_upd);
+        if (n_band) atomicAdd(&slot[kCntBand], (unsigned long long)n_band);
     }
 }
 
@@ -646,10 +638,30 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
             } else {
                 visit = test(vols[lo], frames[vols[lo].frame]);
             }
-            if (t0 + (int)threadIdx.x < total) L.visit[(size_t)item * kVisitPerItem + j] = visit ? 1 : 0;
+            const bool valid = t0 + (int)threadIdx.x < total;
+            if (valid) L.visit[(size_t)item * kVisitPerItem + j] = visit ? 1 : 0;
+            if (L.list) {
+                // append the items of this wavefront (64 / zchunk whole items:
+                // t0 is a multiple of the block size and zchunk divides 64)
+                // that have a visited brick, in item order within the wavefront
+                const int lane = threadIdx.x & 63;
+                const uint64_t m = __ballot(valid && visit);
+                const uint64_t grp = (m >> (lane & ~(zchunk - 1))) & ((1ull << zchunk) - 1ull);
+                const bool head = valid && j == 0 && grp != 0;
+                const uint64_t hm = __ballot(head);
+                if (hm) {
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&L.list_count[L.hdr->list_parity], (uint32_t)__popcll(hm));
+                    base = __shfl(base, 0);
+                    if (head) L.list[base + __popcll(hm & ((1ull << lane) - 1ull))] = item;
+                }
+            }
         }
         return;
     }
+    // the other count, for the next launch (the previous one, which used it,
+    // has finished)
+    if (L.list_count && blockIdx.x == 0 && threadIdx.x == 0) L.list_count[L.hdr->list_parity ^ 1] = 0;
     const int total = hdr->total_z;
     for (int f = blockIdx.x; f < hdr->nstreams; f += kZtBlocks) {
         float* rm = frames[f].rmax;

@@ -101,12 +101,16 @@ struct Scratch {
     int rmax_cap = 0;        // floats in rmax
     float* best_t = nullptr;
     int32_t* best_id = nullptr;
+    int best_cap = 0;           // pixels best_t / best_id hold
     float* ztab = nullptr;  // integration z table (3 floats per entry)
     int ztab_cap = 0;
     float* tmax = nullptr;   // maximum range per 8x8 pixel tile
     int tmax_cap = 0;
     uint8_t* visit = nullptr;  // integration: brick visit mask per item
     int visit_cap = 0;
+    int32_t* list = nullptr;   // integration: visited items (visit_cap entries)
+    uint32_t* list_count = nullptr;  // two counts, zeroed at allocation
+    int list_parity = 0;
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
     int32_t* tile_order = nullptr;
     int tiles_cap = 0;
@@ -173,6 +177,9 @@ struct StepGraph {
     int ztab_cap = 0;
     uint8_t* visit = nullptr;  // brick visit mask per integration item
     int visit_cap = 0;
+    int32_t* list = nullptr;   // visited integration items (visit_cap entries)
+    uint32_t* list_count = nullptr;  // two counts, zeroed at allocation
+    int list_parity = 0;
     RayBoundEntry* rb_entries = nullptr;  // raycast range-bound footprints (one per brick)
     int rb_entries_cap = 0;
     uint32_t* rb_counts = nullptr;        // 2 * max_vols
@@ -605,6 +612,20 @@ double box_distance(mvf_ctx* c, const Volume& v, const float* T)
     return std::sqrt(d2);
 }
 
+// Running best (t*, volume id) of a raycast split into waves, for npix
+// output pixels.
+mvf_status get_best_buffers(Scratch* s, int npix)
+{
+    if (npix <= s->best_cap && s->best_t) return MVF_OK;
+    if (s->best_t) { CHECK_HIP(hipFree(s->best_t)); s->best_t = nullptr; }
+    if (s->best_id) { CHECK_HIP(hipFree(s->best_id)); s->best_id = nullptr; }
+    s->best_cap = 0;
+    CHECK_HIP(hipMalloc((void**)&s->best_t, (size_t)npix * sizeof(float)));
+    CHECK_HIP(hipMalloc((void**)&s->best_id, (size_t)npix * sizeof(int32_t)));
+    s->best_cap = npix;
+    return MVF_OK;
+}
+
 mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratch** out)
 {
     Scratch& s = c->scratch[sid];
@@ -623,19 +644,13 @@ mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratc
     if (w * h > s.w * s.h || !s.range) {
         if (s.range) { CHECK_HIP(hipFree(s.range)); s.range = nullptr; }
         if (s.color) { CHECK_HIP(hipFree(s.color)); s.color = nullptr; }
-        if (s.best_t) { CHECK_HIP(hipFree(s.best_t)); s.best_t = nullptr; }
-        if (s.best_id) { CHECK_HIP(hipFree(s.best_id)); s.best_id = nullptr; }
         const size_t n = (size_t)std::max(w * h, s.w * s.h);
         CHECK_HIP(hipMalloc((void**)&s.range, (n + 64) * sizeof(float)));  // + the zero range behind the image
         CHECK_HIP(hipMalloc((void**)&s.color, n * sizeof(uint32_t)));
         s.w = w;
         s.h = h;
     }
-    if (need_best && !s.best_t) {
-        const size_t n = (size_t)s.w * s.h;
-        CHECK_HIP(hipMalloc((void**)&s.best_t, n * sizeof(float)));
-        CHECK_HIP(hipMalloc((void**)&s.best_id, n * sizeof(int32_t)));
-    }
+    if (need_best) CHECK_ST(get_best_buffers(&s, w * h));
     *out = &s;
     return MVF_OK;
 }
@@ -862,10 +877,17 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
         if (sc->visit) {
             CHECK_HIP(hipStreamSynchronize(stream));
             CHECK_HIP(hipFree(sc->visit));
+            CHECK_HIP(hipFree(sc->list));
             sc->visit = nullptr;
+            sc->list = nullptr;
         }
         CHECK_HIP(hipMalloc((void**)&sc->visit, (size_t)max_items * kVisitPerItem));
+        CHECK_HIP(hipMalloc((void**)&sc->list, (size_t)max_items * sizeof(int32_t)));
         sc->visit_cap = max_items;
+    }
+    if (!sc->list_count) {
+        CHECK_HIP(hipMalloc((void**)&sc->list_count, 2 * sizeof(uint32_t)));
+        CHECK_HIP(hipMemset(sc->list_count, 0, 2 * sizeof(uint32_t)));
     }
     bool order_pending = sc->tile_cost && sc->last_tiles > 0;  // once per call
     for (auto& wave : waves) {
@@ -899,6 +921,8 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             p.bricks = (int)v.nbricks;
             h->total_bricks = (int)align_up((size_t)p.bricks, 64);
             h->total_z = kBrick * v.bd[2];
+            h->list_parity = sc->list_parity;
+            sc->list_parity ^= 1;
             ib[0] = 0;
             ib[1] = p.items;
             bb[0] = 0;
@@ -915,7 +939,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             order_pending = false;
             IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit,
                               order ? sc->tile_cost : nullptr, order ? sc->tile_order : nullptr,
-                              order ? sc->last_tiles : 0};
+                              order ? sc->last_tiles : 0, sc->list, sc->list_count};
             if (order) sc->order_ready_tiles = sc->last_tiles;
             CHECK_LAUNCH(launch_ztable(L, (p.items * kZChunk + 255) / 256, stream));
             // with timing, the kernel's dispatch records the event pair
@@ -1052,7 +1076,10 @@ mvf_status destroy_step_graph(mvf_ctx* c)
     if (g.dev) { CHECK_HIP(hipFree(g.dev)); g.dev = nullptr; }
     if (g.ztab) { CHECK_HIP(hipFree(g.ztab)); g.ztab = nullptr; }
     if (g.visit) { CHECK_HIP(hipFree(g.visit)); g.visit = nullptr; }
+    if (g.list) { CHECK_HIP(hipFree(g.list)); g.list = nullptr; }
+    if (g.list_count) { CHECK_HIP(hipFree(g.list_count)); g.list_count = nullptr; }
     g.visit_cap = 0;
+    g.list_parity = 0;
     if (g.rb_entries) { CHECK_HIP(hipFree(g.rb_entries)); g.rb_entries = nullptr; }
     if (g.rb_counts) { CHECK_HIP(hipFree(g.rb_counts)); g.rb_counts = nullptr; }
     g.rb_entries_cap = 0;
@@ -1348,6 +1375,8 @@ mvf_status mvf_destroy(mvf_ctx* c)
         if (s.ztab) (void)hipFree(s.ztab);
         if (s.tmax) (void)hipFree(s.tmax);
         if (s.visit) (void)hipFree(s.visit);
+        if (s.list) (void)hipFree(s.list);
+        if (s.list_count) (void)hipFree(s.list_count);
         if (s.rb_lo) (void)hipFree(s.rb_lo);
         if (s.rb_hi) (void)hipFree(s.rb_hi);
         if (s.rb_entries) (void)hipFree(s.rb_entries);
@@ -1785,22 +1814,30 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
                 return set_error(MVF_ERR_UNSUPPORTED, "batched step needs all volumes on one grid");
         }
     }
-    uint64_t total = 0;
-    for (int id : all) total += c->vols[id].bytes;
-    if (total > c->budget)
-        return set_error(MVF_ERR_BUDGET, "active volumes of the step (%llu bytes) exceed the budget",
-                         (unsigned long long)total);
-    CHECK_ST(ensure_resident(c, all, s));
+    // volumes that do not all fit the budget are processed in waves (the
+    // paper's memory passing, down to one volume at a time): each wave is one
+    // replay of the captured step over the wave's volumes, raycasts merged
+    // through the per-pixel best (t*, id) of the earlier waves
+    std::vector<std::vector<int>> waves = plan_waves(c, all);
+    if (waves.empty()) waves.push_back({});
+    const bool multi_wave = waves.size() > 1;
 
     bool tuning = false;
     const std::string key = step_key(c, n, outs, all);
-    const mvf_schedule sch = pick_schedule(c, key, &tuning);
+    mvf_schedule sch = pick_schedule(c, key, &tuning);
+    if (multi_wave && tuning) {
+        // a step split into waves is not a representative sample for the tuner
+        tuning = false;
+        sch = c->tune_cache.count(key) ? c->tune_cache[key].first : c->fixed_sched;
+        if (c->tune_mode != MVF_AUTOTUNE_OFF && !c->tune_cache.count(key)) sch = mvf_schedule{4, 0, kRayLanes, 0};
+    }
     StepGraph& G = c->step;
     int max_w = 0, max_h = 0;
     for (int i = 0; i < n; ++i) {
         max_w = std::max(max_w, frames[i].frame.width);
         max_h = std::max(max_h, frames[i].frame.height);
     }
+    // capacities from the whole set (every wave is a subset of it)
     int ztotal = 0, items_total = 0, bricks_total = 0;
     for (int id : all) {
         const Volume& v = c->vols[id];
@@ -1847,6 +1884,9 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         CHECK_HIP(hipMalloc((void**)&G.ztab, (size_t)G.ztab_cap * 3 * sizeof(float)));
         G.visit_cap = std::max(items_total * 2, 1024);
         CHECK_HIP(hipMalloc((void**)&G.visit, (size_t)G.visit_cap * kVisitPerItem));
+        CHECK_HIP(hipMalloc((void**)&G.list, (size_t)G.visit_cap * sizeof(int32_t)));
+        CHECK_HIP(hipMalloc((void**)&G.list_count, 2 * sizeof(uint32_t)));
+        CHECK_HIP(hipMemset(G.list_count, 0, 2 * sizeof(uint32_t)));
         int counts_cap = 0;
         CHECK_ST(get_footprint_buffers(&G.rb_entries, &G.rb_entries_cap, &G.rb_counts, &counts_cap,
                                        std::max(bricks_total * 2, 1024), G.max_vols));
@@ -1862,174 +1902,196 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         G.ray_blocks = ray_blocks(tiles);
         CHECK_ST(alloc_tile_buffers(tiles, &G.tile_cost, &G.tile_order));
     }
-    // scratch per stream
+    // scratch per stream (with the running best of a multi-wave raycast)
     std::vector<Scratch*> sc(n);
     for (int i = 0; i < n; ++i)
     {
         CHECK_ST(get_scratch(c, frames[i].stream_id, frames[i].frame.width, frames[i].frame.height, false, &sc[i]));
         CHECK_ST(get_bound_buffers(sc[i], outs[i].width, outs[i].height));
+        if (multi_wave) CHECK_ST(get_best_buffers(sc[i], outs[i].width * outs[i].height));
     }
-
-    // host image of the tables, uploaded to G.dev before the graph runs
-    int slot;
-    Writer w;
-    CHECK_ST(arena_acquire(c, &slot, &w));
-    uint8_t* img = w.host;
-    memset(img, 0, G.dev_bytes);
-    w.used = G.dev_bytes;
-    LaunchHeader* h = reinterpret_cast<LaunchHeader*>(img + G.off_hdr);
-    PrepItem* prep = reinterpret_cast<PrepItem*>(img + G.off_prep);
-    DevFrame* dfr = reinterpret_cast<DevFrame*>(img + G.off_frames);
-    DevVolume* vt = reinterpret_cast<DevVolume*>(img + G.off_vols);
-    int32_t* ib = reinterpret_cast<int32_t*>(img + G.off_items);
-    int32_t* lists = reinterpret_cast<int32_t*>(img + G.off_lists);
-    int32_t* lb = reinterpret_cast<int32_t*>(img + G.off_lbase);
-    int32_t* tb = reinterpret_cast<int32_t*>(img + G.off_tbase);
-    int32_t* bbase = reinterpret_cast<int32_t*>(img + G.off_bbase);
-    int nbr = 0;
-    int nv = 0;
-    int items = 0;
-    int zt = 0;
-    int tiles = 0;
-    const int zc = sch.zchunk;
-    lb[0] = 0;
-    tb[0] = 0;
+    // nearest-first order of each stream's volumes (raycast lists; only speed)
+    std::vector<std::vector<int>> order(n);
     for (int i = 0; i < n; ++i) {
-        const mvf_stream_frame& fr = frames[i];
-        PrepItem& p = prep[i];
-        p.depth = fr.frame.depth;
-        p.rgb = fr.frame.rgb;
-        p.depth_pitch = fr.frame.depth_pitch ? fr.frame.depth_pitch : fr.frame.width;
-        p.rgb_pitch = fr.frame.rgb_pitch ? fr.frame.rgb_pitch : 3 * fr.frame.width;
-        p.width = fr.frame.width;
-        p.height = fr.frame.height;
-        p.fx = fr.K.fx; p.fy = fr.K.fy; p.cx = fr.K.cx; p.cy = fr.K.cy;
-        p.range = sc[i]->range;
-        p.color = sc[i]->color;
-        p.rmax = sc[i]->rmax;
-        p.tmax = sc[i]->tmax;
-        fill_frame(&dfr[i], sc[i], fr.frame.width, fr.frame.height, fr.T_wc, fr.K);
-        set_bounds(&dfr[i], sc[i], outs[i].width, outs[i].height);
-        if (!fr.frame.rgb) dfr[i].color = nullptr;
-        dfr[i].depth = outs[i].depth;
-        dfr[i].vertex = outs[i].vertex;
-        dfr[i].normal = outs[i].normal;
-        dfr[i].hit = outs[i].hit;
-        dfr[i].out_w = outs[i].width;
-        dfr[i].out_h = outs[i].height;
-        // this stream's volumes, nearest first for the raycast list
-        std::vector<int> ids = per[i];
-        std::vector<double> dist(ids.size());
-        for (size_t j = 0; j < ids.size(); ++j) dist[j] = box_distance(c, c->vols[ids[j]], fr.T_wc);
-        std::vector<int> order(ids.size());
-        for (size_t j = 0; j < ids.size(); ++j) order[j] = (int)j;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return dist[a] < dist[b] || (dist[a] == dist[b] && ids[a] < ids[b]);
+        std::vector<double> dist;
+        for (int id : per[i]) dist.push_back(box_distance(c, c->vols[id], frames[i].T_wc));
+        std::vector<int> ord(per[i].size());
+        for (size_t j = 0; j < ord.size(); ++j) ord[j] = (int)j;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+            return dist[a] < dist[b] || (dist[a] == dist[b] && per[i][a] < per[i][b]);
         });
-        const int first = nv;
-        for (size_t j = 0; j < ids.size(); ++j) {
-            Volume& v = c->vols[ids[j]];
-            vt[nv] = make_dev(c, v);
-            vt[nv].frame = i;
-            vt[nv].zt_base = zt;
-            zt += kBrick * v.bd[2];
-            ib[nv] = items;
-            bbase[nv] = nbr;
-            nbr += (int)align_up(v.nbricks, 64);  // volumes start on a wavefront
-            items += v.bd[0] * v.bd[1] * ((v.bd[2] + zc - 1) / zc);
-            ++nv;
-        }
-        for (size_t j = 0; j < ids.size(); ++j) lists[first + j] = first + order[j];
-        lb[i + 1] = nv;
-        tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
-        tb[i + 1] = tiles;
+        for (int j : ord) order[i].push_back(per[i][j]);
     }
-    ib[nv] = items;
-    bbase[nv] = nbr;
-    h->nvol = nv;
-    h->total_bricks = nbr;
-    h->total_items = items;
-    h->total_z = zt;
-    h->zchunk = zc;
-    h->nstreams = n;
-    h->total_tiles = tiles;
-    h->first_wave = 1;
-    h->rp = grid0 >= 0 ? ray_params(c, c->grids[grid0]) : RayParams{1.0f, 0};
-    h->rb_parity = G.rb_parity;
-    G.rb_parity ^= 1;
-    // The graph's first node uploads this image into its fixed tables; the
-    // node's source is pointed at this step's arena slot.
-    if (!G.valid) {
-        hipStream_t cs = c->capture_stream;
-        const LaunchHeader* dh = reinterpret_cast<const LaunchHeader*>(G.dev + G.off_hdr);
-        const PrepItem* dprep = reinterpret_cast<const PrepItem*>(G.dev + G.off_prep);
-        const DevFrame* dframes = reinterpret_cast<const DevFrame*>(G.dev + G.off_frames);
-        const DevVolume* dvols = reinterpret_cast<const DevVolume*>(G.dev + G.off_vols);
-        const int32_t* ditems = reinterpret_cast<const int32_t*>(G.dev + G.off_items);
-        const int32_t* dlists = reinterpret_cast<const int32_t*>(G.dev + G.off_lists);
-        const int32_t* dlb = reinterpret_cast<const int32_t*>(G.dev + G.off_lbase);
-        const int32_t* dtb = reinterpret_cast<const int32_t*>(G.dev + G.off_tbase);
-        const int32_t* dbb = reinterpret_cast<const int32_t*>(G.dev + G.off_bbase);
-        CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        int e1 = (int)hipMemcpyAsync(G.dev, w.host, G.dev_bytes, hipMemcpyHostToDevice, cs);
-        if (!e1) e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
-        // integration's block 0 orders the raycast's tile groups (slowest of
-        // the last step first)
-        IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit,
-                           G.tile_cost, G.tile_order, G.ray_tiles};
-        int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items * zc + 255) / 256), cs);
-        // one wavefront per work item of the captured volume set (a larger
-        // set later is walked by the kernel's grid-stride loop)
-        G.integ_blocks = (sch.persistent ? c->n_cus * 8 : std::max(c->n_cus * 8, (items + 3) / 4)) + 1;
-        if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
-        // the last distance pass also collects the raycast range-bound
-        // footprints; the merge folds them per cell
-        const RayBounds RB{G.rb_entries, G.rb_counts, G.max_vols};
-        if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs, dframes, RB);
-        if (!e2) e2 = launch_ray_bounds_merge(dh, dframes, dlists, dlb, dbb, RB, n, G.max_cells_x, G.max_cells_y, cs);
-        RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th, sch.ray_lanes, G.tile_cost, G.tile_order};
-        int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
-        hipError_t ee = hipStreamEndCapture(cs, &G.graph);
-        if (e3) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString((hipError_t)e3));
-        if (ee != hipSuccess) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString(ee));
-        CHECK_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
-        size_t nn = 0;
-        CHECK_HIP(hipGraphGetNodes(G.graph, nullptr, &nn));
-        std::vector<hipGraphNode_t> nodes(nn);
-        CHECK_HIP(hipGraphGetNodes(G.graph, nodes.data(), &nn));
-        G.copy_node = nullptr;
-        for (hipGraphNode_t nd : nodes) {
-            hipGraphNodeType ty;
-            CHECK_HIP(hipGraphNodeGetType(nd, &ty));
-            if (ty == hipGraphNodeTypeMemcpy) G.copy_node = nd;
-        }
-        if (!G.copy_node) return set_error(MVF_ERR_HIP, "step capture: no table upload node");
-        G.valid = true;
-    } else {
-        CHECK_HIP(hipGraphExecMemcpyNodeSetParams1D(G.exec, G.copy_node, G.dev, w.host, G.dev_bytes,
-                                                    hipMemcpyHostToDevice));
-    }
+    const RayParams rp = grid0 >= 0 ? ray_params(c, c->grids[grid0]) : RayParams{1.0f, 0};
+
     hipEvent_t t0;
     CHECK_ST(timing_begin(c, s, &t0));
-    hipEvent_t tune_a = nullptr, tune_b = nullptr;
-    if (tuning) {
-        CHECK_ST(get_event(c, &tune_a));
-        CHECK_ST(get_event(c, &tune_b));
-        CHECK_HIP(hipEventRecord(tune_a, s));
-    }
-    CHECK_HIP(hipGraphLaunch(G.exec, s));
-    if (tuning) {
-        CHECK_HIP(hipEventRecord(tune_b, s));
-        c->tuning.ev.push_back(std::make_pair(tune_a, tune_b));
-        c->tuning.next += 1;
+    int last_slot = -1;
+    for (size_t wi = 0; wi < waves.size(); ++wi) {
+        const std::vector<int>& wave = waves[wi];
+        CHECK_ST(ensure_resident(c, wave, s));
+        std::vector<char> in_wave(c->vols.size(), 0);
+        for (int id : wave) in_wave[id] = 1;
+        // host image of the tables, uploaded to G.dev by the graph's first node
+        int slot;
+        Writer w;
+        CHECK_ST(arena_acquire(c, &slot, &w));
+        uint8_t* img = w.host;
+        memset(img, 0, G.dev_bytes);
+        w.used = G.dev_bytes;
+        LaunchHeader* h = reinterpret_cast<LaunchHeader*>(img + G.off_hdr);
+        PrepItem* prep = reinterpret_cast<PrepItem*>(img + G.off_prep);
+        DevFrame* dfr = reinterpret_cast<DevFrame*>(img + G.off_frames);
+        DevVolume* vt = reinterpret_cast<DevVolume*>(img + G.off_vols);
+        int32_t* ib = reinterpret_cast<int32_t*>(img + G.off_items);
+        int32_t* lists = reinterpret_cast<int32_t*>(img + G.off_lists);
+        int32_t* lb = reinterpret_cast<int32_t*>(img + G.off_lbase);
+        int32_t* tb = reinterpret_cast<int32_t*>(img + G.off_tbase);
+        int32_t* bbase = reinterpret_cast<int32_t*>(img + G.off_bbase);
+        int nbr = 0, nv = 0, items = 0, zt = 0, tiles = 0;
+        const int zc = sch.zchunk;
+        lb[0] = 0;
+        tb[0] = 0;
+        for (int i = 0; i < n; ++i) {
+            const mvf_stream_frame& fr = frames[i];
+            PrepItem& p = prep[i];
+            p.depth = fr.frame.depth;
+            p.rgb = fr.frame.rgb;
+            p.depth_pitch = fr.frame.depth_pitch ? fr.frame.depth_pitch : fr.frame.width;
+            p.rgb_pitch = fr.frame.rgb_pitch ? fr.frame.rgb_pitch : 3 * fr.frame.width;
+            p.width = fr.frame.width;
+            p.height = fr.frame.height;
+            p.fx = fr.K.fx; p.fy = fr.K.fy; p.cx = fr.K.cx; p.cy = fr.K.cy;
+            p.range = sc[i]->range;
+            p.color = sc[i]->color;
+            p.rmax = sc[i]->rmax;
+            p.tmax = sc[i]->tmax;
+            fill_frame(&dfr[i], sc[i], fr.frame.width, fr.frame.height, fr.T_wc, fr.K);
+            set_bounds(&dfr[i], sc[i], outs[i].width, outs[i].height);
+            if (!fr.frame.rgb) dfr[i].color = nullptr;
+            dfr[i].depth = outs[i].depth;
+            dfr[i].vertex = outs[i].vertex;
+            dfr[i].normal = outs[i].normal;
+            dfr[i].hit = outs[i].hit;
+            dfr[i].out_w = outs[i].width;
+            dfr[i].out_h = outs[i].height;
+            if (multi_wave) {
+                dfr[i].best_t = sc[i]->best_t;
+                dfr[i].best_id = sc[i]->best_id;
+            }
+            // this stream's volumes of the wave: table entries in id order,
+            // the raycast list nearest first
+            const int first = nv;
+            std::vector<int> slot_of(c->vols.size(), -1);
+            for (int id : per[i]) {
+                if (!in_wave[id]) continue;
+                Volume& v = c->vols[id];
+                vt[nv] = make_dev(c, v);
+                vt[nv].frame = i;
+                vt[nv].zt_base = zt;
+                zt += kBrick * v.bd[2];
+                ib[nv] = items;
+                bbase[nv] = nbr;
+                nbr += (int)align_up(v.nbricks, 64);  // volumes start on a wavefront
+                items += v.bd[0] * v.bd[1] * ((v.bd[2] + zc - 1) / zc);
+                slot_of[id] = nv;
+                ++nv;
+            }
+            int li = first;
+            for (int id : order[i])
+                if (slot_of[id] >= 0) lists[li++] = slot_of[id];
+            lb[i + 1] = nv;
+            tiles += ((outs[i].width + tw - 1) / tw) * ((outs[i].height + th - 1) / th);
+            tb[i + 1] = tiles;
+        }
+        ib[nv] = items;
+        bbase[nv] = nbr;
+        h->nvol = nv;
+        h->total_bricks = nbr;
+        h->total_items = items;
+        h->total_z = zt;
+        h->zchunk = zc;
+        h->nstreams = n;
+        h->total_tiles = tiles;
+        h->first_wave = wi == 0 ? 1 : 0;
+        h->rp = rp;
+        h->rb_parity = G.rb_parity;
+        G.rb_parity ^= 1;
+        h->list_parity = G.list_parity;
+        G.list_parity ^= 1;
+        // The graph's first node uploads this image into its fixed tables; the
+        // node's source is pointed at this wave's arena slot.
+        if (!G.valid) {
+            hipStream_t cs = c->capture_stream;
+            const LaunchHeader* dh = reinterpret_cast<const LaunchHeader*>(G.dev + G.off_hdr);
+            const PrepItem* dprep = reinterpret_cast<const PrepItem*>(G.dev + G.off_prep);
+            const DevFrame* dframes = reinterpret_cast<const DevFrame*>(G.dev + G.off_frames);
+            const DevVolume* dvols = reinterpret_cast<const DevVolume*>(G.dev + G.off_vols);
+            const int32_t* ditems = reinterpret_cast<const int32_t*>(G.dev + G.off_items);
+            const int32_t* dlists = reinterpret_cast<const int32_t*>(G.dev + G.off_lists);
+            const int32_t* dlb = reinterpret_cast<const int32_t*>(G.dev + G.off_lbase);
+            const int32_t* dtb = reinterpret_cast<const int32_t*>(G.dev + G.off_tbase);
+            const int32_t* dbb = reinterpret_cast<const int32_t*>(G.dev + G.off_bbase);
+            CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            int e1 = (int)hipMemcpyAsync(G.dev, w.host, G.dev_bytes, hipMemcpyHostToDevice, cs);
+            if (!e1) e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
+            // integration's block 0 orders the raycast's tile groups (slowest of
+            // the last step first)
+            IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit,
+                               G.tile_cost, G.tile_order, G.ray_tiles, G.list, G.list_count};
+            int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items_total * zc + 255) / 256), cs);
+            // one wavefront per work item of the whole volume set (a larger
+            // set later is walked by the kernel's grid-stride loop)
+            G.integ_blocks = (sch.persistent ? c->n_cus * 8 : std::max(c->n_cus * 8, (items_total + 3) / 4)) + 1;
+            if (!e2) e2 = launch_integrate(IL, G.integ_blocks, cs);
+            // the last distance pass also collects the raycast range-bound
+            // footprints; the merge folds them per cell
+            const RayBounds RB{G.rb_entries, G.rb_counts, G.max_vols};
+            if (!e2) e2 = launch_brick_distance(dh, dvols, dbb, c->n_cus * 4, cs, dframes, RB);
+            if (!e2) e2 = launch_ray_bounds_merge(dh, dframes, dlists, dlb, dbb, RB, n, G.max_cells_x, G.max_cells_y, cs);
+            RaycastLaunch RL{dh, dvols, dframes, dlists, dlb, dtb, tw, th, sch.ray_lanes, G.tile_cost, G.tile_order};
+            int e3 = e2 ? e2 : launch_raycast(RL, G.ray_blocks, cs);
+            hipError_t ee = hipStreamEndCapture(cs, &G.graph);
+            if (e3) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString((hipError_t)e3));
+            if (ee != hipSuccess) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString(ee));
+            CHECK_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+            size_t nn = 0;
+            CHECK_HIP(hipGraphGetNodes(G.graph, nullptr, &nn));
+            std::vector<hipGraphNode_t> nodes(nn);
+            CHECK_HIP(hipGraphGetNodes(G.graph, nodes.data(), &nn));
+            G.copy_node = nullptr;
+            for (hipGraphNode_t nd : nodes) {
+                hipGraphNodeType ty;
+                CHECK_HIP(hipGraphNodeGetType(nd, &ty));
+                if (ty == hipGraphNodeTypeMemcpy) G.copy_node = nd;
+            }
+            if (!G.copy_node) return set_error(MVF_ERR_HIP, "step capture: no table upload node");
+            G.valid = true;
+        } else {
+            CHECK_HIP(hipGraphExecMemcpyNodeSetParams1D(G.exec, G.copy_node, G.dev, w.host, G.dev_bytes,
+                                                        hipMemcpyHostToDevice));
+        }
+        hipEvent_t tune_a = nullptr, tune_b = nullptr;
+        if (tuning) {
+            CHECK_ST(get_event(c, &tune_a));
+            CHECK_ST(get_event(c, &tune_b));
+            CHECK_HIP(hipEventRecord(tune_a, s));
+        }
+        CHECK_HIP(hipGraphLaunch(G.exec, s));
+        if (tuning) {
+            CHECK_HIP(hipEventRecord(tune_b, s));
+            c->tuning.ev.push_back(std::make_pair(tune_a, tune_b));
+            c->tuning.next += 1;
+        }
+        CHECK_ST(arena_release(c, slot, s));  // reused once the replay that reads it is done
+        last_slot = slot;
     }
     CHECK_ST(timing_end(c, s, t0, 2));
     c->last_sched = sch;
-    CHECK_ST(arena_release(c, slot, s));  // reused once the replay that reads it is done
     if (tuning) CHECK_ST(finish_tuning(c));
     c->stats.step_launches += 1;
     for (int i = 0; i < n; ++i) c->stats.pixels_raycast += (uint64_t)outs[i].width * outs[i].height;
-    return mark_tail_recorded(c, s, c->arena.ev[slot]);
+    return mark_tail_recorded(c, s, c->arena.ev[last_slot]);
 }
 
 mvf_status mvf_set_schedule(mvf_ctx* c, const mvf_schedule* sched)

@@ -188,11 +188,14 @@ def test_tiled_8x257_large_room(mvf, large, mode):
         print(f"[parity] tiled 8 x 257^3 via {mode}: hits {n}, ambiguous fraction {amb.mean():.2e}", flush=True)
 
 
+@pytest.mark.parametrize("mode", ["plain", "step"])
 @pytest.mark.parametrize("n,budget_volumes", [(64, 1), (64, 3), (416, 1)])
-def test_budget_runs_vs_oracle(mvf, n, budget_volumes):
+def test_budget_runs_vs_oracle(mvf, n, budget_volumes, mode):
     """Eight (n/2 + 1)^3 subvolumes fused and raycast with room for only
     `budget_volumes` of them on the device (waves and swaps, the paper's
-    memory passing) against the oracle's eight volumes."""
+    memory passing), through the plain calls or the captured step (one
+    replay per wave), against the oracle's eight volumes."""
+    import torch
     seq = S.small_room_sequence(seed=1)
     K = seq.K.as_array()
     og = O.OGrid((-1.0, -1.0, -1.0), 2.0 / n, 4.0, 128)
@@ -208,9 +211,16 @@ def test_budget_runs_vs_oracle(mvf, n, budget_volumes):
             d, c = seq.frame(i)
             for v in ovs:
                 O.integrate(v, og, d, c, K, seq.poses[i])
-            ctx.integrate(t(d), t(c), seq.poses[i], K)
+            if mode == "step":
+                out = {"depth": torch.empty((240, 320), device=dev()),
+                       "vertex": torch.empty((240, 320, 3), device=dev()),
+                       "normal": torch.empty((240, 320, 3), device=dev()),
+                       "hit": torch.empty((240, 320), dtype=torch.int32, device=dev())}
+                ctx.step([(0, t(d), t(c), seq.poses[i], K)], [out])
+            else:
+                ctx.integrate(t(d), t(c), seq.poses[i], K)
             if i in (3, 9):
-                g = _np(ctx.raycast(seq.poses[i], K, 320, 240))
+                g = _np(out if mode == "step" else ctx.raycast(seq.poses[i], K, 320, 240))
                 devs = [ctx.read_volume(v) for v in ids]
                 for (F, W, Cc), v in zip(devs, ovs):
                     _cmp_volume(F, W, Cc, v)
