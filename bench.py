@@ -29,7 +29,9 @@ Phases (all run by default):
   multi        32 independent rooms, 1-4 uneven volumes of 128^3..384^3 each,
                distinct 640x480 frames of each room's 100-frame path; the
                batched step against the rooms' plain calls
-  corridor     dynamic placement down a 20 m corridor under an 8 GB budget
+  corridor     dynamic placement down a 20 m corridor: volumes of three sizes
+               (512^3, 384^3, 256^3) under an 8 GB budget, through mvf_step
+               and through the plain calls
   diffray      pose refinement through the differentiable raycast at 512^3
 
 Prints one JSON line.  python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -402,11 +404,19 @@ def phase_multi(mvf, torch, n_rooms=32, n_frames=100, warmup=10):
     return res
 
 
-def phase_corridor(mvf, torch, n_steps=100, stride=10, d_v=384, n_max=16, budget_gb=8.0):
+CORRIDOR_CLASSES = [(512, 4), (384, 6), (256, 6)]
+
+
+def phase_corridor(mvf, torch, n_steps=40, stride=10, classes=CORRIDOR_CLASSES, budget_gb=8.0):
     """Dynamic placement down the 20 m corridor: every `stride`-th frame of the
-    2000-frame walk is integrated into the live volumes, raycast, then the
-    endpoint-count placement adds/removes d_v^3 volumes (n_max live, beta 1.5)
-    under an HBM budget, so that volumes swap to and from host memory."""
+    2000-frame walk is integrated into the live volumes and raycast in one
+    mvf_step (one graph replay, or one per wave when the live volumes exceed
+    the budget), then the endpoint-count placement adds/removes volumes of
+    three sizes (512^3, 384^3, 256^3 at 2.93 mm: 1.5, 1.125 and 0.75 m; at
+    most 4, 6 and 6 live, the largest taking the highest-count regions,
+    beta 1.5) under an 8 GB device budget (16 live volumes need 9.8 GB), so
+    that volumes swap to and from host memory.  The same walk through the
+    plain calls is timed beside it."""
     from synth import scenes as S
     seq = S.corridor_sequence(seed=3, n_frames=2000)
     K = seq.K.as_array()
@@ -420,34 +430,41 @@ def phase_corridor(mvf, torch, n_steps=100, stride=10, d_v=384, n_max=16, budget
            "vertex": torch.empty((H_IMG, W_IMG, 3), device=dev),
            "normal": torch.empty((H_IMG, W_IMG, 3), device=dev),
            "hit": torch.empty((H_IMG, W_IMG), dtype=torch.int32, device=dev)}
-    with mvf.Context(budget_bytes=int(budget_gb * (1 << 30)), timing=False) as ctx:
-        gid = ctx.grid((0.0, -1.0, 0.0), 0.00293, 4.0, 128)
-        added = removed = 0
-        hits = []
-        place_ms = []
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for j, i in enumerate(idx):
-            d, c = frames[j]
-            ctx.integrate(d, c, seq.poses[i], K)
-            ctx.raycast(seq.poses[i], K, W_IMG, H_IMG, out=out)
-            tp = time.perf_counter()
-            a, r, _ = ctx.placement_update(d, seq.poses[i], K, gid, d_v, n_max, 1.5)
-            place_ms.append(1e3 * (time.perf_counter() - tp))
-            added += len(a)
-            removed += len(r)
-            if j % 10 == 9:
-                hits.append(float((out["depth"] > 0).float().mean()))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t1
-        st = ctx.stats()
-    return {"steps": n_steps, "frame_stride": stride, "d_v": d_v, "n_max": n_max, "budget_gb": budget_gb,
-            "ms_per_step": 1e3 * wall / n_steps, "placement_ms_median": float(np.median(place_ms)),
-            "volumes_added": added, "volumes_removed": removed,
-            "swaps_in": st["swaps_in"], "swaps_out": st["swaps_out"],
-            "h2d_gb": st["bytes_h2d"] / 1e9, "d2h_gb": st["bytes_d2h"] / 1e9,
-            "swap_gb_per_s_of_wall": (st["bytes_h2d"] + st["bytes_d2h"]) / 1e9 / wall,
-            "voxel_updates_per_s": st["voxels_updated"] / wall, "hit_fraction_mean": float(np.mean(hits))}
+    res = {"steps": n_steps, "frame_stride": stride, "classes": [list(c) for c in classes], "budget_gb": budget_gb}
+    for path in ("step", "plain"):
+        with mvf.Context(budget_bytes=int(budget_gb * (1 << 30)), timing=False) as ctx:
+            gid = ctx.grid((0.0, -1.0, 0.0), 0.00293, 4.0, 128)
+            added = removed = 0
+            hits = []
+            place_ms = []
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for j, i in enumerate(idx):
+                d, c = frames[j]
+                if path == "step":
+                    ctx.step([(0, d, c, seq.poses[i], K)], [out])
+                else:
+                    ctx.integrate(d, c, seq.poses[i], K)
+                    ctx.raycast(seq.poses[i], K, W_IMG, H_IMG, out=out)
+                tp = time.perf_counter()
+                a, r, _ = ctx.placement_update_classes(d, seq.poses[i], K, gid, classes, 1.5)
+                place_ms.append(1e3 * (time.perf_counter() - tp))
+                added += len(a)
+                removed += len(r)
+                if j % 10 == 9:
+                    hits.append(float((out["depth"] > 0).float().mean()))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            st = ctx.stats()
+        res[path] = {"ms_per_step": 1e3 * wall / n_steps, "placement_ms_median": float(np.median(place_ms)),
+                     "volumes_added": added, "volumes_removed": removed,
+                     "swaps_in": st["swaps_in"], "swaps_out": st["swaps_out"],
+                     "h2d_gb": st["bytes_h2d"] / 1e9, "d2h_gb": st["bytes_d2h"] / 1e9,
+                     "swap_gb_per_s_of_wall": (st["bytes_h2d"] + st["bytes_d2h"]) / 1e9 / wall,
+                     "voxel_updates_per_s": st["voxels_updated"] / wall, "hit_fraction_mean": float(np.mean(hits))}
+        log(f"corridor {path}: {res[path]['ms_per_step']:.2f} ms per step")
+    res["batched_vs_plain_speedup"] = res["plain"]["ms_per_step"] / res["step"]["ms_per_step"]
+    return res
 
 
 EXTRA_PHASES = {"probe": phase_probe, "small": phase_small, "multi": phase_multi, "corridor": phase_corridor,

@@ -304,6 +304,40 @@ mvf_status mvf_placement_update(mvf_ctx* ctx, int32_t stream_id, const mvf_frame
                                 const float T_wc[12], const mvf_intrinsics* K,
                                 const mvf_placement_params* p, mvf_placement_result* r,
                                 void* stream);
+/* Volumes of several sizes on one grid: the insertion/removal rule with
+ * the size chosen by count rank (Dynamic Mapping for SLAM: f may set the
+ * volume parameters).  Classes are taken in the given order, the first
+ * taking the highest-count regions.  Class i counts, on its own lattice
+ * (side classes[i].d_v - 2 voxels), only the endpoints that no live volume
+ * of classes 0..i-1 (as updated this frame) contains, then keeps at most
+ * classes[i].quota volumes by the same rule as mvf_placement_update (count
+ * order, hysteresis beta, translations unique within a class).  A volume
+ * whose endpoints a larger volume has taken over counts 0 and yields to the
+ * next candidate that beats it.  With one class this is
+ * mvf_placement_update.  Volumes are keyed per stream by (d_v, cell): a
+ * cell seen before reuses its volume (state kept on the host).
+ * MVF_ERR_INVALID_ARG for n_classes outside [1, MVF_MAX_PLACEMENT_CLASSES],
+ * a d_v outside [3, 2048] or given twice, a negative quota or quotas summing
+ * above 64.  n_cells in the result counts distinct (class, cell) pairs.
+ * Synchronises on `stream` (one count and readback per class). */
+#define MVF_MAX_PLACEMENT_CLASSES 8
+typedef struct {
+    int32_t d_v;    /* voxels per side of this class's volumes (>= 3) */
+    int32_t quota;  /* most live volumes of this class (>= 0) */
+} mvf_placement_class;
+
+typedef struct {
+    int32_t grid_id;
+    int32_t n_classes;
+    mvf_placement_class classes[MVF_MAX_PLACEMENT_CLASSES];
+    float beta;         /* a newcomer must exceed beta x the lowest count; >= 1 */
+    int32_t reserved;
+} mvf_placement_class_params;
+
+mvf_status mvf_placement_update_classes(mvf_ctx* ctx, int32_t stream_id, const mvf_frame* frame,
+                                        const float T_wc[12], const mvf_intrinsics* K,
+                                        const mvf_placement_class_params* p, mvf_placement_result* r,
+                                        void* stream);
 /* The endpoint counts alone: up to max_cells (cell xyz, count) tuples written
  * to host `cells` (3 ints) and `counts`; *n_cells = number of distinct cells.
  * Synchronises on `stream`. */

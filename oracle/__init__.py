@@ -214,6 +214,34 @@ def depth_grad(vol: OVolume, grid: OGrid, K, T64, width, height, kcells, grad_de
     return gxi, gF
 
 
+def extract(vol: OVolume, grid: OGrid, F32: Optional[np.ndarray] = None,
+            max_points: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Surface points of one volume: at most one vertex per voxel, at the
+    linear zero crossing on the first edge (x, y, z) leaving the voxel that
+    changes sign inside the truncation band, with the cell's trilinear
+    gradient as normal.  ``F32``: the binary32 TSDF to read (default: F
+    rounded).  Returns V, N (n x 3, binary64, world) and G (n x 3 global
+    voxel), in global voxel order (z, y, x)."""
+    F = _f32(F32 if F32 is not None else vol.F32())
+    if F.shape != vol.W.shape:
+        raise ValueError("F32 must have the volume's shape")
+    cap = int(max_points if max_points is not None else max(1, vol.W.size // 4))
+    while True:
+        V = np.zeros((cap, 3))
+        N = np.zeros((cap, 3))
+        G = np.zeros((cap, 3), np.int32)
+        n = C.c_int64()
+        r = lib().orc_extract(_p(np.asarray(vol.dims, np.int32)), _p(np.asarray(vol.offset, np.int32)), _p(F),
+                              _p(np.ascontiguousarray(vol.W)), _p(grid.arr4()), C.c_int64(cap), _p(V), _p(N),
+                              _p(G), C.byref(n))
+        if r != 0:
+            raise ValueError("orc_extract rejected its arguments")
+        if n.value <= cap or max_points is not None:
+            k = min(n.value, cap)
+            return dict(V=V[:k], N=N[:k], G=G[:k], n=int(n.value))
+        cap = n.value
+
+
 # --------------------------------------------------------------------------
 # SE(3)
 # --------------------------------------------------------------------------
@@ -313,3 +341,66 @@ def placement_policy(active: Sequence[Tuple[int, int, int]],
         else:
             break
     return H, added, removed
+
+
+def placement_endpoints(depth, K, T, grid: OGrid, d_vs: Sequence[int]):
+    """Per valid depth pixel: the global voxel g (int3) holding its ray
+    endpoint, and its cell on the placement lattice of each side d_v in
+    ``d_vs``.  The voxel is the cell of the side-one lattice (d_v = 3:
+    s (d_v - 2) = s), so both come from the same binary32 endpoint formula.
+    Returns (g of shape (n, 3), {d_v: cells of shape (n, 3)})."""
+    depth = _f32(depth)
+    h, w = depth.shape
+    out = {}
+    ok = np.ones(h * w, bool)
+    for d in [3, *d_vs]:
+        cells = np.zeros((h * w, 3), np.int32)
+        valid = np.zeros(h * w, np.uint8)
+        r = lib().orc_placement_cells(_p(depth), C.c_int(w), C.c_int(h), _p(_f32(K)),
+                                      _p(_f32(np.asarray(T).reshape(12))), _p(grid.arr4()),
+                                      C.c_int(int(d)), _p(cells), _p(valid))
+        if r != 0:
+            raise ValueError("orc_placement_cells rejected its arguments")
+        out[int(d)] = cells
+        ok &= valid.astype(bool)
+    return out[3][ok], {int(d): out[int(d)][ok] for d in d_vs}
+
+
+def placement_policy_classes(active: Dict[int, Sequence[Tuple[int, int, int]]], g: np.ndarray,
+                             cells: Dict[int, np.ndarray], classes: Sequence[Tuple[int, int]],
+                             beta: float = 1.5):
+    """One insertion/removal step over volume classes of different sizes on
+    one grid (Dynamic Mapping for SLAM: f may choose the volume parameters;
+    here the size by count rank).
+
+    ``classes``: (d_v, quota) in rank order, the first class taking the
+    highest-count regions.  ``active``: per d_v the cells of its live
+    volumes; ``g`` (n, 3): the voxel of each valid ray endpoint; ``cells``:
+    per d_v the endpoint cells on that class's lattice (h_t = k (d_v - 2)).
+
+    Classes are taken in order.  Each counts only the endpoints that no live
+    volume of an earlier class (as updated this frame) contains, and runs
+    the single-size rule of ``placement_policy`` with n_max = its quota.  So
+    the largest volumes go where most rays end, the next class covers the
+    endpoints they miss, and a volume whose endpoints a larger volume has
+    taken over counts 0 and is displaced by the next candidate that beats
+    it.  Translations are unique within a class.  Returns ({d_v: new
+    active}, {d_v: added}, {d_v: removed})."""
+    g = np.asarray(g, np.int64).reshape(-1, 3)
+    covered = np.zeros(len(g), bool)
+    new_active, added, removed = {}, {}, {}
+    for d_v, quota in classes:
+        kc = np.asarray(cells[d_v], np.int64).reshape(-1, 3)[~covered]
+        # count equal cells: sort them (numpy's lexsort) and measure the runs
+        counts: Dict[Tuple[int, int, int], int] = {}
+        if len(kc):
+            ks = kc[np.lexsort((kc[:, 2], kc[:, 1], kc[:, 0]))]
+            starts = np.flatnonzero(np.concatenate([[True], np.any(ks[1:] != ks[:-1], axis=1)]))
+            ends = np.concatenate([starts[1:], [len(ks)]])
+            counts = {tuple(int(x) for x in ks[a]): int(b - a) for a, b in zip(starts, ends)}
+        H, a, r = placement_policy(active.get(d_v, []), counts, quota, beta)
+        new_active[d_v], added[d_v], removed[d_v] = H, a, r
+        for k in H:
+            lo = np.asarray(k, np.int64) * (d_v - 2)
+            covered |= np.all((g >= lo) & (g < lo + d_v), axis=1)
+    return new_active, added, removed

@@ -587,6 +587,82 @@ int orc_placement_cells(const float* depth, int width, int height,
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Surface points (Input and Output: the vertex set V with normals N, at most
+ * one vertex per voxel; Metrics: a voxel that the surface crosses gets a
+ * vertex).  Readings of the paper taken here:
+ *  - voxel g emits a vertex when its cell [g, g + 1]^3 lies in the volume
+ *    and is observed at all 8 corners (W > 0), and the TSDF changes sign
+ *    along one of the three edges leaving g (one end > 0, the other <= 0)
+ *    with both ends inside the truncation band (|F| < 1);
+ *  - the first such edge in the order x, y, z gives the vertex: the linear
+ *    zero crossing c(g) + s t e_a with t = F(g) / (F(g) - F(g + e_a)) and
+ *    c(g) = o + s (g + 1/2) the voxel centre;
+ *  - the normal is the gradient of the cell's trilinear interpolant at the
+ *    vertex, normalised (it points to F > 0, the observed free space).
+ * The sign and band tests read the binary32 F; positions and normals are
+ * binary64.  Points come in global voxel order (z, then y, then x), with
+ * their global voxel index in G.  At most max_points are written; *n_out
+ * is the total.
+ * ------------------------------------------------------------------------ */
+int orc_extract(const int32_t dims[3], const int32_t off[3], const float* F,
+                const uint16_t* W, const float grid[4], int64_t max_points,
+                double* V, double* N, int32_t* G, int64_t* n_out)
+{
+    const double o[3] = { grid[0], grid[1], grid[2] };
+    const double s = grid[3];
+    int64_t n = 0;
+    if (dims[0] < 2 || dims[1] < 2 || dims[2] < 2) { *n_out = 0; return 0; }
+    for (int z = 0; z + 1 < dims[2]; ++z)
+        for (int y = 0; y + 1 < dims[1]; ++y)
+            for (int x = 0; x + 1 < dims[0]; ++x) {
+                /* the cell's corners, c[k] at (x + (k & 1), y + (k >> 1 & 1), z + (k >> 2)) */
+                float c[8];
+                int observed = 1;
+                for (int k = 0; k < 8 && observed; ++k) {
+                    const int64_t i = vidx(dims, x + (k & 1), y + ((k >> 1) & 1), z + (k >> 2));
+                    observed = W[i] > 0;
+                    c[k] = F[i];
+                }
+                if (!observed) continue;
+                /* edges leaving g: +x is corner 1, +y corner 2, +z corner 4 */
+                int axis = -1;
+                for (int a = 0; a < 3 && axis < 0; ++a) {
+                    const float f0 = c[0], f1 = c[1 << a];
+                    const int in_band = fabsf(f0) < 1.0f && fabsf(f1) < 1.0f;
+                    const int change = (f0 > 0.0f && f1 <= 0.0f) || (f0 <= 0.0f && f1 > 0.0f);
+                    if (in_band && change) axis = a;
+                }
+                if (axis < 0) continue;
+                const double f0 = c[0], f1 = c[1 << axis];
+                const double t = f0 / (f0 - f1);
+                double fr[3] = { 0.0, 0.0, 0.0 };
+                fr[axis] = t;
+                const int g[3] = { off[0] + x, off[1] + y, off[2] + z };
+                double gr[3] = { 0.0, 0.0, 0.0 };
+                for (int k = 0; k < 8; ++k) {
+                    const int b[3] = { k & 1, (k >> 1) & 1, k >> 2 };
+                    for (int a = 0; a < 3; ++a) {
+                        double w = b[a] ? 1.0 : -1.0;
+                        for (int q = 0; q < 3; ++q)
+                            if (q != a) w *= b[q] ? fr[q] : 1.0 - fr[q];
+                        gr[a] += w * (double)c[k];
+                    }
+                }
+                const double len = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+                if (n < max_points) {
+                    for (int a = 0; a < 3; ++a) {
+                        V[3 * n + a] = o[a] + s * ((double)g[a] + 0.5 + fr[a]);
+                        N[3 * n + a] = len > 0.0 ? gr[a] / len : NAN;
+                        G[3 * n + a] = g[a];
+                    }
+                }
+                ++n;
+            }
+    *n_out = n;
+    return 0;
+}
+
 /* Threads the oracle's parallel loops use (for reporting CPU timings). */
 #ifdef _OPENMP
 #include <omp.h>

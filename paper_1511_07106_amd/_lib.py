@@ -78,6 +78,19 @@ class mvf_placement_params(C.Structure):
     _fields_ = [("grid_id", C.c_int32), ("d_v", C.c_int32), ("n_max", C.c_int32), ("beta", C.c_float)]
 
 
+class mvf_placement_class(C.Structure):
+    _fields_ = [("d_v", C.c_int32), ("quota", C.c_int32)]
+
+
+MVF_MAX_PLACEMENT_CLASSES = 8
+
+
+class mvf_placement_class_params(C.Structure):
+    _fields_ = [("grid_id", C.c_int32), ("n_classes", C.c_int32),
+                ("classes", mvf_placement_class * MVF_MAX_PLACEMENT_CLASSES), ("beta", C.c_float),
+                ("reserved", C.c_int32)]
+
+
 class mvf_placement_result(C.Structure):
     _fields_ = [("n_added", C.c_int32), ("n_removed", C.c_int32), ("added", C.c_int32 * 64),
                 ("removed", C.c_int32 * 64), ("n_cells", C.c_int32), ("reserved", C.c_int32)]
@@ -122,6 +135,8 @@ SIGNATURES = {
     "mvf_autotune": [P, I32, C.c_char_p],
     "mvf_placement_update": [P, I32, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics),
                              C.POINTER(mvf_placement_params), C.POINTER(mvf_placement_result), P],
+    "mvf_placement_update_classes": [P, I32, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics),
+                                     C.POINTER(mvf_placement_class_params), C.POINTER(mvf_placement_result), P],
     "mvf_placement_count": [P, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics), I32, I32, PI32, PI32,
                             I32, PI32, P],
     "mvf_placement_policy": [PI32, I32, PI32, PI32, I32, I32, C.c_float, PI32, PI32, PI32, PI32, PI32, PI32],

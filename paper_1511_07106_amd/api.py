@@ -289,6 +289,27 @@ class Context:
                 "mvf_placement_update")
         return list(r.added[:r.n_added]), list(r.removed[:r.n_removed]), r.n_cells
 
+    def placement_update_classes(self, depth, T, K, grid_id: int, classes, beta: float = 1.5,
+                                 stream_id: int = 0, stream=None):
+        """Placement with volumes of several sizes: ``classes`` is a list of
+        (d_v, quota) in rank order (the first class takes the highest-count
+        regions).  Returns (added ids, removed ids, distinct cells)."""
+        f = self._frame(depth, None)
+        p = L.mvf_placement_class_params()
+        p.grid_id = int(grid_id)
+        p.n_classes = len(classes)
+        if not 1 <= len(classes) <= L.MVF_MAX_PLACEMENT_CLASSES:
+            raise ValueError(f"between 1 and {L.MVF_MAX_PLACEMENT_CLASSES} classes")
+        for i, (d_v, quota) in enumerate(classes):
+            p.classes[i].d_v = int(d_v)
+            p.classes[i].quota = int(quota)
+        p.beta = float(beta)
+        r = L.mvf_placement_result()
+        L.check(self.lib.mvf_placement_update_classes(self.h, int(stream_id), C.byref(f), _pose(T),
+                                                      C.byref(_K(K)), C.byref(p), C.byref(r), _stream(stream)),
+                "mvf_placement_update_classes")
+        return list(r.added[:r.n_added]), list(r.removed[:r.n_removed]), r.n_cells
+
     # -- differentiable raycast ------------------------------------------------
     @staticmethod
     def _dense(F, W, origin, voxel_size, offset=(0, 0, 0)) -> L.mvf_dense_tsdf:

@@ -276,7 +276,8 @@ int launch_placement_clear(unsigned long long* table, int table_size, void* stre
 int launch_placement_count(const float* depth, int depth_pitch, int width, int height,
                            float fx, float fy, float cx, float cy, const float* T,
                            float o0, float o1, float o2, float cell,
-                           unsigned long long* table, int table_size, int* overflow, void* stream);
+                           unsigned long long* table, int table_size, int* overflow,
+                           const int32_t* boxes, int n_boxes, float voxel, void* stream);
 
 struct DiffVolume {
     const float* F;

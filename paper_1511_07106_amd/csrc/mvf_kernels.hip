@@ -1886,7 +1886,8 @@ static __device__ __forceinline__ unsigned long long pack_cell(int kx, int ky, i
 __global__ __launch_bounds__(256) void mvf_placement_count_kernel(
     const float* __restrict__ depth, int depth_pitch, int width, int height, float fx, float fy,
     float cx, float cy, const float* __restrict__ Tp, float o0, float o1, float o2, float cell,
-    unsigned long long* table, int table_size, int* overflow)
+    unsigned long long* table, int table_size, int* overflow, const int32_t* __restrict__ boxes,
+    int n_boxes, float voxel)
 {
     const int u = blockIdx.x * 32 + (threadIdx.x & 31);
     const int v = blockIdx.y * 8 + (threadIdx.x >> 5);
@@ -1901,12 +1902,31 @@ __global__ __launch_bounds__(256) void mvf_placement_count_kernel(
     const float q0 = Dz * ra, q1 = Dz * rb, q2 = Dz;
     const float o[3] = { o0, o1, o2 };
     int k[3];
+    float e[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        const float e = (((T[4 * r + 0] * q0) + (T[4 * r + 1] * q1)) + (T[4 * r + 2] * q2)) + T[4 * r + 3];
-        const float kf = floorf((e - o[r]) / cell);
+        e[r] = (((T[4 * r + 0] * q0) + (T[4 * r + 1] * q1)) + (T[4 * r + 2] * q2)) + T[4 * r + 3];
+        const float kf = floorf((e[r] - o[r]) / cell);
         if (!(kf >= -1048576.0f && kf < 1048576.0f)) { atomicOr(overflow, 2); return; }
         k[r] = (int)kf;
+    }
+    if (n_boxes > 0) {
+        // endpoints inside a listed volume (global voxels [h_t, h_t + dims))
+        // are not counted; the voxel is the cell of the side-one lattice
+        int g[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const float gf = floorf((e[r] - o[r]) / voxel);
+            if (!(gf >= -1073741824.0f && gf < 1073741824.0f)) { atomicOr(overflow, 2); return; }
+            g[r] = (int)gf;
+        }
+        for (int b = 0; b < n_boxes; ++b) {
+            const int32_t* B = boxes + 6 * b;
+            bool in = true;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) in = in && g[r] >= B[r] && (int64_t)g[r] < (int64_t)B[r] + B[3 + r];
+            if (in) return;
+        }
     }
     const unsigned long long key = pack_cell(k[0], k[1], k[2]);
     unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 40) & (unsigned)(table_size - 1);
@@ -1940,11 +1960,13 @@ int launch_placement_clear(unsigned long long* table, int table_size, void* stre
 
 int launch_placement_count(const float* depth, int depth_pitch, int width, int height, float fx, float fy,
                            float cx, float cy, const float* T, float o0, float o1, float o2, float cell,
-                           unsigned long long* table, int table_size, int* overflow, void* stream)
+                           unsigned long long* table, int table_size, int* overflow, const int32_t* boxes,
+                           int n_boxes, float voxel, void* stream)
 {
     dim3 grid((width + 31) / 32, (height + 7) / 8);
     hipLaunchKernelGGL(mvf_placement_count_kernel, grid, dim3(256), 0, (hipStream_t)stream, depth, depth_pitch,
-                       width, height, fx, fy, cx, cy, T, o0, o1, o2, cell, table, table_size, overflow);
+                       width, height, fx, fy, cx, cy, T, o0, o1, o2, cell, table, table_size, overflow, boxes,
+                       n_boxes, voxel);
     return (int)hipGetLastError();
 }
 

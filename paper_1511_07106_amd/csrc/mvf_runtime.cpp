@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -229,10 +230,13 @@ struct mvf_ctx {
         std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // per launch
     } tuning;
     // placement bookkeeping: per stream, cell -> volume id (volumes created by placement)
+    // per stream: volumes created by placement, keyed by (d_v, cell)
     std::map<int, std::map<std::vector<int>, int>> placed;
     unsigned long long* place_table = nullptr;
     int* place_overflow = nullptr;
     float* place_T = nullptr;
+    int32_t* place_boxes = nullptr;  // kMaxPlaceBoxes x (h_t, dims)
+    static constexpr int kMaxPlaceBoxes = 64;
     static constexpr int kPlaceTable = 8192;
     double* diff_partials = nullptr;
     int diff_partials_n = 0;
@@ -1403,6 +1407,7 @@ mvf_status mvf_destroy(mvf_ctx* c)
     if (c->place_table) (void)hipFree(c->place_table);
     if (c->place_overflow) (void)hipFree(c->place_overflow);
     if (c->place_T) (void)hipFree(c->place_T);
+    if (c->place_boxes) (void)hipFree(c->place_boxes);
     if (c->diff_partials) (void)hipFree(c->diff_partials);
     if (c->diff_summary) (void)hipFree(c->diff_summary);
     if (c->tail) (void)hipEventDestroy(c->tail);
@@ -2192,23 +2197,32 @@ mvf_status mvf_placement_policy(const int32_t* active, int32_t n_active, const i
     return MVF_OK;
 }
 
+// Endpoint counts per cell of the lattice of side d_v - 2 voxels, leaving out
+// endpoints inside any of `boxes` (h_t[3], dims[3] each; at most
+// kMaxPlaceBoxes).  Synchronises on s.
 static mvf_status placement_count_impl(mvf_ctx* c, const mvf_frame* f, const float* T, const mvf_intrinsics* K,
-                                       const Grid& g, int d_v, std::vector<std::pair<std::vector<int>, int>>* out,
-                                       hipStream_t s)
+                                       const Grid& g, int d_v, const std::vector<int32_t>& boxes,
+                                       std::vector<std::pair<std::vector<int>, int>>* out, hipStream_t s)
 {
     if (!c->place_table) {
         CHECK_HIP(hipMalloc((void**)&c->place_table, sizeof(unsigned long long) * 2 * mvf_ctx::kPlaceTable));
         CHECK_HIP(hipMalloc((void**)&c->place_overflow, 256));
         CHECK_HIP(hipMalloc((void**)&c->place_T, 256));
+        CHECK_HIP(hipMalloc((void**)&c->place_boxes, sizeof(int32_t) * 6 * mvf_ctx::kMaxPlaceBoxes));
     }
+    const int n_boxes = (int)boxes.size() / 6;
+    if (n_boxes > mvf_ctx::kMaxPlaceBoxes) return set_error(MVF_ERR_INVALID_ARG, "too many placement boxes");
     const float cell = g.d.voxel_size * (float)(d_v - 2);
     CHECK_HIP(hipMemcpyAsync(c->place_T, T, sizeof(float) * 12, hipMemcpyHostToDevice, s));
+    if (n_boxes)
+        CHECK_HIP(hipMemcpyAsync(c->place_boxes, boxes.data(), sizeof(int32_t) * boxes.size(), hipMemcpyHostToDevice,
+                                 s));
     CHECK_LAUNCH(launch_placement_clear(c->place_table, mvf_ctx::kPlaceTable, s));
     CHECK_HIP(hipMemsetAsync(c->place_overflow, 0, sizeof(int), s));
     CHECK_LAUNCH(launch_placement_count(f->depth, f->depth_pitch ? f->depth_pitch : f->width, f->width, f->height,
                                         K->fx, K->fy, K->cx, K->cy, c->place_T, g.d.origin[0], g.d.origin[1],
                                         g.d.origin[2], cell, c->place_table, mvf_ctx::kPlaceTable,
-                                        c->place_overflow, s));
+                                        c->place_overflow, c->place_boxes, n_boxes, g.d.voxel_size, s));
     std::vector<unsigned long long> tab(2 * mvf_ctx::kPlaceTable);
     int ovf = 0;
     CHECK_HIP(hipMemcpyAsync(tab.data(), c->place_table, tab.size() * 8, hipMemcpyDeviceToHost, s));
@@ -2243,7 +2257,7 @@ mvf_status mvf_placement_count(mvf_ctx* c, const mvf_frame* f, const float T_wc[
     hipStream_t s = (hipStream_t)stream;
     CHECK_ST(order_after_previous(c, s));
     std::vector<std::pair<std::vector<int>, int>> res;
-    CHECK_ST(placement_count_impl(c, f, T_wc, K, c->grids[grid_id], d_v, &res, s));
+    CHECK_ST(placement_count_impl(c, f, T_wc, K, c->grids[grid_id], d_v, {}, &res, s));
     *n_cells = (int32_t)res.size();
     for (int i = 0; i < (int)res.size() && i < max_cells; ++i) {
         for (int a = 0; a < 3; ++a) cells[3 * i + a] = res[i].first[a];
@@ -2252,68 +2266,108 @@ mvf_status mvf_placement_count(mvf_ctx* c, const mvf_frame* f, const float T_wc[
     return mark_tail(c, s);
 }
 
-mvf_status mvf_placement_update(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
-                                const mvf_intrinsics* K, const mvf_placement_params* p, mvf_placement_result* r,
-                                void* stream)
+mvf_status mvf_placement_update_classes(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
+                                        const mvf_intrinsics* K, const mvf_placement_class_params* p,
+                                        mvf_placement_result* r, void* stream)
 {
     if (!c || !p || !r) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
     CHECK_ST(check_frame(f));
     if (!T_wc || !finite_pose(T_wc) || !valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "bad pose or intrinsics");
     if (p->grid_id < 0 || p->grid_id >= (int32_t)c->grids.size()) return set_error(MVF_ERR_NOT_FOUND, "grid %d", p->grid_id);
-    if (p->d_v < 3 || p->d_v > 2048) return set_error(MVF_ERR_INVALID_ARG, "d_v out of range");
-    if (p->n_max < 0 || p->n_max > 64) return set_error(MVF_ERR_INVALID_ARG, "n_max must be in [0, 64]");
+    if (p->n_classes < 1 || p->n_classes > MVF_MAX_PLACEMENT_CLASSES)
+        return set_error(MVF_ERR_INVALID_ARG, "n_classes must be in [1, %d]", MVF_MAX_PLACEMENT_CLASSES);
+    int quota_sum = 0;
+    for (int ci = 0; ci < p->n_classes; ++ci) {
+        const mvf_placement_class& pc = p->classes[ci];
+        if (pc.d_v < 3 || pc.d_v > 2048) return set_error(MVF_ERR_INVALID_ARG, "class %d: d_v out of range", ci);
+        if (pc.quota < 0) return set_error(MVF_ERR_INVALID_ARG, "class %d: negative quota", ci);
+        for (int cj = 0; cj < ci; ++cj)
+            if (p->classes[cj].d_v == pc.d_v) return set_error(MVF_ERR_INVALID_ARG, "class d_v %d twice", pc.d_v);
+        quota_sum += pc.quota;
+    }
+    if (quota_sum > 64) return set_error(MVF_ERR_INVALID_ARG, "the quotas sum to %d > 64", quota_sum);
     if (!(p->beta >= 1.0f)) return set_error(MVF_ERR_INVALID_ARG, "beta must be >= 1");
     if (sid < 0) return set_error(MVF_ERR_INVALID_ARG, "stream_id must be >= 0");
     CHECK_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     CHECK_ST(order_after_previous(c, s));
-    std::vector<std::pair<std::vector<int>, int>> res;
-    CHECK_ST(placement_count_impl(c, f, T_wc, K, c->grids[p->grid_id], p->d_v, &res, s));
     memset(r, 0, sizeof(*r));
-    r->n_cells = (int32_t)res.size();
     auto& placed = c->placed[sid];
-    std::vector<int32_t> act, cellv, cntv;
-    for (auto& kv : placed) {
-        Volume* v = find_volume(c, kv.second);
-        if (v && v->active) act.insert(act.end(), kv.first.begin(), kv.first.end());
-    }
-    for (auto& e : res) {
-        cellv.insert(cellv.end(), e.first.begin(), e.first.end());
-        cntv.push_back(e.second);
-    }
-    const int n_act = (int)act.size() / 3;
-    std::vector<int32_t> out(3 * std::max(1, p->n_max)), add(3 * (n_act + (int)res.size() + 1)),
-        rem(3 * (n_act + (int)res.size() + 1));
-    int32_t n_out = 0, n_add = 0, n_rem = 0;
-    CHECK_ST(mvf_placement_policy(act.data(), n_act, cellv.data(), cntv.data(), (int32_t)res.size(), p->n_max,
-                                  p->beta, out.data(), &n_out, add.data(), &n_add, rem.data(), &n_rem));
-    for (int i = 0; i < n_rem && r->n_removed < 64; ++i) {
-        std::vector<int> k = { rem[3 * i], rem[3 * i + 1], rem[3 * i + 2] };
-        const int id = placed[k];
-        CHECK_ST(mvf_volume_evict(c, id, MVF_EVICT_SWAP_OUT));
-        r->removed[r->n_removed++] = id;
-    }
-    for (int i = 0; i < n_add && r->n_added < 64; ++i) {
-        std::vector<int> k = { add[3 * i], add[3 * i + 1], add[3 * i + 2] };
-        int id;
-        auto it = placed.find(k);
-        if (it != placed.end() && find_volume(c, it->second)) {
-            id = it->second;  // seen before: state kept on the host
-        } else {
-            mvf_volume_desc d{};
-            d.grid_id = p->grid_id;
-            for (int a = 0; a < 3; ++a) {
-                d.offset[a] = k[a] * (p->d_v - 2);
-                d.dims[a] = p->d_v;
-            }
-            d.stream_id = sid;
-            CHECK_ST(mvf_volume_create(c, &d, &id));
-            placed[k] = id;
+    // live volumes of the classes already updated this frame: their
+    // endpoints are not counted for the later classes
+    std::vector<int32_t> boxes;
+    std::set<std::vector<int>> cells_seen;
+    for (int ci = 0; ci < p->n_classes; ++ci) {
+        const int d_v = p->classes[ci].d_v;
+        std::vector<std::pair<std::vector<int>, int>> res;
+        CHECK_ST(placement_count_impl(c, f, T_wc, K, c->grids[p->grid_id], d_v, boxes, &res, s));
+        for (auto& e : res) cells_seen.insert({d_v, e.first[0], e.first[1], e.first[2]});
+        std::vector<int32_t> act, cellv, cntv;
+        for (auto& kv : placed) {
+            if (kv.first[0] != d_v) continue;
+            Volume* v = find_volume(c, kv.second);
+            if (v && v->active) act.insert(act.end(), kv.first.begin() + 1, kv.first.end());
         }
-        CHECK_ST(mvf_volume_place(c, id));
-        r->added[r->n_added++] = id;
+        for (auto& e : res) {
+            cellv.insert(cellv.end(), e.first.begin(), e.first.end());
+            cntv.push_back(e.second);
+        }
+        const int n_act = (int)act.size() / 3;
+        const int quota = p->classes[ci].quota;
+        std::vector<int32_t> out(3 * std::max(1, std::max(quota, n_act))), add(3 * (n_act + (int)res.size() + 1)),
+            rem(3 * (n_act + (int)res.size() + 1));
+        int32_t n_out = 0, n_add = 0, n_rem = 0;
+        CHECK_ST(mvf_placement_policy(act.data(), n_act, cellv.data(), cntv.data(), (int32_t)res.size(), quota,
+                                      p->beta, out.data(), &n_out, add.data(), &n_add, rem.data(), &n_rem));
+        for (int i = 0; i < n_rem; ++i) {
+            const std::vector<int> k = { d_v, rem[3 * i], rem[3 * i + 1], rem[3 * i + 2] };
+            const int id = placed[k];
+            CHECK_ST(mvf_volume_evict(c, id, MVF_EVICT_SWAP_OUT));
+            if (r->n_removed < 64) r->removed[r->n_removed++] = id;
+        }
+        for (int i = 0; i < n_add; ++i) {
+            const std::vector<int> k = { d_v, add[3 * i], add[3 * i + 1], add[3 * i + 2] };
+            int id;
+            auto it = placed.find(k);
+            if (it != placed.end() && find_volume(c, it->second)) {
+                id = it->second;  // seen before: state kept on the host
+            } else {
+                mvf_volume_desc d{};
+                d.grid_id = p->grid_id;
+                for (int a = 0; a < 3; ++a) {
+                    d.offset[a] = k[1 + a] * (d_v - 2);
+                    d.dims[a] = d_v;
+                }
+                d.stream_id = sid;
+                CHECK_ST(mvf_volume_create(c, &d, &id));
+                placed[k] = id;
+            }
+            CHECK_ST(mvf_volume_place(c, id));
+            if (r->n_added < 64) r->added[r->n_added++] = id;
+        }
+        for (int i = 0; i < n_out; ++i) {
+            const int32_t hb[6] = { out[3 * i] * (d_v - 2), out[3 * i + 1] * (d_v - 2), out[3 * i + 2] * (d_v - 2),
+                                    d_v, d_v, d_v };
+            boxes.insert(boxes.end(), hb, hb + 6);
+        }
     }
+    r->n_cells = (int32_t)cells_seen.size();
     return mark_tail(c, s);
+}
+
+mvf_status mvf_placement_update(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
+                                const mvf_intrinsics* K, const mvf_placement_params* p, mvf_placement_result* r,
+                                void* stream)
+{
+    if (!c || !p || !r) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    if (p->n_max < 0 || p->n_max > 64) return set_error(MVF_ERR_INVALID_ARG, "n_max must be in [0, 64]");
+    mvf_placement_class_params q{};
+    q.grid_id = p->grid_id;
+    q.n_classes = 1;
+    q.classes[0].d_v = p->d_v;
+    q.classes[0].quota = p->n_max;
+    q.beta = p->beta;
+    return mvf_placement_update_classes(c, sid, f, T_wc, K, &q, r, stream);
 }
 
 // ---- differentiable raycast --------------------------------------------------------

@@ -61,3 +61,43 @@ def test_corridor_placement_sequence(mvf):
             assert sorted(cell_of[v] for v in added) == sorted(a_o)
             assert sorted(cell_of[v] for v in removed) == sorted(r_o)
         assert len(cell_of) > n_max  # the walk displaced volumes
+
+
+def test_corridor_class_placement_sequence(mvf):
+    """The corridor walk with volumes of three sizes (512^3, 384^3 and 256^3
+    at 2.93 mm: sides 1.5, 1.125 and 0.75 m; at most 4, 6 and 6 live, taken
+    in that rank order): after every step the live (size, cell) set, the
+    added and the removed volumes equal the oracle's class rule on the
+    oracle's endpoints."""
+    seq = S.corridor_sequence(seed=3, n_frames=2000)
+    s = 0.00293
+    classes = [(512, 4), (384, 6), (256, 6)]
+    beta = 1.5
+    og = O.OGrid((0.0, -1.0, 0.0), s)
+    K = seq.K.as_array()
+    H = {d: [] for d, _ in classes}
+    log("class placement sequence corridor")
+    with mvf.Context() as ctx:
+        gid = ctx.grid(og.origin, s)
+        key_of = {}
+        n_disp = 0
+        idx = list(range(0, 2000, 40))
+        for i, (d, _) in zip(idx, seq.frames(idx, threads=16)):
+            added, removed, ncells = ctx.placement_update_classes(t(d), seq.poses[i], K, gid, classes, beta)
+            g, cells = O.placement_endpoints(d, K, seq.poses[i], og, [c for c, _ in classes])
+            H, a_o, r_o = O.placement_policy_classes(H, g, cells, classes, beta)
+            for vid in added:
+                dv = ctx.dims(vid)[0]
+                assert ctx.dims(vid) == (dv, dv, dv)
+                key_of[vid] = (dv, tuple(int(x) // (dv - 2) for x in ctx.offset(vid)))
+            live = sorted(key_of[v] for v in key_of if ctx.query(v)[2])
+            expect = sorted((dv, k) for dv in H for k in H[dv])
+            assert live == expect, (i, live, expect)
+            assert sorted(key_of[v] for v in added) == sorted((dv, k) for dv in a_o for k in a_o[dv])
+            assert sorted(key_of[v] for v in removed) == sorted((dv, k) for dv in r_o for k in r_o[dv])
+            n_disp += len(removed)
+            for dv, q in classes:
+                assert len(H[dv]) <= q
+        # every class is used and the walk displaced volumes of each size
+        assert {k[0] for k in key_of.values()} == {512, 384, 256}
+        assert n_disp > 0

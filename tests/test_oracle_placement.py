@@ -81,3 +81,78 @@ def test_endpoints_fall_in_their_cells():
     assert rel.min() > -1e-5 and rel.max() < 1 + 1e-5
     counts = O.placement_counts(d, K, T, grid, d_v)
     assert sum(counts.values()) == w * h and len(counts) >= 4
+
+
+# -- volumes of several sizes (Dynamic Mapping for SLAM: f chooses the
+# volume parameters, here the size by count rank) --------------------------
+
+CLASS_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "placement_class_cases.json")
+
+
+def _class_cases():
+    with open(CLASS_GOLDEN) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _class_cases(), ids=lambda c: c["name"])
+def test_class_policy_golden(case):
+    g, cells = [], {d: [] for d, _ in case["classes"]}
+    for gx, n in case["endpoints"]:
+        for _ in range(n):
+            g.append((gx, 0, 0))
+            for d in cells:
+                cells[d].append((gx // (d - 2), 0, 0))
+    active = {int(d): [tuple(k) for k in v] for d, v in case["active"].items()}
+    H, added, removed = O.placement_policy_classes(active, np.array(g).reshape(-1, 3),
+                                                   {d: np.array(v).reshape(-1, 3) for d, v in cells.items()},
+                                                   [tuple(c) for c in case["classes"]], case["beta"])
+    for d, quota in case["classes"]:
+        key = str(d)
+        assert sorted(H[d]) == sorted(tuple(k) for k in case["expect_active"][key]), (d, H[d])
+        assert sorted(added[d]) == sorted(tuple(k) for k in case["expect_added"][key]), (d, added[d])
+        assert sorted(removed[d]) == sorted(tuple(k) for k in case["expect_removed"][key]), (d, removed[d])
+        assert len(H[d]) <= quota and len(set(H[d])) == len(H[d])
+
+
+def test_one_class_is_the_single_size_rule():
+    """With one class nothing is excluded: the step equals the single-size
+    rule on the same frame's counts."""
+    seq = S.small_room_sequence()
+    K = seq.K.as_array()
+    grid = O.OGrid((-2.0, -2.0, -2.0), 4.0 / 256)
+    d_v = 34
+    active = []
+    for i in range(6):
+        d, _ = seq.frame(i)
+        counts = O.placement_counts(d, K, seq.poses[i], grid, d_v)
+        H1, a1, r1 = O.placement_policy(active, counts, 5, 1.5)
+        g, cells = O.placement_endpoints(d, K, seq.poses[i], grid, [d_v])
+        H2, a2, r2 = O.placement_policy_classes({d_v: active}, g, cells, [(d_v, 5)], 1.5)
+        assert (H1, a1, r1) == (H2[d_v], a2[d_v], r2[d_v])
+        active = H1
+
+
+def test_endpoint_voxels_match_binary64_geometry():
+    """The voxel g each counted endpoint is assigned to (the side-one
+    lattice) contains the endpoint recomputed in binary64, up to rounding
+    at the faces, and the class cell of an endpoint equals floor(g / (d_v -
+    2)) except for endpoints that rounding puts on the other side of a cell
+    face (a sliver of at most a few ulp)."""
+    seq = S.small_room_sequence()
+    d, _ = seq.frame(4)
+    T = seq.poses[4]
+    K = seq.K.as_array()
+    grid = O.OGrid((-2.0, -2.0, -2.0), 4.0 / 256)
+    g, cells = O.placement_endpoints(d, K, T, grid, [34, 66])
+    h, w = d.shape
+    u, v = np.meshgrid(np.arange(w), np.arange(h))
+    ok = (d > 0) & np.isfinite(d)
+    q = np.stack([d * (u - K[2]) / K[0], d * (v - K[3]) / K[1], d], -1)[ok].astype(np.float64)
+    T32 = np.asarray(T, np.float32).astype(np.float64)
+    e = q @ T32[:, :3].T + T32[:, 3]
+    rel = (e - np.asarray(grid.arr4()[:3], np.float64)) / np.float64(np.float32(grid.voxel_size)) - g
+    assert len(g) == ok.sum()
+    assert rel.min() > -1e-3 and rel.max() < 1 + 1e-3
+    for dv, kc in cells.items():
+        same = np.all(np.floor_divide(g, dv - 2) == kc, axis=1)
+        assert same.mean() > 0.999, (dv, same.mean())
