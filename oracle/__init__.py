@@ -404,3 +404,109 @@ def placement_policy_classes(active: Dict[int, Sequence[Tuple[int, int, int]]], 
             lo = np.asarray(k, np.int64) * (d_v - 2)
             covered |= np.all((g >= lo) & (g < lo + d_v), axis=1)
     return new_active, added, removed
+
+
+# --------------------------------------------------------------------------
+# Camera tracking (Depth Map Conversion; Camera Tracking: KinectFusion's
+# projective point-to-plane ICP)
+# --------------------------------------------------------------------------
+
+ICP_LEVELS = 3
+ICP_ITERS = (10, 5, 4)        # iterations at levels 0 (full), 1, 2; run coarse to fine
+ICP_EPS_D = 0.1               # metres
+ICP_COS_THETA = float(np.float32(np.cos(np.radians(20.0))))
+ICP_TAU = 0.03                # pyramid: depths within this of the block's first valid one
+
+
+def level_K(K, level: int) -> np.ndarray:
+    """Intrinsics of pyramid level l: f / 2^l, (c + 1/2) / 2^l - 1/2 (binary32)."""
+    K = _f32(K)
+    sc = np.float32(0.5 ** level)
+    h = np.float32(0.5)
+    return _f32([K[0] * sc, K[1] * sc, (K[2] + h) * sc - h, (K[3] + h) * sc - h])
+
+
+def depth_pyramid(depth, levels: int = ICP_LEVELS, tau: float = ICP_TAU) -> List[np.ndarray]:
+    out = [_f32(depth)]
+    for _ in range(1, levels):
+        d = out[-1]
+        h, w = d.shape
+        d2 = np.zeros((h // 2, w // 2), np.float32)
+        lib().orc_depth_down(_p(d), C.c_int(w), C.c_int(h), C.c_float(tau), _p(d2))
+        out.append(d2)
+    return out
+
+
+def vertex_normal(depth, K) -> Tuple[np.ndarray, np.ndarray]:
+    """Vertex and normal maps (h, w, 3) in camera coordinates (NaN: none)."""
+    d = _f32(depth)
+    h, w = d.shape
+    V = np.zeros((h, w, 3), np.float32)
+    N = np.zeros((h, w, 3), np.float32)
+    lib().orc_vertex_normal(_p(d), C.c_int(w), C.c_int(h), _p(_f32(K)), _p(V), _p(N))
+    return V, N
+
+
+def model_down(V, N) -> Tuple[np.ndarray, np.ndarray]:
+    V = _f32(V)
+    N = _f32(N)
+    h, w = V.shape[:2]
+    V2 = np.zeros((h // 2, w // 2, 3), np.float32)
+    N2 = np.zeros((h // 2, w // 2, 3), np.float32)
+    lib().orc_model_down(_p(V), _p(N), C.c_int(w), C.c_int(h), _p(V2), _p(N2))
+    return V2, N2
+
+
+def icp_reduce(V, N, Vm, Nm, K_level, T, Tm, eps_d: float = ICP_EPS_D, cos_theta: float = ICP_COS_THETA):
+    """One association pass: (A 6x6, b 6, inlier count, sum r^2, inlier mask)
+    for the estimate T (rounded to binary32 for the decisions)."""
+    V, N, Vm, Nm = _f32(V), _f32(N), _f32(Vm), _f32(Nm)
+    h, w = V.shape[:2]
+    hm, wm = Vm.shape[:2]
+    sums = np.zeros(29)
+    inl = np.zeros((h, w), np.uint8)
+    lib().orc_icp_reduce(_p(V), _p(N), C.c_int(w), C.c_int(h), _p(Vm), _p(Nm), C.c_int(wm), C.c_int(hm),
+                         _p(_f32(K_level)), _p(_f32(np.asarray(T).reshape(12))),
+                         _p(_f32(np.asarray(Tm).reshape(12))), C.c_float(eps_d), C.c_float(cos_theta),
+                         _p(sums), _p(inl))
+    A = np.zeros((6, 6))
+    k = 0
+    for i in range(6):
+        for j in range(i, 6):
+            A[i, j] = A[j, i] = sums[k]
+            k += 1
+    return A, sums[21:27].copy(), int(sums[27]), float(sums[28]), inl
+
+
+def icp_track(depth, K, Vm0, Nm0, Tm, T_init, iters=ICP_ITERS, eps_d: float = ICP_EPS_D,
+              cos_theta: float = ICP_COS_THETA, tau: float = ICP_TAU):
+    """Pose of the frame `depth` against the model maps (Vm0, Nm0: world
+    vertex and normal maps rendered at pose Tm, full resolution), from the
+    estimate T_init: levels coarse to fine, `iters[l]` Gauss-Newton steps at
+    level l, each solving A xi = -b (binary64) and applying T <- Exp(xi) T.
+    A step with fewer than 6 pairs, or whose A is not positive definite, leaves
+    T unchanged.  Returns (T, per-step list of (level, pairs, sum r^2))."""
+    levels = len(iters)
+    D = depth_pyramid(depth, levels, tau)
+    Vm, Nm = [_f32(Vm0)], [_f32(Nm0)]
+    for _ in range(1, levels):
+        v2, n2 = model_down(Vm[-1], Nm[-1])
+        Vm.append(v2)
+        Nm.append(n2)
+    T = np.asarray(T_init, np.float64).reshape(3, 4).copy()
+    log = []
+    for lvl in reversed(range(levels)):
+        Kl = level_K(K, lvl)
+        V, N = vertex_normal(D[lvl], Kl)
+        for _ in range(iters[lvl]):
+            A, b, n, e, _ = icp_reduce(V, N, Vm[lvl], Nm[lvl], Kl, T, Tm, eps_d, cos_theta)
+            log.append((lvl, n, e))
+            if n < 6:
+                continue
+            try:
+                L = np.linalg.cholesky(A)
+            except np.linalg.LinAlgError:
+                continue
+            xi = -np.linalg.solve(L.T, np.linalg.solve(L, b))
+            T = compose(se3_exp(xi), T)
+    return T, log

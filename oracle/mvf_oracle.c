@@ -663,6 +663,166 @@ int orc_extract(const int32_t dims[3], const int32_t off[3], const float* F,
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Camera tracking (Depth Map Conversion and Camera Tracking sections; the
+ * tracker itself is the projective point-to-plane ICP of KinectFusion that
+ * the paper cites).  Readings of the paper taken here:
+ *  - vertex v(x, y) = K^-1 [x, y, 1]^T D(x, y) for a valid depth (> 0 and
+ *    finite), in camera coordinates; NaN otherwise;
+ *  - normal n(x, y) = (v(x+1, y) - v(x, y)) x (v(x, y+1) - v(x, y)),
+ *    normalised; NaN when one of the three vertices is missing, outside the
+ *    image, or the cross product is zero.  Its sign is not used: the
+ *    compatibility test compares |n . n_model|;
+ *  - a pyramid of depth maps: level l+1 (floor(w/2) x floor(h/2)) holds the
+ *    mean of the valid depths of the 2x2 block whose difference from the
+ *    block's first valid depth (order (0,0), (1,0), (0,1), (1,1)) is at
+ *    most `tau` metres, 0 when none is valid; intrinsics of level l are
+ *    f / 2^l and (c + 1/2) / 2^l - 1/2;
+ *  - the model (the raycast vertex and normal maps of the previous pose,
+ *    world coordinates) at level l+1 takes the sample (2x, 2y) of level l;
+ *  - projective association: the current vertex moved by the estimate,
+ *    v_g = R v + t, is projected into the model's camera with the level's
+ *    intrinsics to the nearest pixel; the pair is used when that pixel is
+ *    in the image and holds a model vertex, |v_g - v_m| <= eps_d and
+ *    |R n . n_m| >= cos_theta;
+ *  - point-to-plane error sum ((v_g - v_m) . n_m)^2, linearised for a left
+ *    perturbation Exp(xi) T, xi = (rho, omega): residual r = n_m . (v_g -
+ *    v_m), Jacobian J = [n_m, v_g x n_m]; the normal equations are
+ *    A = sum J J^T, b = sum J r and the update solves A xi = -b.
+ * Decisions (validity, the pixel, both tests) are binary32 with one rounding
+ * per written operation; J, r and the sums are binary64.
+ * ------------------------------------------------------------------------ */
+static inline int depth_ok(float d) { return d > 0.0f && d <= 3.4e38f; }
+
+/* Level l+1 depth (w2 = w / 2, h2 = h / 2) from level l. */
+int orc_depth_down(const float* D, int w, int h, float tau, float* D2)
+{
+    const int w2 = w / 2, h2 = h / 2;
+    for (int y = 0; y < h2; ++y)
+        for (int x = 0; x < w2; ++x) {
+            const float q[4] = { D[(2 * y) * w + 2 * x], D[(2 * y) * w + 2 * x + 1],
+                                 D[(2 * y + 1) * w + 2 * x], D[(2 * y + 1) * w + 2 * x + 1] };
+            int have = 0;
+            float ref = 0.0f, sum = 0.0f;
+            int n = 0;
+            for (int k = 0; k < 4; ++k) {
+                if (!depth_ok(q[k])) continue;
+                if (!have) { ref = q[k]; have = 1; }
+                if (fabsf(q[k] - ref) <= tau) { sum = sum + q[k]; ++n; }
+            }
+            D2[y * w2 + x] = n ? sum / (float)n : 0.0f;
+        }
+    return 0;
+}
+
+static void vertex32(const float* D, int w, int x, int y, const float K[4], float v[3])
+{
+    const float d = D[y * w + x];
+    if (!depth_ok(d)) { v[0] = v[1] = v[2] = NAN; return; }
+    v[0] = (((float)x - K[2]) / K[0]) * d;
+    v[1] = (((float)y - K[3]) / K[1]) * d;
+    v[2] = d;
+}
+
+/* Vertex and normal maps (w x h x 3, camera frame) of a depth map. */
+int orc_vertex_normal(const float* D, int w, int h, const float K[4], float* V, float* N)
+{
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            float v00[3], v10[3], v01[3];
+            vertex32(D, w, x, y, K, v00);
+            float* vo = V + 3 * ((int64_t)y * w + x);
+            float* no = N + 3 * ((int64_t)y * w + x);
+            vo[0] = v00[0]; vo[1] = v00[1]; vo[2] = v00[2];
+            no[0] = no[1] = no[2] = NAN;
+            if (isnan(v00[2]) || x + 1 >= w || y + 1 >= h) continue;
+            vertex32(D, w, x + 1, y, K, v10);
+            vertex32(D, w, x, y + 1, K, v01);
+            if (isnan(v10[2]) || isnan(v01[2])) continue;
+            const float a[3] = { v10[0] - v00[0], v10[1] - v00[1], v10[2] - v00[2] };
+            const float b[3] = { v01[0] - v00[0], v01[1] - v00[1], v01[2] - v00[2] };
+            const float c[3] = { (a[1] * b[2]) - (a[2] * b[1]), (a[2] * b[0]) - (a[0] * b[2]),
+                                 (a[0] * b[1]) - (a[1] * b[0]) };
+            const float len = sqrtf(((c[0] * c[0]) + (c[1] * c[1])) + (c[2] * c[2]));
+            if (!(len > 0.0f)) continue;
+            no[0] = c[0] / len; no[1] = c[1] / len; no[2] = c[2] / len;
+        }
+    return 0;
+}
+
+/* Model maps of level l+1 from level l: sample (2x, 2y). */
+int orc_model_down(const float* V, const float* N, int w, int h, float* V2, float* N2)
+{
+    const int w2 = w / 2, h2 = h / 2;
+    for (int y = 0; y < h2; ++y)
+        for (int x = 0; x < w2; ++x)
+            for (int a = 0; a < 3; ++a) {
+                V2[3 * ((int64_t)y * w2 + x) + a] = V[3 * ((int64_t)(2 * y) * w + 2 * x) + a];
+                N2[3 * ((int64_t)y * w2 + x) + a] = N[3 * ((int64_t)(2 * y) * w + 2 * x) + a];
+            }
+    return 0;
+}
+
+/* One association + normal-equation pass.  V, N: current maps (w x h,
+ * camera frame); Vm, Nm: model maps (wm x hm, world); Km: the level's
+ * intrinsics (model and current images share them); T: the estimate;
+ * Tm: the model's camera-to-world pose.  sums: A (upper triangle, row by
+ * row, 21), b (6), inlier count, sum r^2.  inlier: per current pixel. */
+int orc_icp_reduce(const float* V, const float* N, int w, int h, const float* Vm, const float* Nm, int wm,
+                   int hm, const float Km[4], const float T[12], const float Tm[12], float eps_d,
+                   float cos_theta, double sums[29], uint8_t* inlier)
+{
+    double acc[29];
+    for (int i = 0; i < 29; ++i) acc[i] = 0.0;
+    const float e2 = eps_d * eps_d;
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            const int64_t p = (int64_t)y * w + x;
+            if (inlier) inlier[p] = 0;
+            const float* v = V + 3 * p;
+            const float* n = N + 3 * p;
+            if (isnan(v[0]) || isnan(v[1]) || isnan(v[2]) || isnan(n[0]) || isnan(n[1]) || isnan(n[2])) continue;
+            float vg[3], ng[3], d[3], q[3];
+            for (int a = 0; a < 3; ++a) {
+                vg[a] = (((T[4 * a] * v[0]) + (T[4 * a + 1] * v[1])) + (T[4 * a + 2] * v[2])) + T[4 * a + 3];
+                ng[a] = ((T[4 * a] * n[0]) + (T[4 * a + 1] * n[1])) + (T[4 * a + 2] * n[2]);
+                d[a] = vg[a] - Tm[4 * a + 3];
+            }
+            for (int a = 0; a < 3; ++a) q[a] = ((Tm[a] * d[0]) + (Tm[4 + a] * d[1])) + (Tm[8 + a] * d[2]);
+            if (!(q[2] > 0.0f)) continue;
+            const float iz = 1.0f / q[2];
+            const float ur = floorf((((Km[0] * q[0]) * iz) + Km[2]) + 0.5f);
+            const float vr = floorf((((Km[1] * q[1]) * iz) + Km[3]) + 0.5f);
+            if (!(ur >= 0.0f && ur <= (float)(wm - 1) && vr >= 0.0f && vr <= (float)(hm - 1))) continue;
+            const int64_t m = (int64_t)vr * wm + (int64_t)ur;
+            const float* vm = Vm + 3 * m;
+            const float* nm = Nm + 3 * m;
+            if (isnan(vm[0]) || isnan(vm[1]) || isnan(vm[2]) || isnan(nm[0]) || isnan(nm[1]) || isnan(nm[2]))
+                continue;
+            const float dv[3] = { vg[0] - vm[0], vg[1] - vm[1], vg[2] - vm[2] };
+            const float dist2 = ((dv[0] * dv[0]) + (dv[1] * dv[1])) + (dv[2] * dv[2]);
+            if (!(dist2 <= e2)) continue;
+            const float dot = ((ng[0] * nm[0]) + (ng[1] * nm[1])) + (ng[2] * nm[2]);
+            if (!(fabsf(dot) >= cos_theta)) continue;
+            if (inlier) inlier[p] = 1;
+            /* binary64 from here */
+            const double g[3] = { vg[0], vg[1], vg[2] };
+            const double nn[3] = { nm[0], nm[1], nm[2] };
+            const double r = nn[0] * (g[0] - (double)vm[0]) + nn[1] * (g[1] - (double)vm[1]) +
+                             nn[2] * (g[2] - (double)vm[2]);
+            const double J[6] = { nn[0], nn[1], nn[2], g[1] * nn[2] - g[2] * nn[1], g[2] * nn[0] - g[0] * nn[2],
+                                  g[0] * nn[1] - g[1] * nn[0] };
+            int k = 0;
+            for (int i = 0; i < 6; ++i)
+                for (int j = i; j < 6; ++j) acc[k++] += J[i] * J[j];
+            for (int i = 0; i < 6; ++i) acc[21 + i] += J[i] * r;
+            acc[27] += 1.0;
+            acc[28] += r * r;
+        }
+    for (int i = 0; i < 29; ++i) sums[i] = acc[i];
+    return 0;
+}
+
 /* Threads the oracle's parallel loops use (for reporting CPU timings). */
 #ifdef _OPENMP
 #include <omp.h>
