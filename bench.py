@@ -33,6 +33,13 @@ Phases (all run by default):
                (512^3, 384^3, 256^3) under an 8 GB budget, through mvf_step
                and through the plain calls
   diffray      pose refinement through the differentiable raycast at 512^3
+  passing      the memory-passing regime: time per frame against the number of
+               512^3 volumes with a device budget of one volume, and resident
+  tracking     the per-frame loop with ICP camera tracking against the last
+               raycast (the 512^3 large room): time per part and pose error
+  table1       surface points of one 512^3 volume vs eight 512^3 volumes over
+               the same 3 m cube: point count and distance to the analytic
+               surface (the paper's resolution and accuracy metrics)
 
 Prints one JSON line.  python bench.py [--steps K] [--warmup W] [--gpus 1]
 [--phases a,b,...] [--no-cpu]
@@ -300,7 +307,8 @@ def phase_diffray(mvf, torch, n_poses=16, n_steps=50):
                 xi = torch.zeros(6, dtype=torch.float64, requires_grad=True)
                 a, b = _events(torch)
                 a.record()
-                depth = DiffRaycast.apply(F, xi, W, ctx, (-1.0, -1.0, -1.0), 2.0 / n, T, K, W_IMG, H_IMG)
+                # F and W stay fixed: generation 1 keeps the library's copy
+                depth = DiffRaycast.apply(F, xi, W, ctx, (-1.0, -1.0, -1.0), 2.0 / n, T, K, W_IMG, H_IMG, 1)
                 b.record()
                 loss = depth_loss(depth, target)
                 c_, d_ = _events(torch)
@@ -467,9 +475,166 @@ def phase_corridor(mvf, torch, n_steps=40, stride=10, classes=CORRIDOR_CLASSES, 
     return res
 
 
+def phase_table1(mvf, torch, n_frames=90):
+    """A synthetic stand-in for the paper's single-volume vs eight-volume
+    comparison: the large room's first n_frames 640x480 frames (device
+    rendered, noisy) fused into one 512^3 volume over the 3 m cube (5.86 mm
+    voxels; its 511 cells span 3 m) and into eight 512^3 volumes of 1.5 m
+    forming the same cube (2.94 mm voxels, neighbours sharing one voxel
+    layer, so every cell lies in exactly one volume).  Surface points of every volume are extracted
+    on the device; resolution = point count, accuracy = distance of each
+    point to the analytic scene surface (mean, median, standard deviation)."""
+    from synth import scenes as S
+    from synth.device_render import DeviceRenderer
+    seq = S.large_room_sequence(seed=2, noise=True)
+    K = seq.K.as_array()
+    dev = torch.device("cuda", 0)
+    rd = DeviceRenderer(seq.scene, seq.K, dev, noise_seed=seq.seed)
+    frames = [rd.frame(seq.poses[i], i) for i in range(n_frames)]
+    res = {"frames": n_frames, "image": [W_IMG, H_IMG]}
+    for name, n_side, s in (("single_512", 1, EXTENT / (N_VOX - 1)), ("eight_512", 2, EXTENT / (2 * N_VOX - 2))):
+        with mvf.Context() as ctx:
+            gid = ctx.grid((-EXTENT / 2,) * 3, s, 4.0, 128)
+            ids = [ctx.volume(gid, (ox * (N_VOX - 1), oy * (N_VOX - 1), oz * (N_VOX - 1)), (N_VOX,) * 3)
+                   for oz in range(n_side) for oy in range(n_side) for ox in range(n_side)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i, (d, c) in enumerate(frames):
+                ctx.integrate(d, c, seq.poses[i], K)
+            torch.cuda.synchronize()
+            t_fuse = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            pts = [ctx.extract(v, with_index=False) for v in ids]
+            torch.cuda.synchronize()
+            t_extract = time.perf_counter() - t0
+            V = np.concatenate([p["V"].cpu().numpy() for p in pts]).astype(np.float64)
+        dist = np.abs(S.scene_sdf(seq.scene, V))
+        res[name] = {"volumes": len(ids), "voxel_mm": 1e3 * s, "vertices": int(V.shape[0]),
+                     "mean_mm": 1e3 * float(dist.mean()), "median_mm": 1e3 * float(np.median(dist)),
+                     "std_mm": 1e3 * float(dist.std()), "fuse_ms_per_frame": 1e3 * t_fuse / n_frames,
+                     "extract_ms": 1e3 * t_extract}
+        log(f"table1 {name}: {V.shape[0]} points, mean {res[name]['mean_mm']:.2f} mm")
+        del pts, V, dist
+    del frames
+    res["vertex_ratio"] = res["eight_512"]["vertices"] / max(1, res["single_512"]["vertices"])
+    return res
+
+
+def phase_passing(mvf, torch, counts=(1, 2, 4, 8, 16), frames=6, warmup=2):
+    """The paper's memory-passing regime (its runtime experiment): N volumes of
+    512^3 (1.5 m, 2.93 mm voxels) in a 4 x 2 x 2 block in front of the camera,
+    all in view, every voxel in front of a far plane and so updated in every
+    frame, through mvf_step with a device budget of one volume (every volume
+    is uploaded, integrated, raycast and downloaded on every frame, in waves
+    of one) and with no budget (all resident).  Time per frame against N."""
+    dev = torch.device("cuda", 0)
+    s = 1.5 / N_VOX
+    T = np.zeros((3, 4))
+    T[:, :3] = np.eye(3)
+    T[:, 3] = [0.0, 0.0, -3.5]
+    K = np.array([525.0, 525.0, 319.5, 239.5], np.float32)
+    depth = torch.full((H_IMG, W_IMG), 8.0, dtype=torch.float32, device=dev)
+    rgb = torch.zeros((H_IMG, W_IMG, 3), dtype=torch.uint8, device=dev)
+    offs = [(ix * N_VOX, iy * N_VOX, iz * N_VOX) for iz in range(2) for iy in range(2) for ix in range(4)]
+    out = {"depth": torch.empty((H_IMG, W_IMG), device=dev),
+           "vertex": torch.empty((H_IMG, W_IMG, 3), device=dev),
+           "normal": torch.empty((H_IMG, W_IMG, 3), device=dev),
+           "hit": torch.empty((H_IMG, W_IMG), dtype=torch.int32, device=dev)}
+    res = {"volume": [N_VOX] * 3, "volume_gb": None, "frames": frames, "path": "mvf_step", "rows": []}
+    for n in counts:
+        row = {"volumes": n}
+        for mode in ("budget_one_volume", "resident"):
+            with mvf.Context(timing=False) as ctx:
+                gid = ctx.grid((-3.0, -1.5, 0.0), s, 4.0, 128)
+                ids = [ctx.volume(gid, o, (N_VOX,) * 3) for o in offs[:n]]
+                vbytes = ctx.query(ids[0])[1]
+                res["volume_gb"] = vbytes / 1e9
+                if mode == "budget_one_volume":
+                    ctx.set_budget(vbytes)
+                for _ in range(warmup):
+                    ctx.step([(0, depth, rgb, T, K)], [out])
+                torch.cuda.synchronize()
+                ctx.reset_stats()
+                t0 = time.perf_counter()
+                for _ in range(frames):
+                    ctx.step([(0, depth, rgb, T, K)], [out])
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                st = ctx.stats()
+            row[mode] = {"ms_per_frame": 1e3 * wall / frames,
+                         "voxel_updates_per_frame": st["voxels_updated"] / frames,
+                         "h2d_gb_per_frame": st["bytes_h2d"] / 1e9 / frames,
+                         "d2h_gb_per_frame": st["bytes_d2h"] / 1e9 / frames,
+                         "swap_gb_per_s": (st["bytes_h2d"] + st["bytes_d2h"]) / 1e9 / wall}
+        log(f"passing {n} volumes: {row['budget_one_volume']['ms_per_frame']:.1f} ms per frame with one "
+            f"volume's budget, {row['resident']['ms_per_frame']:.2f} ms resident")
+        res["rows"].append(row)
+    # least-squares slope of time per frame against N
+    ns = np.array([r["volumes"] for r in res["rows"]], np.float64)
+    for mode in ("budget_one_volume", "resident"):
+        ts = np.array([r[mode]["ms_per_frame"] for r in res["rows"]])
+        res[f"{mode}_ms_per_added_volume"] = float(np.polyfit(ns, ts, 1)[0])
+    return res
+
+
+def phase_tracking(mvf, torch, n_frames=100):
+    """The per-frame loop with tracking (the paper's Fig. 4 order): each new
+    640x480 frame of the large room (device rendered, noisy) is tracked by
+    ICP against the raycast of the previous pose, then fused into the 512^3
+    volume at the tracked pose and raycast there for the next frame.  Reports
+    the time of each part and the tracked trajectory's error against the
+    true poses (frame 0 is fused at its true pose)."""
+    from synth import scenes as S
+    from synth.device_render import DeviceRenderer
+    seq = S.large_room_sequence(seed=2, noise=True)
+    K = seq.K.as_array()
+    dev = torch.device("cuda", 0)
+    rd = DeviceRenderer(seq.scene, seq.K, dev, noise_seed=seq.seed)
+    frames = [rd.frame(seq.poses[i], i) for i in range(n_frames)]
+
+    def outs():
+        return {"depth": torch.empty((H_IMG, W_IMG), device=dev),
+                "vertex": torch.empty((H_IMG, W_IMG, 3), device=dev),
+                "normal": torch.empty((H_IMG, W_IMG, 3), device=dev),
+                "hit": torch.empty((H_IMG, W_IMG), dtype=torch.int32, device=dev)}
+
+    maps = [outs(), outs()]
+    err_t, err_r, t_track, t_rest, pairs = [], [], [], [], []
+    with mvf.Context() as ctx:
+        gid = ctx.grid((-EXTENT / 2,) * 3, EXTENT / N_VOX, 4.0, 128)
+        ctx.volume(gid, (0, 0, 0), (N_VOX,) * 3)
+        T = seq.poses[0]
+        ctx.integrate(frames[0][0], frames[0][1], T, K)
+        ctx.raycast(T, K, W_IMG, H_IMG, out=maps[0])
+        torch.cuda.synchronize()
+        for i in range(1, n_frames):
+            d, c = frames[i]
+            t0 = time.perf_counter()
+            T_new, st = ctx.track(d, K, maps[(i - 1) % 2], T, T)
+            t1 = time.perf_counter()
+            ctx.integrate(d, c, T_new, K)
+            ctx.raycast(T_new, K, W_IMG, H_IMG, out=maps[i % 2])
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            T = T_new
+            t_track.append(1e3 * (t1 - t0))
+            t_rest.append(1e3 * (t2 - t1))
+            pairs.append(st["pairs"][-1])
+            Tg = seq.poses[i]
+            err_t.append(1e3 * float(np.linalg.norm(T[:, 3] - Tg[:, 3])))
+            R = T[:, :3].T @ Tg[:, :3]
+            err_r.append(float(np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1)))))
+    return {"frames": n_frames, "iters": [10, 5, 4], "track_ms_median": float(np.median(t_track)),
+            "integrate_raycast_ms_median": float(np.median(t_rest)),
+            "trans_err_mm_mean": float(np.mean(err_t)), "trans_err_mm_max": float(np.max(err_t)),
+            "trans_err_mm_last": err_t[-1], "rot_err_deg_mean": float(np.mean(err_r)),
+            "rot_err_deg_max": float(np.max(err_r)), "pairs_median": float(np.median(pairs))}
+
+
 EXTRA_PHASES = {"probe": phase_probe, "small": phase_small, "multi": phase_multi, "corridor": phase_corridor,
-                "diffray": phase_diffray}
-DEFAULT_PHASES = "single,single_step,tiled,batched,probe,small,multi,corridor,diffray"
+                "diffray": phase_diffray, "table1": phase_table1, "passing": phase_passing,
+                "tracking": phase_tracking}
+DEFAULT_PHASES = "single,single_step,tiled,batched,probe,small,multi,corridor,diffray,table1,passing,tracking"
 
 
 def cpu_model() -> str:
@@ -569,6 +734,12 @@ def config_summary(phases):
         out["diffray_512"] = g("diffray")
     if g("probe"):
         out["roofline_probe_512"] = g("probe")
+    if g("table1"):
+        out["surface_points_single_vs_eight"] = g("table1")
+    if g("passing"):
+        out["memory_passing_sweep"] = g("passing")
+    if g("tracking"):
+        out["tracked_large_room_512"] = g("tracking")
     return out
 
 

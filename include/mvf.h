@@ -189,6 +189,26 @@ mvf_status mvf_volume_write(mvf_ctx* ctx, int32_t vol_id, const float* F, const 
  * a corner F <= 0, Raycasting section); a diagnostic for tests.  Either
  * pointer may be NULL. */
 mvf_status mvf_volume_brick_summary(mvf_ctx* ctx, int32_t vol_id, uint8_t* flag, uint8_t* dist);
+/* Surface points of a volume (Input and Output: the output vertex set V
+ * with normals N, at most one vertex per voxel; Metrics: a voxel that the
+ * surface crosses gets a vertex; Insertion and Removal: the point cloud of a
+ * removed volume is downloaded).  Voxel g gives a vertex when its cell
+ * [g, g+1]^3 lies in the volume with all 8 corners observed (W > 0) and F
+ * changes sign inside the band (|F| < 1; one end > 0, the other <= 0)
+ * along one of the edges +x, +y, +z leaving g: the first such edge in that
+ * order holds the vertex, at the linear zero crossing, with the normalised
+ * gradient of the cell's trilinear TSDF there as its normal (pointing into
+ * observed free space).
+ * V, N: device float32 buffers of cap x 3 (world metres; unit normals).
+ * G: device int32 cap x 3 global voxel indices of the emitting voxels, or
+ * NULL.  Points are written in brick order (8^3 bricks, z-fastest brick
+ * numbering; inside a brick z-slice by z-slice, x fastest), a fixed order.
+ * *n_total (host) receives the number of points; min(n_total, cap) are
+ * written (cap = 0 only counts, and V, N may then be NULL).  The volume is
+ * made device-resident first (under the budget, like integration).  Runs
+ * on `stream` and synchronises it.  A never-observed volume gives 0. */
+mvf_status mvf_volume_extract(mvf_ctx* ctx, int32_t vol_id, float* V, float* N, int32_t* G,
+                              int64_t cap, int64_t* n_total, void* stream);
 /* The descriptor a volume was created with (also for volumes the
  * placement step created). */
 mvf_status mvf_volume_describe(mvf_ctx* ctx, int32_t vol_id, mvf_volume_desc* out);
@@ -338,6 +358,30 @@ mvf_status mvf_placement_update_classes(mvf_ctx* ctx, int32_t stream_id, const m
                                         const float T_wc[12], const mvf_intrinsics* K,
                                         const mvf_placement_class_params* p, mvf_placement_result* r,
                                         void* stream);
+/* User-defined insertion f (Dynamic Volume Allocation, Input and Output: f
+ * and g may be any functions of the frames and the live volumes; Dynamic
+ * Mapping for SLAM, e.g. a higher resolution where an application wants
+ * it).  For each class in order the library counts the endpoints on the
+ * device exactly as mvf_placement_update_classes does (excluding those held
+ * by live volumes of the earlier classes), then calls fn on the host with:
+ * the class index and d_v; the class's live cells (n_live x 3 ints); this
+ * frame's (cell, count) pairs (n_cells); the class quota.  fn writes the
+ * class's live cells after the update (at most quota, no cell twice) to
+ * keep (3 ints each, room for quota cells) and their number to *n_keep, and
+ * returns 0 (non-zero aborts with MVF_ERR_STATE; cells already placed or
+ * removed for earlier classes stay so).  The removal g follows: live cells
+ * not kept are evicted and swapped out; kept cells not live are placed
+ * (reusing the volume a cell had before).  beta is not used.  Other errors
+ * as mvf_placement_update_classes; MVF_ERR_INVALID_ARG when fn keeps too
+ * many cells, one twice, or one whose offset k (d_v - 2) lies beyond 2^22.
+ * The arrays passed to fn are valid during the call only. */
+typedef int32_t (*mvf_placement_fn)(void* user, int32_t class_index, int32_t d_v, const int32_t* live,
+                                    int32_t n_live, const int32_t* cells, const int32_t* counts,
+                                    int32_t n_cells, int32_t quota, int32_t* keep, int32_t* n_keep);
+mvf_status mvf_placement_update_custom(mvf_ctx* ctx, int32_t stream_id, const mvf_frame* frame,
+                                       const float T_wc[12], const mvf_intrinsics* K,
+                                       const mvf_placement_class_params* p, mvf_placement_fn fn,
+                                       void* user, mvf_placement_result* r, void* stream);
 /* The endpoint counts alone: up to max_cells (cell xyz, count) tuples written
  * to host `cells` (3 ints) and `counts`; *n_cells = number of distinct cells.
  * Synchronises on `stream`. */
@@ -355,6 +399,64 @@ mvf_status mvf_placement_policy(const int32_t* active, int32_t n_active, const i
                                 int32_t* added, int32_t* n_added, int32_t* removed,
                                 int32_t* n_removed);
 
+/* ---- camera tracking (Depth Map Conversion; Camera Tracking) ------------ */
+
+/* The model the frame is tracked against: the vertex and normal maps of
+ * the last raycast (as written by mvf_raycast / mvf_step: world frame,
+ * NaN where no surface), device float32 height x width x 3 each, and the
+ * camera-to-world pose they were rendered from. */
+typedef struct {
+    const float* vertex;
+    const float* normal;
+    int32_t width, height;
+    float T_wc[12];
+} mvf_track_model;
+
+typedef struct {
+    int32_t levels;     /* pyramid levels, 1..3 */
+    int32_t iters[3];   /* Gauss-Newton steps at levels 0 (full), 1, 2; run coarse to fine; <= 64 in all */
+    float eps_d;        /* association distance, metres (> 0) */
+    float cos_theta;    /* association normal test |n . n_model| >= cos_theta, in [0, 1] */
+    float tau;          /* pyramid: depths within tau metres of the 2x2 block's first valid one */
+    int32_t reserved;
+} mvf_track_params;
+
+typedef struct {
+    int32_t steps;          /* Gauss-Newton steps run */
+    int32_t pairs[64];      /* per step: associated pairs */
+    double sq_err[64];      /* per step: sum of squared point-to-plane residuals (m^2) */
+} mvf_track_stats;
+
+/* Depth Map Conversion alone: the vertex map v = K^-1 [x y 1]^T D and the
+ * normal map (v(x+1, y) - v(x, y)) x (v(x, y+1) - v(x, y)), normalised, of
+ * pyramid level `level` (0..2; the pyramid as in mvf_track, with tau), in
+ * camera coordinates, NaN where undefined: device float32 V and N of
+ * (height >> level) x (width >> level) x 3 each.  Runs on `stream` (it
+ * synchronises it when level > 0, to free the pyramid). */
+mvf_status mvf_depth_maps(mvf_ctx* ctx, const mvf_frame* frame, const mvf_intrinsics* K, int32_t level,
+                          float tau, float* V, float* N, void* stream);
+/* Pose of a depth frame by projective point-to-plane ICP (Camera Tracking:
+ * the KinectFusion tracker the paper cites), from the estimate T_init
+ * (host, row-major 3x4 camera-to-world, binary64) to T_out.
+ * Depth map conversion: vertex v = K^-1 [x y 1]^T D, normal n = (v(x+1, y)
+ * - v(x, y)) x (v(x, y+1) - v(x, y)) normalised; a pyramid of `levels`
+ * depth maps, level l+1 the mean of each 2x2 block's valid depths within
+ * tau of its first valid one, with intrinsics f / 2^l, (c + 1/2) / 2^l -
+ * 1/2; the model maps of level l+1 take the sample (2x, 2y) of level l.
+ * Each step associates every pixel with a valid vertex and normal: v_g =
+ * T v is projected into the model's camera to the nearest pixel; the pair
+ * counts when that pixel holds a model vertex v_m, |v_g - v_m| <= eps_d and
+ * |R n . n_m| >= cos_theta.  With r = n_m . (v_g - v_m) and J = [n_m,
+ * v_g x n_m] the step solves (sum J J^T) xi = -sum J r (binary64, Cholesky)
+ * and sets T <- Exp(xi) T, xi = (rho, omega); a step with fewer than 6
+ * pairs or a matrix that is not positive definite leaves T unchanged.
+ * Decisions are binary32 (the estimate rounded to binary32), sums binary64.
+ * The model maps must have the frame's size.  Runs on `stream`, all steps
+ * without a host round trip, then synchronises it.  stats may be NULL. */
+mvf_status mvf_track(mvf_ctx* ctx, const mvf_frame* frame, const mvf_intrinsics* K,
+                     const mvf_track_model* model, const double T_init[12], const mvf_track_params* p,
+                     double T_out[12], mvf_track_stats* stats, void* stream);
+
 /* ---- differentiable raycast ------------------------------------------- */
 
 typedef struct {
@@ -364,11 +466,20 @@ typedef struct {
     int32_t offset[3];
     float origin[3];
     float voxel_size;
+    /* 0: F and W may have changed since the last call.  Otherwise the
+     * caller's promise that they are unchanged since the last forward call
+     * with the same pointers, description and generation; bump it after
+     * changing either plane. */
+    uint64_t generation;
 } mvf_dense_tsdf;
 
 /* Raycast depth of one dense volume (same rules as mvf_raycast) and a
  * per-pixel record of the crossing (k of the second sample, -1 = none),
- * device int32 H*W. */
+ * device int32 H*W.  The context keeps a brick-layout copy of the volume
+ * (an internal volume with its skip summaries, counted against the device
+ * budget), rebuilt from F and W unless the generation rule above lets the
+ * last one stand; the march is that of mvf_raycast.  dims <= 2048 per axis
+ * and at most 2^30 voxels once padded to 8^3 bricks. */
 mvf_status mvf_diffray_forward(mvf_ctx* ctx, const mvf_dense_tsdf* v, const float T_wc[12],
                                const mvf_intrinsics* K, int32_t width, int32_t height,
                                float* depth, int32_t* record, void* stream);

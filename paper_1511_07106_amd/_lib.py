@@ -98,7 +98,21 @@ class mvf_placement_result(C.Structure):
 
 class mvf_dense_tsdf(C.Structure):
     _fields_ = [("F", C.c_void_p), ("W", C.c_void_p), ("dims", C.c_int32 * 3), ("offset", C.c_int32 * 3),
-                ("origin", C.c_float * 3), ("voxel_size", C.c_float)]
+                ("origin", C.c_float * 3), ("voxel_size", C.c_float), ("generation", C.c_uint64)]
+
+
+class mvf_track_model(C.Structure):
+    _fields_ = [("vertex", C.c_void_p), ("normal", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32),
+                ("T_wc", C.c_float * 12)]
+
+
+class mvf_track_params(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("iters", C.c_int32 * 3), ("eps_d", C.c_float), ("cos_theta", C.c_float),
+                ("tau", C.c_float), ("reserved", C.c_int32)]
+
+
+class mvf_track_stats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("pairs", C.c_int32 * 64), ("sq_err", C.c_double * 64)]
 
 
 P = C.c_void_p
@@ -106,6 +120,10 @@ I32 = C.c_int32
 PI32 = C.POINTER(C.c_int32)
 PF = C.POINTER(C.c_float)
 PD = C.POINTER(C.c_double)
+
+# user-defined placement function (mvf_placement_fn)
+PLACEMENT_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_int32, C.c_int32, PI32, C.c_int32, PI32, PI32, C.c_int32,
+                           C.c_int32, PI32, PI32)
 
 # name -> (argtypes); every function returns mvf_status (int32) unless listed
 SIGNATURES = {
@@ -127,6 +145,7 @@ SIGNATURES = {
     "mvf_volume_write": [P, I32, P, P, P],
     "mvf_volume_query": [P, I32, PI32, C.POINTER(C.c_uint64), PI32],
     "mvf_volume_describe": [P, I32, C.POINTER(mvf_volume_desc)],
+    "mvf_volume_extract": [P, I32, P, P, P, C.c_int64, C.POINTER(C.c_int64), P],
     "mvf_integrate": [P, I32, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics), P],
     "mvf_raycast": [P, I32, PF, C.POINTER(mvf_intrinsics), C.POINTER(mvf_raycast_out), P],
     "mvf_step": [P, I32, C.POINTER(mvf_stream_frame), C.POINTER(mvf_raycast_out), P],
@@ -137,6 +156,9 @@ SIGNATURES = {
                              C.POINTER(mvf_placement_params), C.POINTER(mvf_placement_result), P],
     "mvf_placement_update_classes": [P, I32, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics),
                                      C.POINTER(mvf_placement_class_params), C.POINTER(mvf_placement_result), P],
+    "mvf_placement_update_custom": [P, I32, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics),
+                                    C.POINTER(mvf_placement_class_params), PLACEMENT_FN, P,
+                                    C.POINTER(mvf_placement_result), P],
     "mvf_placement_count": [P, C.POINTER(mvf_frame), PF, C.POINTER(mvf_intrinsics), I32, I32, PI32, PI32,
                             I32, PI32, P],
     "mvf_placement_policy": [PI32, I32, PI32, PI32, I32, I32, C.c_float, PI32, PI32, PI32, PI32, PI32, PI32],
@@ -145,6 +167,9 @@ SIGNATURES = {
                              P, P],
     "mvf_diffray_backward_noalloc": [P, C.POINTER(mvf_dense_tsdf), PF, C.POINTER(mvf_intrinsics), I32, I32, P, P,
                                      P, P, P],
+    "mvf_depth_maps": [P, C.POINTER(mvf_frame), C.POINTER(mvf_intrinsics), I32, C.c_float, P, P, P],
+    "mvf_track": [P, C.POINTER(mvf_frame), C.POINTER(mvf_intrinsics), C.POINTER(mvf_track_model), PD,
+                  C.POINTER(mvf_track_params), PD, C.POINTER(mvf_track_stats), P],
     "mvf_pose_retract": [PD, PD, PD],
     "mvf_pose_right_jacobian": [PD, PD],
 }

@@ -175,6 +175,36 @@ class Context:
                                                   dist.ctypes.data_as(C.c_void_p)), "mvf_volume_brick_summary")
         return flag, dist
 
+    def extract(self, vid: int, with_index: bool = True, stream=None):
+        """Surface points of a volume on the device: dict of V, N ((n, 3)
+        float32 tensors, world metres and unit normals) and G ((n, 3) int32
+        global voxel indices, if with_index), in the library's brick order.
+        Counts first, then allocates exactly and emits."""
+        torch = _torch()
+        n = C.c_int64()
+        L.check(self.lib.mvf_volume_extract(self.h, int(vid), None, None, None, 0, C.byref(n), _stream(stream)),
+                "mvf_volume_extract")
+        dev = torch.device("cuda", self.device)
+        k = int(n.value)
+        V = torch.empty((k, 3), dtype=torch.float32, device=dev)
+        N = torch.empty((k, 3), dtype=torch.float32, device=dev)
+        G = torch.empty((k, 3), dtype=torch.int32, device=dev) if with_index else None
+        if k:
+            L.check(self.lib.mvf_volume_extract(self.h, int(vid), C.c_void_p(V.data_ptr()),
+                                                C.c_void_p(N.data_ptr()),
+                                                C.c_void_p(G.data_ptr()) if G is not None else None,
+                                                k, C.byref(n), _stream(stream)), "mvf_volume_extract")
+        out = {"V": V, "N": N, "n": k}
+        if G is not None:
+            out["G"] = G
+        return out
+
+    def export_points(self, vids, with_index: bool = False):
+        """The surface points of each volume in vids (for instance the ids a
+        placement update removed: the paper downloads a removed volume's
+        point cloud), as {id: extract(id)}."""
+        return {int(v): self.extract(int(v), with_index=with_index) for v in vids}
+
     def write_volume(self, vid: int, F=None, W=None, rgba=None) -> None:
         nx, ny, nz = self.dims(vid)
         arrs = []
@@ -310,9 +340,95 @@ class Context:
                 "mvf_placement_update_classes")
         return list(r.added[:r.n_added]), list(r.removed[:r.n_removed]), r.n_cells
 
+    def placement_update_custom(self, depth, T, K, grid_id: int, classes, policy, stream_id: int = 0,
+                                stream=None):
+        """Placement with a user-defined insertion f.  ``classes``: (d_v,
+        quota) in rank order.  ``policy(class_index, d_v, live, counts,
+        quota)`` gets the class's live cells (list of 3-tuples) and this
+        frame's endpoint counts ({cell: count}, counted on the device) and
+        returns the class's live cells after the update (at most quota).
+        Returns (added ids, removed ids, distinct cells)."""
+        f = self._frame(depth, None)
+        p = L.mvf_placement_class_params()
+        p.grid_id = int(grid_id)
+        if not 1 <= len(classes) <= L.MVF_MAX_PLACEMENT_CLASSES:
+            raise ValueError(f"between 1 and {L.MVF_MAX_PLACEMENT_CLASSES} classes")
+        p.n_classes = len(classes)
+        for i, (d_v, quota) in enumerate(classes):
+            p.classes[i].d_v = int(d_v)
+            p.classes[i].quota = int(quota)
+        p.beta = 1.0
+        failure = []
+
+        def trampoline(_user, ci, d_v, live, n_live, cells, counts, n_cells, quota, keep, n_keep):
+            try:
+                lv = [(live[3 * i], live[3 * i + 1], live[3 * i + 2]) for i in range(n_live)]
+                cnt = {(cells[3 * i], cells[3 * i + 1], cells[3 * i + 2]): counts[i] for i in range(n_cells)}
+                out = [tuple(int(x) for x in k) for k in policy(int(ci), int(d_v), lv, cnt, int(quota))]
+                if len(out) > quota:
+                    raise ValueError(f"policy kept {len(out)} cells, quota {quota}")
+                for i, k in enumerate(out):
+                    keep[3 * i], keep[3 * i + 1], keep[3 * i + 2] = k
+                n_keep[0] = len(out)
+                return 0
+            except BaseException as e:  # noqa: BLE001 -- re-raised after the C call returns
+                failure.append(e)
+                return 1
+
+        cb = L.PLACEMENT_FN(trampoline)
+        r = L.mvf_placement_result()
+        st = self.lib.mvf_placement_update_custom(self.h, int(stream_id), C.byref(f), _pose(T), C.byref(_K(K)),
+                                                  C.byref(p), cb, None, C.byref(r), _stream(stream))
+        if failure:
+            raise failure[0]
+        L.check(st, "mvf_placement_update_custom")
+        return list(r.added[:r.n_added]), list(r.removed[:r.n_removed]), r.n_cells
+
+    # -- camera tracking ------------------------------------------------------
+    def depth_maps(self, depth, K, level: int = 0, tau: float = 0.03, stream=None):
+        """Vertex and normal maps ((h >> level, w >> level, 3) float32 tensors,
+        camera frame, NaN where undefined) of a depth frame's pyramid level."""
+        torch = _torch()
+        f = self._frame(depth, None)
+        H, W = depth.shape
+        dev = depth.device
+        V = torch.empty((H >> level, W >> level, 3), dtype=torch.float32, device=dev)
+        N = torch.empty_like(V)
+        L.check(self.lib.mvf_depth_maps(self.h, C.byref(f), C.byref(_K(K)), int(level), float(tau),
+                                        C.c_void_p(V.data_ptr()), C.c_void_p(N.data_ptr()), _stream(stream)),
+                "mvf_depth_maps")
+        return V, N
+
+    def track(self, depth, K, model, T_model, T_init, iters=(10, 5, 4), eps_d: float = 0.1,
+              cos_theta: float = 0.9396926164627075, tau: float = 0.03, stream=None):
+        """Pose of `depth` by projective point-to-plane ICP against `model`
+        (a dict with the previous raycast's "vertex" and "normal" maps, world
+        frame, rendered at T_model), from T_init.  iters: Gauss-Newton steps
+        at levels 0, 1, 2 (its length sets the pyramid depth).  Returns
+        (T (3, 4) float64, {"pairs": [...], "sq_err": [...]} per step)."""
+        torch = _torch()
+        f = self._frame(depth, None)
+        H, W = depth.shape
+        m = L.mvf_track_model()
+        m.vertex = _dev_ptr(model["vertex"], torch.float32, (H, W, 3), "model vertex")
+        m.normal = _dev_ptr(model["normal"], torch.float32, (H, W, 3), "model normal")
+        m.width, m.height = W, H
+        m.T_wc = _pose(T_model)
+        p = L.mvf_track_params()
+        p.levels = len(iters)
+        for i, n in enumerate(iters):
+            p.iters[i] = int(n)
+        p.eps_d, p.cos_theta, p.tau = float(eps_d), float(cos_theta), float(tau)
+        Ti = np.ascontiguousarray(np.asarray(T_init, np.float64).reshape(12))
+        To = np.zeros(12)
+        st = L.mvf_track_stats()
+        L.check(self.lib.mvf_track(self.h, C.byref(f), C.byref(_K(K)), C.byref(m), Ti.ctypes.data_as(L.PD),
+                                   C.byref(p), To.ctypes.data_as(L.PD), C.byref(st), _stream(stream)), "mvf_track")
+        return To.reshape(3, 4), {"pairs": list(st.pairs[:st.steps]), "sq_err": list(st.sq_err[:st.steps])}
+
     # -- differentiable raycast ------------------------------------------------
     @staticmethod
-    def _dense(F, W, origin, voxel_size, offset=(0, 0, 0)) -> L.mvf_dense_tsdf:
+    def _dense(F, W, origin, voxel_size, offset=(0, 0, 0), generation: int = 0) -> L.mvf_dense_tsdf:
         torch = _torch()
         if F.dim() != 3 or W.shape != F.shape:
             raise ValueError("F and W must be (nz, ny, nx) of equal shape")
@@ -320,15 +436,19 @@ class Context:
         return L.mvf_dense_tsdf(_dev_ptr(F, torch.float32, name="F"), _dev_ptr(W, torch.int16, name="W")
                                 if W.dtype == torch.int16 else _dev_ptr(W, torch.uint16, name="W"),
                                 (C.c_int32 * 3)(nx, ny, nz), (C.c_int32 * 3)(*[int(x) for x in offset]),
-                                (C.c_float * 3)(*[float(x) for x in origin]), float(voxel_size))
+                                (C.c_float * 3)(*[float(x) for x in origin]), float(voxel_size), int(generation))
 
     def diffray_forward(self, F, W, origin, voxel_size, T, K, width, height, offset=(0, 0, 0),
-                        stream=None):
+                        stream=None, generation: int = 0):
+        """Depth (H, W) float32 and crossing record (H, W) int32.  generation:
+        0 rebuilds the library's copy of (F, W) on this call; a non-zero value
+        reuses the copy built by the last call with the same tensors and
+        generation (bump it after changing F or W)."""
         torch = _torch()
         dev = F.device
         depth = torch.empty((height, width), dtype=torch.float32, device=dev)
         record = torch.empty((height, width), dtype=torch.int32, device=dev)
-        v = self._dense(F, W, origin, voxel_size, offset)
+        v = self._dense(F, W, origin, voxel_size, offset, generation)
         L.check(self.lib.mvf_diffray_forward(self.h, C.byref(v), _pose(T), C.byref(_K(K)), int(width),
                                              int(height), C.c_void_p(depth.data_ptr()),
                                              C.c_void_p(record.data_ptr()), _stream(stream)),

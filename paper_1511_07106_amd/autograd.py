@@ -9,7 +9,7 @@ from .api import Context, pose_retract, pose_right_jacobian
 
 
 class DiffRaycast(torch.autograd.Function):
-    """depth = DiffRaycast.apply(F, xi, W, ctx, origin, voxel_size, T0, K, width, height)
+    """depth = DiffRaycast.apply(F, xi, W, ctx, origin, voxel_size, T0, K, width, height[, generation])
 
     F: (nz, ny, nx) float32 TSDF on the device (truncation units), W: weights
     of the same shape (uint16/int16; 0 = unobserved), xi: 6-vector (rho,
@@ -17,12 +17,16 @@ class DiffRaycast(torch.autograd.Function):
     dL/dF and dL/dxi: the kernel's gradient g for a right perturbation at T
     is mapped through the right Jacobian of Exp at xi (dL/dxi = J_r(xi)^T g,
     equal to g at xi = 0).  The crossing found by the forward is held fixed.
+    generation (default 0: rebuild every call) lets the forward reuse the
+    library's brick-layout copy of (F, W) while F and W stay unchanged; bump
+    it whenever either changes.
     """
 
     @staticmethod
-    def forward(ctx, F, xi, W, mvf: Context, origin, voxel_size, T0, K, width, height):
+    def forward(ctx, F, xi, W, mvf: Context, origin, voxel_size, T0, K, width, height, generation=0):
         T = pose_retract(T0, xi.detach().double().cpu().numpy())
-        depth, record = mvf.diffray_forward(F.detach(), W, origin, voxel_size, T, K, width, height)
+        depth, record = mvf.diffray_forward(F.detach(), W, origin, voxel_size, T, K, width, height,
+                                            generation=generation)
         ctx.save_for_backward(F, W, record)
         ctx.mvf = mvf
         ctx.params = (origin, voxel_size, T, K)
@@ -44,7 +48,7 @@ class DiffRaycast(torch.autograd.Function):
             gxi = torch.from_numpy(g).to(device=ctx.xi_device, dtype=ctx.xi_dtype)
         else:
             gxi = None
-        return grad_F, gxi, None, None, None, None, None, None, None, None
+        return grad_F, gxi, None, None, None, None, None, None, None, None, None
 
 
 def depth_loss(pred, target, gate: float = 0.05):

@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmvf.so")
 ARCH = os.environ.get("MVF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["mvf_kernels.hip", "mvf_runtime.cpp"]
+SOURCES = ["mvf_kernels.hip", "mvf_track.hip", "mvf_runtime.cpp"]
 # self-test of hardware arithmetic the kernels rely on (GPU tests only)
 SELFTEST_SRC = "mvf_selftest.hip"
 SELFTEST_LIB = os.path.join(PKG, "libmvf_selftest.so")

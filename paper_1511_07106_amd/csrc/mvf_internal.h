@@ -99,6 +99,7 @@ struct DevFrame {
     int32_t* hit;
     float* best_t;           // per-pixel running best (multi-wave raycast)
     int32_t* best_id;
+    int32_t* record;         // per pixel: k of the nearest crossing's second sample, -1 = none; or null
     int32_t out_w, out_h;
     // raycast range bounds per 8x8 output-pixel cell (cells_x * cells_y,
     // row-major), or null: the nearest and farthest camera distance of any
@@ -271,6 +272,12 @@ int launch_ray_bounds_merge(const LaunchHeader* hdr, const DevFrame* frames, con
 int launch_to_canonical(DevVolume v, float* F, uint16_t* W, uint32_t* C, void* stream);
 int launch_from_canonical(DevVolume v, const float* F, const uint16_t* W, const uint32_t* C,
                           void* stream);
+// Surface points of one volume: per-brick counts, their exclusive prefix sum
+// (offsets, nbricks entries; total[0] = the sum) and, when cap > 0, the
+// emission of the first cap points (V, N: 3 floats each; G: 3 ints, or null)
+// in brick order.  counts: nbricks entries.
+int launch_extract(DevVolume v, uint32_t* counts, unsigned long long* offsets, long long* total, float* V,
+                   float* N, int32_t* G, long long cap, void* stream);
 int launch_fill_u64(unsigned long long* p, int n, unsigned long long value, void* stream);
 int launch_placement_clear(unsigned long long* table, int table_size, void* stream);
 int launch_placement_count(const float* depth, int depth_pitch, int width, int height,
@@ -279,6 +286,43 @@ int launch_placement_count(const float* depth, int depth_pitch, int width, int h
                            unsigned long long* table, int table_size, int* overflow,
                            const int32_t* boxes, int n_boxes, float voxel, void* stream);
 
+// Camera tracking (mvf_track.hip).  The pose estimate and the statistics of
+// every Gauss-Newton step live in device memory.
+constexpr int kTrackSums = 29;          // A (21, upper triangle), b (6), pairs, sum r^2
+constexpr int kTrackThreads = 256;
+constexpr int kTrackPixPerThread = 4;
+constexpr int kTrackMaxSteps = 64;
+
+struct TrackState {
+    double T[12];        // estimate, camera-to-world, row-major 3x4
+    float T32[12];       // its binary32 rounding (the association reads it)
+    int32_t steps;
+    int32_t pairs[kTrackMaxSteps];
+    double sq_err[kTrackMaxSteps];
+};
+
+struct TrackLaunch {
+    const float* V;      // current level: vertex and normal maps, w x h x 3, camera frame
+    const float* N;
+    int32_t w, h;
+    const float* Vm;     // model level: world maps of the same size
+    const float* Nm;
+    float fx, fy, cx, cy;
+    float Tm[12];        // the model's camera-to-world pose
+    float eps_d, cos_theta;
+    TrackState* state;
+    double* partials;    // track_blocks(w, h) x kTrackSums
+    uint8_t* inlier;     // per current pixel, or null
+};
+
+int launch_track_down(const float* D, int pitch, int w, int h, float tau, float* D2, void* stream);
+int launch_track_vn(const float* D, int pitch, int w, int h, const float K[4], float* V, float* N, void* stream);
+int launch_track_model_down(const float* V, const float* N, int w, int h, float* V2, float* N2, void* stream);
+int track_blocks(int w, int h);
+// Association + reduction, then the solve and update of step `step`.
+int launch_icp_step(const TrackLaunch& L, TrackState* state, int step, void* stream);
+int launch_track_init(TrackState* state, void* stream);
+
 struct DiffVolume {
     const float* F;
     const uint16_t* W;
@@ -286,19 +330,7 @@ struct DiffVolume {
     int32_t off[3];
     float o[3];
     float s, inv_s;
-    // skip summary over 8^3 bricks of the dense volume (x-fastest brick
-    // order), or null: Chebyshev distance in bricks (cap kDistCap) to the
-    // nearest brick holding the base voxel of a cell with an observed corner
-    // F <= 2^-100
-    const uint8_t* dist;
-    int32_t bd[3];
 };
-// Skip summary of a dense volume: work planes of 4 * nbricks bytes, result
-// in dist (nbricks bytes).
-int launch_dense_summary(const DiffVolume& v, uint8_t* work, uint8_t* dist, void* stream);
-int launch_diffray_forward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy,
-                           int width, int height, RayParams rp, float* depth, int32_t* record,
-                           void* stream);
 int launch_diffray_backward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy,
                             int width, int height, RayParams rp, const float* grad_depth,
                             const int32_t* record, float* grad_F, double* partials,

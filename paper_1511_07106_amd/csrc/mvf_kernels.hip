@@ -1350,6 +1350,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
     float best_t = pinf();
     int best_id = 0x7fffffff;
     int best_vol = -1;
+    int best_k = -1;
     int best_cell[3] = {0, 0, 0};
     if (!H.first_wave) {
         const int prev = Fr.best_id[p];
@@ -1368,6 +1369,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
         if (found) {
             best_t = ts;
             best_id = V.id;
+            best_k = ks;
             best_vol = cptr(L.lists)[li];
             best_cell[0] = cell[0]; best_cell[1] = cell[1]; best_cell[2] = cell[2];
         }
@@ -1383,6 +1385,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
         if (Fr.vertex) { Fr.vertex[3 * p] = x[0]; Fr.vertex[3 * p + 1] = x[1]; Fr.vertex[3 * p + 2] = x[2]; }
         if (Fr.normal) { Fr.normal[3 * p] = n[0]; Fr.normal[3 * p + 1] = n[1]; Fr.normal[3 * p + 2] = n[2]; }
         if (Fr.hit) Fr.hit[p] = V.id;
+        if (Fr.record) Fr.record[p] = best_k;
         if (Fr.best_t) { Fr.best_t[p] = best_t; Fr.best_id[p] = best_id; }
     } else if (H.first_wave) {
         const float qn = qnan();
@@ -1390,6 +1393,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
         if (Fr.vertex) { Fr.vertex[3 * p] = qn; Fr.vertex[3 * p + 1] = qn; Fr.vertex[3 * p + 2] = qn; }
         if (Fr.normal) { Fr.normal[3 * p] = qn; Fr.normal[3 * p + 1] = qn; Fr.normal[3 * p + 2] = qn; }
         if (Fr.hit) Fr.hit[p] = -1;
+        if (Fr.record) Fr.record[p] = -1;
         if (Fr.best_t) { Fr.best_t[p] = pinf(); Fr.best_id[p] = -1; }
     }
 }
@@ -1971,6 +1975,180 @@ int launch_placement_count(const float* depth, int depth_pitch, int width, int h
 }
 
 // ---------------------------------------------------------------------------
+// Surface points (Input and Output: the vertex set V with normals N, at most
+// one vertex per voxel; Metrics: a voxel the surface crosses gets a vertex).
+// Voxel g emits a vertex when its cell [g, g + 1]^3 lies in the volume, all
+// 8 corners are observed (not NaN), and F changes sign (one end > 0, the
+// other <= 0) inside the band (|F| < 1) along one of the edges +x, +y, +z
+// leaving g; the first such edge in that order holds the vertex, at the
+// linear zero crossing, and the normal is the normalised gradient of the
+// cell's trilinear interpolant there.  A cell whose base voxel lies in a
+// sub-block with a clear cell-mask bit has no corner F <= 2^-100, hence no
+// sign change: such z-slice pairs and bricks are skipped.
+//
+// Three launches: per-brick counts (one wavefront per brick), an exclusive
+// prefix sum over the bricks, and the emission, which writes brick by brick
+// (inside a brick z-slice by z-slice, x fastest), so the order is fixed.
+// ---------------------------------------------------------------------------
+struct SurfVoxel {
+    bool emit;
+    int axis;
+    float c[8];   // corner (x + (k & 1), y + (k >> 1 & 1), z + (k >> 2))
+};
+
+static __device__ __forceinline__ void surf_voxel(const DevVolume& v, GPTR(const float) F, int gx, int gy, int gz,
+                                                  SurfVoxel& S)
+{
+    S.emit = false;
+    S.axis = -1;
+    if (gx + 1 >= v.dims[0] || gy + 1 >= v.dims[1] || gz + 1 >= v.dims[2]) return;
+    bool observed = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int x = gx + (k & 1), y = gy + ((k >> 1) & 1), z = gz + (k >> 2);
+        const size_t o = brick_index(v.bd, x >> 3, y >> 3, z >> 3) * kBrickVox +
+                         (size_t)(((z & 7) << 6) | ((y & 7) << 3) | (x & 7));
+        S.c[k] = F[o];
+        observed &= !__builtin_isnan(S.c[k]);
+    }
+    if (!observed) return;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float f0 = S.c[0], f1 = S.c[1 << a];
+        const bool in_band = fabsf(f0) < 1.0f && fabsf(f1) < 1.0f;
+        const bool change = (f0 > 0.0f && f1 <= 0.0f) || (f0 <= 0.0f && f1 > 0.0f);
+        if (S.axis < 0 && in_band && change) S.axis = a;
+    }
+    S.emit = S.axis >= 0;
+}
+
+// Bits of the cell mask for the two z-slices 2 zp and 2 zp + 1 of a brick.
+static __device__ __forceinline__ uint32_t cmask_pair(uint64_t cm, int zp)
+{
+    return (uint32_t)((cm >> (16 * zp)) & 0xffffu);
+}
+
+__global__ __launch_bounds__(256) void mvf_extract_count_kernel(DevVolume v, size_t nbricks, uint32_t* counts)
+{
+    const int lane = threadIdx.x & 63;
+    const int lx = lane & 7, ly = lane >> 3;
+    GPTR(const float) F = gptr((const float*)v.F);
+    const size_t waves = (size_t)gridDim.x * (blockDim.x >> 6);
+    for (size_t b = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nbricks; b += waves) {
+        const uint64_t cm = v.cmask[b];
+        uint32_t n = 0;
+        if (cm) {
+            const int bz = (int)(b % v.bd[2]);
+            const size_t t = b / v.bd[2];
+            const int by = (int)(t % v.bd[1]), bx = (int)(t / v.bd[1]);
+            for (int zp = 0; zp < 4; ++zp) {
+                if (!cmask_pair(cm, zp)) continue;
+                for (int dz = 0; dz < 2; ++dz) {
+                    SurfVoxel S;
+                    surf_voxel(v, F, 8 * bx + lx, 8 * by + ly, 8 * bz + 2 * zp + dz, S);
+                    n += (uint32_t)__popcll(__ballot(S.emit));
+                }
+            }
+        }
+        if (lane == 0) counts[b] = n;
+    }
+}
+
+// Exclusive prefix sum of n counts by one block of 1024 threads (each takes
+// a contiguous run); total[0] = the sum.
+__global__ __launch_bounds__(1024) void mvf_extract_scan_kernel(const uint32_t* counts, size_t n,
+                                                                unsigned long long* offsets,
+                                                                long long* total)
+{
+    __shared__ unsigned long long part[1024];
+    const size_t per = (n + 1023) / 1024;
+    const size_t lo = min(n, (size_t)threadIdx.x * per), hi = min(n, lo + per);
+    unsigned long long s = 0;
+    for (size_t i = lo; i < hi; ++i) s += counts[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const unsigned long long add = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0ull;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    unsigned long long run = part[threadIdx.x] - s;
+    for (size_t i = lo; i < hi; ++i) {
+        offsets[i] = run;
+        run += counts[i];
+    }
+    if (threadIdx.x == 1023) total[0] = (long long)part[1023];
+}
+
+__global__ __launch_bounds__(256) void mvf_extract_emit_kernel(DevVolume v, size_t nbricks,
+                                                               const unsigned long long* offsets, float* V, float* N,
+                                                               int32_t* G, long long cap)
+{
+    const int lane = threadIdx.x & 63;
+    const int lx = lane & 7, ly = lane >> 3;
+    GPTR(const float) F = gptr((const float*)v.F);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const size_t waves = (size_t)gridDim.x * (blockDim.x >> 6);
+    for (size_t b = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nbricks; b += waves) {
+        const uint64_t cm = v.cmask[b];
+        if (!cm) continue;
+        unsigned long long base = offsets[b];
+        if ((long long)base >= cap) continue;
+        const int bz = (int)(b % v.bd[2]);
+        const size_t t = b / v.bd[2];
+        const int by = (int)(t % v.bd[1]), bx = (int)(t / v.bd[1]);
+        for (int zp = 0; zp < 4; ++zp) {
+            if (!cmask_pair(cm, zp)) continue;
+            for (int dz = 0; dz < 2; ++dz) {
+                const int gx = 8 * bx + lx, gy = 8 * by + ly, gz = 8 * bz + 2 * zp + dz;
+                SurfVoxel S;
+                surf_voxel(v, F, gx, gy, gz, S);
+                const unsigned long long m = __ballot(S.emit);
+                const unsigned long long idx = base + (unsigned long long)__popcll(m & below);
+                base += (unsigned long long)__popcll(m);
+                if (!S.emit || (long long)idx >= cap) continue;
+                const float* c = S.c;
+                const int a = S.axis;
+                const float f0 = c[0], f1 = c[1 << a];
+                float fr[3] = { 0.0f, 0.0f, 0.0f };
+                fr[a] = f0 / (f0 - f1);
+                // gradient of the trilinear interpolant at fr (local units)
+                const float c00 = lerp32(c[0], c[1], fr[0]), c10 = lerp32(c[2], c[3], fr[0]);
+                const float c01 = lerp32(c[4], c[5], fr[0]), c11 = lerp32(c[6], c[7], fr[0]);
+                const float g0 = lerp32(lerp32(c[1] - c[0], c[3] - c[2], fr[1]),
+                                        lerp32(c[5] - c[4], c[7] - c[6], fr[1]), fr[2]);
+                const float g1 = lerp32(c10 - c00, c11 - c01, fr[2]);
+                const float g2 = lerp32(c01, c11, fr[1]) - lerp32(c00, c10, fr[1]);
+                const float len = sqrtf((g0 * g0 + g1 * g1) + g2 * g2);
+                const float inv = len > 0.0f ? 1.0f / len : qnan();
+                const int g[3] = { v.off[0] + gx, v.off[1] + gy, v.off[2] + gz };
+                const float gr[3] = { g0, g1, g2 };
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    V[3 * idx + q] = v.o[q] + v.s * (((float)g[q] + 0.5f) + fr[q]);
+                    N[3 * idx + q] = gr[q] * inv;
+                    if (G) G[3 * idx + q] = g[q];
+                }
+            }
+        }
+    }
+}
+
+int launch_extract(DevVolume v, uint32_t* counts, unsigned long long* offsets, long long* total, float* V,
+                   float* N, int32_t* G, long long cap, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = (size_t)v.bd[0] * v.bd[1] * v.bd[2];
+    const unsigned blocks = (unsigned)std::min<size_t>(65536, (nb + 3) / 4);
+    hipLaunchKernelGGL(mvf_extract_count_kernel, dim3(blocks), dim3(256), 0, s, v, nb, counts);
+    hipLaunchKernelGGL(mvf_extract_scan_kernel, dim3(1), dim3(1024), 0, s, counts, nb, offsets, total);
+    if (cap > 0)
+        hipLaunchKernelGGL(mvf_extract_emit_kernel, dim3(blocks), dim3(256), 0, s, v, nb, offsets, V, N, G, cap);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Differentiable raycast on one dense x-fastest volume (F, W).  The forward
 // is the same march (binary32 contract; validity from W), skipping bricks by
 // a summary computed for the call; it records k of the crossing's second
@@ -1980,6 +2158,11 @@ int launch_placement_count(const float* depth, int depth_pitch, int width, int h
 // dL/dxi per block into binary64 partials, summed by a second kernel in a
 // fixed order (deterministic).
 // ---------------------------------------------------------------------------
+static __device__ __forceinline__ double lerp64(double a, double b, double t)
+{
+    return a * (1.0 - t) + b * t;
+}
+
 struct DSample {
     int i[3];
     float f[3];
@@ -2047,203 +2230,6 @@ struct PoseArgs {
     float T[12];
 };
 
-// Skip summary of a dense volume.  Pass 0: per brick, some voxel observed
-// with F <= 2^-100 (one wavefront per brick).  Pass 1: the cell flag, some
-// brick of b + {0,1}^3 flagged (a cell with base voxel in b has its corners
-// there).  Passes 2-4: capped Chebyshev distance along x, y, z.
-__global__ __launch_bounds__(256) void mvf_dense_flag_kernel(DiffVolume v, uint8_t* flag, int nb)
-{
-    const int lane = threadIdx.x & 63;
-    const int x = lane & 7, y = lane >> 3;
-    const int waves = gridDim.x * (blockDim.x >> 6);
-    for (int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nb; b += waves) {
-        const int bx = b % v.bd[0], t = b / v.bd[0];
-        const int by = t % v.bd[1], bz = t / v.bd[1];
-        const int gx = 8 * bx + x, gy = 8 * by + y;
-        bool any = false;
-        if (gx < v.dims[0] && gy < v.dims[1]) {
-            for (int z = 8 * bz; z < min(8 * bz + 8, v.dims[2]); ++z) {
-                const size_t id = ((size_t)z * v.dims[1] + gy) * v.dims[0] + gx;
-                any |= (v.W[id] != 0) && (v.F[id] <= kFlagThreshold);
-            }
-        }
-        const unsigned long long m = __ballot(any);
-        if (lane == 0) flag[b] = m ? 1 : 0;
-    }
-}
-
-__global__ __launch_bounds__(256) void mvf_dense_dist_kernel(DiffVolume v, const uint8_t* in, uint8_t* out, int nb,
-                                                             int pass)
-{
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
-        const int bx = b % v.bd[0], t = b / v.bd[0];
-        const int by = t % v.bd[1], bz = t / v.bd[1];
-        const int sy = v.bd[0], sz = v.bd[0] * v.bd[1];
-        if (pass == 1) {
-            bool f = false;
-            for (int dz = 0; dz < 2; ++dz)
-                for (int dy = 0; dy < 2; ++dy)
-                    for (int dx = 0; dx < 2; ++dx)
-                        if (bx + dx < v.bd[0] && by + dy < v.bd[1] && bz + dz < v.bd[2])
-                            f |= in[b + dx + dy * sy + dz * sz] != 0;
-            out[b] = f ? 1 : 0;
-            continue;
-        }
-        const int pos = pass == 2 ? bx : (pass == 3 ? by : bz);
-        const int len = v.bd[pass - 2];
-        const int stride = pass == 2 ? 1 : (pass == 3 ? sy : sz);
-        int d = kDistCap;
-        for (int o = -kDistCap; o <= kDistCap; ++o) {
-            const int q = pos + o;
-            if (q < 0 || q >= len) continue;
-            const int val = in[b + o * stride];
-            d = pass == 2 ? (val ? min(d, abs(o)) : d) : min(d, max(abs(o), val));
-        }
-        out[b] = (uint8_t)d;
-    }
-}
-
-int launch_dense_summary(const DiffVolume& v, uint8_t* work, uint8_t* dist, void* stream)
-{
-    const int nb = v.bd[0] * v.bd[1] * v.bd[2];
-    hipStream_t s = (hipStream_t)stream;
-    uint8_t* flag = work;
-    uint8_t* cflag = work + nb;
-    uint8_t* t0 = work + 2 * (size_t)nb;
-    uint8_t* t1 = work + 3 * (size_t)nb;
-    const int wblocks = (int)std::min<long long>(65536, ((long long)nb + 3) / 4);
-    hipLaunchKernelGGL(mvf_dense_flag_kernel, dim3(wblocks), dim3(256), 0, s, v, flag, nb);
-    const int blocks = (int)std::min<long long>(4096, ((long long)nb + 255) / 256);
-    hipLaunchKernelGGL(mvf_dense_dist_kernel, dim3(blocks), dim3(256), 0, s, v, flag, cflag, nb, 1);
-    hipLaunchKernelGGL(mvf_dense_dist_kernel, dim3(blocks), dim3(256), 0, s, v, cflag, t0, nb, 2);
-    hipLaunchKernelGGL(mvf_dense_dist_kernel, dim3(blocks), dim3(256), 0, s, v, t0, t1, nb, 3);
-    hipLaunchKernelGGL(mvf_dense_dist_kernel, dim3(blocks), dim3(256), 0, s, v, t1, dist, nb, 4);
-    return (int)hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void mvf_diffray_forward_kernel(DiffVolume v, PoseArgs P, float fx, float fy,
-                                                                  float cx, float cy, int width, int height,
-                                                                  RayParams rp, float* depth, int32_t* record)
-{
-    const int u = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int vv = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (u >= width || vv >= height) return;
-    const size_t p = (size_t)vv * width + u;
-    Ray r;
-    float dh[3];
-    make_ray(u, vv, fx, fy, cx, cy, P.T, r, dh);
-    // conservative k range (domain box grown by a voxel, +-2 samples)
-    float t0 = 0.0f, t1 = (float)rp.kmax * rp.delta;
-    bool none = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float lo = v.o[a] + v.s * ((float)v.off[a] + 0.5f) - v.s;
-        const float hi = v.o[a] + v.s * ((float)v.off[a] + (float)v.dims[a] - 0.5f) + v.s;
-        if (r.dw[a] == 0.0f) {
-            if (r.C[a] < lo || r.C[a] > hi) none = true;
-        } else {
-            float ta = (lo - r.C[a]) / r.dw[a], tb = (hi - r.C[a]) / r.dw[a];
-            if (ta > tb) { const float t = ta; ta = tb; tb = t; }
-            t0 = fmaxf(t0, ta);
-            t1 = fminf(t1, tb);
-        }
-    }
-    float ts = 0.0f;
-    int kfound = -1;
-    if (!none && t0 <= t1) {
-        const int k0 = max(1, (int)floorf(t0 / rp.delta) - 2);
-        const int k1 = min(rp.kmax, (int)ceilf(t1 / rp.delta) + 2);
-        // per-sample advance in local voxel units (skipping only; the 0.01
-        // voxel shrink of the skip box absorbs rounding)
-        float dl[3], inv_dl[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            dl[a] = rp.delta * r.dw[a] * v.inv_s;
-            inv_dl[a] = __builtin_amdgcn_rcpf(dl[a]);
-        }
-        GPTR(const uint8_t) const distp = gptr(v.dist);
-        uint32_t cb = 0xffffffffu;
-        int cD = 0;
-        int prev_k = -2;
-        bool prev_ok = false;
-        float Fprev = 0.0f;
-        int k = k0;
-        while (k <= k1) {
-            const float tk = (float)k * rp.delta;
-            if (v.dist) {
-                // samples whose cell base lies in bricks with no cell that
-                // has an observed corner F <= 0 cannot be the far end of a
-                // crossing: skip them while they stay in the clear cube
-                float l[3];
-                bool dom = true;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float x = r.C[a] + (tk * r.dw[a]);
-                    l[a] = (((x - v.o[a]) * v.inv_s) - 0.5f) - (float)v.off[a];
-                    dom &= l[a] >= 0.0f && l[a] < (float)(v.dims[a] - 1);
-                }
-                if (dom) {
-                    int bi[3];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) bi[a] = ((int)floorf(l[a])) >> 3;
-                    const uint32_t b = (uint32_t)((bi[2] * v.bd[1] + bi[1]) * v.bd[0] + bi[0]);
-                    if (b != cb) {
-                        cb = b;
-                        cD = ld_elem(distp, b);
-                    }
-                    if (cD >= 1) {
-                        float m = 1e30f;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const float A = (float)(8 * (bi[a] - (cD - 1)));
-                            const float B = (float)(8 * (bi[a] + cD));
-                            if (dl[a] > 0.0f) m = fminf(m, (B - 0.01f - l[a]) * inv_dl[a]);
-                            else if (dl[a] < 0.0f) m = fminf(m, (l[a] - (A + 0.01f)) * -inv_dl[a]);
-                        }
-                        int jump = (int)fminf(fmaxf(m, 0.0f), 4096.0f);
-                        if (jump < 1) jump = 1;
-                        prev_k = -2;
-                        prev_ok = false;
-                        k += jump;
-                        continue;
-                    }
-                }
-            }
-            if (prev_k != k - 1) {
-                DSample P;
-                dense_sample(v, r, (float)(k - 1) * rp.delta, P);
-                prev_ok = P.ok;
-                Fprev = P.F;
-            }
-            DSample S;
-            dense_sample(v, r, tk, S);
-            if (prev_ok && S.ok && Fprev > 0.0f && S.F <= 0.0f) {
-                const float ta = (float)(k - 1) * rp.delta;
-                ts = ta + ((rp.delta * Fprev) / (Fprev - S.F));
-                kfound = k;
-                break;
-            }
-            prev_k = k;
-            prev_ok = S.ok;
-            Fprev = S.F;
-            ++k;
-        }
-    }
-    depth[p] = kfound >= 0 ? ts * dh[2] : 0.0f;
-    record[p] = kfound;
-}
-
-int launch_diffray_forward(DiffVolume v, const float* T, float fx, float fy, float cx, float cy, int width,
-                           int height, RayParams rp, float* depth, int32_t* record, void* stream)
-{
-    PoseArgs P;
-    for (int i = 0; i < 12; ++i) P.T[i] = T[i];
-    dim3 grid((width + 15) / 16, (height + 15) / 16);
-    hipLaunchKernelGGL(mvf_diffray_forward_kernel, grid, dim3(256), 0, (hipStream_t)stream, v, P, fx, fy, cx, cy,
-                       width, height, rp, depth, record);
-    return (int)hipGetLastError();
-}
-
 __global__ __launch_bounds__(256) void mvf_diffray_backward_kernel(
     DiffVolume v, PoseArgs P, float fx, float fy, float cx, float cy, int width, int height, RayParams rp,
     const float* __restrict__ grad_depth, const int32_t* __restrict__ record, float* grad_F, double* partials)
@@ -2263,47 +2249,80 @@ __global__ __launch_bounds__(256) void mvf_diffray_backward_kernel(
             dense_sample(v, r, (float)(k - 1) * rp.delta, S[0]);
             dense_sample(v, r, (float)k * rp.delta, S[1]);
             if (S[0].ok && S[1].ok) {
-                const float Fa = S[0].F, Fb = S[1].F;
-                const float den = Fa - Fb;
-                const float inv2 = 1.0f / (den * den);
-                const float dt[2] = { -rp.delta * Fb * inv2, rp.delta * Fa * inv2 };
-                const float gz = gd * dh[2];
+                // The binary32 march fixed the structure (k and the two
+                // cells); the values are re-evaluated in binary64 at the
+                // exact sample positions.  A crossing whose two samples are
+                // close in value has dt/dF ~ 1 / (F_a - F_b)^2, so binary32
+                // positions (an ulp of a local coordinate near 512 is 6e-5
+                // voxel) would dominate the gradient of such pixels.
+                double dh64[3], dw64[3];
+                {
+                    const double dc0 = ((double)u - (double)cx) / (double)fx;
+                    const double dc1 = ((double)vv - (double)cy) / (double)fy;
+                    const double n = sqrt(dc0 * dc0 + dc1 * dc1 + 1.0);
+                    dh64[0] = dc0 / n;
+                    dh64[1] = dc1 / n;
+                    dh64[2] = 1.0 / n;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        dw64[a] = (double)P.T[4 * a + 0] * dh64[0] + (double)P.T[4 * a + 1] * dh64[1] +
+                                  (double)P.T[4 * a + 2] * dh64[2];
+                }
+                const double delta = (double)rp.delta;
+                const double s64 = (double)v.s;
+                double Fs[2], fr[2][3], gl[2][3];
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    const DSample& s = S[j];
-                    const float kk = gz * dt[j];
-                    const float t = (float)(k - 1 + j) * rp.delta;
-                    // gradient of the trilinear interpolant w.r.t. the local coordinate
-                    const float* c = s.c;
-                    const float gx = lerp32(lerp32(c[1] - c[0], c[3] - c[2], s.f[1]),
-                                            lerp32(c[5] - c[4], c[7] - c[6], s.f[1]), s.f[2]);
-                    const float c00 = lerp32(c[0], c[1], s.f[0]), c10 = lerp32(c[2], c[3], s.f[0]);
-                    const float c01 = lerp32(c[4], c[5], s.f[0]), c11 = lerp32(c[6], c[7], s.f[0]);
-                    const float gy = lerp32(c10 - c00, c11 - c01, s.f[2]);
-                    const float gzl = lerp32(c01, c11, s.f[1]) - lerp32(c00, c10, s.f[1]);
-                    const float gw[3] = { gx * v.inv_s, gy * v.inv_s, gzl * v.inv_s };
-                    float gc[3], q[3];
+                    const double t = (double)(k - 1 + j) * delta;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const double x = (double)P.T[4 * a + 3] + t * dw64[a];
+                        fr[j][a] = (x - (double)v.o[a]) / s64 - 0.5 - (double)v.off[a] - (double)S[j].i[a];
+                    }
+                    const float* c = S[j].c;
+                    const double f0 = fr[j][0], f1 = fr[j][1], f2 = fr[j][2];
+                    const double c00 = lerp64(c[0], c[1], f0), c10 = lerp64(c[2], c[3], f0);
+                    const double c01 = lerp64(c[4], c[5], f0), c11 = lerp64(c[6], c[7], f0);
+                    const double c0 = lerp64(c00, c10, f1), c1 = lerp64(c01, c11, f1);
+                    gl[j][0] = lerp64(lerp64((double)c[1] - c[0], (double)c[3] - c[2], f1),
+                                      lerp64((double)c[5] - c[4], (double)c[7] - c[6], f1), f2);
+                    gl[j][1] = lerp64(c10 - c00, c11 - c01, f2);
+                    gl[j][2] = c1 - c0;
+                    Fs[j] = lerp64(c0, c1, f2);
+                }
+                const double den = Fs[0] - Fs[1];
+                const double dt[2] = { -delta * Fs[1] / (den * den), delta * Fs[0] / (den * den) };
+                const double gz = (double)gd * dh64[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const double kk = gz * dt[j];
+                    const double t = (double)(k - 1 + j) * delta;
+                    double gc[3], q[3];
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) {
-                        gc[cc] = P.T[cc] * gw[0] + P.T[4 + cc] * gw[1] + P.T[8 + cc] * gw[2];
-                        q[cc] = t * dh[cc];
+                        gc[cc] = ((double)P.T[cc] * gl[j][0] + (double)P.T[4 + cc] * gl[j][1] +
+                                  (double)P.T[8 + cc] * gl[j][2]) / s64;
+                        q[cc] = t * dh64[cc];
                     }
-                    acc[0] += (double)(kk * gc[0]);
-                    acc[1] += (double)(kk * gc[1]);
-                    acc[2] += (double)(kk * gc[2]);
-                    acc[3] += (double)(kk * (q[1] * gc[2] - q[2] * gc[1]));
-                    acc[4] += (double)(kk * (q[2] * gc[0] - q[0] * gc[2]));
-                    acc[5] += (double)(kk * (q[0] * gc[1] - q[1] * gc[0]));
+                    acc[0] += kk * gc[0];
+                    acc[1] += kk * gc[1];
+                    acc[2] += kk * gc[2];
+                    acc[3] += kk * (q[1] * gc[2] - q[2] * gc[1]);
+                    acc[4] += kk * (q[2] * gc[0] - q[0] * gc[2]);
+                    acc[5] += kk * (q[0] * gc[1] - q[1] * gc[0]);
                     if (grad_F) {
+                        const DSample& sm = S[j];
 #pragma unroll
                         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
                             for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
                                 for (int dx = 0; dx < 2; ++dx) {
-                                    const float w = (dx ? s.f[0] : 1.0f - s.f[0]) * (dy ? s.f[1] : 1.0f - s.f[1]) *
-                                                    (dz ? s.f[2] : 1.0f - s.f[2]);
-                                    atomicAdd(&grad_F[dense_idx(v, s.i[0] + dx, s.i[1] + dy, s.i[2] + dz)], kk * w);
+                                    const double w = (dx ? fr[j][0] : 1.0 - fr[j][0]) *
+                                                     (dy ? fr[j][1] : 1.0 - fr[j][1]) *
+                                                     (dz ? fr[j][2] : 1.0 - fr[j][2]);
+                                    atomicAdd(&grad_F[dense_idx(v, sm.i[0] + dx, sm.i[1] + dy, sm.i[2] + dz)],
+                                              (float)(kk * w));
                                 }
                     }
                 }

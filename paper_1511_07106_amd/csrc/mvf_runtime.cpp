@@ -58,6 +58,8 @@ mvf_status set_error(mvf_status st, const char* fmt, ...)
     } while (0)
 
 constexpr size_t kAlign = 256;
+// scratch slot of the differentiable raycast (public stream ids are >= 0)
+constexpr int kDiffStream = -1;
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Grid {
@@ -80,6 +82,7 @@ struct Volume {
     uint64_t last_use = 0;
     hipEvent_t host_ready = nullptr;  // mirror written (swap-out finished)
     bool host_pending = false;
+    bool internal = false;  // the library's own (the differentiable raycast's mirror): no public id
 };
 
 // Swaps move a slab in chunks of kSwapChunk bytes, each with its own event,
@@ -240,8 +243,25 @@ struct mvf_ctx {
     static constexpr int kPlaceTable = 8192;
     double* diff_partials = nullptr;
     int diff_partials_n = 0;
-    uint8_t* diff_summary = nullptr;  // dense-volume skip summary: 5 planes of nbricks bytes
-    size_t diff_summary_n = 0;        // nbricks it holds
+    // brick-layout mirror of the caller's dense volume (differentiable
+    // raycast forward), and what it was built from
+    struct DiffMirror {
+        int vol = -1, grid = -1;
+        const void* F = nullptr;
+        const void* W = nullptr;
+        int dims[3] = {0, 0, 0}, off[3] = {0, 0, 0};
+        float o[3] = {0, 0, 0}, s = 0.0f;
+        uint64_t generation = 0;
+    } diff_mirror;
+    // camera tracking: pyramid maps, partials and the device state, plus a
+    // pinned copy of the state for the result
+    struct TrackScratch {
+        uint8_t* dev = nullptr;
+        size_t bytes = 0;
+        TrackState* host = nullptr;
+    } track;
+    uint8_t* extract_buf = nullptr;   // surface points: per-brick counts (4 B), offsets (8 B), total (8 B)
+    size_t extract_buf_n = 0;         // nbricks it holds
     StepGraph step;
     hipStream_t capture_stream = nullptr;
 };
@@ -321,7 +341,7 @@ mvf_status arena_release(mvf_ctx* c, int slot, hipStream_t stream)
 
 Volume* find_volume(mvf_ctx* c, int32_t id)
 {
-    if (id < 0 || id >= (int32_t)c->vols.size() || !c->vols[id].alive) return nullptr;
+    if (id < 0 || id >= (int32_t)c->vols.size() || !c->vols[id].alive || c->vols[id].internal) return nullptr;
     return &c->vols[id];
 }
 
@@ -960,7 +980,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
 }
 
 mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsics& K, const mvf_raycast_out* out,
-                         const std::vector<int>& ids_in, hipStream_t stream)
+                         const std::vector<int>& ids_in, hipStream_t stream, int32_t* record = nullptr)
 {
     std::vector<int> ids = ids_in;
     // nearest first (ties by id) -- only affects speed, not results
@@ -1011,6 +1031,7 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
         fr->vertex = out->vertex;
         fr->normal = out->normal;
         fr->hit = out->hit;
+        fr->record = record;
         fr->out_w = out->width;
         fr->out_h = out->height;
         if (multi) {
@@ -1059,6 +1080,34 @@ mvf_status raycast_plain(mvf_ctx* c, int sid, const float* T, const mvf_intrinsi
     }
     c->stats.pixels_raycast += (uint64_t)out->width * out->height;
     return MVF_OK;
+}
+
+// Exact recompute of a resident volume's brick summaries (flags, sub-block
+// masks, column words, distances and cell masks) after its planes were
+// overwritten, on `stream`.
+mvf_status recompute_summaries(mvf_ctx* c, const Volume& v, hipStream_t stream)
+{
+    const DevVolume dv = make_dev(c, v);
+    CHECK_LAUNCH(launch_brick_summary(dv, stream));
+    int slot;
+    Writer w;
+    CHECK_ST(arena_acquire(c, &slot, &w));
+    LaunchHeader* dh;
+    LaunchHeader* h = w.alloc<LaunchHeader>(1, &dh);
+    DevVolume* dvv;
+    DevVolume* vt = w.alloc<DevVolume>(1, &dvv);
+    int32_t* dbb;
+    int32_t* bb = w.alloc<int32_t>(2, &dbb);
+    if (!h || !vt || !bb) return set_error(MVF_ERR_INVALID_ARG, "arena overflow");
+    memset(h, 0, sizeof(*h));
+    h->nvol = 1;
+    h->total_bricks = (int)align_up(v.nbricks, 64);
+    *vt = dv;
+    bb[0] = 0;
+    bb[1] = h->total_bricks;
+    CHECK_ST(arena_upload(c, w, stream));
+    CHECK_LAUNCH(launch_brick_distance(dh, dvv, dbb, std::min<int>(1024, ((int)v.nbricks + 255) / 256), stream));
+    return arena_release(c, slot, stream);
 }
 
 std::vector<int> stream_volumes(mvf_ctx* c, int sid, const float* T, const mvf_intrinsics& K, int w, int h)
@@ -1409,7 +1458,9 @@ mvf_status mvf_destroy(mvf_ctx* c)
     if (c->place_T) (void)hipFree(c->place_T);
     if (c->place_boxes) (void)hipFree(c->place_boxes);
     if (c->diff_partials) (void)hipFree(c->diff_partials);
-    if (c->diff_summary) (void)hipFree(c->diff_summary);
+    if (c->extract_buf) (void)hipFree(c->extract_buf);
+    if (c->track.dev) (void)hipFree(c->track.dev);
+    if (c->track.host) (void)hipHostFree(c->track.host);
     if (c->tail) (void)hipEventDestroy(c->tail);
     if (c->d2h_stream) (void)hipStreamDestroy(c->d2h_stream);
     if (c->h2d_stream) (void)hipStreamDestroy(c->h2d_stream);
@@ -1590,6 +1641,47 @@ mvf_status mvf_volume_swap_out(mvf_ctx* c, int32_t id, void* stream)
     return mark_tail(c, s);
 }
 
+mvf_status mvf_volume_extract(mvf_ctx* c, int32_t id, float* V, float* N, int32_t* G, int64_t cap,
+                              int64_t* n_total, void* stream)
+{
+    if (!c || !n_total) return set_error(MVF_ERR_INVALID_ARG, "ctx or n_total is NULL");
+    if (cap < 0) return set_error(MVF_ERR_INVALID_ARG, "cap must be >= 0");
+    if (cap > 0 && (!V || !N)) return set_error(MVF_ERR_INVALID_ARG, "V and N are needed when cap > 0");
+    Volume* v = find_volume(c, id);
+    if (!v) return set_error(MVF_ERR_NOT_FOUND, "volume %d", id);
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    *n_total = 0;
+    if (v->state == State::Empty) return mark_tail(c, s);  // never observed: no surface
+    CHECK_ST(ensure_resident(c, std::vector<int>{id}, s));
+    const size_t nb = v->nbricks;
+    if (nb > c->extract_buf_n) {
+        if (c->extract_buf) {
+            CHECK_HIP(hipStreamSynchronize(s));
+            CHECK_HIP(hipFree(c->extract_buf));
+            c->extract_buf = nullptr;
+            c->extract_buf_n = 0;
+        }
+        if (hipMalloc((void**)&c->extract_buf, align_up(4 * nb, kAlign) + 8 * nb + 8) != hipSuccess) {
+            (void)hipGetLastError();
+            c->extract_buf = nullptr;
+            return set_error(MVF_ERR_OOM, "surface extraction scratch of %zu bricks", nb);
+        }
+        c->extract_buf_n = nb;
+    }
+    uint32_t* counts = reinterpret_cast<uint32_t*>(c->extract_buf);
+    unsigned long long* offsets = reinterpret_cast<unsigned long long*>(c->extract_buf + align_up(4 * nb, kAlign));
+    long long* total = reinterpret_cast<long long*>(offsets + nb);
+    DevVolume dv = make_dev(c, *v);
+    CHECK_LAUNCH(launch_extract(dv, counts, offsets, total, V, N, G, (long long)cap, s));
+    long long n = 0;
+    CHECK_HIP(hipMemcpyAsync(&n, total, sizeof(n), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    *n_total = (int64_t)n;
+    return mark_tail(c, s);
+}
+
 mvf_status mvf_volume_describe(mvf_ctx* c, int32_t id, mvf_volume_desc* out)
 {
     if (!c || !out) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
@@ -1707,31 +1799,16 @@ mvf_status mvf_volume_write(mvf_ctx* c, int32_t id, const float* F, const uint16
         DevVolume dv = make_dev(c, *v);
         int le = launch_volume_init(dv, nullptr);
         if (!le) le = launch_from_canonical(dv, dF, dW, dC, nullptr);
-        if (!le) le = launch_brick_summary(dv, nullptr);
-        if (!le) {
-            int slot;
-            Writer w;
-            mvf_status ast = arena_acquire(c, &slot, &w);
-            if (ast != MVF_OK) return ast;
-            LaunchHeader* dh;
-            LaunchHeader* h = w.alloc<LaunchHeader>(1, &dh);
-            DevVolume* dvv;
-            DevVolume* vt = w.alloc<DevVolume>(1, &dvv);
-            int32_t* dbb;
-            int32_t* bb = w.alloc<int32_t>(2, &dbb);
-            memset(h, 0, sizeof(*h));
-            h->nvol = 1;
-            h->total_bricks = (int)align_up(v->nbricks, 64);
-            *vt = dv;
-            bb[0] = 0;
-            bb[1] = h->total_bricks;
-            ast = arena_upload(c, w, nullptr);
-            if (ast != MVF_OK) return ast;
-            le = launch_brick_distance(dh, dvv, dbb, std::min<int>(1024, ((int)v->nbricks + 255) / 256), nullptr);
-            ast = arena_release(c, slot, nullptr);
-            if (ast != MVF_OK) return ast;
-        }
         if (le) { st = MVF_ERR_HIP; e = (hipError_t)le; }
+        else {
+            const mvf_status sst = recompute_summaries(c, *v, nullptr);
+            if (sst != MVF_OK) {
+                if (dF) (void)hipFree(dF);
+                if (dW) (void)hipFree(dW);
+                if (dC) (void)hipFree(dC);
+                return sst;
+            }
+        }
     }
     if (st == MVF_OK && (e = hipDeviceSynchronize()) != hipSuccess) st = MVF_ERR_HIP;
     if (dF) (void)hipFree(dF);
@@ -2266,9 +2343,13 @@ mvf_status mvf_placement_count(mvf_ctx* c, const mvf_frame* f, const float T_wc[
     return mark_tail(c, s);
 }
 
-mvf_status mvf_placement_update_classes(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
+// Insertion and removal over the classes of p, with the new live cells of
+// each class chosen by the built-in rule (custom == null) or by the caller's
+// function.
+static mvf_status placement_update_impl(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
                                         const mvf_intrinsics* K, const mvf_placement_class_params* p,
-                                        mvf_placement_result* r, void* stream)
+                                        mvf_placement_fn custom, void* user, mvf_placement_result* r,
+                                        void* stream)
 {
     if (!c || !p || !r) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
     CHECK_ST(check_frame(f));
@@ -2286,7 +2367,7 @@ mvf_status mvf_placement_update_classes(mvf_ctx* c, int32_t sid, const mvf_frame
         quota_sum += pc.quota;
     }
     if (quota_sum > 64) return set_error(MVF_ERR_INVALID_ARG, "the quotas sum to %d > 64", quota_sum);
-    if (!(p->beta >= 1.0f)) return set_error(MVF_ERR_INVALID_ARG, "beta must be >= 1");
+    if (!custom && !(p->beta >= 1.0f)) return set_error(MVF_ERR_INVALID_ARG, "beta must be >= 1");
     if (sid < 0) return set_error(MVF_ERR_INVALID_ARG, "stream_id must be >= 0");
     CHECK_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
@@ -2317,8 +2398,42 @@ mvf_status mvf_placement_update_classes(mvf_ctx* c, int32_t sid, const mvf_frame
         std::vector<int32_t> out(3 * std::max(1, std::max(quota, n_act))), add(3 * (n_act + (int)res.size() + 1)),
             rem(3 * (n_act + (int)res.size() + 1));
         int32_t n_out = 0, n_add = 0, n_rem = 0;
-        CHECK_ST(mvf_placement_policy(act.data(), n_act, cellv.data(), cntv.data(), (int32_t)res.size(), quota,
-                                      p->beta, out.data(), &n_out, add.data(), &n_add, rem.data(), &n_rem));
+        if (!custom) {
+            CHECK_ST(mvf_placement_policy(act.data(), n_act, cellv.data(), cntv.data(), (int32_t)res.size(), quota,
+                                          p->beta, out.data(), &n_out, add.data(), &n_add, rem.data(), &n_rem));
+        } else {
+            // the caller's f: the class's live cells after this frame
+            std::vector<int32_t> keep(3 * std::max(1, quota));
+            int32_t n_keep = -1;
+            const int32_t rc = custom(user, ci, d_v, act.data(), n_act, cellv.data(), cntv.data(),
+                                      (int32_t)res.size(), quota, keep.data(), &n_keep);
+            if (rc != 0) return set_error(MVF_ERR_STATE, "placement function returned %d (class %d)", rc, ci);
+            if (n_keep < 0 || n_keep > quota)
+                return set_error(MVF_ERR_INVALID_ARG, "placement function kept %d cells, quota %d", n_keep, quota);
+            std::set<std::vector<int>> kept, live;
+            for (int i = 0; i < n_act; ++i) live.insert({act[3 * i], act[3 * i + 1], act[3 * i + 2]});
+            for (int i = 0; i < n_keep; ++i) {
+                const std::vector<int> k = { keep[3 * i], keep[3 * i + 1], keep[3 * i + 2] };
+                for (int a = 0; a < 3; ++a)
+                    if ((int64_t)k[a] * (d_v - 2) < -(1 << 22) || (int64_t)k[a] * (d_v - 2) > (1 << 22))
+                        return set_error(MVF_ERR_INVALID_ARG, "placement function kept a cell out of range");
+                if (!kept.insert(k).second)
+                    return set_error(MVF_ERR_INVALID_ARG, "placement function kept a cell twice");
+                for (int a = 0; a < 3; ++a) out[3 * i + a] = k[a];
+                if (!live.count(k)) {
+                    for (int a = 0; a < 3; ++a) add[3 * n_add + a] = k[a];
+                    ++n_add;
+                }
+            }
+            n_out = n_keep;
+            for (int i = 0; i < n_act; ++i) {
+                const std::vector<int> k = { act[3 * i], act[3 * i + 1], act[3 * i + 2] };
+                if (!kept.count(k)) {
+                    for (int a = 0; a < 3; ++a) rem[3 * n_rem + a] = k[a];
+                    ++n_rem;
+                }
+            }
+        }
         for (int i = 0; i < n_rem; ++i) {
             const std::vector<int> k = { d_v, rem[3 * i], rem[3 * i + 1], rem[3 * i + 2] };
             const int id = placed[k];
@@ -2355,6 +2470,21 @@ mvf_status mvf_placement_update_classes(mvf_ctx* c, int32_t sid, const mvf_frame
     return mark_tail(c, s);
 }
 
+mvf_status mvf_placement_update_classes(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
+                                        const mvf_intrinsics* K, const mvf_placement_class_params* p,
+                                        mvf_placement_result* r, void* stream)
+{
+    return placement_update_impl(c, sid, f, T_wc, K, p, nullptr, nullptr, r, stream);
+}
+
+mvf_status mvf_placement_update_custom(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
+                                       const mvf_intrinsics* K, const mvf_placement_class_params* p,
+                                       mvf_placement_fn fn, void* user, mvf_placement_result* r, void* stream)
+{
+    if (!fn) return set_error(MVF_ERR_INVALID_ARG, "placement function is NULL");
+    return placement_update_impl(c, sid, f, T_wc, K, p, fn, user, r, stream);
+}
+
 mvf_status mvf_placement_update(mvf_ctx* c, int32_t sid, const mvf_frame* f, const float T_wc[12],
                                 const mvf_intrinsics* K, const mvf_placement_params* p, mvf_placement_result* r,
                                 void* stream)
@@ -2368,6 +2498,197 @@ mvf_status mvf_placement_update(mvf_ctx* c, int32_t sid, const mvf_frame* f, con
     q.classes[0].quota = p->n_max;
     q.beta = p->beta;
     return mvf_placement_update_classes(c, sid, f, T_wc, K, &q, r, stream);
+}
+
+// ---- camera tracking ---------------------------------------------------------------
+
+mvf_status mvf_depth_maps(mvf_ctx* c, const mvf_frame* f, const mvf_intrinsics* K, int32_t level, float tau,
+                          float* V, float* N, void* stream)
+{
+    if (!c || !V || !N) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    CHECK_ST(check_frame(f));
+    if (!valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "intrinsics NULL, not finite or zero focal length");
+    if (level < 0 || level > 2) return set_error(MVF_ERR_INVALID_ARG, "level must be in [0, 2]");
+    if (!(tau >= 0.0f)) return set_error(MVF_ERR_INVALID_ARG, "tau must be >= 0");
+    if ((f->width >> level) < 1 || (f->height >> level) < 1)
+        return set_error(MVF_ERR_INVALID_ARG, "image too small for level %d", level);
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    int w = f->width, h = f->height, pitch = f->depth_pitch ? f->depth_pitch : f->width;
+    const float* D = f->depth;
+    float* tmp[2] = {nullptr, nullptr};
+    mvf_status st = MVF_OK;
+    for (int l = 1; l <= level && st == MVF_OK; ++l) {
+        if (hipMalloc((void**)&tmp[l - 1], sizeof(float) * (size_t)(w / 2) * (h / 2)) != hipSuccess) {
+            (void)hipGetLastError();
+            st = set_error(MVF_ERR_OOM, "depth pyramid level %d", l);
+            break;
+        }
+        const int le = launch_track_down(D, pitch, w, h, tau, tmp[l - 1], s);
+        if (le) st = set_error(MVF_ERR_HIP, "launch: %s", hipGetErrorString((hipError_t)le));
+        D = tmp[l - 1];
+        w /= 2;
+        h /= 2;
+        pitch = w;
+    }
+    if (st == MVF_OK) {
+        const float sc = std::ldexp(1.0f, -level);
+        const float Kl[4] = { K->fx * sc, K->fy * sc, (K->cx + 0.5f) * sc - 0.5f, (K->cy + 0.5f) * sc - 0.5f };
+        const int le = launch_track_vn(D, pitch, w, h, Kl, V, N, s);
+        if (le) st = set_error(MVF_ERR_HIP, "launch: %s", hipGetErrorString((hipError_t)le));
+    }
+    if (tmp[0] || tmp[1]) {
+        const hipError_t e = hipStreamSynchronize(s);
+        for (float* t : tmp)
+            if (t) (void)hipFree(t);
+        if (st == MVF_OK && e != hipSuccess) st = set_error(MVF_ERR_HIP, "%s", hipGetErrorString(e));
+    }
+    if (st != MVF_OK) return st;
+    return mark_tail(c, s);
+}
+
+mvf_status mvf_track(mvf_ctx* c, const mvf_frame* f, const mvf_intrinsics* K, const mvf_track_model* m,
+                     const double T_init[12], const mvf_track_params* p, double T_out[12], mvf_track_stats* st,
+                     void* stream)
+{
+    if (!c || !m || !p || !T_init || !T_out) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    CHECK_ST(check_frame(f));
+    if (!valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "intrinsics NULL, not finite or zero focal length");
+    if (!m->vertex || !m->normal) return set_error(MVF_ERR_INVALID_ARG, "model maps NULL");
+    if (m->width != f->width || m->height != f->height)
+        return set_error(MVF_ERR_INVALID_ARG, "model maps %dx%d differ from the frame %dx%d", m->width, m->height,
+                         f->width, f->height);
+    if (!finite_pose(m->T_wc)) return set_error(MVF_ERR_INVALID_ARG, "model pose not finite");
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(T_init[i])) return set_error(MVF_ERR_INVALID_ARG, "T_init not finite");
+    if (p->levels < 1 || p->levels > 3) return set_error(MVF_ERR_INVALID_ARG, "levels must be in [1, 3]");
+    int nsteps = 0;
+    for (int l = 0; l < p->levels; ++l) {
+        if (p->iters[l] < 0) return set_error(MVF_ERR_INVALID_ARG, "negative iteration count");
+        nsteps += p->iters[l];
+    }
+    if (nsteps > kTrackMaxSteps) return set_error(MVF_ERR_INVALID_ARG, "more than %d steps", kTrackMaxSteps);
+    if (!(p->eps_d > 0.0f) || !(p->cos_theta >= 0.0f && p->cos_theta <= 1.0f) || !(p->tau >= 0.0f))
+        return set_error(MVF_ERR_INVALID_ARG, "eps_d > 0, cos_theta in [0, 1] and tau >= 0 required");
+    if ((f->width >> (p->levels - 1)) < 1 || (f->height >> (p->levels - 1)) < 1)
+        return set_error(MVF_ERR_INVALID_ARG, "image too small for %d levels", p->levels);
+    CHECK_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_ST(order_after_previous(c, s));
+    // scratch: per level depth (levels >= 1), current V and N, model V and N
+    // (levels >= 1); then the partials and the state
+    int w[3], h[3];
+    w[0] = f->width;
+    h[0] = f->height;
+    for (int l = 1; l < 3; ++l) { w[l] = w[l - 1] / 2; h[l] = h[l - 1] / 2; }
+    size_t off = 0;
+    size_t o_d[3] = {0, 0, 0}, o_v[3], o_n[3], o_vm[3] = {0, 0, 0}, o_nm[3] = {0, 0, 0};
+    for (int l = 0; l < p->levels; ++l) {
+        const size_t npx = (size_t)w[l] * h[l];
+        if (l) { o_d[l] = off; off = align_up(off + 4 * npx, kAlign); }
+        o_v[l] = off; off = align_up(off + 12 * npx, kAlign);
+        o_n[l] = off; off = align_up(off + 12 * npx, kAlign);
+        if (l) {
+            o_vm[l] = off; off = align_up(off + 12 * npx, kAlign);
+            o_nm[l] = off; off = align_up(off + 12 * npx, kAlign);
+        }
+    }
+    const size_t o_part = off;
+    off = align_up(off + sizeof(double) * kTrackSums * (size_t)track_blocks(w[0], h[0]), kAlign);
+    const size_t o_state = off;
+    off = align_up(off + sizeof(TrackState), kAlign);
+    auto& tk = c->track;
+    if (off > tk.bytes) {
+        if (tk.dev) {
+            CHECK_HIP(hipStreamSynchronize(s));
+            CHECK_HIP(hipFree(tk.dev));
+            tk.dev = nullptr;
+            tk.bytes = 0;
+        }
+        if (hipMalloc((void**)&tk.dev, off) != hipSuccess) {
+            (void)hipGetLastError();
+            tk.dev = nullptr;
+            return set_error(MVF_ERR_OOM, "tracking scratch of %zu bytes", off);
+        }
+        tk.bytes = off;
+    }
+    if (!tk.host) CHECK_HIP(hipHostMalloc((void**)&tk.host, sizeof(TrackState), hipHostMallocDefault));
+    uint8_t* B = tk.dev;
+    TrackState* dstate = reinterpret_cast<TrackState*>(B + o_state);
+    double* partials = reinterpret_cast<double*>(B + o_part);
+    for (int i = 0; i < 12; ++i) tk.host->T[i] = T_init[i];
+    CHECK_HIP(hipMemcpyAsync(dstate->T, tk.host->T, sizeof(double) * 12, hipMemcpyHostToDevice, s));
+    CHECK_LAUNCH(launch_track_init(dstate, s));
+    // pyramid and maps
+    const float* D[3];
+    int pitch[3];
+    float Kl[3][4];
+    D[0] = f->depth;
+    pitch[0] = f->depth_pitch ? f->depth_pitch : f->width;
+    for (int l = 0; l < p->levels; ++l) {
+        if (l) {
+            float* Dl = reinterpret_cast<float*>(B + o_d[l]);
+            CHECK_LAUNCH(launch_track_down(D[l - 1], pitch[l - 1], w[l - 1], h[l - 1], p->tau, Dl, s));
+            D[l] = Dl;
+            pitch[l] = w[l];
+        }
+        // f / 2^l and (c + 1/2) / 2^l - 1/2 in binary32
+        const float sc = std::ldexp(1.0f, -l);
+        Kl[l][0] = K->fx * sc;
+        Kl[l][1] = K->fy * sc;
+        Kl[l][2] = (K->cx + 0.5f) * sc - 0.5f;
+        Kl[l][3] = (K->cy + 0.5f) * sc - 0.5f;
+        CHECK_LAUNCH(launch_track_vn(D[l], pitch[l], w[l], h[l], Kl[l], reinterpret_cast<float*>(B + o_v[l]),
+                                     reinterpret_cast<float*>(B + o_n[l]), s));
+    }
+    const float* Vm[3];
+    const float* Nm[3];
+    Vm[0] = m->vertex;
+    Nm[0] = m->normal;
+    for (int l = 1; l < p->levels; ++l) {
+        float* v2 = reinterpret_cast<float*>(B + o_vm[l]);
+        float* n2 = reinterpret_cast<float*>(B + o_nm[l]);
+        CHECK_LAUNCH(launch_track_model_down(Vm[l - 1], Nm[l - 1], w[l - 1], h[l - 1], v2, n2, s));
+        Vm[l] = v2;
+        Nm[l] = n2;
+    }
+    // coarse to fine
+    int step = 0;
+    for (int l = p->levels - 1; l >= 0; --l) {
+        for (int it = 0; it < p->iters[l]; ++it) {
+            TrackLaunch L{};
+            L.V = reinterpret_cast<const float*>(B + o_v[l]);
+            L.N = reinterpret_cast<const float*>(B + o_n[l]);
+            L.w = w[l];
+            L.h = h[l];
+            L.Vm = Vm[l];
+            L.Nm = Nm[l];
+            L.fx = Kl[l][0];
+            L.fy = Kl[l][1];
+            L.cx = Kl[l][2];
+            L.cy = Kl[l][3];
+            for (int i = 0; i < 12; ++i) L.Tm[i] = m->T_wc[i];
+            L.eps_d = p->eps_d;
+            L.cos_theta = p->cos_theta;
+            L.state = dstate;
+            L.partials = partials;
+            L.inlier = nullptr;
+            CHECK_LAUNCH(launch_icp_step(L, dstate, step++, s));
+        }
+    }
+    CHECK_HIP(hipMemcpyAsync(tk.host, dstate, sizeof(TrackState), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < 12; ++i) T_out[i] = tk.host->T[i];
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->steps = tk.host->steps;
+        for (int i = 0; i < tk.host->steps && i < kTrackMaxSteps; ++i) {
+            st->pairs[i] = tk.host->pairs[i];
+            st->sq_err[i] = tk.host->sq_err[i];
+        }
+    }
+    return mark_tail(c, s);
 }
 
 // ---- differentiable raycast --------------------------------------------------------
@@ -2387,9 +2708,66 @@ static mvf_status diff_volume(mvf_ctx* c, const mvf_dense_tsdf* v, DiffVolume* o
     }
     out->s = v->voxel_size;
     out->inv_s = 1.0f / v->voxel_size;
-    out->dist = nullptr;
-    for (int a = 0; a < 3; ++a) out->bd[a] = (v->dims[a] + kBrick - 1) / kBrick;
     (void)c;
+    return MVF_OK;
+}
+
+// The differentiable forward raycasts a brick-layout mirror of the caller's
+// dense volume with the plain raycast (same rules, same exact skipping) and
+// records the crossing.  The mirror is an internal volume of the context,
+// rebuilt when the dense volume's description changes, on every call with
+// generation 0, and when the generation differs from the last build's.
+static mvf_status build_diff_mirror(mvf_ctx* c, const mvf_dense_tsdf* v, hipStream_t s)
+{
+    mvf_ctx::DiffMirror& m = c->diff_mirror;
+    const bool same_shape = m.vol >= 0 && m.dims[0] == v->dims[0] && m.dims[1] == v->dims[1] &&
+                            m.dims[2] == v->dims[2];
+    const bool same = same_shape && m.F == v->F && m.W == v->W && v->generation != 0 &&
+                      m.generation == v->generation && m.s == v->voxel_size && m.off[0] == v->offset[0] &&
+                      m.off[1] == v->offset[1] && m.off[2] == v->offset[2] && m.o[0] == v->origin[0] &&
+                      m.o[1] == v->origin[1] && m.o[2] == v->origin[2];
+    if (same) return MVF_OK;
+    if (m.grid < 0) {
+        mvf_grid_desc gd{};
+        gd.voxel_size = v->voxel_size;
+        gd.trunc_voxels = 4.0f;  // unused: the raycast reads F in truncation units
+        gd.w_max = 65535;
+        for (int a = 0; a < 3; ++a) gd.origin[a] = v->origin[a];
+        CHECK_ST(mvf_grid_create(c, &gd, &m.grid));
+    }
+    Grid& g = c->grids[m.grid];
+    g.d.voxel_size = v->voxel_size;
+    for (int a = 0; a < 3; ++a) g.d.origin[a] = v->origin[a];
+    g.mu = g.d.trunc_voxels * g.d.voxel_size;
+    g.inv_s = 1.0f / g.d.voxel_size;
+    g.inv_mu = 1.0f / g.mu;
+    if (!same_shape) {
+        if (m.vol >= 0) {
+            c->vols[m.vol].internal = false;
+            CHECK_ST(mvf_volume_destroy(c, m.vol));
+            m.vol = -1;
+        }
+        mvf_volume_desc d{};
+        d.grid_id = m.grid;
+        for (int a = 0; a < 3; ++a) d.dims[a] = v->dims[a];
+        CHECK_ST(mvf_volume_create(c, &d, &m.vol));
+        c->vols[m.vol].internal = true;
+    }
+    Volume& mv = c->vols[m.vol];
+    for (int a = 0; a < 3; ++a) mv.d.offset[a] = v->offset[a];
+    m.F = nullptr;  // invalid until the import below is enqueued
+    CHECK_ST(ensure_resident(c, std::vector<int>{m.vol}, s));
+    CHECK_LAUNCH(launch_from_canonical(make_dev(c, mv), v->F, v->W, nullptr, s));
+    CHECK_ST(recompute_summaries(c, mv, s));
+    m.F = v->F;
+    m.W = v->W;
+    m.generation = v->generation;
+    m.s = v->voxel_size;
+    for (int a = 0; a < 3; ++a) {
+        m.dims[a] = v->dims[a];
+        m.off[a] = v->offset[a];
+        m.o[a] = v->origin[a];
+    }
     return MVF_OK;
 }
 
@@ -2399,30 +2777,20 @@ mvf_status mvf_diffray_forward(mvf_ctx* c, const mvf_dense_tsdf* v, const float 
     if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
     DiffVolume dv;
     CHECK_ST(diff_volume(c, v, &dv));
+    for (int a = 0; a < 3; ++a)
+        if (v->dims[a] > 2048) return set_error(MVF_ERR_INVALID_ARG, "dense dims above 2048 (forward)");
     if (!T_wc || !finite_pose(T_wc) || !valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "bad pose or intrinsics");
     if (width <= 0 || height <= 0 || width > 16384 || height > 16384 || !depth || !record)
         return set_error(MVF_ERR_INVALID_ARG, "bad output");
     CHECK_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     CHECK_ST(order_after_previous(c, s));
-    RayParams rp;
-    rp.delta = c->cfg.ray_step * v->voxel_size;
-    rp.kmax = (int32_t)std::floor(c->cfg.t_far / rp.delta);
-    // skip summary of the caller's volume, computed for this call
-    const size_t nb = (size_t)dv.bd[0] * dv.bd[1] * dv.bd[2];
-    if (nb > c->diff_summary_n) {
-        if (c->diff_summary) {
-            CHECK_HIP(hipStreamSynchronize(s));
-            CHECK_HIP(hipFree(c->diff_summary));
-            c->diff_summary = nullptr;
-        }
-        CHECK_HIP(hipMalloc((void**)&c->diff_summary, 5 * nb));
-        c->diff_summary_n = nb;
-    }
-    uint8_t* dist = c->diff_summary + 4 * nb;
-    CHECK_LAUNCH(launch_dense_summary(dv, c->diff_summary, dist, s));
-    dv.dist = dist;
-    CHECK_LAUNCH(launch_diffray_forward(dv, T_wc, K->fx, K->fy, K->cx, K->cy, width, height, rp, depth, record, s));
+    CHECK_ST(build_diff_mirror(c, v, s));
+    mvf_raycast_out out{};
+    out.depth = depth;
+    out.width = width;
+    out.height = height;
+    CHECK_ST(raycast_plain(c, kDiffStream, T_wc, *K, &out, std::vector<int>{c->diff_mirror.vol}, s, record));
     return mark_tail(c, s);
 }
 

@@ -37,7 +37,8 @@ def test_struct_layouts_match_header_sizes():
     from paper_1511_07106_amd import _lib as L
     structs = ["mvf_config", "mvf_grid_desc", "mvf_volume_desc", "mvf_intrinsics", "mvf_frame",
                "mvf_raycast_out", "mvf_stats", "mvf_stream_frame", "mvf_placement_params",
-               "mvf_placement_result", "mvf_dense_tsdf", "mvf_placement_class", "mvf_placement_class_params"]
+               "mvf_placement_result", "mvf_dense_tsdf", "mvf_placement_class", "mvf_placement_class_params",
+               "mvf_track_model", "mvf_track_params", "mvf_track_stats"]
     src = '#include <stdio.h>\n#include "mvf.h"\nint main(){\n' + "".join(
         f'printf("{s} %zu\\n", sizeof({s}));\n' for s in structs) + "return 0;}\n"
     with tempfile.TemporaryDirectory() as d:

@@ -54,6 +54,43 @@ def test_forward_matches_oracle(mvf, fused):
         assert dd.max() <= 1e-4
 
 
+def test_forward_generation_reuses_and_rebuilds(mvf, fused):
+    """The forward's copy of (F, W): a non-zero generation reuses it (the
+    same results as a rebuild on every call), a new generation after F
+    changed rebuilds it (the result follows the new field), and a second
+    volume of another shape replaces it."""
+    import torch
+    seq, og, ov = fused
+    K = seq.K.as_array()
+    T = S.perturb_pose(seq.poses[2], np.random.default_rng(13), 0.02, 2.0)
+    log("diffray forward generations 96^3")
+    with mvf.Context() as ctx:
+        F, W = _dense(ov)
+        d0, r0 = ctx.diffray_forward(F, W, og.origin, og.voxel_size, T, K, 320, 240)
+        d1, r1 = ctx.diffray_forward(F, W, og.origin, og.voxel_size, T, K, 320, 240, generation=7)
+        d2, r2 = ctx.diffray_forward(F, W, og.origin, og.voxel_size, T, K, 320, 240, generation=7)
+        assert torch.equal(d0, d1) and torch.equal(d1, d2) and torch.equal(r0, r2)
+        # shift the field by a quarter voxel's worth of truncation units
+        F2 = F - 0.0625
+        F.copy_(F2)
+        F32 = (ov.F32() - np.float32(0.0625)).astype(np.float32)
+        d3, r3 = ctx.diffray_forward(F, W, og.origin, og.voxel_size, T, K, 320, 240, generation=8)
+        rc = O.raycast([ov], og, K, T, 320, 240, F32=[F32])
+        np.testing.assert_array_equal(r3.cpu().numpy(), rc["k"])
+        hit = rc["k"] >= 0
+        dd = np.abs(d3.cpu().numpy().astype(np.float64) - rc["depth"])[hit]
+        assert dd.max() <= 1e-4
+        assert not torch.equal(d3, d1)
+        # another shape: a crop of the volume
+        Fc, Wc = F[8:72, 4:90, 10:60].contiguous(), W[8:72, 4:90, 10:60].contiguous()
+        d4, r4 = ctx.diffray_forward(Fc, Wc, og.origin, og.voxel_size, T, K, 320, 240, offset=(10, 4, 8),
+                                     generation=8)
+        crop = O.OVolume((50, 86, 64), (10, 4, 8), F32[8:72, 4:90, 10:60].astype(np.float64),
+                         ov.W[8:72, 4:90, 10:60].copy(), np.zeros((64, 86, 50, 4), np.uint8))
+        rc4 = O.raycast([crop], og, K, T, 320, 240, F32=[F32[8:72, 4:90, 10:60].copy()])
+        np.testing.assert_array_equal(r4.cpu().numpy(), rc4["k"])
+
+
 def test_backward_matches_oracle_gradient(mvf, fused):
     seq, og, ov = fused
     K = seq.K.as_array()
