@@ -416,6 +416,7 @@ ICP_ITERS = (10, 5, 4)        # iterations at levels 0 (full), 1, 2; run coarse 
 ICP_EPS_D = 0.1               # metres
 ICP_COS_THETA = float(np.float32(np.cos(np.radians(20.0))))
 ICP_TAU = 0.03                # pyramid: depths within this of the block's first valid one
+ICP_SMOOTH = 0.09             # smoothing: neighbours within this of the centre depth (3 x 3 cm)
 
 
 def level_K(K, level: int) -> np.ndarray:
@@ -424,6 +425,16 @@ def level_K(K, level: int) -> np.ndarray:
     sc = np.float32(0.5 ** level)
     h = np.float32(0.5)
     return _f32([K[0] * sc, K[1] * sc, (K[2] + h) * sc - h, (K[3] + h) * sc - h])
+
+
+def depth_smooth(depth, delta: float = ICP_SMOOTH) -> np.ndarray:
+    """Edge-preserving 7x7 binomial smoothing of a depth map (neighbours
+    within delta metres of the centre; invalid pixels give 0)."""
+    d = _f32(depth)
+    h, w = d.shape
+    out = np.zeros_like(d)
+    lib().orc_depth_smooth(_p(d), C.c_int(w), C.c_int(h), C.c_float(delta), _p(out))
+    return out
 
 
 def depth_pyramid(depth, levels: int = ICP_LEVELS, tau: float = ICP_TAU) -> List[np.ndarray]:
@@ -479,15 +490,16 @@ def icp_reduce(V, N, Vm, Nm, K_level, T, Tm, eps_d: float = ICP_EPS_D, cos_theta
 
 
 def icp_track(depth, K, Vm0, Nm0, Tm, T_init, iters=ICP_ITERS, eps_d: float = ICP_EPS_D,
-              cos_theta: float = ICP_COS_THETA, tau: float = ICP_TAU):
+              cos_theta: float = ICP_COS_THETA, tau: float = ICP_TAU, smooth: float = ICP_SMOOTH):
     """Pose of the frame `depth` against the model maps (Vm0, Nm0: world
     vertex and normal maps rendered at pose Tm, full resolution), from the
-    estimate T_init: levels coarse to fine, `iters[l]` Gauss-Newton steps at
-    level l, each solving A xi = -b (binary64) and applying T <- Exp(xi) T.
-    A step with fewer than 6 pairs, or whose A is not positive definite, leaves
-    T unchanged.  Returns (T, per-step list of (level, pairs, sum r^2))."""
+    estimate T_init: the depth smoothed (smooth > 0) then its pyramid; levels
+    coarse to fine, `iters[l]` Gauss-Newton steps at level l, each solving
+    A xi = -b (binary64) and applying T <- Exp(xi) T.  A step with fewer than
+    6 pairs, or whose A is not positive definite, leaves T unchanged.
+    Returns (T, per-step list of (level, pairs, sum r^2))."""
     levels = len(iters)
-    D = depth_pyramid(depth, levels, tau)
+    D = depth_pyramid(depth_smooth(depth, smooth) if smooth > 0 else depth, levels, tau)
     Vm, Nm = [_f32(Vm0)], [_f32(Nm0)]
     for _ in range(1, levels):
         v2, n2 = model_down(Vm[-1], Nm[-1])

@@ -694,6 +694,39 @@ int orc_extract(const int32_t dims[3], const int32_t off[3], const float* F,
  * ------------------------------------------------------------------------ */
 static inline int depth_ok(float d) { return d > 0.0f && d <= 3.4e38f; }
 
+/* Edge-preserving smoothing of the depth map before tracking (the
+ * KinectFusion tracker the paper cites smooths its input with a bilateral
+ * filter; here its range kernel is a window): for a valid pixel p,
+ * D_s(p) = sum_q w(q - p) D(q) / sum_q w(q - p) over the valid q of the 7x7
+ * window around p inside the image with |D(q) - D(p)| <= delta, with the
+ * binomial weights w(dx, dy) = C(6, dx + 3) C(6, dy + 3); invalid pixels
+ * give 0.  Products and sums in binary32, the window row by row. */
+int orc_depth_smooth(const float* D, int w, int h, float delta, float* out)
+{
+    static const float c6[7] = { 1.0f, 6.0f, 15.0f, 20.0f, 15.0f, 6.0f, 1.0f };
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            const float d0 = D[(int64_t)y * w + x];
+            if (!depth_ok(d0)) { out[(int64_t)y * w + x] = 0.0f; continue; }
+            float num = 0.0f, den = 0.0f;
+            for (int dy = -3; dy <= 3; ++dy) {
+                const int yy = y + dy;
+                if (yy < 0 || yy >= h) continue;
+                for (int dx = -3; dx <= 3; ++dx) {
+                    const int xx = x + dx;
+                    if (xx < 0 || xx >= w) continue;
+                    const float d = D[(int64_t)yy * w + xx];
+                    if (!depth_ok(d) || !(fabsf(d - d0) <= delta)) continue;
+                    const float wt = c6[dx + 3] * c6[dy + 3];
+                    num = num + wt * d;
+                    den = den + wt;
+                }
+            }
+            out[(int64_t)y * w + x] = num / den;
+        }
+    return 0;
+}
+
 /* Level l+1 depth (w2 = w / 2, h2 = h / 2) from level l. */
 int orc_depth_down(const float* D, int w, int h, float tau, float* D2)
 {
