@@ -520,7 +520,7 @@ def phase_table1(mvf, torch, n_frames=90):
     return res
 
 
-def phase_passing(mvf, torch, counts=(1, 2, 4, 8, 16), frames=6, warmup=2):
+def phase_passing(mvf, torch, counts=(1, 2, 4, 8, 16), frames=6, warmup=3):
     """The paper's memory-passing regime (its runtime experiment): N volumes of
     512^3 (1.5 m, 2.93 mm voxels) in a 4 x 2 x 2 block in front of the camera,
     all in view, every voxel in front of a far plane and so updated in every
@@ -625,6 +625,7 @@ def phase_tracking(mvf, torch, n_frames=100):
             R = T[:, :3].T @ Tg[:, :3]
             err_r.append(float(np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1)))))
     return {"frames": n_frames, "iters": [10, 5, 4], "track_ms_median": float(np.median(t_track)),
+            "trans_err_mm_first5": [round(e, 3) for e in err_t[:5]],
             "integrate_raycast_ms_median": float(np.median(t_rest)),
             "trans_err_mm_mean": float(np.mean(err_t)), "trans_err_mm_max": float(np.max(err_t)),
             "trans_err_mm_last": err_t[-1], "rot_err_deg_mean": float(np.mean(err_r)),

@@ -418,7 +418,7 @@ typedef struct {
     float eps_d;        /* association distance, metres (> 0) */
     float cos_theta;    /* association normal test |n . n_model| >= cos_theta, in [0, 1] */
     float tau;          /* pyramid: depths within tau metres of the 2x2 block's first valid one */
-    int32_t reserved;
+    float smooth;       /* smoothing window: neighbours within this many metres of the centre depth; 0 = none */
 } mvf_track_params;
 
 typedef struct {
@@ -429,15 +429,19 @@ typedef struct {
 
 /* Depth Map Conversion alone: the vertex map v = K^-1 [x y 1]^T D and the
  * normal map (v(x+1, y) - v(x, y)) x (v(x, y+1) - v(x, y)), normalised, of
- * pyramid level `level` (0..2; the pyramid as in mvf_track, with tau), in
- * camera coordinates, NaN where undefined: device float32 V and N of
- * (height >> level) x (width >> level) x 3 each.  Runs on `stream` (it
- * synchronises it when level > 0, to free the pyramid). */
+ * pyramid level `level` (0..2; smoothing and pyramid as in mvf_track, with
+ * smooth and tau), in camera coordinates, NaN where undefined: device
+ * float32 V and N of (height >> level) x (width >> level) x 3 each.  Runs
+ * on `stream` and synchronises it (to free its temporaries). */
 mvf_status mvf_depth_maps(mvf_ctx* ctx, const mvf_frame* frame, const mvf_intrinsics* K, int32_t level,
-                          float tau, float* V, float* N, void* stream);
+                          float tau, float smooth, float* V, float* N, void* stream);
 /* Pose of a depth frame by projective point-to-plane ICP (Camera Tracking:
  * the KinectFusion tracker the paper cites), from the estimate T_init
  * (host, row-major 3x4 camera-to-world, binary64) to T_out.
+ * The depth is first smoothed (smooth > 0): a valid pixel takes the mean of
+ * the valid depths of its 7x7 window within `smooth` metres of its own,
+ * weighted by the binomial C(6, dx + 3) C(6, dy + 3) (an edge-preserving
+ * filter, as the KinectFusion tracker smooths its input).
  * Depth map conversion: vertex v = K^-1 [x y 1]^T D, normal n = (v(x+1, y)
  * - v(x, y)) x (v(x, y+1) - v(x, y)) normalised; a pyramid of `levels`
  * depth maps, level l+1 the mean of each 2x2 block's valid depths within

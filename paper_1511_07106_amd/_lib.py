@@ -108,7 +108,7 @@ class mvf_track_model(C.Structure):
 
 class mvf_track_params(C.Structure):
     _fields_ = [("levels", C.c_int32), ("iters", C.c_int32 * 3), ("eps_d", C.c_float), ("cos_theta", C.c_float),
-                ("tau", C.c_float), ("reserved", C.c_int32)]
+                ("tau", C.c_float), ("smooth", C.c_float)]
 
 
 class mvf_track_stats(C.Structure):
@@ -167,7 +167,7 @@ SIGNATURES = {
                              P, P],
     "mvf_diffray_backward_noalloc": [P, C.POINTER(mvf_dense_tsdf), PF, C.POINTER(mvf_intrinsics), I32, I32, P, P,
                                      P, P, P],
-    "mvf_depth_maps": [P, C.POINTER(mvf_frame), C.POINTER(mvf_intrinsics), I32, C.c_float, P, P, P],
+    "mvf_depth_maps": [P, C.POINTER(mvf_frame), C.POINTER(mvf_intrinsics), I32, C.c_float, C.c_float, P, P, P],
     "mvf_track": [P, C.POINTER(mvf_frame), C.POINTER(mvf_intrinsics), C.POINTER(mvf_track_model), PD,
                   C.POINTER(mvf_track_params), PD, C.POINTER(mvf_track_stats), P],
     "mvf_pose_retract": [PD, PD, PD],

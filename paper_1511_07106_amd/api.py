@@ -385,22 +385,23 @@ class Context:
         return list(r.added[:r.n_added]), list(r.removed[:r.n_removed]), r.n_cells
 
     # -- camera tracking ------------------------------------------------------
-    def depth_maps(self, depth, K, level: int = 0, tau: float = 0.03, stream=None):
+    def depth_maps(self, depth, K, level: int = 0, tau: float = 0.03, smooth: float = 0.09, stream=None):
         """Vertex and normal maps ((h >> level, w >> level, 3) float32 tensors,
-        camera frame, NaN where undefined) of a depth frame's pyramid level."""
+        camera frame, NaN where undefined) of a depth frame's pyramid level
+        (after the edge-preserving smoothing when smooth > 0)."""
         torch = _torch()
         f = self._frame(depth, None)
         H, W = depth.shape
         dev = depth.device
         V = torch.empty((H >> level, W >> level, 3), dtype=torch.float32, device=dev)
         N = torch.empty_like(V)
-        L.check(self.lib.mvf_depth_maps(self.h, C.byref(f), C.byref(_K(K)), int(level), float(tau),
+        L.check(self.lib.mvf_depth_maps(self.h, C.byref(f), C.byref(_K(K)), int(level), float(tau), float(smooth),
                                         C.c_void_p(V.data_ptr()), C.c_void_p(N.data_ptr()), _stream(stream)),
                 "mvf_depth_maps")
         return V, N
 
     def track(self, depth, K, model, T_model, T_init, iters=(10, 5, 4), eps_d: float = 0.1,
-              cos_theta: float = 0.9396926164627075, tau: float = 0.03, stream=None):
+              cos_theta: float = 0.9396926164627075, tau: float = 0.03, smooth: float = 0.09, stream=None):
         """Pose of `depth` by projective point-to-plane ICP against `model`
         (a dict with the previous raycast's "vertex" and "normal" maps, world
         frame, rendered at T_model), from T_init.  iters: Gauss-Newton steps
@@ -418,7 +419,7 @@ class Context:
         p.levels = len(iters)
         for i, n in enumerate(iters):
             p.iters[i] = int(n)
-        p.eps_d, p.cos_theta, p.tau = float(eps_d), float(cos_theta), float(tau)
+        p.eps_d, p.cos_theta, p.tau, p.smooth = float(eps_d), float(cos_theta), float(tau), float(smooth)
         Ti = np.ascontiguousarray(np.asarray(T_init, np.float64).reshape(12))
         To = np.zeros(12)
         st = L.mvf_track_stats()

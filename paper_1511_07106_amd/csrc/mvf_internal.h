@@ -315,6 +315,8 @@ struct TrackLaunch {
     uint8_t* inlier;     // per current pixel, or null
 };
 
+// Edge-preserving smoothing of a depth map (out: w x h, pitch w).
+int launch_track_smooth(const float* D, int pitch, int w, int h, float delta, float* out, void* stream);
 int launch_track_down(const float* D, int pitch, int w, int h, float tau, float* D2, void* stream);
 int launch_track_vn(const float* D, int pitch, int w, int h, const float K[4], float* V, float* N, void* stream);
 int launch_track_model_down(const float* V, const float* N, int w, int h, float* V2, float* N2, void* stream);

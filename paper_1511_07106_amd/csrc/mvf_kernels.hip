@@ -587,6 +587,10 @@ static __device__ bool brick_may_update(const DevVolume& V, const DevFrame& Fr, 
 // IntegrateLaunch) and each frame's maximum range from the frame-preparation
 // block maxima.  Blocks beyond: the items' brick visit masks.
 constexpr int kZtBlocks = 16;
+// visited items a z-table block holds in LDS before appending them
+constexpr int kZtListBuf = 1024;
+// most blocks of the visit pass (each appends its items with one atomic per flush)
+constexpr int kZtCullBlocksMax = 512;
 
 __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
 {
@@ -600,6 +604,25 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
         const int zchunk = hdr->zchunk;
         const int total = hdr->total_items * zchunk;
         const int stride = (gridDim.x - kZtBlocks) * blockDim.x;
+        const int lane = threadIdx.x & 63;
+        const int wib = threadIdx.x >> 6;
+        // the block's visited items (heads of items with a visited brick),
+        // gathered in LDS over its iterations and appended with one counter
+        // atomic per flush: one atomic per wavefront on a single address
+        // serialised in the L2 and cost ~20 us per frame
+        __shared__ int32_t blk_items[kZtListBuf];
+        __shared__ int blk_n, blk_base;
+        __shared__ int wave_n[4];
+        if (threadIdx.x == 0) blk_n = 0;
+        __syncthreads();
+        auto flush = [&]() {
+            if (threadIdx.x == 0) blk_base = blk_n ? (int)atomicAdd(&L.list_count[L.hdr->list_parity], (uint32_t)blk_n) : 0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < blk_n; i += blockDim.x) L.list[blk_base + i] = blk_items[i];
+            __syncthreads();
+            if (threadIdx.x == 0) blk_n = 0;
+            __syncthreads();
+        };
         for (int t0 = (blockIdx.x - kZtBlocks) * blockDim.x; t0 < total; t0 += stride) {
             const int t = min(t0 + (int)threadIdx.x, total - 1);
             const int item = t / zchunk, j = t - item * zchunk;
@@ -641,22 +664,29 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
             const bool valid = t0 + (int)threadIdx.x < total;
             if (valid) L.visit[(size_t)item * kVisitPerItem + j] = visit ? 1 : 0;
             if (L.list) {
-                // append the items of this wavefront (64 / zchunk whole items:
-                // t0 is a multiple of the block size and zchunk divides 64)
-                // that have a visited brick, in item order within the wavefront
-                const int lane = threadIdx.x & 63;
+                // the items of this wavefront (64 / zchunk whole items: t0
+                // is a multiple of the block size and zchunk divides 64)
+                // with a visited brick, in item order within the block
                 const uint64_t m = __ballot(valid && visit);
                 const uint64_t grp = (m >> (lane & ~(zchunk - 1))) & ((1ull << zchunk) - 1ull);
                 const bool head = valid && j == 0 && grp != 0;
                 const uint64_t hm = __ballot(head);
-                if (hm) {
-                    uint32_t base = 0;
-                    if (lane == 0) base = atomicAdd(&L.list_count[L.hdr->list_parity], (uint32_t)__popcll(hm));
-                    base = __shfl(base, 0);
-                    if (head) L.list[base + __popcll(hm & ((1ull << lane) - 1ull))] = item;
+                if (lane == 0) wave_n[wib] = (int)__popcll(hm);
+                __syncthreads();
+                int off = blk_n, sum = 0;
+                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                    if (w < wib) off += wave_n[w];
+                    sum += wave_n[w];
                 }
+                if (head) blk_items[off + __popcll(hm & ((1ull << lane) - 1ull))] = item;
+                __syncthreads();
+                if (threadIdx.x == 0) blk_n += sum;
+                __syncthreads();
+                // room for the next iteration's items (at most one per thread)
+                if (blk_n + (int)blockDim.x > kZtListBuf) flush();
             }
         }
+        if (L.list) flush();
         return;
     }
     // the other count, for the next launch (the previous one, which used it,
@@ -695,7 +725,8 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
 
 int launch_ztable(const IntegrateLaunch& L, int cull_blocks, void* stream)
 {
-    const int blocks = kZtBlocks + (L.visit ? (cull_blocks > 1 ? cull_blocks : 1) : 0);
+    const int cb = cull_blocks < 1 ? 1 : (cull_blocks > kZtCullBlocksMax ? kZtCullBlocksMax : cull_blocks);
+    const int blocks = kZtBlocks + (L.visit ? cb : 0);
     hipLaunchKernelGGL(mvf_ztable_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, L);
     return (int)hipGetLastError();
 }

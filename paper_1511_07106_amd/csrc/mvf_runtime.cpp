@@ -2503,13 +2503,13 @@ mvf_status mvf_placement_update(mvf_ctx* c, int32_t sid, const mvf_frame* f, con
 // ---- camera tracking ---------------------------------------------------------------
 
 mvf_status mvf_depth_maps(mvf_ctx* c, const mvf_frame* f, const mvf_intrinsics* K, int32_t level, float tau,
-                          float* V, float* N, void* stream)
+                          float smooth, float* V, float* N, void* stream)
 {
     if (!c || !V || !N) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
     CHECK_ST(check_frame(f));
     if (!valid_K(K)) return set_error(MVF_ERR_INVALID_ARG, "intrinsics NULL, not finite or zero focal length");
     if (level < 0 || level > 2) return set_error(MVF_ERR_INVALID_ARG, "level must be in [0, 2]");
-    if (!(tau >= 0.0f)) return set_error(MVF_ERR_INVALID_ARG, "tau must be >= 0");
+    if (!(tau >= 0.0f) || !(smooth >= 0.0f)) return set_error(MVF_ERR_INVALID_ARG, "tau and smooth must be >= 0");
     if ((f->width >> level) < 1 || (f->height >> level) < 1)
         return set_error(MVF_ERR_INVALID_ARG, "image too small for level %d", level);
     CHECK_HIP(hipSetDevice(c->device));
@@ -2517,8 +2517,19 @@ mvf_status mvf_depth_maps(mvf_ctx* c, const mvf_frame* f, const mvf_intrinsics* 
     CHECK_ST(order_after_previous(c, s));
     int w = f->width, h = f->height, pitch = f->depth_pitch ? f->depth_pitch : f->width;
     const float* D = f->depth;
-    float* tmp[2] = {nullptr, nullptr};
+    float* tmp[3] = {nullptr, nullptr, nullptr};
     mvf_status st = MVF_OK;
+    if (smooth > 0.0f) {
+        if (hipMalloc((void**)&tmp[2], sizeof(float) * (size_t)w * h) != hipSuccess) {
+            (void)hipGetLastError();
+            st = set_error(MVF_ERR_OOM, "smoothed depth");
+        } else {
+            const int le = launch_track_smooth(D, pitch, w, h, smooth, tmp[2], s);
+            if (le) st = set_error(MVF_ERR_HIP, "launch: %s", hipGetErrorString((hipError_t)le));
+            D = tmp[2];
+            pitch = w;
+        }
+    }
     for (int l = 1; l <= level && st == MVF_OK; ++l) {
         if (hipMalloc((void**)&tmp[l - 1], sizeof(float) * (size_t)(w / 2) * (h / 2)) != hipSuccess) {
             (void)hipGetLastError();
@@ -2538,7 +2549,7 @@ mvf_status mvf_depth_maps(mvf_ctx* c, const mvf_frame* f, const mvf_intrinsics* 
         const int le = launch_track_vn(D, pitch, w, h, Kl, V, N, s);
         if (le) st = set_error(MVF_ERR_HIP, "launch: %s", hipGetErrorString((hipError_t)le));
     }
-    if (tmp[0] || tmp[1]) {
+    if (tmp[0] || tmp[1] || tmp[2]) {
         const hipError_t e = hipStreamSynchronize(s);
         for (float* t : tmp)
             if (t) (void)hipFree(t);
@@ -2569,8 +2580,9 @@ mvf_status mvf_track(mvf_ctx* c, const mvf_frame* f, const mvf_intrinsics* K, co
         nsteps += p->iters[l];
     }
     if (nsteps > kTrackMaxSteps) return set_error(MVF_ERR_INVALID_ARG, "more than %d steps", kTrackMaxSteps);
-    if (!(p->eps_d > 0.0f) || !(p->cos_theta >= 0.0f && p->cos_theta <= 1.0f) || !(p->tau >= 0.0f))
-        return set_error(MVF_ERR_INVALID_ARG, "eps_d > 0, cos_theta in [0, 1] and tau >= 0 required");
+    if (!(p->eps_d > 0.0f) || !(p->cos_theta >= 0.0f && p->cos_theta <= 1.0f) || !(p->tau >= 0.0f) ||
+        !(p->smooth >= 0.0f))
+        return set_error(MVF_ERR_INVALID_ARG, "eps_d > 0, cos_theta in [0, 1], tau >= 0 and smooth >= 0 required");
     if ((f->width >> (p->levels - 1)) < 1 || (f->height >> (p->levels - 1)) < 1)
         return set_error(MVF_ERR_INVALID_ARG, "image too small for %d levels", p->levels);
     CHECK_HIP(hipSetDevice(c->device));
@@ -2584,6 +2596,8 @@ mvf_status mvf_track(mvf_ctx* c, const mvf_frame* f, const mvf_intrinsics* K, co
     for (int l = 1; l < 3; ++l) { w[l] = w[l - 1] / 2; h[l] = h[l - 1] / 2; }
     size_t off = 0;
     size_t o_d[3] = {0, 0, 0}, o_v[3], o_n[3], o_vm[3] = {0, 0, 0}, o_nm[3] = {0, 0, 0};
+    const size_t o_smooth = off;   // the smoothed full-size depth
+    if (p->smooth > 0.0f) off = align_up(off + 4 * (size_t)w[0] * h[0], kAlign);
     for (int l = 0; l < p->levels; ++l) {
         const size_t npx = (size_t)w[l] * h[l];
         if (l) { o_d[l] = off; off = align_up(off + 4 * npx, kAlign); }
@@ -2626,6 +2640,12 @@ mvf_status mvf_track(mvf_ctx* c, const mvf_frame* f, const mvf_intrinsics* K, co
     float Kl[3][4];
     D[0] = f->depth;
     pitch[0] = f->depth_pitch ? f->depth_pitch : f->width;
+    if (p->smooth > 0.0f) {
+        float* Ds = reinterpret_cast<float*>(B + o_smooth);
+        CHECK_LAUNCH(launch_track_smooth(D[0], pitch[0], w[0], h[0], p->smooth, Ds, s));
+        D[0] = Ds;
+        pitch[0] = w[0];
+    }
     for (int l = 0; l < p->levels; ++l) {
         if (l) {
             float* Dl = reinterpret_cast<float*>(B + o_d[l]);

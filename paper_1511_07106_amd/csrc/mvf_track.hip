@@ -23,6 +23,49 @@ static __device__ __forceinline__ bool depth_valid(float d) { return d > 0.0f &&
 
 static __device__ __forceinline__ float qnanf() { return __builtin_nanf(""); }
 
+// Edge-preserving smoothing before the pyramid: for a valid pixel the
+// binomial-weighted (C(6, dx + 3) C(6, dy + 3)) mean of the valid depths of
+// its 7x7 window inside the image within delta of its own depth; invalid
+// pixels give 0.  Binary32, the window row by row (the weights and their
+// sums are small integers, exact).  A 16x16 tile of pixels reads its
+// 22x22 neighbourhood from LDS.
+__global__ __launch_bounds__(256) void mvf_track_smooth_kernel(const float* __restrict__ D, int pitch, int w, int h,
+                                                               float delta, float* __restrict__ out)
+{
+    __shared__ float tile[22][23];
+    const int x0 = blockIdx.x * 16 - 3, y0 = blockIdx.y * 16 - 3;
+    for (int i = threadIdx.x; i < 22 * 22; i += 256) {
+        const int ty = i / 22, tx = i - ty * 22;
+        const int xx = x0 + tx, yy = y0 + ty;
+        tile[ty][tx] = (xx >= 0 && xx < w && yy >= 0 && yy < h) ? D[(size_t)yy * pitch + xx] : 0.0f;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int x = blockIdx.x * 16 + lx, y = blockIdx.y * 16 + ly;
+    if (x >= w || y >= h) return;
+    const float d0 = tile[ly + 3][lx + 3];
+    float r = 0.0f;
+    if (depth_valid(d0)) {
+        const float c6[7] = { 1.0f, 6.0f, 15.0f, 20.0f, 15.0f, 6.0f, 1.0f };
+        float num = 0.0f, den = 0.0f;
+        for (int dy = -3; dy <= 3; ++dy) {
+            const int yy = y + dy;
+            if (yy < 0 || yy >= h) continue;
+            for (int dx = -3; dx <= 3; ++dx) {
+                const int xx = x + dx;
+                if (xx < 0 || xx >= w) continue;
+                const float d = tile[ly + 3 + dy][lx + 3 + dx];
+                if (!depth_valid(d) || !(fabsf(d - d0) <= delta)) continue;
+                const float wt = c6[dx + 3] * c6[dy + 3];
+                num = num + wt * d;
+                den = den + wt;
+            }
+        }
+        r = num / den;
+    }
+    out[(size_t)y * w + x] = r;
+}
+
 // Level l+1 depth (floor(w/2) x floor(h/2)): mean of the valid depths of the
 // 2x2 block within tau of the block's first valid one (order (0,0), (1,0),
 // (0,1), (1,1)), 0 when the block has none.
@@ -291,6 +334,13 @@ __global__ void mvf_track_init_kernel(TrackState* state)
 {
     if (threadIdx.x < 12) state->T32[threadIdx.x] = (float)state->T[threadIdx.x];
     if (threadIdx.x == 0) state->steps = 0;
+}
+
+int launch_track_smooth(const float* D, int pitch, int w, int h, float delta, float* out, void* stream)
+{
+    dim3 grid((w + 15) / 16, (h + 15) / 16);
+    hipLaunchKernelGGL(mvf_track_smooth_kernel, grid, dim3(256), 0, (hipStream_t)stream, D, pitch, w, h, delta, out);
+    return (int)hipGetLastError();
 }
 
 int launch_track_down(const float* D, int pitch, int w, int h, float tau, float* D2, void* stream)

@@ -43,12 +43,13 @@ def test_depth_maps_bit_exact(mvf, which):
         K = np.array([40.0, 41.0, 26.2, 17.9], np.float32)
     log(f"depth maps {which}")
     with mvf.Context() as ctx:
-        D = O.depth_pyramid(d, 3)
-        for lvl in range(3):
-            V, N = ctx.depth_maps(t(d), K, level=lvl)
-            Vo, No = O.vertex_normal(D[lvl], O.level_K(K, lvl))
-            assert V.shape == Vo.shape
-            assert _same_nan(V.cpu().numpy(), Vo) and _same_nan(N.cpu().numpy(), No), lvl
+        for smooth in (0.0, 0.09):
+            D = O.depth_pyramid(O.depth_smooth(d, smooth) if smooth else d, 3)
+            for lvl in range(3):
+                V, N = ctx.depth_maps(t(d), K, level=lvl, smooth=smooth)
+                Vo, No = O.vertex_normal(D[lvl], O.level_K(K, lvl))
+                assert V.shape == Vo.shape
+                assert _same_nan(V.cpu().numpy(), Vo) and _same_nan(N.cpu().numpy(), No), (smooth, lvl)
 
 
 def _fused_model(mvf, ctx, seq, upto, n=512, extent=3.0):
