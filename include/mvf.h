@@ -126,6 +126,10 @@ typedef struct {
 
 /* Create a context on cfg->device.  cfg may be NULL (defaults).  Output
  * *out owns every volume slab and pinned mirror it creates. */
+/* Test hook: when the environment variable MVF_FAULT_SLAB_ALLOCS = n is set
+ * at creation, the context's next n volume-slab allocations fail as if the
+ * device were out of memory (exercising the drop-the-pool-and-retry path
+ * and the MVF_ERR_OOM return). */
 mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg);
 /* Synchronise and free everything the context owns.  NULL is a no-op. */
 mvf_status mvf_destroy(mvf_ctx* ctx);
@@ -215,6 +219,20 @@ mvf_status mvf_volume_describe(mvf_ctx* ctx, int32_t vol_id, mvf_volume_desc* ou
 /* Resident (1) or not (0), device bytes of its slab, active flag. */
 mvf_status mvf_volume_query(mvf_ctx* ctx, int32_t vol_id, int32_t* resident, uint64_t* bytes,
                             int32_t* active);
+
+/* Checkpoint: write the context's grids, volumes (ids, descriptors, active
+ * flags and full state, brick summaries included) and the placement
+ * bookkeeping to the file `path`.  Synchronising.  The library's internal
+ * volumes are not saved.  The file is in this build's memory layout and
+ * host byte order. */
+mvf_status mvf_checkpoint_save(mvf_ctx* ctx, const char* path);
+/* Resume: restore a checkpoint into a context that has no grids or volumes
+ * yet (MVF_ERR_STATE otherwise).  Ids are those of the saved context;
+ * volumes with state come back in host memory (swapped out) and are
+ * uploaded when first needed.  MVF_ERR_INVALID_ARG for a file that is not
+ * such a checkpoint, is truncated, or holds another layout; the context is
+ * then left empty. */
+mvf_status mvf_checkpoint_load(mvf_ctx* ctx, const char* path);
 
 /* ---- per-frame hot path ----------------------------------------------- */
 

@@ -170,6 +170,8 @@ SIGNATURES = {
     "mvf_depth_maps": [P, C.POINTER(mvf_frame), C.POINTER(mvf_intrinsics), I32, C.c_float, C.c_float, P, P, P],
     "mvf_track": [P, C.POINTER(mvf_frame), C.POINTER(mvf_intrinsics), C.POINTER(mvf_track_model), PD,
                   C.POINTER(mvf_track_params), PD, C.POINTER(mvf_track_stats), P],
+    "mvf_checkpoint_save": [P, C.c_char_p],
+    "mvf_checkpoint_load": [P, C.c_char_p],
     "mvf_pose_retract": [PD, PD, PD],
     "mvf_pose_right_jacobian": [PD, PD],
 }

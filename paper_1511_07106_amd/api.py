@@ -8,6 +8,7 @@ Poses are 3x4 camera-to-world [R | t] (OpenCV axes), intrinsics
 from __future__ import annotations
 
 import ctypes as C
+import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -204,6 +205,15 @@ class Context:
         placement update removed: the paper downloads a removed volume's
         point cloud), as {id: extract(id)}."""
         return {int(v): self.extract(int(v), with_index=with_index) for v in vids}
+
+    def save(self, path: str) -> None:
+        """Checkpoint the context (grids, volumes and their state, placement
+        bookkeeping) to `path`."""
+        L.check(self.lib.mvf_checkpoint_save(self.h, os.fsencode(path)), "mvf_checkpoint_save")
+
+    def load(self, path: str) -> None:
+        """Restore a checkpoint into this (empty) context."""
+        L.check(self.lib.mvf_checkpoint_load(self.h, os.fsencode(path)), "mvf_checkpoint_load")
 
     def write_volume(self, vid: int, F=None, W=None, rgba=None) -> None:
         nx, ny, nz = self.dims(vid)

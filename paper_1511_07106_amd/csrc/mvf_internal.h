@@ -87,7 +87,8 @@ struct DevFrame {
     const uint32_t* color;   // H*W packed RGB (may be null)
     float* rmax;             // [0]: max range of the frame (for clipping); [1 + b]: per prep block
     int32_t rmax_parts;      // prep blocks of this frame (ceil(width / 32) * ceil(height / 8))
-    const float* tmax;       // maximum range of each 8x8 pixel tile (row-major), or null
+    const float* tmax;       // maximum range of each 8x8 pixel tile (row-major), then the minimum of each
+                             // (tiles_x * tiles_y further on; 0 where a pixel has no range), or null
     int32_t tiles_x, tiles_y;
     int32_t width, height;
     float fx, fy, cx, cy;
@@ -165,7 +166,8 @@ struct PrepItem {
     float* range;
     uint32_t* color;
     float* rmax;             // [0] frame's maximum range, [1 + b] maximum of prep block b
-    float* tmax;             // maximum range of each 8x8 pixel tile, ceil(width / 8) per row
+    float* tmax;             // maximum range of each 8x8 pixel tile, ceil(width / 8) per row; the
+                             // minima follow (ceil(width / 8) * ceil(height / 8) further on)
 };
 
 // Integration work item: a brick column (8x8 voxel columns) of one volume

@@ -88,20 +88,28 @@ __global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __r
     }
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         it.range[(size_t)it.width * it.height] = 0.0f;
-    // maxima of the block's four 8x8 tiles: a wavefront holds two rows of
-    // 32 pixels, a tile's part of it is 8 consecutive lanes in each half
-    float tm = R;
-    for (int o = 1; o <= 4; o <<= 1) tm = fmaxf(tm, __shfl_xor(tm, o));
+    // maxima and minima of the block's four 8x8 tiles: a wavefront holds
+    // two rows of 32 pixels, a tile's part of it is 8 consecutive lanes in
+    // each half (pixels outside the image count as range 0)
+    float tm = R, tn = R;
+    for (int o = 1; o <= 4; o <<= 1) {
+        tm = fmaxf(tm, __shfl_xor(tm, o));
+        tn = fminf(tn, __shfl_xor(tn, o));
+    }
     tm = fmaxf(tm, __shfl_xor(tm, 32));
+    tn = fminf(tn, __shfl_xor(tn, 32));
     // block maximum into this block's slot; the z-table kernel reduces the
     // slots (no atomics on one address)
     float m = tm;
     for (int o = 8; o <= 16; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
     __shared__ float wmax[4];
-    __shared__ float tw[4][4];
+    __shared__ float tw[4][4], tnw[4][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) wmax[wv] = m;
-    if (lane < 32 && (lane & 7) == 0) tw[wv][lane >> 3] = tm;
+    if (lane < 32 && (lane & 7) == 0) {
+        tw[wv][lane >> 3] = tm;
+        tnw[wv][lane >> 3] = tn;
+    }
     __syncthreads();
     const int gx = (it.width + 31) / 32, gy = (it.height + 7) / 8;
     if (threadIdx.x == 0 && (int)blockIdx.x < gx && (int)blockIdx.y < gy) {
@@ -113,6 +121,9 @@ __global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __r
     if (it.tmax && threadIdx.x < 4 && tx < tiles_x && (int)blockIdx.y < gy) {
         const int t = threadIdx.x;
         it.tmax[blockIdx.y * tiles_x + tx] = fmaxf(fmaxf(tw[0][t], tw[1][t]), fmaxf(tw[2][t], tw[3][t]));
+        // the minima follow the maxima (tiles_x * tiles_y of each)
+        it.tmax[(size_t)tiles_x * gy + blockIdx.y * tiles_x + tx] =
+            fminf(fminf(tnw[0][t], tnw[1][t]), fminf(tnw[2][t], tnw[3][t]));
     }
 }
 
@@ -386,6 +397,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
             const size_t base = colbase + (size_t)bz * kBrickVox;
             GPTR(float) const pF = vF + base;
             GPTR(uint16_t) const pW = vW + base;
+            // the brick's flags after an update that may write F <= 2^-100
+            auto mark = [&](bool flag_here, const bool (&fz)[kBrick / 2]) {
+                if (__ballot(flag_here) != 0) {
+                    uint64_t fm = 0;
+#pragma unroll
+                    for (int zp = 0; zp < kBrick / 2; ++zp)
+                        fm |= (uint64_t)subblock_bits(__ballot(fz[zp])) << (16 * zp);
+                    if (lane == 0) {
+                        const size_t b = brick_index(V.bd, bxi, byi, bz);
+                        V.flag[b] = 1;
+                        atomicOr((unsigned long long*)&V.fmask[b], (unsigned long long)fm);
+                        const size_t cw = (size_t)(bxi * V.bd[1] + byi) * col_words(V.bd[2]) + (bz >> 6);
+                        atomicOr((unsigned long long*)&V.colm[cw], 1ull << (bz & 63));
+                    }
+                }
+            };
+            if ((vis >> (8 * (bz - bz0) + 1)) & 1ull) {
+                // deep brick (the visit pass proved R - rho > mu for every
+                // voxel): each voxel inside the volume is updated with
+                // phi = 1 and none is in the colour band, so the projection
+                // and the range gathers are not needed
+                const int nz_here = min(kBrick, V.dims[2] - zb);
+                float Fo[kBrick];
+                uint16_t Wo[kBrick];
+                bool uv[kBrick];
+#pragma unroll
+                for (int zz = 0; zz < kBrick; ++zz) {
+                    uv[zz] = col_ok & (zz < nz_here);
+                    Fo[zz] = 0.0f;
+                    Wo[zz] = 0;
+                    if (uv[zz]) {
+                        Fo[zz] = __builtin_nontemporal_load(&pF[zz * 64]);
+                        Wo[zz] = __builtin_nontemporal_load(&pW[zz * 64]);
+                    }
+                }
+                bool flag_here = false;
+                bool fz[kBrick / 2] = {false, false, false, false};
+#pragma unroll
+                for (int zz = 0; zz < kBrick; ++zz) {
+                    n_upd += (unsigned)__popcll(__ballot(uv[zz]));
+                    const int w = Wo[zz];
+                    const float Wf = (float)w;
+                    const float den = Wf + 1.0f;
+                    float r = __builtin_amdgcn_rcpf(den);
+                    r = fmaf(r, fmaf(-den, r, 1.0f), r);
+                    const float Fn = (w == 0) ? 1.0f : fmaf(Fo[zz], Wf, 1.0f) * r;
+                    if (uv[zz]) {
+                        pF[zz * 64] = Fn;
+                        pW[zz * 64] = (uint16_t)min(w + 1, V.w_max);
+                    }
+                    const bool fl = uv[zz] & (Fn <= kFlagThreshold);
+                    flag_here |= fl;
+                    fz[zz >> 1] |= fl;
+                }
+                mark(flag_here, fz);
+                continue;
+            }
             // the brick's 8 z-table entries, one scalar block
             struct ZRow { float v[3 * kBrick]; };
             const ZRow zr = *(CPTR(ZRow))(ztab + 3 * (V.zt_base + zb));
@@ -508,19 +576,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
                     }
                 }
             }
-            if (__ballot(flag_here) != 0) {
-                uint64_t fm = 0;
-#pragma unroll
-                for (int zp = 0; zp < kBrick / 2; ++zp)
-                    fm |= (uint64_t)subblock_bits(__ballot(fz[zp])) << (16 * zp);
-                if (lane == 0) {
-                    const size_t b = brick_index(V.bd, bxi, byi, bz);
-                    V.flag[b] = 1;
-                    atomicOr((unsigned long long*)&V.fmask[b], (unsigned long long)fm);
-                    const size_t cw = (size_t)(bxi * V.bd[1] + byi) * col_words(V.bd[2]) + (bz >> 6);
-                    atomicOr((unsigned long long*)&V.colm[cw], 1ull << (bz & 63));
-                }
-            }
+            mark(flag_here, fz);
         }
     }
     // counters: the wave's totals (the same in every lane), one atomic each
@@ -533,26 +589,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
     }
 }
 
-// Whether brick [lo, hi] (the box of its voxel centres, world frame) may
-// hold a voxel that the frame updates.  It may not when it projects outside
-// the image, when the pixels it projects to hold no measurement, or when
-// every voxel centre lies farther from the camera than mu beyond the
-// largest range of those pixels (then R - rho < -mu for each voxel).  The
-// pixels are bounded by the 8x8 tiles under the projected box grown by one
-// pixel (at most 4x4 tiles are read; a larger footprint is visited);
-// margins of 1e-4 m plus 1e-5 of the distance cover the binary32 rounding
-// of the voxel test.  Anything else is visited.
-static __device__ bool brick_may_update(const DevVolume& V, const DevFrame& Fr, const float lo[3], const float hi[3])
+// Class of brick [lo, hi] (the box of its voxel centres, world frame) for
+// the frame: 0 when no voxel of it can be updated, 2 when every voxel of it
+// inside the volume is updated with phi = 1 and lies outside the colour band
+// ("deep": in front of the measured surface by more than mu everywhere),
+// else 1 (visited, decided voxel by voxel).
+// - 0: the box projects outside the image, or the pixels it projects to
+//   hold no measurement, or every voxel centre lies farther from the camera
+//   than mu beyond the largest range of those pixels (then R - rho < -mu).
+// - 2: the box lies in front of the camera and its projection, grown by a
+//   pixel, inside the image, so every voxel's nearest pixel is in the image
+//   and among the tiles read; those tiles hold valid ranges only, and their
+//   smallest range exceeds the farthest voxel distance by more than mu.
+//   Then R - rho > mu for every voxel: the update test passes, phi = 1 and
+//   the band test fails, whatever the voxel.
+// The pixels are bounded by the 8x8 tiles (maxima and minima of the range)
+// under the projected box grown by one pixel (at most 4x4 tiles are read; a
+// larger footprint is class 1); margins of 1e-4 m plus 1e-5 of the distance
+// cover the binary32 rounding of the voxel test.
+static __device__ int brick_class(const DevVolume& V, const DevFrame& Fr, const float lo[3], const float hi[3])
 {
     const float c[3] = {Fr.T[3], Fr.T[7], Fr.T[11]};
-    float d2 = 0.0f;
+    float d2 = 0.0f, d2f = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float e = fmaxf(fmaxf(lo[a] - c[a], c[a] - hi[a]), 0.0f);
+        const float f = fmaxf(fabsf(lo[a] - c[a]), fabsf(hi[a] - c[a]));
         d2 += e * e;
+        d2f += f * f;
     }
     const float dmin = sqrtf(d2) * (1.0f - 1e-5f) - 1e-4f;
-    if (!(dmin > V.mu)) return true;
+    if (!(dmin > V.mu)) return 1;
     float u0 = INFINITY, u1 = -INFINITY, v0 = INFINITY, v1 = -INFINITY;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -562,25 +629,36 @@ static __device__ bool brick_may_update(const DevVolume& V, const DevFrame& Fr, 
         const float px = Fr.T[0] * dx + Fr.T[4] * dy + Fr.T[8] * dz;
         const float py = Fr.T[1] * dx + Fr.T[5] * dy + Fr.T[9] * dz;
         const float pz = Fr.T[2] * dx + Fr.T[6] * dy + Fr.T[10] * dz;
-        if (!(pz > 0.01f)) return true;
+        if (!(pz > 0.01f)) return 1;
         const float iz = __builtin_amdgcn_rcpf(pz);  // relative error 2^-22: far inside the margin
         const float u = Fr.fx * px * iz + Fr.cx;
         const float v = Fr.fy * py * iz + Fr.cy;
         u0 = fminf(u0, u); u1 = fmaxf(u1, u);
         v0 = fminf(v0, v); v1 = fmaxf(v1, v);
     }
-    const float a0 = fmaxf(floorf(u0 - 0.5f), 0.0f), a1 = fminf(floorf(u1 + 1.5f), (float)(Fr.width - 1));
-    const float b0 = fmaxf(floorf(v0 - 0.5f), 0.0f), b1 = fminf(floorf(v1 + 1.5f), (float)(Fr.height - 1));
-    if (!(a0 <= a1 && b0 <= b1)) return false;  // outside the image
+    const float g0 = floorf(u0 - 0.5f), g1 = floorf(u1 + 1.5f);
+    const float h0 = floorf(v0 - 0.5f), h1 = floorf(v1 + 1.5f);
+    const bool inside = g0 >= 0.0f && g1 <= (float)(Fr.width - 1) && h0 >= 0.0f && h1 <= (float)(Fr.height - 1);
+    const float a0 = fmaxf(g0, 0.0f), a1 = fminf(g1, (float)(Fr.width - 1));
+    const float b0 = fmaxf(h0, 0.0f), b1 = fminf(h1, (float)(Fr.height - 1));
+    if (!(a0 <= a1 && b0 <= b1)) return 0;  // outside the image
     const int ta0 = (int)a0 >> 3, tb0 = (int)b0 >> 3;
     const int nx = ((int)a1 >> 3) - ta0 + 1, ny = ((int)b1 >> 3) - tb0 + 1;
-    if (nx > 4 || ny > 4) return true;
-    float mR = 0.0f;
+    if (nx > 4 || ny > 4) return 1;
+    const float* tmin = Fr.tmax + (size_t)Fr.tiles_x * Fr.tiles_y;
+    float mR = 0.0f, mn = INFINITY;
 #pragma unroll
     for (int k = 0; k < 16; ++k)
-        if ((k & 3) < nx && (k >> 2) < ny) mR = fmaxf(mR, Fr.tmax[(tb0 + (k >> 2)) * Fr.tiles_x + ta0 + (k & 3)]);
-    if (mR == 0.0f) return false;  // no measurement under the brick
-    return !(dmin > mR + V.mu);
+        if ((k & 3) < nx && (k >> 2) < ny) {
+            const int t = (tb0 + (k >> 2)) * Fr.tiles_x + ta0 + (k & 3);
+            mR = fmaxf(mR, Fr.tmax[t]);
+            mn = fminf(mn, tmin[t]);
+        }
+    if (mR == 0.0f) return 0;  // no measurement under the brick
+    if (dmin > mR + V.mu) return 0;
+    const float dmax = sqrtf(d2f) * (1.0f + 1e-5f) + 1e-4f;
+    if (inside && mn - dmax > V.mu * (1.0f + 1e-5f) + 1e-4f) return 2;
+    return 1;
 }
 
 // Blocks [0, kZtBlocks): the z table of every volume of the launch (see
@@ -631,7 +709,7 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
                 const int mid = (lo + hi + 1) >> 1;
                 if (L.item_base[mid] <= item) lo = mid; else hi = mid - 1;
             }
-            auto test = [&](const DevVolume& V, const DevFrame& Fr) {
+            auto test = [&](const DevVolume& V, const DevFrame& Fr) -> int {
                 const int local = item - L.item_base[lo];
                 const int ncols = V.bd[0] * V.bd[1];
                 const int zc = local / ncols;
@@ -639,8 +717,8 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
                 const int byi = col / V.bd[0];
                 const int bxi = col - byi * V.bd[0];
                 const int bz = zc * zchunk + j;
-                if (bz >= V.bd[2]) return false;
-                if (!Fr.tmax) return true;
+                if (bz >= V.bd[2]) return 0;
+                if (!Fr.tmax) return 1;
                 const int i0[3] = {bxi * kBrick, byi * kBrick, bz * kBrick};
                 float blo[3], bhi[3];
 #pragma unroll
@@ -649,20 +727,22 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
                     blo[a] = V.o[a] + (V.s * ((float)(V.off[a] + i0[a]) + 0.5f));
                     bhi[a] = V.o[a] + (V.s * ((float)(V.off[a] + i1) + 0.5f));
                 }
-                return brick_may_update(V, Fr, blo, bhi);
+                return brick_class(V, Fr, blo, bhi);
             };
             // a wavefront whose bricks share one volume reads the volume
             // and frame tables with scalar loads
             const int lo0 = wave_uniform(lo);
-            bool visit;
+            int cls;
             if (__ballot(lo != lo0) == 0) {
                 const DevVolume V = cptr(vols)[lo0];
-                visit = test(V, cptr(frames)[V.frame]);
+                cls = test(V, cptr(frames)[V.frame]);
             } else {
-                visit = test(vols[lo], frames[vols[lo].frame]);
+                cls = test(vols[lo], frames[vols[lo].frame]);
             }
+            const bool visit = cls != 0;
             const bool valid = t0 + (int)threadIdx.x < total;
-            if (valid) L.visit[(size_t)item * kVisitPerItem + j] = visit ? 1 : 0;
+            // byte: bit 0 visit, bit 1 every voxel updated with phi = 1
+            if (valid) L.visit[(size_t)item * kVisitPerItem + j] = cls == 2 ? 3 : (visit ? 1 : 0);
             if (L.list) {
                 // the items of this wavefront (64 / zchunk whole items: t0
                 // is a multiple of the block size and zchunk divides 64)

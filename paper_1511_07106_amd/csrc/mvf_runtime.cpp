@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -108,7 +109,7 @@ struct Scratch {
     int best_cap = 0;           // pixels best_t / best_id hold
     float* ztab = nullptr;  // integration z table (3 floats per entry)
     int ztab_cap = 0;
-    float* tmax = nullptr;   // maximum range per 8x8 pixel tile
+    float* tmax = nullptr;   // maximum range per 8x8 pixel tile, then the minima (2 x tmax_cap)
     int tmax_cap = 0;
     uint8_t* visit = nullptr;  // integration: brick visit mask per item
     int visit_cap = 0;
@@ -211,6 +212,10 @@ struct mvf_ctx {
     uint64_t pooled_bytes = 0;    // slabs in the free pool
     std::vector<Slab> pool;
     uint64_t tick = 0;
+    // failure injection for tests: this many of the next volume-slab
+    // allocations fail as if the device were out of memory (from the
+    // environment variable MVF_FAULT_SLAB_ALLOCS at context creation)
+    int fault_slab_allocs = 0;
     mvf_stats stats{};
     Arena arena;
     std::vector<TimedPair> timed;
@@ -456,7 +461,15 @@ mvf_status get_slab(mvf_ctx* c, Volume& v, hipStream_t stream, std::vector<hipEv
         }
     }
     CHECK_ST(release_pool(c, v.bytes));
-    hipError_t e = hipMalloc((void**)&v.dev, v.bytes);
+    auto alloc = [&]() -> hipError_t {
+        if (c->fault_slab_allocs > 0) {
+            --c->fault_slab_allocs;
+            v.dev = nullptr;
+            return hipErrorOutOfMemory;
+        }
+        return hipMalloc((void**)&v.dev, v.bytes);
+    };
+    hipError_t e = alloc();
     if (e != hipSuccess) {
         (void)hipGetLastError();
         // drop every pooled slab and retry once
@@ -465,7 +478,7 @@ mvf_status get_slab(mvf_ctx* c, Volume& v, hipStream_t stream, std::vector<hipEv
         mvf_status st = release_pool(c, 0);
         c->budget = saved;
         if (st != MVF_OK) return st;
-        e = hipMalloc((void**)&v.dev, v.bytes);
+        e = alloc();
         if (e != hipSuccess) {
             (void)hipGetLastError();
             v.dev = nullptr;
@@ -662,7 +675,8 @@ mvf_status get_scratch(mvf_ctx* c, int sid, int w, int h, bool need_best, Scratc
     const int ntiles = ((w + 7) / 8) * ((h + 7) / 8);
     if (ntiles > s.tmax_cap) {
         if (s.tmax) { CHECK_HIP(hipFree(s.tmax)); s.tmax = nullptr; }
-        CHECK_HIP(hipMalloc((void**)&s.tmax, (size_t)ntiles * sizeof(float)));
+        // maxima, then minima, of the range over each 8x8 tile
+        CHECK_HIP(hipMalloc((void**)&s.tmax, 2 * (size_t)ntiles * sizeof(float)));
         s.tmax_cap = ntiles;
     }
     if (w * h > s.w * s.h || !s.range) {
@@ -1373,6 +1387,7 @@ mvf_status mvf_create(mvf_ctx** out, const mvf_config* cfg)
     c->cfg = c0;
     c->device = c0.device;
     c->budget = c0.hbm_budget_bytes ? c0.hbm_budget_bytes : ~0ull;
+    if (const char* fs = getenv("MVF_FAULT_SLAB_ALLOCS")) c->fault_slab_allocs = std::max(0, atoi(fs));
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c0.device) == hipSuccess) c->n_cus = prop.multiProcessorCount;
     auto fail = [&](mvf_status st) {
@@ -2498,6 +2513,133 @@ mvf_status mvf_placement_update(mvf_ctx* c, int32_t sid, const mvf_frame* f, con
     q.classes[0].quota = p->n_max;
     q.beta = p->beta;
     return mvf_placement_update_classes(c, sid, f, T_wc, K, &q, r, stream);
+}
+
+// ---- checkpoint and resume ---------------------------------------------------------
+
+namespace {
+constexpr char kCkptMagic[8] = {'M', 'V', 'F', 'C', 'K', 'P', 'T', 1};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptVolume {
+    int32_t alive, active, has_state, reserved;
+    mvf_volume_desc d;
+    uint64_t bytes, nbricks;
+};
+
+struct CkptPlaced {
+    int32_t stream, d_v, cell[3], vol;
+};
+
+struct FileCloser {
+    FILE* f;
+    ~FileCloser() { if (f) fclose(f); }
+};
+}  // namespace
+
+mvf_status mvf_checkpoint_save(mvf_ctx* c, const char* path)
+{
+    if (!c || !path) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    CHECK_ST(mvf_synchronize(c));
+    FileCloser fc{fopen(path, "wb")};
+    if (!fc.f) return set_error(MVF_ERR_INVALID_ARG, "cannot open %s for writing", path);
+    std::vector<CkptPlaced> placed;
+    for (auto& kv : c->placed)
+        for (auto& e : kv.second)
+            placed.push_back(CkptPlaced{kv.first, e.first[0], {e.first[1], e.first[2], e.first[3]}, e.second});
+    const uint32_t hdr[4] = {kCkptVersion, (uint32_t)c->grids.size(), (uint32_t)c->vols.size(),
+                             (uint32_t)placed.size()};
+    bool ok = fwrite(kCkptMagic, 1, 8, fc.f) == 8 && fwrite(hdr, sizeof(hdr), 1, fc.f) == 1;
+    for (const Grid& g : c->grids) ok = ok && fwrite(&g.d, sizeof(g.d), 1, fc.f) == 1;
+    std::vector<uint8_t> buf;
+    for (const Volume& v : c->vols) {
+        CkptVolume cv{};
+        cv.alive = v.alive && !v.internal;
+        cv.active = v.active;
+        cv.has_state = cv.alive && v.state != State::Empty;
+        cv.d = v.d;
+        cv.bytes = v.bytes;
+        cv.nbricks = v.nbricks;
+        ok = ok && fwrite(&cv, sizeof(cv), 1, fc.f) == 1;
+        if (!cv.has_state || !ok) continue;
+        const uint8_t* src = v.host;
+        if (v.state == State::Device) {
+            buf.resize(v.bytes);
+            CHECK_HIP(hipMemcpy(buf.data(), v.dev, v.bytes, hipMemcpyDeviceToHost));
+            src = buf.data();
+        }
+        ok = ok && fwrite(src, 1, v.bytes, fc.f) == v.bytes;
+    }
+    if (!placed.empty()) ok = ok && fwrite(placed.data(), sizeof(CkptPlaced), placed.size(), fc.f) == placed.size();
+    if (!ok) return set_error(MVF_ERR_INVALID_ARG, "writing %s failed", path);
+    return MVF_OK;
+}
+
+mvf_status mvf_checkpoint_load(mvf_ctx* c, const char* path)
+{
+    if (!c || !path) return set_error(MVF_ERR_INVALID_ARG, "NULL argument");
+    if (!c->grids.empty() || !c->vols.empty())
+        return set_error(MVF_ERR_STATE, "a checkpoint loads into a context without grids or volumes");
+    CHECK_HIP(hipSetDevice(c->device));
+    FileCloser fc{fopen(path, "rb")};
+    if (!fc.f) return set_error(MVF_ERR_INVALID_ARG, "cannot open %s", path);
+    char magic[8];
+    uint32_t hdr[4];
+    if (fread(magic, 1, 8, fc.f) != 8 || memcmp(magic, kCkptMagic, 8) != 0 || fread(hdr, sizeof(hdr), 1, fc.f) != 1 ||
+        hdr[0] != kCkptVersion || hdr[1] > (1u << 20) || hdr[2] > (1u << 24) || hdr[3] > (1u << 24))
+        return set_error(MVF_ERR_INVALID_ARG, "%s is not a checkpoint of this version", path);
+    mvf_status st = MVF_OK;
+    for (uint32_t i = 0; i < hdr[1] && st == MVF_OK; ++i) {
+        mvf_grid_desc d;
+        int32_t gid;
+        if (fread(&d, sizeof(d), 1, fc.f) != 1) st = set_error(MVF_ERR_INVALID_ARG, "%s: truncated grids", path);
+        else st = mvf_grid_create(c, &d, &gid);
+    }
+    for (uint32_t i = 0; i < hdr[2] && st == MVF_OK; ++i) {
+        CkptVolume cv;
+        if (fread(&cv, sizeof(cv), 1, fc.f) != 1) { st = set_error(MVF_ERR_INVALID_ARG, "%s: truncated volumes", path); break; }
+        if (!cv.alive) {
+            c->vols.push_back(Volume());  // keeps the ids of the later volumes
+            continue;
+        }
+        int32_t id;
+        st = mvf_volume_create(c, &cv.d, &id);
+        if (st != MVF_OK) break;
+        Volume& v = c->vols[id];
+        if (id != (int32_t)i || v.bytes != cv.bytes || v.nbricks != cv.nbricks) {
+            st = set_error(MVF_ERR_INVALID_ARG, "%s: volume %u does not match this library's layout", path, i);
+            break;
+        }
+        v.active = cv.active != 0;
+        if (!cv.has_state) continue;
+        if (hipHostMalloc((void**)&v.host, v.bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            v.host = nullptr;
+            st = set_error(MVF_ERR_OOM, "pinned host memory of %zu bytes", v.bytes);
+            break;
+        }
+        if (fread(v.host, 1, v.bytes, fc.f) != v.bytes) { st = set_error(MVF_ERR_INVALID_ARG, "%s: truncated state", path); break; }
+        v.state = State::Host;
+        v.host_pending = false;
+    }
+    for (uint32_t i = 0; i < hdr[3] && st == MVF_OK; ++i) {
+        CkptPlaced e;
+        if (fread(&e, sizeof(e), 1, fc.f) != 1) { st = set_error(MVF_ERR_INVALID_ARG, "%s: truncated placement", path); break; }
+        if (e.vol < 0 || e.vol >= (int32_t)c->vols.size() || !c->vols[e.vol].alive) {
+            st = set_error(MVF_ERR_INVALID_ARG, "%s: placement entry names no volume", path);
+            break;
+        }
+        c->placed[e.stream][std::vector<int>{e.d_v, e.cell[0], e.cell[1], e.cell[2]}] = e.vol;
+    }
+    if (st != MVF_OK) {
+        // leave the context empty again
+        for (Volume& v : c->vols)
+            if (v.host) (void)hipHostFree(v.host);
+        c->vols.clear();
+        c->grids.clear();
+        c->placed.clear();
+    }
+    return st;
 }
 
 // ---- camera tracking ---------------------------------------------------------------

@@ -150,3 +150,38 @@ def test_large_room_512_full_volume(mvf):
         ids, ovs = fuse_both(ctx, gid, og, [((0, 0, 0), (n, n, n))], seq, [0, 150, 299])
         _, W, _, err = compare_volume(ctx, ids[0], ovs[0])
         log(f"512^3 ok: observed {(W > 0).sum()} voxels, max |dF| {err:.2e}")
+
+
+@pytest.mark.parametrize("plane_z", [2.0, 5.0])
+def test_far_plane_every_voxel(mvf, plane_z):
+    """A volume wholly in view in front of a fronto-parallel plane (the
+    roofline probe's geometry, small): at 5 m every voxel lies more than mu
+    in front of the plane, so whole bricks take the update with phi = 1
+    without their own projection; at 2.0 m the plane cuts the far end of
+    the volume (colour band, negative side, unobserved voxels behind).  Both
+    equal the oracle: W and colour bit-exact, F within 1e-5."""
+    n = 72
+    s = 0.01
+    origin = (-0.36, -0.36, 1.5)
+    K = np.array([300.0, 300.0, 159.5, 119.5], np.float32)
+    T = np.zeros((3, 4))
+    T[:, :3] = np.eye(3)
+    depth = np.full((240, 320), plane_z, np.float32)
+    depth[:3, :] = 0.0                      # a few invalid rows at the top
+    rgb = np.zeros((240, 320, 3), np.uint8)
+    rgb[..., 0] = 200
+    og = O.OGrid(origin, s, 4.0, 128)
+    log(f"far plane z={plane_z}, {n}^3")
+    with mvf.Context() as ctx:
+        gid = ctx.grid(origin, s, 4.0, 128)
+        vid = ctx.volume(gid, (0, 0, 0), (n, n, n))
+        ov = O.OVolume.empty((n, n, n))
+        for k in range(3):
+            O.integrate(ov, og, depth, rgb, K, T)
+            ctx.integrate(t(depth), t(rgb), T, K)
+        F, W, Cc = ctx.read_volume(vid)
+        np.testing.assert_array_equal(W, ov.W)
+        np.testing.assert_array_equal(Cc, ov.Cc)
+        assert np.abs(F.astype(np.float64) - ov.F).max() <= 1e-5
+        if plane_z > 4:
+            assert int((W == 3).sum()) > 0.9 * n ** 3

@@ -62,6 +62,7 @@ def test_small_room_end_to_end(mvf):
         ids, ovs = fuse_both(ctx, gid, og, [((0, 0, 0), (128, 128, 128))], seq, range(10))
         g, rc = raycast_both(ctx, ovs, og, K, seq.poses[9], 320, 240)
         amb = rc["ambiguous"].astype(bool)
+        print(f"[parity] small room 128^3 end to end: ambiguous fraction {amb.mean():.2e}", flush=True)
         assert amb.mean() < 1e-2
         hit_g, hit_o = g["hit"] >= 0, rc["hit"] >= 0
         np.testing.assert_array_equal(hit_g[~amb], hit_o[~amb])
