@@ -195,13 +195,18 @@ struct IntegrateLaunch {
     const uint32_t* tile_cost;
     int32_t* tile_order;
     int32_t order_tiles;
-    // visited items, compacted (needs visit): the z-table launch appends
-    // every item with a visited brick to list (room for total_items) and
-    // counts them in list_count[hdr->list_parity]; integration walks the
-    // list.  The z-table launch also zeroes list_count[list_parity ^ 1] for
-    // the next launch, so the two counts must be zero before first use.
+    // visited work, compacted (needs visit): the z-table launch appends
+    // every item with a brick to visit voxel by voxel to list (room for
+    // total_items) and every deep brick (each voxel updated with phi = 1,
+    // proved by the visit test) as item * 8 + j to deep_list (room for
+    // total_items * zchunk); list_count[hdr->list_parity] counts both (items
+    // in the low 32 bits, deep bricks in the high 32).  Integration gives
+    // each entry a wavefront.  The z-table launch also zeroes
+    // list_count[list_parity ^ 1] for the next launch, so the two words must
+    // be zero before first use.
     int32_t* list;
-    uint32_t* list_count;
+    unsigned long long* list_count;
+    int32_t* deep_list;
 };
 constexpr int kVisitPerItem = 8;
 

@@ -285,6 +285,94 @@ static __device__ __forceinline__ void clip_halfline(float a, float b, float& zl
     }
 }
 
+// The flags of brick (bxi, byi, bz) after an update that may have written
+// F <= 2^-100 in the lanes with flag_here (fz: per pair of z-slices).
+static __device__ __forceinline__ void mark_brick(const DevVolume& V, int bxi, int byi, int bz, bool flag_here,
+                                                  const bool (&fz)[kBrick / 2], int lane)
+{
+    if (__ballot(flag_here) != 0) {
+        uint64_t fm = 0;
+#pragma unroll
+        for (int zp = 0; zp < kBrick / 2; ++zp)
+            fm |= (uint64_t)subblock_bits(__ballot(fz[zp])) << (16 * zp);
+        if (lane == 0) {
+            const size_t b = brick_index(V.bd, bxi, byi, bz);
+            V.flag[b] = 1;
+            atomicOr((unsigned long long*)&V.fmask[b], (unsigned long long)fm);
+            const size_t cw = (size_t)(bxi * V.bd[1] + byi) * col_words(V.bd[2]) + (bz >> 6);
+            atomicOr((unsigned long long*)&V.colm[cw], 1ull << (bz & 63));
+        }
+    }
+}
+
+// One deep brick (entry e = item * 8 + j of the deep list: brick j of the
+// item): the visit pass proved R - rho > mu for every voxel, so each voxel
+// inside the volume is updated with phi = 1 and none is in the colour band;
+// neither the projection nor the range gathers are needed.  A wavefront per
+// brick: its F and W loads (3 KB) are in flight together.
+static __device__ __forceinline__ void integrate_deep_brick(const IntegrateLaunch& L, int e, int zchunk, int nvol,
+                                                            int lane, unsigned& n_upd)
+{
+    const int item = e >> 3, j = e & 7;
+    CPTR(int32_t) const item_base = cptr(L.item_base);
+    int lo = 0, hi = nvol - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (item_base[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    lo = wave_uniform(lo);
+    const DevVolume V = cptr(L.vols)[lo];
+    const int local = item - item_base[lo];
+    const int ncols = V.bd[0] * V.bd[1];
+    const int zc = local / ncols;
+    const int col = local - zc * ncols;
+    const int byi = col / V.bd[0];
+    const int bxi = col - byi * V.bd[0];
+    const int bz = zc * zchunk + j;
+    const int x = bxi * kBrick + (lane & 7);
+    const int y = byi * kBrick + (lane >> 3);
+    const bool col_ok = x < V.dims[0] && y < V.dims[1];
+    const int nz_here = min(kBrick, V.dims[2] - bz * kBrick);
+    const size_t base = brick_index(V.bd, bxi, byi, bz) * kBrickVox + lane;
+    GPTR(float) const pF = gptr(V.F) + base;
+    GPTR(uint16_t) const pW = gptr(V.W) + base;
+    float Fo[kBrick];
+    uint16_t Wo[kBrick];
+    bool uv[kBrick];
+#pragma unroll
+    for (int zz = 0; zz < kBrick; ++zz) {
+        uv[zz] = col_ok & (zz < nz_here);
+        Fo[zz] = 0.0f;
+        Wo[zz] = 0;
+        if (uv[zz]) {
+            Fo[zz] = __builtin_nontemporal_load(&pF[zz * 64]);
+            Wo[zz] = __builtin_nontemporal_load(&pW[zz * 64]);
+        }
+    }
+    bool flag_here = false;
+    bool fz[kBrick / 2] = {false, false, false, false};
+#pragma unroll
+    for (int zz = 0; zz < kBrick; ++zz) {
+        n_upd += (unsigned)__popcll(__ballot(uv[zz]));
+        const int w = Wo[zz];
+        const float Wf = (float)w;
+        // phi = 1: the running average of the general path with the same
+        // reciprocal, so the stored bits are the same
+        const float den = Wf + 1.0f;
+        float r = __builtin_amdgcn_rcpf(den);
+        r = fmaf(r, fmaf(-den, r, 1.0f), r);
+        const float Fn = (w == 0) ? 1.0f : fmaf(Fo[zz], Wf, 1.0f) * r;
+        if (uv[zz]) {
+            pF[zz * 64] = Fn;
+            pW[zz * 64] = (uint16_t)min(w + 1, V.w_max);
+        }
+        const bool fl = uv[zz] & (Fn <= kFlagThreshold);
+        flag_here |= fl;
+        fz[zz >> 1] |= fl;
+    }
+    mark_brick(V, bxi, byi, bz, flag_here, fz, lane);
+}
+
 // eight wavefronts per SIMD: the kernel is latency-bound, and its state fits 64 VGPRs
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void mvf_integrate_kernel(IntegrateLaunch L)
 {
@@ -304,11 +392,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
     const int nvol = L.hdr->nvol;
     const int zchunk = L.hdr->zchunk;
     CPTR(float) const ztab = cptr(L.ztab);
-    // with a list, only the items that have a visited brick (about a third
-    // of a frame's items) get a wavefront
-    const int n_work = L.list ? (int)cptr(L.list_count)[L.hdr->list_parity] : L.hdr->total_items;
+    // with a list, only the items that have a brick to visit voxel by voxel
+    // get a wavefront, and every deep brick one of its own after them
+    const unsigned long long lc = L.list ? cptr(L.list_count)[L.hdr->list_parity] : 0ull;
+    const int n_items = L.list ? (int)(lc & 0xffffffffull) : L.hdr->total_items;
+    const int n_work = n_items + (int)(lc >> 32);
 
     for (int w = wave_uniform(((int)blockIdx.x - b0) * wpb + wib); w < n_work; w += total_waves) {
+        if (w >= n_items) {
+            integrate_deep_brick(L, cptr(L.deep_list)[w - n_items], zchunk, nvol, lane, n_upd);
+            continue;
+        }
         const int item = L.list ? cptr(L.list)[w] : w;
         // bricks of the item that may hold an updated voxel (bytes from
         // zchunk on are not written by the visit pass)
@@ -397,63 +491,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
             const size_t base = colbase + (size_t)bz * kBrickVox;
             GPTR(float) const pF = vF + base;
             GPTR(uint16_t) const pW = vW + base;
-            // the brick's flags after an update that may write F <= 2^-100
-            auto mark = [&](bool flag_here, const bool (&fz)[kBrick / 2]) {
-                if (__ballot(flag_here) != 0) {
-                    uint64_t fm = 0;
-#pragma unroll
-                    for (int zp = 0; zp < kBrick / 2; ++zp)
-                        fm |= (uint64_t)subblock_bits(__ballot(fz[zp])) << (16 * zp);
-                    if (lane == 0) {
-                        const size_t b = brick_index(V.bd, bxi, byi, bz);
-                        V.flag[b] = 1;
-                        atomicOr((unsigned long long*)&V.fmask[b], (unsigned long long)fm);
-                        const size_t cw = (size_t)(bxi * V.bd[1] + byi) * col_words(V.bd[2]) + (bz >> 6);
-                        atomicOr((unsigned long long*)&V.colm[cw], 1ull << (bz & 63));
-                    }
-                }
-            };
-            if ((vis >> (8 * (bz - bz0) + 1)) & 1ull) {
-                // deep brick (the visit pass proved R - rho > mu for every
-                // voxel): each voxel inside the volume is updated with
-                // phi = 1 and none is in the colour band, so the projection
-                // and the range gathers are not needed
-                const int nz_here = min(kBrick, V.dims[2] - zb);
-                float Fo[kBrick];
-                uint16_t Wo[kBrick];
-                bool uv[kBrick];
-#pragma unroll
-                for (int zz = 0; zz < kBrick; ++zz) {
-                    uv[zz] = col_ok & (zz < nz_here);
-                    Fo[zz] = 0.0f;
-                    Wo[zz] = 0;
-                    if (uv[zz]) {
-                        Fo[zz] = __builtin_nontemporal_load(&pF[zz * 64]);
-                        Wo[zz] = __builtin_nontemporal_load(&pW[zz * 64]);
-                    }
-                }
-                bool flag_here = false;
-                bool fz[kBrick / 2] = {false, false, false, false};
-#pragma unroll
-                for (int zz = 0; zz < kBrick; ++zz) {
-                    n_upd += (unsigned)__popcll(__ballot(uv[zz]));
-                    const int w = Wo[zz];
-                    const float Wf = (float)w;
-                    const float den = Wf + 1.0f;
-                    float r = __builtin_amdgcn_rcpf(den);
-                    r = fmaf(r, fmaf(-den, r, 1.0f), r);
-                    const float Fn = (w == 0) ? 1.0f : fmaf(Fo[zz], Wf, 1.0f) * r;
-                    if (uv[zz]) {
-                        pF[zz * 64] = Fn;
-                        pW[zz * 64] = (uint16_t)min(w + 1, V.w_max);
-                    }
-                    const bool fl = uv[zz] & (Fn <= kFlagThreshold);
-                    flag_here |= fl;
-                    fz[zz >> 1] |= fl;
-                }
-                mark(flag_here, fz);
-                continue;
-            }
+            // a deep brick has a wavefront of its own (integrate_deep_brick)
+            if ((vis >> (8 * (bz - bz0) + 1)) & 1ull) continue;
             // the brick's 8 z-table entries, one scalar block
             struct ZRow { float v[3 * kBrick]; };
             const ZRow zr = *(CPTR(ZRow))(ztab + 3 * (V.zt_base + zb));
@@ -576,7 +615,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
                     }
                 }
             }
-            mark(flag_here, fz);
+            mark_brick(V, bxi, byi, bz, flag_here, fz, lane);
         }
     }
     // counters: the wave's totals (the same in every lane), one atomic each
@@ -620,6 +659,42 @@ static __device__ int brick_class(const DevVolume& V, const DevFrame& Fr, const 
     }
     const float dmin = sqrtf(d2) * (1.0f - 1e-5f) - 1e-4f;
     if (!(dmin > V.mu)) return 1;
+    {
+        // cheap rejection of a box wholly outside the view (most bricks of a
+        // volume): the largest value over the box of each side plane's
+        // linear form, the planes one pixel beyond the image; a box with a
+        // negative maximum (by a margin far above the rounding) projects
+        // nowhere into the image, and one wholly behind the camera holds no
+        // voxel with pz > 0
+        float cw[3], ew[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cw[a] = 0.5f * (lo[a] + hi[a]) - c[a];
+            ew[a] = 0.5f * (hi[a] - lo[a]);
+        }
+        const float* T = Fr.T;
+        const float pcx = T[0] * cw[0] + T[4] * cw[1] + T[8] * cw[2];
+        const float pcy = T[1] * cw[0] + T[5] * cw[1] + T[9] * cw[2];
+        const float pcz = T[2] * cw[0] + T[6] * cw[1] + T[10] * cw[2];
+        const float ecz = fabsf(T[2]) * ew[0] + fabsf(T[6]) * ew[1] + fabsf(T[10]) * ew[2];
+        if (pcz + ecz < -1e-3f) return 0;
+        if (pcz - ecz > 0.01f) {
+            const float A[4] = {Fr.fx, -Fr.fx, 0.0f, 0.0f};
+            const float B[4] = {0.0f, 0.0f, Fr.fy, -Fr.fy};
+            const float Cc[4] = {Fr.cx + 1.5f, (float)Fr.width + 0.5f - Fr.cx, Fr.cy + 1.5f,
+                                 (float)Fr.height + 0.5f - Fr.cy};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float Lc = A[q] * pcx + B[q] * pcy + Cc[q] * pcz;
+                float Le = 0.0f;
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    Le += fabsf(A[q] * T[4 * b] + B[q] * T[4 * b + 1] + Cc[q] * T[4 * b + 2]) * ew[b];
+                const float margin = 1e-4f * (fabsf(A[q]) + fabsf(B[q]) + fabsf(Cc[q])) * (fabsf(pcz) + ecz + 1.0f);
+                if (Lc + Le < -margin) return 0;
+            }
+        }
+    }
     float u0 = INFINITY, u1 = -INFINITY, v0 = INFINITY, v1 = -INFINITY;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -689,16 +764,30 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
         // atomic per flush: one atomic per wavefront on a single address
         // serialised in the L2 and cost ~20 us per frame
         __shared__ int32_t blk_items[kZtListBuf];
-        __shared__ int blk_n, blk_base;
-        __shared__ int wave_n[4];
-        if (threadIdx.x == 0) blk_n = 0;
+        __shared__ int32_t blk_deep[kZtListBuf];
+        __shared__ int blk_n, blk_base, blk_dn, blk_dbase;
+        __shared__ int wave_n[4], wave_dn[4];
+        if (threadIdx.x == 0) {
+            blk_n = 0;
+            blk_dn = 0;
+        }
         __syncthreads();
         auto flush = [&]() {
-            if (threadIdx.x == 0) blk_base = blk_n ? (int)atomicAdd(&L.list_count[L.hdr->list_parity], (uint32_t)blk_n) : 0;
+            if (threadIdx.x == 0) {
+                // both counts in one 64-bit word: one atomic per flush
+                const unsigned long long add = (unsigned long long)blk_n | ((unsigned long long)blk_dn << 32);
+                const unsigned long long old = add ? atomicAdd(&L.list_count[L.hdr->list_parity], add) : 0ull;
+                blk_base = (int)(old & 0xffffffffull);
+                blk_dbase = (int)(old >> 32);
+            }
             __syncthreads();
             for (int i = threadIdx.x; i < blk_n; i += blockDim.x) L.list[blk_base + i] = blk_items[i];
+            for (int i = threadIdx.x; i < blk_dn; i += blockDim.x) L.deep_list[blk_dbase + i] = blk_deep[i];
             __syncthreads();
-            if (threadIdx.x == 0) blk_n = 0;
+            if (threadIdx.x == 0) {
+                blk_n = 0;
+                blk_dn = 0;
+            }
             __syncthreads();
         };
         for (int t0 = (blockIdx.x - kZtBlocks) * blockDim.x; t0 < total; t0 += stride) {
@@ -739,31 +828,47 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
             } else {
                 cls = test(vols[lo], frames[vols[lo].frame]);
             }
+            // deep bricks get wavefronts of their own only with the lists
+            const bool deep = cls == 2 && L.list != nullptr;
             const bool visit = cls != 0;
             const bool valid = t0 + (int)threadIdx.x < total;
-            // byte: bit 0 visit, bit 1 every voxel updated with phi = 1
-            if (valid) L.visit[(size_t)item * kVisitPerItem + j] = cls == 2 ? 3 : (visit ? 1 : 0);
+            // byte: bit 0 visit, bit 1 deep (done by a wavefront of its own)
+            if (valid) L.visit[(size_t)item * kVisitPerItem + j] = deep ? 3 : (visit ? 1 : 0);
             if (L.list) {
                 // the items of this wavefront (64 / zchunk whole items: t0
                 // is a multiple of the block size and zchunk divides 64)
-                // with a visited brick, in item order within the block
-                const uint64_t m = __ballot(valid && visit);
+                // with a brick to visit voxel by voxel, in item order within
+                // the block; the deep bricks, in brick order
+                const uint64_t m = __ballot(valid && visit && !deep);
                 const uint64_t grp = (m >> (lane & ~(zchunk - 1))) & ((1ull << zchunk) - 1ull);
                 const bool head = valid && j == 0 && grp != 0;
                 const uint64_t hm = __ballot(head);
-                if (lane == 0) wave_n[wib] = (int)__popcll(hm);
-                __syncthreads();
-                int off = blk_n, sum = 0;
-                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-                    if (w < wib) off += wave_n[w];
-                    sum += wave_n[w];
+                const uint64_t dm = __ballot(valid && deep);
+                if (lane == 0) {
+                    wave_n[wib] = (int)__popcll(hm);
+                    wave_dn[wib] = (int)__popcll(dm);
                 }
-                if (head) blk_items[off + __popcll(hm & ((1ull << lane) - 1ull))] = item;
                 __syncthreads();
-                if (threadIdx.x == 0) blk_n += sum;
+                int off = blk_n, sum = 0, doff = blk_dn, dsum = 0;
+                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                    if (w < wib) {
+                        off += wave_n[w];
+                        doff += wave_dn[w];
+                    }
+                    sum += wave_n[w];
+                    dsum += wave_dn[w];
+                }
+                const uint64_t below = (1ull << lane) - 1ull;
+                if (head) blk_items[off + __popcll(hm & below)] = item;
+                if (valid && deep) blk_deep[doff + __popcll(dm & below)] = item * 8 + j;
                 __syncthreads();
-                // room for the next iteration's items (at most one per thread)
-                if (blk_n + (int)blockDim.x > kZtListBuf) flush();
+                if (threadIdx.x == 0) {
+                    blk_n += sum;
+                    blk_dn += dsum;
+                }
+                __syncthreads();
+                // room for the next iteration's entries (at most one per thread)
+                if (blk_n + (int)blockDim.x > kZtListBuf || blk_dn + (int)blockDim.x > kZtListBuf) flush();
             }
         }
         if (L.list) flush();
@@ -771,7 +876,7 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
     }
     // the other count, for the next launch (the previous one, which used it,
     // has finished)
-    if (L.list_count && blockIdx.x == 0 && threadIdx.x == 0) L.list_count[L.hdr->list_parity ^ 1] = 0;
+    if (L.list_count && blockIdx.x == 0 && threadIdx.x == 0) L.list_count[L.hdr->list_parity ^ 1] = 0ull;
     const int total = hdr->total_z;
     for (int f = blockIdx.x; f < hdr->nstreams; f += kZtBlocks) {
         float* rm = frames[f].rmax;

@@ -113,8 +113,8 @@ struct Scratch {
     int tmax_cap = 0;
     uint8_t* visit = nullptr;  // integration: brick visit mask per item
     int visit_cap = 0;
-    int32_t* list = nullptr;   // integration: visited items (visit_cap entries)
-    uint32_t* list_count = nullptr;  // two counts, zeroed at allocation
+    int32_t* list = nullptr;   // integration: visited items (visit_cap entries), then deep bricks (8 per item)
+    unsigned long long* list_count = nullptr;  // two count words, zeroed at allocation
     int list_parity = 0;
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
     int32_t* tile_order = nullptr;
@@ -182,8 +182,8 @@ struct StepGraph {
     int ztab_cap = 0;
     uint8_t* visit = nullptr;  // brick visit mask per integration item
     int visit_cap = 0;
-    int32_t* list = nullptr;   // visited integration items (visit_cap entries)
-    uint32_t* list_count = nullptr;  // two counts, zeroed at allocation
+    int32_t* list = nullptr;   // visited integration items (visit_cap entries), then deep bricks (8 per item)
+    unsigned long long* list_count = nullptr;  // two count words, zeroed at allocation
     int list_parity = 0;
     RayBoundEntry* rb_entries = nullptr;  // raycast range-bound footprints (one per brick)
     int rb_entries_cap = 0;
@@ -920,12 +920,13 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             sc->list = nullptr;
         }
         CHECK_HIP(hipMalloc((void**)&sc->visit, (size_t)max_items * kVisitPerItem));
-        CHECK_HIP(hipMalloc((void**)&sc->list, (size_t)max_items * sizeof(int32_t)));
+        // the item list, then the deep-brick list (kVisitPerItem per item)
+        CHECK_HIP(hipMalloc((void**)&sc->list, (size_t)max_items * (1 + kVisitPerItem) * sizeof(int32_t)));
         sc->visit_cap = max_items;
     }
     if (!sc->list_count) {
-        CHECK_HIP(hipMalloc((void**)&sc->list_count, 2 * sizeof(uint32_t)));
-        CHECK_HIP(hipMemset(sc->list_count, 0, 2 * sizeof(uint32_t)));
+        CHECK_HIP(hipMalloc((void**)&sc->list_count, 2 * sizeof(unsigned long long)));
+        CHECK_HIP(hipMemset(sc->list_count, 0, 2 * sizeof(unsigned long long)));
     }
     bool order_pending = sc->tile_cost && sc->last_tiles > 0;  // once per call
     for (auto& wave : waves) {
@@ -977,7 +978,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             order_pending = false;
             IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit,
                               order ? sc->tile_cost : nullptr, order ? sc->tile_order : nullptr,
-                              order ? sc->last_tiles : 0, sc->list, sc->list_count};
+                              order ? sc->last_tiles : 0, sc->list, sc->list_count, sc->list + sc->visit_cap};
             if (order) sc->order_ready_tiles = sc->last_tiles;
             CHECK_LAUNCH(launch_ztable(L, (p.items * kZChunk + 255) / 256, stream));
             // with timing, the kernel's dispatch records the event pair
@@ -1981,9 +1982,9 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         CHECK_HIP(hipMalloc((void**)&G.ztab, (size_t)G.ztab_cap * 3 * sizeof(float)));
         G.visit_cap = std::max(items_total * 2, 1024);
         CHECK_HIP(hipMalloc((void**)&G.visit, (size_t)G.visit_cap * kVisitPerItem));
-        CHECK_HIP(hipMalloc((void**)&G.list, (size_t)G.visit_cap * sizeof(int32_t)));
-        CHECK_HIP(hipMalloc((void**)&G.list_count, 2 * sizeof(uint32_t)));
-        CHECK_HIP(hipMemset(G.list_count, 0, 2 * sizeof(uint32_t)));
+        CHECK_HIP(hipMalloc((void**)&G.list, (size_t)G.visit_cap * (1 + kVisitPerItem) * sizeof(int32_t)));
+        CHECK_HIP(hipMalloc((void**)&G.list_count, 2 * sizeof(unsigned long long)));
+        CHECK_HIP(hipMemset(G.list_count, 0, 2 * sizeof(unsigned long long)));
         int counts_cap = 0;
         CHECK_ST(get_footprint_buffers(&G.rb_entries, &G.rb_entries_cap, &G.rb_counts, &counts_cap,
                                        std::max(bricks_total * 2, 1024), G.max_vols));
@@ -2135,7 +2136,8 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             // integration's block 0 orders the raycast's tile groups (slowest of
             // the last step first)
             IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit,
-                               G.tile_cost, G.tile_order, G.ray_tiles, G.list, G.list_count};
+                               G.tile_cost, G.tile_order, G.ray_tiles, G.list, G.list_count,
+                               G.list + G.visit_cap};
             int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items_total * zc + 255) / 256), cs);
             // one wavefront per work item of the whole volume set (a larger
             // set later is walked by the kernel's grid-stride loop)
