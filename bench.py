@@ -155,7 +155,8 @@ def run_phase(mvf, torch, phase, dev_frames, poses, K, warmup, steps, timed=Fals
     r = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "voxels_updated": st["voxels_updated"],
          "voxels_band": st["voxels_band"], "integrate_ms": st["integrate_ms"], "raycast_ms": st["raycast_ms"],
          "step_ms": st["step_ms"], "integrate_launches": st["integrate_launches"],
-         "raycast_launches": st["raycast_launches"], "hit_fraction_last": hit_frac}
+         "raycast_launches": st["raycast_launches"], "hit_fraction_last": hit_frac,
+         "bricks_projected_per_step": st["bricks_projected"] / steps, "bricks_deep_per_step": st["bricks_deep"] / steps}
     if sched:
         r["schedule"] = sched
     r["voxel_updates_per_s"] = st["voxels_updated"] / wall
@@ -818,7 +819,8 @@ def main():
     steps = args.steps
     # roofline of the integration kernel
     upd, band = main_ph["voxels_updated"], main_ph["voxels_band"]
-    launches = max(1, main_ph["integrate_launches"])
+    # the graph path counts no launches of its own: one integration launch per step
+    launches = main_ph["integrate_launches"] or steps
     bytes_per_launch = (B_UPDATED * upd + B_BAND * band + B_PIXEL * W_IMG * H_IMG * steps) / launches
     achieved = None
     if main_ph["integrate_ms"] > 0:

@@ -120,6 +120,9 @@ typedef struct {
     uint64_t resident_bytes;     /* device bytes held by volumes now */
     int32_t resident_volumes;
     int32_t reserved;
+    uint64_t bricks_projected;   /* bricks integrated voxel by voxel (projection, range gather) */
+    uint64_t bricks_deep;        /* bricks updated wholesale with phi = 1 (in front of the
+                                    measured surface by more than mu everywhere) */
 } mvf_stats;
 
 /* ---- context ---------------------------------------------------------- */

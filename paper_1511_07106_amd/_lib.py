@@ -61,7 +61,8 @@ class mvf_stats(C.Structure):
                 ("swaps_out", C.c_uint64), ("integrate_launches", C.c_uint64),
                 ("raycast_launches", C.c_uint64), ("step_launches", C.c_uint64),
                 ("integrate_ms", C.c_double), ("raycast_ms", C.c_double), ("step_ms", C.c_double),
-                ("resident_bytes", C.c_uint64), ("resident_volumes", C.c_int32), ("reserved", C.c_int32)]
+                ("resident_bytes", C.c_uint64), ("resident_volumes", C.c_int32), ("reserved", C.c_int32),
+                ("bricks_projected", C.c_uint64), ("bricks_deep", C.c_uint64)]
 
 
 class mvf_stream_frame(C.Structure):

@@ -119,7 +119,7 @@ struct RayParams {
 // 64-bit counters written by kernels.  kCntSlots copies, each on its own
 // 128-byte line (slot k at counters + k * kCntNum), spread the atomics of
 // many blocks over several addresses; a reader sums the slots.
-enum Counter { kCntUpdated = 0, kCntBand = 1, kCntNum = 16 };
+enum Counter { kCntUpdated = 0, kCntBand = 1, kCntBricks = 2, kCntDeep = 3, kCntNum = 16 };
 constexpr int kCntSlots = 64;
 
 // Launch parameters that live in device memory, so that a captured graph
@@ -196,14 +196,14 @@ struct IntegrateLaunch {
     int32_t* tile_order;
     int32_t order_tiles;
     // visited work, compacted (needs visit): the z-table launch appends
-    // every item with a brick to visit voxel by voxel to list (room for
-    // total_items) and every deep brick (each voxel updated with phi = 1,
-    // proved by the visit test) as item * 8 + j to deep_list (room for
-    // total_items * zchunk); list_count[hdr->list_parity] counts both (items
+    // every brick to visit voxel by voxel to list and every deep brick (each
+    // voxel updated with phi = 1, proved by the visit test) to deep_list,
+    // both as item * 8 + j (brick j of the item; room for total_items *
+    // zchunk each); list_count[hdr->list_parity] counts both (visited bricks
     // in the low 32 bits, deep bricks in the high 32).  Integration gives
-    // each entry a wavefront.  The z-table launch also zeroes
-    // list_count[list_parity ^ 1] for the next launch, so the two words must
-    // be zero before first use.
+    // each entry a wavefront, the visited bricks first.  The z-table launch
+    // also zeroes list_count[list_parity ^ 1] for the next launch, so the
+    // two words must be zero before first use.
     int32_t* list;
     unsigned long long* list_count;
     int32_t* deep_list;

@@ -388,22 +388,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
     const int wib = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     const int total_waves = ((int)gridDim.x - b0) * wpb;
-    unsigned n_upd = 0, n_band = 0;  // wave totals
+    unsigned n_upd = 0, n_band = 0, n_brk = 0, n_deep = 0;  // wave totals
     const int nvol = L.hdr->nvol;
     const int zchunk = L.hdr->zchunk;
     CPTR(float) const ztab = cptr(L.ztab);
-    // with a list, only the items that have a brick to visit voxel by voxel
-    // get a wavefront, and every deep brick one of its own after them
+    // with a list, every brick to visit voxel by voxel gets a wavefront, and
+    // every deep brick one of its own after them (a wavefront per brick:
+    // items of several visited bricks, walked by one wavefront, were the
+    // launch's longest waves)
     const unsigned long long lc = L.list ? cptr(L.list_count)[L.hdr->list_parity] : 0ull;
-    const int n_items = L.list ? (int)(lc & 0xffffffffull) : L.hdr->total_items;
-    const int n_work = n_items + (int)(lc >> 32);
+    // visited bricks (or, without a list, items), then deep bricks
+    const int n_vis = L.list ? (int)(lc & 0xffffffffull) : L.hdr->total_items;
+    const int n_work = n_vis + (int)(lc >> 32);
 
     for (int w = wave_uniform(((int)blockIdx.x - b0) * wpb + wib); w < n_work; w += total_waves) {
-        if (w >= n_items) {
-            integrate_deep_brick(L, cptr(L.deep_list)[w - n_items], zchunk, nvol, lane, n_upd);
+        if (w >= n_vis) {
+            integrate_deep_brick(L, cptr(L.deep_list)[w - n_vis], zchunk, nvol, lane, n_upd);
+            ++n_deep;
             continue;
         }
-        const int item = L.list ? cptr(L.list)[w] : w;
+        // brick j0 of the item from a list entry, else the whole item
+        const int e = L.list ? cptr(L.list)[w] : 0;
+        const int item = L.list ? e >> 3 : w;
+        const int j0 = L.list ? e & 7 : 0;
+        const int j1 = L.list ? j0 + 1 : zchunk;
         // bricks of the item that may hold an updated voxel (bytes from
         // zchunk on are not written by the visit pass)
         const uint64_t vis = L.visit ? cptr((const uint64_t*)L.visit)[item] &
@@ -484,7 +492,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
         const float mu_f = V.mu + 0x1p-46f;
 
         const size_t colbase = brick_index(V.bd, bxi, byi, 0) * kBrickVox + lane;
-        for (int bz = bz0; bz < bz1; ++bz) {
+        for (int bz = bz0 + j0; bz < min(bz0 + j1, bz1); ++bz) {
             const int zb = bz * kBrick;
             const bool mine = zlo < zb + kBrick && zhi > zb;
             if (!((vis >> (8 * (bz - bz0))) & 1ull) || __ballot(mine) == 0) continue;
@@ -497,6 +505,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
             struct ZRow { float v[3 * kBrick]; };
             const ZRow zr = *(CPTR(ZRow))(ztab + 3 * (V.zt_base + zb));
             const int nz_here = min(kBrick, V.dims[2] - zb);
+            ++n_brk;
             // phase 1: camera-frame position and nearest pixel of 8 voxels.
             // The pixel coordinates are clamped into the image (a NaN goes
             // to 0); the voxel projects into the image iff clamping left them
@@ -621,10 +630,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void m
     // counters: the wave's totals (the same in every lane), one atomic each
     // into one of kCntSlots copies; no block barrier, so a wavefront that
     // finishes early frees its slot at once
-    if (lane == 0 && L.counters && (n_upd | n_band)) {
+    if (lane == 0 && L.counters && (n_upd | n_band | n_brk | n_deep)) {
         unsigned long long* slot = L.counters + ((((int)blockIdx.x - b0) * wpb + wib) % kCntSlots) * kCntNum;
         if (n_upd) atomicAdd(&slot[kCntUpdated], (unsigned long long)n_upd);
         if (n_band) atomicAdd(&slot[kCntBand], (unsigned long long)n_band);
+        if (n_brk) atomicAdd(&slot[kCntBricks], (unsigned long long)n_brk);
+        if (n_deep) atomicAdd(&slot[kCntDeep], (unsigned long long)n_deep);
     }
 }
 
@@ -759,10 +770,10 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
         const int stride = (gridDim.x - kZtBlocks) * blockDim.x;
         const int lane = threadIdx.x & 63;
         const int wib = threadIdx.x >> 6;
-        // the block's visited items (heads of items with a visited brick),
-        // gathered in LDS over its iterations and appended with one counter
-        // atomic per flush: one atomic per wavefront on a single address
-        // serialised in the L2 and cost ~20 us per frame
+        // the block's visited and deep bricks, gathered in LDS over its
+        // iterations and appended with one counter atomic per flush: one
+        // atomic per wavefront on a single address serialised in the L2 and
+        // cost ~20 us per frame
         __shared__ int32_t blk_items[kZtListBuf];
         __shared__ int32_t blk_deep[kZtListBuf];
         __shared__ int blk_n, blk_base, blk_dn, blk_dbase;
@@ -835,14 +846,10 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
             // byte: bit 0 visit, bit 1 deep (done by a wavefront of its own)
             if (valid) L.visit[(size_t)item * kVisitPerItem + j] = deep ? 3 : (visit ? 1 : 0);
             if (L.list) {
-                // the items of this wavefront (64 / zchunk whole items: t0
-                // is a multiple of the block size and zchunk divides 64)
-                // with a brick to visit voxel by voxel, in item order within
-                // the block; the deep bricks, in brick order
-                const uint64_t m = __ballot(valid && visit && !deep);
-                const uint64_t grp = (m >> (lane & ~(zchunk - 1))) & ((1ull << zchunk) - 1ull);
-                const bool head = valid && j == 0 && grp != 0;
-                const uint64_t hm = __ballot(head);
+                // the bricks of this wavefront to visit voxel by voxel, and
+                // the deep ones, each in brick order within the block
+                const bool proj = valid && visit && !deep;
+                const uint64_t hm = __ballot(proj);
                 const uint64_t dm = __ballot(valid && deep);
                 if (lane == 0) {
                     wave_n[wib] = (int)__popcll(hm);
@@ -859,7 +866,7 @@ __global__ __launch_bounds__(256) void mvf_ztable_kernel(IntegrateLaunch L)
                     dsum += wave_dn[w];
                 }
                 const uint64_t below = (1ull << lane) - 1ull;
-                if (head) blk_items[off + __popcll(hm & below)] = item;
+                if (proj) blk_items[off + __popcll(hm & below)] = item * 8 + j;
                 if (valid && deep) blk_deep[doff + __popcll(dm & below)] = item * 8 + j;
                 __syncthreads();
                 if (threadIdx.x == 0) {

@@ -113,7 +113,7 @@ struct Scratch {
     int tmax_cap = 0;
     uint8_t* visit = nullptr;  // integration: brick visit mask per item
     int visit_cap = 0;
-    int32_t* list = nullptr;   // integration: visited items (visit_cap entries), then deep bricks (8 per item)
+    int32_t* list = nullptr;   // integration: visited bricks, then deep bricks (8 per item each)
     unsigned long long* list_count = nullptr;  // two count words, zeroed at allocation
     int list_parity = 0;
     uint32_t* tile_cost = nullptr;  // raycast tiles: last duration, then launch order
@@ -182,7 +182,7 @@ struct StepGraph {
     int ztab_cap = 0;
     uint8_t* visit = nullptr;  // brick visit mask per integration item
     int visit_cap = 0;
-    int32_t* list = nullptr;   // visited integration items (visit_cap entries), then deep bricks (8 per item)
+    int32_t* list = nullptr;   // integration: visited bricks, then deep bricks (8 per item each)
     unsigned long long* list_count = nullptr;  // two count words, zeroed at allocation
     int list_parity = 0;
     RayBoundEntry* rb_entries = nullptr;  // raycast range-bound footprints (one per brick)
@@ -920,8 +920,8 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             sc->list = nullptr;
         }
         CHECK_HIP(hipMalloc((void**)&sc->visit, (size_t)max_items * kVisitPerItem));
-        // the item list, then the deep-brick list (kVisitPerItem per item)
-        CHECK_HIP(hipMalloc((void**)&sc->list, (size_t)max_items * (1 + kVisitPerItem) * sizeof(int32_t)));
+        // the visited-brick list, then the deep-brick list (kVisitPerItem per item each)
+        CHECK_HIP(hipMalloc((void**)&sc->list, (size_t)max_items * (2 * kVisitPerItem) * sizeof(int32_t)));
         sc->visit_cap = max_items;
     }
     if (!sc->list_count) {
@@ -978,7 +978,8 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
             order_pending = false;
             IntegrateLaunch L{p.dh, p.dv, dfr, p.dib, c->counters, sc->ztab, sc->visit,
                               order ? sc->tile_cost : nullptr, order ? sc->tile_order : nullptr,
-                              order ? sc->last_tiles : 0, sc->list, sc->list_count, sc->list + sc->visit_cap};
+                              order ? sc->last_tiles : 0, sc->list, sc->list_count,
+                              sc->list + (size_t)sc->visit_cap * kVisitPerItem};
             if (order) sc->order_ready_tiles = sc->last_tiles;
             CHECK_LAUNCH(launch_ztable(L, (p.items * kZChunk + 255) / 256, stream));
             // with timing, the kernel's dispatch records the event pair
@@ -1516,9 +1517,13 @@ mvf_status mvf_get_stats(mvf_ctx* c, mvf_stats* out)
     *out = c->stats;
     out->voxels_updated = 0;
     out->voxels_band = 0;
+    out->bricks_projected = 0;
+    out->bricks_deep = 0;
     for (int k = 0; k < kCntSlots; ++k) {
         out->voxels_updated += cnt[(size_t)k * kCntNum + kCntUpdated];
         out->voxels_band += cnt[(size_t)k * kCntNum + kCntBand];
+        out->bricks_projected += cnt[(size_t)k * kCntNum + kCntBricks];
+        out->bricks_deep += cnt[(size_t)k * kCntNum + kCntDeep];
     }
     out->resident_bytes = c->resident_bytes;
     int n = 0;
@@ -1982,7 +1987,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         CHECK_HIP(hipMalloc((void**)&G.ztab, (size_t)G.ztab_cap * 3 * sizeof(float)));
         G.visit_cap = std::max(items_total * 2, 1024);
         CHECK_HIP(hipMalloc((void**)&G.visit, (size_t)G.visit_cap * kVisitPerItem));
-        CHECK_HIP(hipMalloc((void**)&G.list, (size_t)G.visit_cap * (1 + kVisitPerItem) * sizeof(int32_t)));
+        CHECK_HIP(hipMalloc((void**)&G.list, (size_t)G.visit_cap * (2 * kVisitPerItem) * sizeof(int32_t)));
         CHECK_HIP(hipMalloc((void**)&G.list_count, 2 * sizeof(unsigned long long)));
         CHECK_HIP(hipMemset(G.list_count, 0, 2 * sizeof(unsigned long long)));
         int counts_cap = 0;
@@ -2137,7 +2142,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             // the last step first)
             IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit,
                                G.tile_cost, G.tile_order, G.ray_tiles, G.list, G.list_count,
-                               G.list + G.visit_cap};
+                               G.list + (size_t)G.visit_cap * kVisitPerItem};
             int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items_total * zc + 255) / 256), cs);
             // one wavefront per work item of the whole volume set (a larger
             // set later is walked by the kernel's grid-stride loop)
