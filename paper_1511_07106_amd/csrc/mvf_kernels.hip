@@ -172,8 +172,10 @@ int launch_volume_init(DevVolume v, void* stream)
 // Launch order of the raycast tile groups: counting sort of their summed
 // last durations, longest first, by half octaves (the leading two bits).
 // Run by one block of any size: each thread takes kOrderBatch groups per
-// round with all their loads in flight, and lanes of a wavefront that fall
-// into the same bin share one LDS atomic.  The cost array holds
+// round with all their loads in flight, and counts and places them with
+// LDS atomics (aggregating a wavefront's lanes per bin with ballots first
+// serialised the block: up to ~90 us per order in the integration launch's
+// block 0, longer than the integration it runs beside).  The cost array holds
 // ray_groups(n) * kRayGroup entries (zero past n).
 constexpr int kOrderBins = 64;
 constexpr int kOrderBatch = 4;
@@ -191,7 +193,6 @@ static __device__ void tile_order_block(const uint32_t* __restrict__ cost, int32
 {
     static_assert(kRayGroup == 4, "one uint4 of costs per group");
     const int ng = ray_groups(ntiles);
-    const int lane = threadIdx.x & 63;
     const int nt = blockDim.x;
     const uint4* c4 = reinterpret_cast<const uint4*>(cost);
     for (int i = threadIdx.x; i < kOrderBins; i += nt) hist[i] = 0;
@@ -207,20 +208,12 @@ static __device__ void tile_order_block(const uint32_t* __restrict__ cost, int32
 #pragma unroll
             for (int k = 0; k < kOrderBatch; ++k) {
                 const int g = g0 + k * nt + (int)threadIdx.x;
-                const int bin = g < ng ? cost_bin(c[k]) : -1;
-                unsigned long long todo = __ballot(bin >= 0);
-                while (todo) {
-                    const int leader = __ffsll(todo) - 1;
-                    const int b = __shfl(bin, leader);
-                    const unsigned long long m = __ballot(bin == b);
-                    int base = 0;
-                    if (lane == leader) base = atomicAdd(&hist[b], (int)__popcll(m));
-                    if (pass == 1) {
-                        base = __shfl(base, leader);
-                        if (bin == b) order[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = g;
-                    }
-                    todo &= ~m;
-                }
+                if (g >= ng) continue;
+                const int bin = cost_bin(c[k]);
+                // the place within a bin is the atomics' order (the launch
+                // order only steers the timing)
+                if (pass == 0) atomicAdd(&hist[bin], 1);
+                else order[atomicAdd(&hist[bin], 1)] = g;
             }
         }
         __syncthreads();
