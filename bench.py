@@ -283,6 +283,19 @@ def phase_diffray(mvf, torch, n_poses=16, n_steps=50):
         for i, (d, c) in enumerate(frames):
             ctx.integrate(torch.from_numpy(d).to(dev), torch.from_numpy(c).to(dev), seq.poses[i], K)
         ctx.synchronize()
+        # the plain raycast of the same volume at the same (perturbed) poses,
+        # timed the same way as the differentiable forward below
+        rng_p = np.random.default_rng(5)
+        plain_ms = []
+        for pi in [int(x) for x in np.linspace(0, 59, n_poses)]:
+            Tp = S.perturb_pose(seq.poses[pi], rng_p, 0.02, 2.0)
+            for _ in range(4):
+                a, b = _events(torch)
+                a.record()
+                ctx.raycast(Tp, K, W_IMG, H_IMG)
+                b.record()
+                torch.cuda.synchronize()
+                plain_ms.append(a.elapsed_time(b))
         F_np, W_np, _ = ctx.read_volume(vid)
     F = torch.from_numpy(F_np).to(dev)
     W = torch.from_numpy(W_np.view(np.int16)).to(dev)
@@ -327,6 +340,8 @@ def phase_diffray(mvf, torch, n_poses=16, n_steps=50):
     return {"poses": n_poses, "steps": n_steps, "image": [W_IMG, H_IMG], "volume": [n, n, n],
             "forward_ms_median": float(np.median(fwd_ms)), "backward_ms_median": float(np.median(bwd_ms)),
             "backward_over_forward": float(np.median(bwd_ms) / np.median(fwd_ms)),
+            "plain_raycast_ms_median": float(np.median(plain_ms)),
+            "forward_over_plain_raycast": float(np.median(fwd_ms) / np.median(plain_ms)),
             "trans_err_mm_before": 1e3 * float(np.mean(err0)), "trans_err_mm_after": 1e3 * float(np.mean(err1)),
             "rot_err_deg_before": float(np.mean(rot0)), "rot_err_deg_after": float(np.mean(rot1)),
             "loss_ratio_median": float(np.median(loss_ratio)),

@@ -143,7 +143,7 @@ def test_step_512_large_room(mvf, large, sched):
                 amb = _end_to_end(g, [ref], og, K, seq.poses[i], [vid])
                 print(f"[parity] step 512^3 sched {sched} frame {i}: max|dF| {err:.2e}, hits {n}, "
                       f"ambiguous fraction {amb:.2e}", flush=True)
-                assert amb < 1e-3
+                assert amb < 1e-4   # measured 4.2e-5 and 4.9e-5 on these frames
         if cache:
             assert ctx.schedule() == tuned
 
@@ -187,6 +187,7 @@ def test_tiled_8x257_large_room(mvf, large, mode):
         amb = rc1["ambiguous"].astype(bool)
         np.testing.assert_array_equal(g["hit"][~amb] >= 0, rc1["hit"][~amb] >= 0)
         print(f"[parity] tiled 8 x 257^3 via {mode}: hits {n}, ambiguous fraction {amb.mean():.2e}", flush=True)
+        assert amb.mean() < 1e-4   # measured 4.2e-5
 
 
 @pytest.mark.parametrize("mode", ["plain", "step"])

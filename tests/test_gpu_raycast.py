@@ -63,7 +63,8 @@ def test_small_room_end_to_end(mvf):
         g, rc = raycast_both(ctx, ovs, og, K, seq.poses[9], 320, 240)
         amb = rc["ambiguous"].astype(bool)
         print(f"[parity] small room 128^3 end to end: ambiguous fraction {amb.mean():.2e}", flush=True)
-        assert amb.mean() < 1e-2
+        # measured 2.6e-5 on this scene; the parity bar for end-to-end maps is 1e-4
+        assert amb.mean() < 1e-4
         hit_g, hit_o = g["hit"] >= 0, rc["hit"] >= 0
         np.testing.assert_array_equal(hit_g[~amb], hit_o[~amb])
         both = hit_g & hit_o & ~amb
