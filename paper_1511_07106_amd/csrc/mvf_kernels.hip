@@ -708,21 +708,24 @@ static __device__ int brick_class(const DevVolume& V, const DevFrame& Fr, const 
         const float pcz = T[2] * cw[0] + T[6] * cw[1] + T[10] * cw[2];
         const float ecz = fabsf(T[2]) * ew[0] + fabsf(T[6]) * ew[1] + fabsf(T[10]) * ew[2];
         if (pcz + ecz < -1e-3f) return 0;
-        if (pcz - ecz > 0.01f) {
-            const float A[4] = {Fr.fx, -Fr.fx, 0.0f, 0.0f};
-            const float B[4] = {0.0f, 0.0f, Fr.fy, -Fr.fy};
-            const float Cc[4] = {Fr.cx + 1.5f, (float)Fr.width + 0.5f - Fr.cx, Fr.cy + 1.5f,
-                                 (float)Fr.height + 0.5f - Fr.cy};
+        // the side planes pass through the camera centre: a point with pz > 0
+        // projects inside the grown image iff all four forms are >= 0, so the
+        // test also holds for a box across the camera plane (around a camera
+        // inside the volume; such boxes were all visited before, and most of
+        // them have no column in the view)
+        const float A[4] = {Fr.fx, -Fr.fx, 0.0f, 0.0f};
+        const float B[4] = {0.0f, 0.0f, Fr.fy, -Fr.fy};
+        const float Cc[4] = {Fr.cx + 1.5f, (float)Fr.width + 0.5f - Fr.cx, Fr.cy + 1.5f,
+                             (float)Fr.height + 0.5f - Fr.cy};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float Lc = A[q] * pcx + B[q] * pcy + Cc[q] * pcz;
-                float Le = 0.0f;
+        for (int q = 0; q < 4; ++q) {
+            const float Lc = A[q] * pcx + B[q] * pcy + Cc[q] * pcz;
+            float Le = 0.0f;
 #pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    Le += fabsf(A[q] * T[4 * b] + B[q] * T[4 * b + 1] + Cc[q] * T[4 * b + 2]) * ew[b];
-                const float margin = 1e-4f * (fabsf(A[q]) + fabsf(B[q]) + fabsf(Cc[q])) * (fabsf(pcz) + ecz + 1.0f);
-                if (Lc + Le < -margin) return 0;
-            }
+            for (int b = 0; b < 3; ++b)
+                Le += fabsf(A[q] * T[4 * b] + B[q] * T[4 * b + 1] + Cc[q] * T[4 * b + 2]) * ew[b];
+            const float margin = 1e-4f * (fabsf(A[q]) + fabsf(B[q]) + fabsf(Cc[q])) * (fabsf(pcz) + ecz + 1.0f);
+            if (Lc + Le < -margin) return 0;
         }
     }
     float u0 = INFINITY, u1 = -INFINITY, v0 = INFINITY, v1 = -INFINITY;
