@@ -243,10 +243,11 @@ struct RaycastLaunch {
 // as int (0 = success).
 int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream);
 int launch_volume_init(DevVolume v, void* stream);
-// The z table of a launch and, when L.visit is set, the items' brick visit
-// masks (cull_blocks blocks of 256 threads walk the items); must precede
+// The z table of a launch and, when L.visit is set, the visit pass over
+// the launch's `bricks` bricks (total_items * zchunk; one thread per brick,
+// up to 512 blocks of 512 threads, which then walk the rest); must precede
 // launch_integrate on the stream.
-int launch_ztable(const IntegrateLaunch& L, int cull_blocks, void* stream);
+int launch_ztable(const IntegrateLaunch& L, int bricks, void* stream);
 // Integration kernel: blocks of 256 threads, 4 items in flight per block; a
 // grid smaller than total_items / 4 walks the items (plus block 0 when
 // L.tile_order is set).

@@ -981,7 +981,7 @@ mvf_status integrate_plain(mvf_ctx* c, int sid, const mvf_frame* f, const float*
                               order ? sc->last_tiles : 0, sc->list, sc->list_count,
                               sc->list + (size_t)sc->visit_cap * kVisitPerItem};
             if (order) sc->order_ready_tiles = sc->last_tiles;
-            CHECK_LAUNCH(launch_ztable(L, (p.items * kZChunk + 255) / 256, stream));
+            CHECK_LAUNCH(launch_ztable(L, p.items * kZChunk, stream));
             // with timing, the kernel's dispatch records the event pair
             hipEvent_t t0, t1;
             CHECK_ST(timing_pair(c, &t0, &t1));
@@ -2143,7 +2143,7 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit,
                                G.tile_cost, G.tile_order, G.ray_tiles, G.list, G.list_count,
                                G.list + (size_t)G.visit_cap * kVisitPerItem};
-            int e2 = e1 ? e1 : launch_ztable(IL, std::max(c->n_cus, (items_total * zc + 255) / 256), cs);
+            int e2 = e1 ? e1 : launch_ztable(IL, items_total * zc, cs);
             // one wavefront per work item of the whole volume set (a larger
             // set later is walked by the kernel's grid-stride loop)
             G.integ_blocks = (sch.persistent ? c->n_cus * 8 : std::max(c->n_cus * 8, (items_total + 3) / 4)) + 1;
