@@ -180,8 +180,17 @@ def test_far_plane_every_voxel(mvf, plane_z):
             O.integrate(ov, og, depth, rgb, K, T)
             ctx.integrate(t(depth), t(rgb), T, K)
         F, W, Cc = ctx.read_volume(vid)
+        st = ctx.stats()
         np.testing.assert_array_equal(W, ov.W)
         np.testing.assert_array_equal(Cc, ov.Cc)
         assert np.abs(F.astype(np.float64) - ov.F).max() <= 1e-5
+        # the counters: every update counted once, each brick in at most one class
+        assert st["voxels_updated"] == int(ov.W.sum())
+        nb = (n // 8) ** 3
+        assert st["bricks_projected"] + st["bricks_deep"] <= 3 * nb
         if plane_z > 4:
             assert int((W == 3).sum()) > 0.9 * n ** 3
+            # bricks under the invalid top rows are visited, the rest deep
+            assert st["bricks_deep"] > 0.8 * 3 * nb, st
+        else:
+            assert st["bricks_projected"] > 0 and st["bricks_deep"] > 0, st
