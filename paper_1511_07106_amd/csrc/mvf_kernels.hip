@@ -231,23 +231,24 @@ static __device__ void tile_order_block(const uint32_t* __restrict__ cost, int32
 }
 
 // ---------------------------------------------------------------------------
-// Integration.  One wavefront owns an 8x8 tile of voxel columns (one brick
-// column) and walks z through a chunk of bricks; each lane is one column
-// (Volumetric Integration section: one thread per (x, y), iterating z).  A
-// z-slice of a brick is 64 consecutive voxels, so every load/store of the
-// wave is one contiguous 256-byte (F, C) or 128-byte (W) access.  A
-// conservative per-column z interval (frustum, near plane, farthest range
-// of the frame) skips bricks no lane needs; the exact binary32 test decides
-// every voxel of a visited brick.
+// Integration.  A wavefront owns the 8x8 voxel columns of a brick and walks
+// its 8 z-slices; each lane is one column (Volumetric Integration section:
+// one thread per (x, y), iterating z).  A z-slice of a brick is 64
+// consecutive voxels, so every load/store of the wave is one contiguous
+// 256-byte (F, C) or 128-byte (W) access.  The visit pass before the launch
+// lists the bricks to decide voxel by voxel and the "deep" ones, updated
+// wholesale with phi = 1; a conservative per-column z interval (frustum,
+// near plane, farthest range of the frame) masks lanes, and the exact
+// binary32 test decides every voxel of a visited brick.
 //
 // Per voxel the work is the projection (one division), a gather of the
 // measured range, a square root and the running average.  The camera-frame
 // offset of each z, the same for all lanes, comes from a table computed by
-// a small kernel before the launch (scalar loads).  The square root uses the hardware estimate and takes the correctly
-// rounded value only in lanes where the estimate lies within its error
-// bound of the truncation band: elsewhere the update test, the band test
-// and the stored value (phi = 1, or no update) do not depend on which of
-// the two roots is used.
+// a small kernel before the launch (scalar loads).  The square root uses
+// the hardware estimate and takes the correctly rounded value only in lanes
+// where the estimate lies within its error bound of the truncation band:
+// elsewhere the update test, the band test and the stored value (phi = 1,
+// or no update) do not depend on which of the two roots is used.
 // ---------------------------------------------------------------------------
 
 // n / d for n < 2^17 and 1 <= d <= 256 exactly: a quotient from the
