@@ -245,7 +245,7 @@ int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* 
 int launch_volume_init(DevVolume v, void* stream);
 // The z table of a launch and, when L.visit is set, the visit pass over
 // the launch's `bricks` bricks (total_items * zchunk; one thread per brick,
-// up to 512 blocks of 512 threads, which then walk the rest); must precede
+// up to 2048 blocks of 512 threads, which then walk the rest); must precede
 // launch_integrate on the stream.
 int launch_ztable(const IntegrateLaunch& L, int bricks, void* stream);
 // Integration kernel: blocks of 256 threads, 4 items in flight per block; a

@@ -776,8 +776,11 @@ static __device__ int brick_class(const DevVolume& V, const DevFrame& Fr, const 
 constexpr int kZtBlocks = 16;
 // visited items a z-table block holds in LDS before appending them
 constexpr int kZtListBuf = 1024;
-// most blocks of the visit pass (each appends its bricks with one atomic per flush)
-constexpr int kZtCullBlocksMax = 512;
+// most blocks of the visit pass (each appends its bricks with one atomic per
+// flush): one brick per thread up to 1M bricks (the 32-room workload's 73
+// volumes: 90 us of visit pass with 512 blocks, each thread walking about
+// eleven bricks in turn)
+constexpr int kZtCullBlocksMax = 2048;
 // threads of a z-table launch's blocks: a visit block of 512 threads takes one
 // brick per thread on a 512^3 volume (10.7 us per frame on the large room,
 // against 13.2 us with 256 threads and two bricks each, 11.4 with 1024)
