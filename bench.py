@@ -767,6 +767,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--phases", default=DEFAULT_PHASES, help="comma list of phases (default: all)")
+    ap.add_argument("--schedule-cache", default=None,
+                    help="path prefix of the captured phases' schedule files: read when present (no tuning), "
+                         "else tuned and written (to profile a run with the schedule of an unprofiled one)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the phases, copy a buffer of this size 5 times (counter calibration)")
     args = ap.parse_args()
@@ -799,10 +802,15 @@ def main():
             cache = None
             if ph in ("single_step", "batched"):
                 # the batched form's autotuner picks the launch schedule on a
-                # separate context first (untimed)
-                cache = os.path.join(tempfile.mkdtemp(prefix="mvf_tune_"), "schedules.jsonl")
-                run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps, tune_cache=cache,
-                          tune=True)
+                # separate context first (untimed), unless a schedule file of
+                # an earlier run is given
+                if args.schedule_cache:
+                    cache = f"{args.schedule_cache}_{ph}.jsonl"
+                else:
+                    cache = os.path.join(tempfile.mkdtemp(prefix="mvf_tune_"), "schedules.jsonl")
+                if not os.path.exists(cache):
+                    run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps, tune_cache=cache,
+                              tune=True)
             phases[ph] = run_phase(mvf, torch, ph, dev_frames, poses, K, args.warmup, args.steps,
                                    tune_cache=cache)
             if ph in ("single", "tiled"):

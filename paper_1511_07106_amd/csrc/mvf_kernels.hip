@@ -1377,14 +1377,18 @@ static __host__ __device__ bool march_volume(const DevVolume& V, const Ray& r, f
 
 #if defined(__HIP_DEVICE_COMPILE__)
 // March one volume with the P lanes of a group (lane j of the group; all P
-// lanes carry the same ray and take the same path through the loop).  Each
-// round covers a window of P consecutive samples: every lane makes the skip
-// decision of its own sample; if no sample of the window may be the far end
-// of a crossing the group jumps past the longest clear run, otherwise every
-// lane evaluates its sample (one round of gathers for the window) and the
-// first crossing in sample order is taken, exactly as the sequential march
-// would find it.  When the sample before the window was not evaluated the
-// window starts one sample earlier so that it serves as the near end.
+// lanes carry the same ray and take the same path through the loop).  A
+// round starts at sample w0: every lane makes the skip decision of sample
+// w0 + j; if no sample of that window may be the far end of a crossing the
+// group jumps past the longest clear run, otherwise the group evaluates
+// kEvalWindows consecutive windows (lane j: samples w0 + w*P + j, all their
+// gathers in flight together) and takes the first crossing in sample order,
+// exactly as the sequential march would find it.  When the sample before
+// the round was not evaluated, w0 is that sample so that it serves as the
+// near end.  Rays that graze a surface evaluate long stretches of samples;
+// two windows a round halve their rounds of dependent loads.
+constexpr int kEvalWindows = 2;
+
 template <int P>
 static __device__ bool march_volume_group(const DevVolume& V, const Ray& r, float delta, int kmax, float best_t,
                                           int best_id, float& tstar, int& kstar, int cell[3], int j)
@@ -1443,41 +1447,100 @@ static __device__ bool march_volume_group(const DevVolume& V, const Ray& r, floa
             k = rmax;
             continue;
         }
-        float Fk = 0.0f;
-        bool ok = false;
-        if (dom) ok = eval_sample(V, l, Fk);
-        float Fn = __shfl_up(Fk, 1, P);
-        int okn = __shfl_up((int)ok, 1, P);
-        if (j == 0) { Fn = Fprev; okn = prev_ok; }
-        const bool excl = far && (float)(sidx - 1) * delta > best_t;   // the sequential march stops first
-        const bool cross = far && !excl && okn && ok && Fn > 0.0f && Fk <= 0.0f;
-        const uint32_t cross_g = (uint32_t)(__ballot(cross) >> gbase) & gm;
-        const uint32_t excl_g = (uint32_t)(__ballot(excl) >> gbase) & gm;
-        const int jc = cross_g ? __ffs(cross_g) - 1 : P;
-        const int je = excl_g ? __ffs(excl_g) - 1 : P;
+        // evaluation round: kEvalWindows windows of P consecutive samples
+        // from w0, lane j taking sample w0 + w*P + j of window w.  Samples of
+        // the later windows are evaluated without a skip test: a sample the
+        // test would pass over cannot be the far end of a crossing, so the
+        // first crossing found is still the sequential march's.  All gathers
+        // are issued before any is used (a sample outside the domain reads
+        // cell 0 and is discarded).
+        constexpr int S = kEvalWindows;
+        float Fs[S], Fns[S];
+        int oks[S], ics[S][3];
+        uint32_t cross_all = 0, excl_all = 0;
+        {
+            float cs[S][8], fs[S][3];
+            bool doms[S];
+#pragma unroll
+            for (int w = 0; w < S; ++w) {
+                float ls[3];
+                if (w == 0) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) ls[a] = l[a];
+                    doms[w] = dom;
+                } else {
+                    sample_coord(V, r, (float)(sidx + w * P) * delta, ls);
+                    doms[w] = sidx + w * P <= k1 && in_domain(V, ls);
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float fl = floorf(ls[a]);
+                    ics[w][a] = doms[w] ? (int)fl : 0;
+                    fs[w][a] = ls[a] - fl;
+                }
+                gather8(V, ics[w], cs[w]);
+            }
+            float Fc = Fprev;
+            int okc = prev_ok;
+#pragma unroll
+            for (int w = 0; w < S; ++w) {
+                const float Fk = trilinear(cs[w], fs[w]);
+                const bool ok = doms[w] && !isnan(Fk);
+                Fs[w] = Fk;
+                oks[w] = ok;
+                float Fn = __shfl_up(Fk, 1, P);
+                int okn = __shfl_up((int)ok, 1, P);
+                if (j == 0) { Fn = Fc; okn = okc; }
+                Fns[w] = Fn;
+                Fc = __shfl(Fk, gbase + P - 1);
+                okc = __shfl((int)ok, gbase + P - 1);
+                const int si = sidx + w * P;
+                const bool farw = si >= k && si <= k1;
+                const bool excl = farw && (float)(si - 1) * delta > best_t;   // the sequential march stops first
+                const bool cross = farw && !excl && okn && ok && Fn > 0.0f && Fk <= 0.0f;
+                cross_all |= ((uint32_t)(__ballot(cross) >> gbase) & gm) << (w * P);
+                excl_all |= ((uint32_t)(__ballot(excl) >> gbase) & gm) << (w * P);
+            }
+        }
+        const int jc = cross_all ? __ffs(cross_all) - 1 : S * P;
+        const int je = excl_all ? __ffs(excl_all) - 1 : S * P;
         if (jc < je) {
+            const int wc = jc / P, lc = jc - wc * P;
+            float Fn = 0.0f, Fk = 0.0f;
+            int ic[3] = {0, 0, 0};
+#pragma unroll
+            for (int w = 0; w < S; ++w)
+                if (w == wc) {
+                    Fn = Fns[w]; Fk = Fs[w];
+                    ic[0] = ics[w][0]; ic[1] = ics[w][1]; ic[2] = ics[w][2];
+                }
             float ts = 0.0f;
             int acc = 0;
-            if (j == jc) {
-                const float ta = (float)(sidx - 1) * delta;
+            if (j == lc) {
+                const float ta = (float)(w0 + jc - 1) * delta;
                 ts = ta + ((delta * Fn) / (Fn - Fk));
                 acc = (ts < best_t || (ts == best_t && V.id < best_id)) ? 1 : 0;
             }
-            ts = __shfl(ts, gbase + jc);
-            acc = __shfl(acc, gbase + jc);
+            ts = __shfl(ts, gbase + lc);
+            acc = __shfl(acc, gbase + lc);
             if (!acc) return false;
             tstar = ts;
             kstar = w0 + jc;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) cell[a] = __shfl(i[a], gbase + jc);
+            for (int a = 0; a < 3; ++a) cell[a] = __shfl(ic[a], gbase + lc);
             return true;
         }
-        if (je < P) return false;
-        // no crossing: the window's last far-end sample becomes the previous one
-        const int last = min(w0 + P - 1, k1);
-        const int jl = last - w0;
-        prev_ok = __shfl((int)ok, gbase + jl) != 0;
-        Fprev = __shfl(Fk, gbase + jl);
+        if (je < S * P) return false;
+        // no crossing: the last far-end sample becomes the previous one
+        const int last = min(w0 + S * P - 1, k1);
+        const int jl = last - w0, wl = jl / P, ll = jl - wl * P;
+        float Fl = 0.0f;
+        int okl = 0;
+#pragma unroll
+        for (int w = 0; w < S; ++w)
+            if (w == wl) { Fl = Fs[w]; okl = oks[w]; }
+        prev_ok = __shfl(okl, gbase + ll) != 0;
+        Fprev = __shfl(Fl, gbase + ll);
         prev_k = last;
         k = last + 1;
     }
@@ -1523,7 +1586,7 @@ static __host__ __device__ void raycast_pixel(const RaycastLaunch& L, const Laun
                                               int j = 0);
 
 template <int P>
-__global__ __launch_bounds__(64) void mvf_raycast_kernel(RaycastLaunch L)
+__global__ __launch_bounds__(64, 5) void mvf_raycast_kernel(RaycastLaunch L)
 {
     const LaunchHeader H = *cptr(L.hdr);
     // Tile groups are taken in the launch order (the slowest groups of the
