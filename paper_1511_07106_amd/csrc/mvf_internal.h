@@ -241,7 +241,14 @@ struct RaycastLaunch {
 
 // Host-side launchers (defined in mvf_kernels.hip).  All return hipError_t
 // as int (0 = success).
-int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream);
+// Frame preparation of n frames.  With tsrc set (a captured step) the items
+// are read from pinned host memory and the launch also copies tbytes (a
+// multiple of 16, 16-byte aligned) from tsrc to tdst; set_frame_prep_node
+// points such a node of an instantiated graph at another host slot.
+int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream, const void* tsrc = nullptr,
+                      void* tdst = nullptr, size_t tbytes = 0);
+int set_frame_prep_node(void* exec, void* node, const PrepItem* items, int n, int max_w, int max_h, const void* tsrc,
+                        void* tdst, size_t tbytes);
 int launch_volume_init(DevVolume v, void* stream);
 // The z table of a launch and, when L.visit is set, the visit pass over
 // the launch's `bricks` bricks (total_items * zchunk; one thread per brick,

@@ -63,9 +63,19 @@ static __host__ __device__ __forceinline__ size_t brick_index(const int bd[3], i
 // The range map holds one more element, range[W * H] = 0, read by voxels
 // that project outside the image.  The maximum range is reduced from
 // per-block maxima by the z-table kernel, which runs before integration.
+// In a captured step the items are read from the step's pinned host slot,
+// and every thread of the launch also copies one 16-byte word of the slot's
+// table image to the tables' device home (tsrc, tdst: n16 words), which the
+// later kernels of the step read.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __restrict__ items)
+__global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __restrict__ items, const uint4* tsrc,
+                                                             uint4* tdst, uint32_t n16)
 {
+    if (tsrc) {
+        const uint32_t nt = gridDim.x * gridDim.y * gridDim.z * 256u;
+        const uint32_t t = ((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 256u + threadIdx.x;
+        for (uint32_t i = t; i < n16; i += nt) tdst[i] = tsrc[i];
+    }
     const PrepItem& it = items[blockIdx.z];
     const int u = blockIdx.x * 32 + (threadIdx.x & 31);
     const int v = blockIdx.y * 8 + (threadIdx.x >> 5);
@@ -127,13 +137,36 @@ __global__ __launch_bounds__(256) void mvf_frame_prep_kernel(const PrepItem* __r
     }
 }
 
-int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream)
+int launch_frame_prep(const PrepItem* items, int n, int max_w, int max_h, void* stream, const void* tsrc,
+                      void* tdst, size_t tbytes)
 {
     if (n <= 0) return 0;
+    if (tsrc && ((tbytes & 15) || ((uintptr_t)tsrc & 15) || ((uintptr_t)tdst & 15))) return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;
     dim3 grid((max_w + 31) / 32, (max_h + 7) / 8, n);
-    hipLaunchKernelGGL(mvf_frame_prep_kernel, grid, dim3(256), 0, s, items);
+    hipLaunchKernelGGL(mvf_frame_prep_kernel, grid, dim3(256), 0, s, items, (const uint4*)tsrc, (uint4*)tdst,
+                       (uint32_t)(tsrc ? tbytes / 16 : 0));
     return (int)hipGetLastError();
+}
+
+int set_frame_prep_node(void* exec, void* node, const PrepItem* items, int n, int max_w, int max_h, const void* tsrc,
+                        void* tdst, size_t tbytes)
+{
+    if (n <= 0 || !tsrc || (tbytes & 15) || ((uintptr_t)tsrc & 15) || ((uintptr_t)tdst & 15))
+        return (int)hipErrorInvalidValue;
+    const PrepItem* a0 = items;
+    const uint4* a1 = (const uint4*)tsrc;
+    uint4* a2 = (uint4*)tdst;
+    uint32_t a3 = (uint32_t)(tbytes / 16);
+    void* args[] = {(void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3};
+    hipKernelNodeParams p{};
+    p.func = reinterpret_cast<void*>(mvf_frame_prep_kernel);
+    p.gridDim = dim3((max_w + 31) / 32, (max_h + 7) / 8, n);
+    p.blockDim = dim3(256);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    return (int)hipGraphExecKernelNodeSetParams((hipGraphExec_t)exec, (hipGraphNode_t)node, &p);
 }
 
 // ---------------------------------------------------------------------------
@@ -1100,24 +1133,6 @@ static __host__ __device__ __forceinline__ bool eval_sample_cached(const DevVolu
         cc.i[2] = i[2];
     }
     Fk = trilinear(cc.c, f);
-    return !isnan(Fk);
-}
-
-// The same without the cache (the group march: a lane's successive samples
-// are a window apart, rarely in one cell).
-static __device__ __forceinline__ bool eval_sample(const DevVolume& V, const float l[3], float& Fk)
-{
-    int i[3];
-    float f[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float fl = floorf(l[a]);
-        i[a] = (int)fl;
-        f[a] = l[a] - fl;
-    }
-    float c[8];
-    gather8(V, i, c);
-    Fk = trilinear(c, f);
     return !isnan(Fk);
 }
 

@@ -171,7 +171,7 @@ struct StepGraph {
     std::vector<int> widths, heights, out_w, out_h;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy_node = nullptr;  // table upload (first node)
+    hipGraphNode_t copy_node = nullptr;  // frame preparation, which also uploads the tables (the root)
     // persistent device tables read by the captured kernels
     uint8_t* dev = nullptr;
     size_t dev_bytes = 0;
@@ -2122,12 +2122,11 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
         G.rb_parity ^= 1;
         h->list_parity = G.list_parity;
         G.list_parity ^= 1;
-        // The graph's first node uploads this image into its fixed tables; the
-        // node's source is pointed at this wave's arena slot.
+        // The graph's first node (frame preparation) copies this image into the
+        // fixed tables; its source is pointed at this wave's arena slot.
         if (!G.valid) {
             hipStream_t cs = c->capture_stream;
             const LaunchHeader* dh = reinterpret_cast<const LaunchHeader*>(G.dev + G.off_hdr);
-            const PrepItem* dprep = reinterpret_cast<const PrepItem*>(G.dev + G.off_prep);
             const DevFrame* dframes = reinterpret_cast<const DevFrame*>(G.dev + G.off_frames);
             const DevVolume* dvols = reinterpret_cast<const DevVolume*>(G.dev + G.off_vols);
             const int32_t* ditems = reinterpret_cast<const int32_t*>(G.dev + G.off_items);
@@ -2136,8 +2135,10 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             const int32_t* dtb = reinterpret_cast<const int32_t*>(G.dev + G.off_tbase);
             const int32_t* dbb = reinterpret_cast<const int32_t*>(G.dev + G.off_bbase);
             CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            int e1 = (int)hipMemcpyAsync(G.dev, w.host, G.dev_bytes, hipMemcpyHostToDevice, cs);
-            if (!e1) e1 = launch_frame_prep(dprep, n, G.max_w, G.max_h, cs);
+            // the first node reads this step's prep items from the slot and
+            // copies the slot's tables to G.dev
+            int e1 = launch_frame_prep(reinterpret_cast<const PrepItem*>(w.host + G.off_prep), n, G.max_w, G.max_h, cs,
+                                       w.host, G.dev, G.dev_bytes);
             // integration's block 0 orders the raycast's tile groups (slowest of
             // the last step first)
             IntegrateLaunch IL{dh, dvols, dframes, ditems, c->counters, G.ztab, G.visit,
@@ -2159,21 +2160,16 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             if (e3) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString((hipError_t)e3));
             if (ee != hipSuccess) return set_error(MVF_ERR_HIP, "step capture: %s", hipGetErrorString(ee));
             CHECK_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
-            size_t nn = 0;
-            CHECK_HIP(hipGraphGetNodes(G.graph, nullptr, &nn));
-            std::vector<hipGraphNode_t> nodes(nn);
-            CHECK_HIP(hipGraphGetNodes(G.graph, nodes.data(), &nn));
+            // frame preparation (with the table upload) is the graph's only root
             G.copy_node = nullptr;
-            for (hipGraphNode_t nd : nodes) {
-                hipGraphNodeType ty;
-                CHECK_HIP(hipGraphNodeGetType(nd, &ty));
-                if (ty == hipGraphNodeTypeMemcpy) G.copy_node = nd;
-            }
-            if (!G.copy_node) return set_error(MVF_ERR_HIP, "step capture: no table upload node");
+            size_t nr = 1;
+            CHECK_HIP(hipGraphGetRootNodes(G.graph, &G.copy_node, &nr));
+            if (nr != 1 || !G.copy_node) return set_error(MVF_ERR_HIP, "step capture: no frame preparation node");
             G.valid = true;
         } else {
-            CHECK_HIP(hipGraphExecMemcpyNodeSetParams1D(G.exec, G.copy_node, G.dev, w.host, G.dev_bytes,
-                                                        hipMemcpyHostToDevice));
+            CHECK_HIP((hipError_t)set_frame_prep_node(G.exec, G.copy_node,
+                                                      reinterpret_cast<const PrepItem*>(w.host + G.off_prep), n,
+                                                      G.max_w, G.max_h, w.host, G.dev, G.dev_bytes));
         }
         hipEvent_t tune_a = nullptr, tune_b = nullptr;
         if (tuning) {
