@@ -80,6 +80,62 @@ def test_step_equals_plain(mvf, n_streams):
                 np.testing.assert_array_equal(a[k].view(np.uint8), b[k].view(np.uint8))
 
 
+def test_step_mixed_image_sizes_equals_plain(mvf):
+    """Streams of different, ragged image sizes in one step (frame
+    preparation runs over the largest image and each stream masks its own
+    bounds; its items are read from the step's host slot): the same bits as
+    the plain calls."""
+    import torch
+    sizes = [(160, 120), (97, 61), (128, 96)]
+    seqs = []
+    for i, (w, h) in enumerate(sizes):
+        K = S.Intrinsics(w * 0.82, w * 0.82, (w - 1) / 2, (h - 1) / 2, w, h)
+        seqs.append(S.small_room_sequence(seed=2000 + i, n_frames=8, K=K))
+    # a lattice over the whole 4 m room, so that the volumes hold wall and
+    # sphere surfaces in most frames
+    layouts = [[((0, 0, 0), (57, 40, 57))], [((5, 3, 9), (33, 57, 40)), ((30, 0, 0), (24, 24, 33))],
+               [((10, 10, 0), (40, 33, 57))]]
+    origin, s = (-2.2, -2.2, -2.2), 4.4 / 64
+    log("batched step vs plain, mixed image sizes")
+    res = []
+    for batched in (False, True):
+        with mvf.Context() as ctx:
+            gid = ctx.grid(origin, s)
+            ids = [[ctx.volume(gid, off, dims, stream_id=i) for off, dims in layouts[i]] for i in range(len(seqs))]
+            maps = []
+            for f in range(0, 8, 2):
+                frames, outs = [], []
+                for i, seq in enumerate(seqs):
+                    d, c = seq.frame(f)
+                    frames.append((i, t(d), t(c), seq.poses[f], seq.K.as_array()))
+                if batched:
+                    outs = [{"depth": torch.empty((h, w), device="cuda"),
+                             "vertex": torch.empty((h, w, 3), device="cuda"),
+                             "normal": torch.empty((h, w, 3), device="cuda"),
+                             "hit": torch.empty((h, w), dtype=torch.int32, device="cuda")} for w, h in sizes]
+                    ctx.step(frames, outs)
+                else:
+                    for (sid, d, c, T, KK), (w, h) in zip(frames, sizes):
+                        ctx.integrate(d, c, T, KK, stream_id=sid)
+                        outs.append(ctx.raycast(T, KK, w, h, stream_id=sid))
+                maps.append([{k: v.cpu().numpy() for k, v in o.items()} for o in outs])
+            vols = [[ctx.read_volume(v) for v in per] for per in ids]
+            st = ctx.stats()
+            res.append((maps, vols, st))
+    (m0, v0, s0), (m1, v1, s1) = res
+    assert s1["step_launches"] == 4 and s0["voxels_updated"] == s1["voxels_updated"] > 0
+    assert all(int((W > 0).sum()) > 0 for per in v1 for _, W, _ in per)
+    for a, b in zip(v0, v1):
+        for x, y in zip(a, b):
+            for p, q in zip(x, y):
+                np.testing.assert_array_equal(p.view(np.uint8), q.view(np.uint8))
+    assert sum(int((a["hit"] >= 0).sum()) for fa in m0 for a in fa) > 1000
+    for fa, fb in zip(m0, m1):
+        for a, b in zip(fa, fb):
+            for k in a:
+                np.testing.assert_array_equal(a[k].view(np.uint8), b[k].view(np.uint8))
+
+
 def _run_steps(mvf, seqs, layouts, n_frames, configure=None):
     import torch
     origin, s = (-1.0, -1.0, -1.0), 2.0 / 64
