@@ -788,14 +788,22 @@ static __device__ int brick_class(const DevVolume& V, const DevFrame& Fr, const 
     const int nx = ((int)a1 >> 3) - ta0 + 1, ny = ((int)b1 >> 3) - tb0 + 1;
     if (nx > 4 || ny > 4) return 1;
     const float* tmin = Fr.tmax + (size_t)Fr.tiles_x * Fr.tiles_y;
+    // 16 tiles, each index clamped into the nx x ny rectangle (repeats of its
+    // tiles leave the maximum and minimum as they are): the loads carry no
+    // condition, so all of them are in flight at once
+    float tx[16], tn[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int t = (tb0 + min(k >> 2, ny - 1)) * Fr.tiles_x + ta0 + min(k & 3, nx - 1);
+        tx[k] = Fr.tmax[t];
+        tn[k] = tmin[t];
+    }
     float mR = 0.0f, mn = INFINITY;
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-        if ((k & 3) < nx && (k >> 2) < ny) {
-            const int t = (tb0 + (k >> 2)) * Fr.tiles_x + ta0 + (k & 3);
-            mR = fmaxf(mR, Fr.tmax[t]);
-            mn = fminf(mn, tmin[t]);
-        }
+    for (int k = 0; k < 16; ++k) {
+        mR = fmaxf(mR, tx[k]);
+        mn = fminf(mn, tn[k]);
+    }
     if (mR == 0.0f) return 0;  // no measurement under the brick
     if (dmin > mR + V.mu) return 0;
     const float dmax = sqrtf(d2f) * (1.0f + 1e-5f) + 1e-4f;
