@@ -132,15 +132,24 @@ struct Scratch {
 };
 
 // Ring of pinned host + device slots for per-launch tables.  A slot is
-// reused only after the event recorded behind the launches that read it.
+// reused only after an event recorded behind the launches that read it.
+// Captured steps release their slots in batches of kBatch behind one event
+// (each event record between two graph launches cost the step 3-6 us); the
+// batch's last slot is the latest in ring order, so every slot of a batch is
+// reacquired, and has waited, before that slot's event is recorded again.
 struct Arena {
     static constexpr int kSlots = 32;
+    static constexpr int kBatch = 4;
     static constexpr size_t kSlotBytes = 1 << 20;
     uint8_t* host = nullptr;
     uint8_t* dev = nullptr;
     hipEvent_t ev[kSlots] = {};
+    hipEvent_t wait_ev[kSlots] = {};   // the event a pending slot waits on before reuse
     bool pending[kSlots] = {};
     int next = 0;
+    int open[kBatch] = {};             // step slots released since the last record
+    int n_open = 0;
+    hipStream_t open_stream = nullptr;
 };
 
 struct Writer {
@@ -224,6 +233,7 @@ struct mvf_ctx {
     hipEvent_t tail_ev = nullptr;  // the event that marks the end of the last call (tail or an arena event)
     hipStream_t tail_stream = nullptr;
     bool tail_valid = false;
+    bool tail_pending = false;     // the last call was a step whose arena batch is not recorded yet
     int n_cus = 256;
     // step schedule and its autotuner
     mvf_schedule fixed_sched{4, 0, kRayLanes, 0};
@@ -287,10 +297,36 @@ mvf_status get_event(mvf_ctx* c, hipEvent_t* ev)
     return MVF_OK;
 }
 
+// Record one event behind the step slots released since the last record;
+// each of them waits on it before reuse.  When the last call was such a
+// step, the event becomes the tail.
+mvf_status arena_flush(mvf_ctx* c)
+{
+    Arena& A = c->arena;
+    if (A.n_open == 0) return MVF_OK;
+    const int last = A.open[A.n_open - 1];
+    CHECK_HIP(hipEventRecord(A.ev[last], A.open_stream));
+    for (int i = 0; i < A.n_open; ++i) {
+        A.wait_ev[A.open[i]] = A.ev[last];
+        A.pending[A.open[i]] = true;
+    }
+    A.n_open = 0;
+    if (c->tail_pending) {
+        c->tail_ev = A.ev[last];
+        c->tail_stream = A.open_stream;
+        c->tail_valid = true;
+        c->tail_pending = false;
+    }
+    return MVF_OK;
+}
+
 // Make `stream` run after everything the previous call enqueued.
 mvf_status order_after_previous(mvf_ctx* c, hipStream_t stream)
 {
-    if (c->tail_valid && c->tail_stream != stream) CHECK_HIP(hipStreamWaitEvent(stream, c->tail_ev, 0));
+    if (c->tail_valid && c->tail_stream != stream) {
+        if (c->tail_pending) CHECK_ST(arena_flush(c));
+        CHECK_HIP(hipStreamWaitEvent(stream, c->tail_ev, 0));
+    }
     return MVF_OK;
 }
 
@@ -300,26 +336,23 @@ mvf_status mark_tail(mvf_ctx* c, hipStream_t stream)
     c->tail_ev = c->tail;
     c->tail_stream = stream;
     c->tail_valid = true;
+    c->tail_pending = false;
     return MVF_OK;
 }
 
-// mark_tail with an event just recorded on `stream` behind the call's work
-// (one event record fewer per call)
-mvf_status mark_tail_recorded(mvf_ctx* c, hipStream_t stream, hipEvent_t ev)
-{
-    c->tail_ev = ev;
-    c->tail_stream = stream;
-    c->tail_valid = true;
-    return MVF_OK;
-}
 
 mvf_status arena_acquire(mvf_ctx* c, int* slot, Writer* w)
 {
     Arena& A = c->arena;
     int s = A.next;
     A.next = (A.next + 1) % Arena::kSlots;
+    for (int i = 0; i < A.n_open; ++i)
+        if (A.open[i] == s) {
+            CHECK_ST(arena_flush(c));
+            break;
+        }
     if (A.pending[s]) {
-        CHECK_HIP(hipEventSynchronize(A.ev[s]));
+        CHECK_HIP(hipEventSynchronize(A.wait_ev[s]));
         A.pending[s] = false;
     }
     *slot = s;
@@ -339,8 +372,26 @@ mvf_status arena_upload(mvf_ctx* c, const Writer& w, hipStream_t stream)
 
 mvf_status arena_release(mvf_ctx* c, int slot, hipStream_t stream)
 {
+    CHECK_ST(arena_flush(c));
     CHECK_HIP(hipEventRecord(c->arena.ev[slot], stream));
+    c->arena.wait_ev[slot] = c->arena.ev[slot];
     c->arena.pending[slot] = true;
+    return MVF_OK;
+}
+
+// A captured step's slot: released with the next kBatch - 1 step slots of
+// the same stream behind one event (arena_flush); the call's tail is that
+// event once recorded.
+mvf_status arena_release_step(mvf_ctx* c, int slot, hipStream_t stream)
+{
+    Arena& A = c->arena;
+    if (A.n_open && A.open_stream != stream) CHECK_ST(arena_flush(c));
+    A.open[A.n_open++] = slot;
+    A.open_stream = stream;
+    c->tail_stream = stream;
+    c->tail_valid = true;
+    c->tail_pending = true;
+    if (A.n_open == Arena::kBatch) CHECK_ST(arena_flush(c));
     return MVF_OK;
 }
 
@@ -1491,6 +1542,7 @@ mvf_status mvf_synchronize(mvf_ctx* c)
 {
     if (!c) return set_error(MVF_ERR_INVALID_ARG, "ctx is NULL");
     CHECK_HIP(hipSetDevice(c->device));
+    CHECK_ST(arena_flush(c));
     if (c->tail_valid) CHECK_HIP(hipEventSynchronize(c->tail_ev));
     CHECK_HIP(hipStreamSynchronize(c->d2h_stream));
     CHECK_HIP(hipStreamSynchronize(c->h2d_stream));
@@ -2029,7 +2081,6 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
 
     hipEvent_t t0;
     CHECK_ST(timing_begin(c, s, &t0));
-    int last_slot = -1;
     for (size_t wi = 0; wi < waves.size(); ++wi) {
         const std::vector<int>& wave = waves[wi];
         CHECK_ST(ensure_resident(c, wave, s));
@@ -2183,15 +2234,14 @@ mvf_status mvf_step(mvf_ctx* c, int32_t n, const mvf_stream_frame* frames, const
             c->tuning.ev.push_back(std::make_pair(tune_a, tune_b));
             c->tuning.next += 1;
         }
-        CHECK_ST(arena_release(c, slot, s));  // reused once the replay that reads it is done
-        last_slot = slot;
+        CHECK_ST(arena_release_step(c, slot, s));  // reused once the replay that reads it is done
     }
     CHECK_ST(timing_end(c, s, t0, 2));
     c->last_sched = sch;
     if (tuning) CHECK_ST(finish_tuning(c));
     c->stats.step_launches += 1;
     for (int i = 0; i < n; ++i) c->stats.pixels_raycast += (uint64_t)outs[i].width * outs[i].height;
-    return mark_tail_recorded(c, s, c->arena.ev[last_slot]);
+    return MVF_OK;
 }
 
 mvf_status mvf_set_schedule(mvf_ctx* c, const mvf_schedule* sched)
